@@ -1,0 +1,170 @@
+/*
+ * tg.h — C ABI of the MI355X graph library (libtg.so).
+ *
+ * The library runs the data-parallel hot path of a hybrid bulk-synchronous
+ * (BSP) graph engine — Gharaibeh et al., "Efficient Large-Scale Graph
+ * Processing on Hybrid CPU and GPU Systems" (TOTEM):
+ *   - CSR partitions (section 4.3.1) built by degree centrality (section 6.2),
+ *   - per-partition superstep kernels: BFS frontier expansion (section 6.3.2,
+ *     Figure 11), SSSP relaxation (section 7.3, Figure 20), the PageRank pull
+ *     gather (section 7.1, Figure 14) and Brandes betweenness built from the
+ *     same superstep (section 7.2, Figure 18),
+ *   - boundary messages reduced at the source partition (section 3.4,
+ *     section 4.3.2) and exchanged with a host-thread partition over PCIe
+ *     once per superstep (section 4.1).
+ *
+ * Conventions for every call:
+ *   - Vertex ids at the ABI are the caller's original int32 ids in [0, V).
+ *     V <= INT32_MAX; edge counts and offsets are int64.
+ *   - Every function returns TG_OK (0) or a negative tg_status and, on error,
+ *     sets a thread-local message readable with tg_last_error().  Output
+ *     buffers are undefined after an error.  No C++ exception crosses the ABI.
+ *   - Graphs and partitions are library-owned (opaque handles, freed with
+ *     graph_free / partition_free).  Output buffers are caller-owned device
+ *     memory (for example a torch tensor's data pointer).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Algorithm calls
+ *     enqueue their kernels on it, so they are ordered after the caller's
+ *     earlier work on that stream, and return only when the results are in
+ *     the output buffer (host-blocking).
+ *   - A partition holds per-call scratch memory; calls on one partition must
+ *     not overlap (one host thread at a time per partition).
+ */
+#ifndef TG_H
+#define TG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tg_graph tg_graph;         /* host-resident validated CSR     */
+typedef struct tg_partition tg_partition; /* device (+host) partitions       */
+
+typedef enum {
+  TG_OK = 0,
+  TG_EINVAL = -1,        /* malformed argument or graph                   */
+  TG_ENOMEM = -2,        /* host or device allocation failed              */
+  TG_EDEVICE = -3,       /* a HIP runtime call failed                     */
+  TG_ERANGE = -4,        /* a result does not fit its output type         */
+  TG_EUNSUPPORTED = -5,  /* the request needs data the graph does not have */
+  TG_ETIMEOUT = -6       /* a wait ran out of time                        */
+} tg_status;
+
+/* Partitioning strategies of section 6.3.1: HIGH puts the highest-degree
+ * vertices on the host, LOW the lowest-degree ones, RAND a random subset. */
+enum { TG_PART_HIGH = 0, TG_PART_LOW = 1, TG_PART_RAND = 2 };
+
+/* PageRank treatment of out-degree-0 vertices: UNIFORM spreads their rank
+ * over all vertices (mass is conserved); DROP discards it. */
+enum { TG_PR_DANGLING_UNIFORM = 0, TG_PR_DANGLING_DROP = 1 };
+
+/* graph_load_csr flags */
+#define TG_PTRS_DEVICE 0x1u /* the three arrays are device pointers          */
+#define TG_VALIDATE 0x2u    /* check offsets, ids and weights (O(V + E))      */
+#define TG_SYMMETRIC 0x4u   /* caller asserts u->v in E iff v->u in E (with
+                               equal weights); checked when TG_VALIDATE     */
+
+/* Level / distance value of an unreachable vertex. */
+#define TG_INF INT32_MAX
+
+/* Load a CSR graph (section 4.3.1: offsets array V and destination array E).
+ *   row_offsets  [V+1] int64, row_offsets[0] == 0, non-decreasing,
+ *                row_offsets[V] == num_edges.
+ *   col_indices  [E] int32 destination ids in [0, V).
+ *   weights      [E] int32 edge weights >= 1, or NULL (then sssp() returns
+ *                TG_EUNSUPPORTED).
+ * The arrays are copied; the caller keeps ownership.  Self-loops and
+ * duplicate edges are kept as given.  With TG_PTRS_DEVICE the copy is a
+ * device-to-host transfer enqueued on `stream`.
+ * Errors: TG_EINVAL for a malformed graph (only detected with TG_VALIDATE,
+ * except sizes and NULL pointers, which are always checked), TG_ENOMEM. */
+int graph_load_csr(int64_t num_vertices, int64_t num_edges,
+                   const int64_t *row_offsets, const int32_t *col_indices,
+                   const int32_t *weights, uint32_t flags, void *stream,
+                   tg_graph **out);
+
+/* Partition a loaded graph by degree centrality (section 6.2) and place it
+ * on the device.  Vertices are relabelled in order of decreasing out-degree
+ * so that each degree bin (thread / wavefront / block / multi-block per
+ * vertex) is a contiguous id range.
+ *   strategy        TG_PART_HIGH, TG_PART_LOW or TG_PART_RAND.
+ *   cpu_edge_share  alpha in [0, 1): share of the edges kept on host threads.
+ *                   0 places the whole graph on the GPU.  For alpha > 0 the
+ *                   host partition takes whole vertices, in strategy order,
+ *                   until it holds at least alpha * E edges (section 6.3.1).
+ *   seed            drives TG_PART_RAND only.
+ *   tuning_json     NULL for the built-in degree thresholds, or a JSON object
+ *                   with any of "hub_min_deg", "block_min_deg",
+ *                   "wave_min_deg", "g16_min_deg", "g4_min_deg", "hub_chunk"
+ *                   (as written by the autotuner).
+ * Errors: TG_EINVAL, TG_ENOMEM, TG_EDEVICE. */
+int partition_by_degree(const tg_graph *g, int strategy, double cpu_edge_share,
+                        uint64_t seed, const char *tuning_json,
+                        tg_partition **out);
+
+/* Level-synchronous breadth-first search (section 6.3.2, Figure 11).
+ *   roots     host array of num_roots original vertex ids.
+ *   levels    device int32 [num_roots * V]; row r holds the level of every
+ *             vertex from roots[r] (TG_INF when unreachable).
+ *   parents   NULL, or device int32 [num_roots * V]: parent[root] = root,
+ *             -1 when unreachable, otherwise an in-neighbour one level up
+ *             (the lowest such id in the partition's internal order).
+ * Errors: TG_EINVAL (root out of range, NULL output), TG_ENOMEM, TG_EDEVICE. */
+int bfs(const tg_partition *p, const int32_t *roots, int32_t num_roots,
+        int32_t *levels, int32_t *parents, void *stream);
+
+/* Single-source shortest paths by frontier Bellman-Ford (section 7.3,
+ * Figure 20) over the int32 weights given to graph_load_csr.
+ *   dist      device int32 [num_roots * V] (TG_INF when unreachable).
+ * Errors: TG_EUNSUPPORTED (graph loaded without weights), TG_ERANGE (a
+ * finite distance is >= INT32_MAX), TG_EINVAL, TG_ENOMEM, TG_EDEVICE. */
+int sssp(const tg_partition *p, const int32_t *roots, int32_t num_roots,
+         int32_t *dist, void *stream);
+
+/* PageRank by synchronous power iteration with a pull gather over in-edges
+ * (section 7.1, Figure 14): r_0 = 1/V and
+ *   r_{k+1}(v) = (1 - d)/V + d * (sum_{u->v} r_k(u)/outdeg(u) + D_k/V),
+ * where D_k is the rank held by out-degree-0 vertices (UNIFORM) or 0 (DROP).
+ *   rank      device float [V] receives r_iterations.
+ * Ranks are fp32; sums are accumulated in fp64.
+ * Errors: TG_EINVAL (damping outside [0, 1], iterations < 0, bad mode),
+ * TG_ENOMEM, TG_EDEVICE. */
+int pagerank(const tg_partition *p, float damping, int32_t iterations,
+             int32_t dangling_mode, float *rank, void *stream);
+
+/* Brandes betweenness centrality (section 7.2, Figure 18): a forward BFS
+ * superstep counting shortest paths sigma (fp64, exact below 2^53) and a
+ * backward superstep accumulating dependencies delta (fp32) with the
+ * (1 + delta) term of Brandes' recurrence.
+ *   sources   host array of num_sources original ids (repeats allowed).
+ *   scores    device float [V]: sum over the given sources s of delta_s(v)
+ *             for v != s — ordered pairs, not halved, not normalised.
+ * Errors: TG_EINVAL, TG_ENOMEM, TG_EDEVICE, TG_ERANGE (a path count reached
+ * 2^53, beyond which fp64 counts are no longer exact). */
+int bc(const tg_partition *p, const int32_t *sources, int32_t num_sources,
+       float *scores, void *stream);
+
+void graph_free(tg_graph *g);
+void partition_free(tg_partition *p);
+
+/* Thread-local description of the last failing call on this thread. */
+const char *tg_last_error(void);
+
+/* JSON description of a partition: vertex/edge counts per side, degree-bin
+ * boundaries, boundary (outbox/inbox) sizes with and without reduction, and
+ * the space formula of section 4.3.3.  Returns the needed length (excluding
+ * the terminator) or a negative tg_status. */
+int partition_info(const tg_partition *p, char *json, size_t cap);
+
+/* JSON statistics of the last algorithm call on this thread: supersteps,
+ * per-phase milliseconds (GPU compute, host compute, exchange), bytes
+ * exchanged, relaxations.  Same return convention as partition_info. */
+int tg_last_stats(char *json, size_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TG_H */

@@ -1,0 +1,703 @@
+// C ABI entry points, graph loading and validation, partition by degree
+// centrality (section 6.2), device memory and error reporting.
+#include <hip/hip_runtime.h>
+#include <omp.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "hybrid.h"
+#include "tg_internal.h"
+
+using namespace tg;
+
+// ---------------------------------------------------------------- errors
+namespace {
+thread_local std::string g_err;
+thread_local std::string g_stats;
+}  // namespace
+
+namespace tg {
+
+int set_error(int code, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+void clear_error() { g_err.clear(); }
+
+void stats_reset(const char *algo) {
+  g_stats = std::string("{\"algorithm\":\"") + algo + "\"";
+}
+
+void stats_add(const char *key, double value) {
+  char buf[128];
+  snprintf(buf, sizeof(buf), ",\"%s\":%.17g", key, value);
+  g_stats += buf;
+}
+
+// --------------------------------------------------------- device memory
+int DevArena::alloc(void **p, size_t n) {
+  if (n == 0) n = 256;
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, n);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return set_error(TG_ENOMEM, "hipMalloc(%zu bytes) failed: %s", n, hipGetErrorString(e));
+  }
+  ptrs.push_back(q);
+  bytes += n;
+  *p = q;
+  return TG_OK;
+}
+
+void DevArena::release() {
+  for (void *q : ptrs) (void)hipFree(q);
+  ptrs.clear();
+  bytes = 0;
+}
+
+Workspace::~Workspace() {
+  if (h_plan) (void)hipHostFree(h_plan);
+  if (h_flags) (void)hipHostFree(h_flags);
+  if (h_work) (void)hipHostFree(h_work);
+}
+
+int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
+  if (cap_n == g.n && hub_chunks_needed <= hub_chunks_cap) return TG_OK;
+  arena.release();
+  const int64_t n = g.n;
+  nwords = ((n + 31) / 32 + 1023) / 1024 * 1024;
+  if (nwords == 0) nwords = 1024;
+  TG_TRY(dalloc(arena, &bits_a, nwords));
+  TG_TRY(dalloc(arena, &bits_b, nwords));
+  TG_TRY(dalloc(arena, &bits_c, nwords));
+  TG_TRY(dalloc(arena, &queue, n + 1));
+  TG_TRY(dalloc(arena, &state, n + 1));
+  TG_TRY(dalloc(arena, &cbuf[0], n + 1));
+  TG_TRY(dalloc(arena, &cbuf[1], n + 1));
+  TG_TRY(dalloc(arena, &sigma, n + 1));
+  TG_TRY(dalloc(arena, &delta, n + 1));
+  TG_TRY(dalloc(arena, &bc_acc, n + 1));
+  partials_cap = 16384;
+  TG_TRY(dalloc(arena, &partials, partials_cap));
+  // frontier hub chunks are bounded by E / chunk + (hub vertices)
+  // (hub_chunk >= 256, so a frontier has at most E/256 + hubs chunks)
+  int64_t chunks = std::max<int64_t>(hub_chunks_needed, g.m / 256 + g.max_out_hubs + 1);
+  chunks = std::max<int64_t>(chunks, g.pr.work.vb[1] + 1);
+  hub_chunks_cap = chunks;
+  TG_TRY(dalloc(arena, &hub_partials, chunks));
+  const int64_t hubs = std::max<int64_t>(g.max_out_hubs, g.pr.nh) + 1;
+  TG_TRY(dalloc(arena, &hub_dangling, hubs));
+  TG_TRY(dalloc(arena, &hub_counters, hubs));
+  TG_TRY(dalloc(arena, &hubpref, hubs + 1));
+  TG_TRY(dalloc(arena, &scalars, 16));
+  TG_TRY(dalloc(arena, &counters, 64));
+  TG_TRY(dalloc(arena, &work, 8));
+  TG_TRY(dalloc(arena, &bcount, nwords / 1024 + 1));
+  TG_TRY(dalloc(arena, &plan, 1));
+  TG_HIP(hipMemset(bits_a, 0, nwords * sizeof(uint32_t)));
+  TG_HIP(hipMemset(bits_b, 0, nwords * sizeof(uint32_t)));
+  TG_HIP(hipMemset(bits_c, 0, nwords * sizeof(uint32_t)));
+  TG_HIP(hipMemset(hub_counters, 0, hubs * sizeof(uint32_t)));
+  TG_HIP(hipMemset(counters, 0, 64 * sizeof(uint32_t)));
+  TG_HIP(hipMemset(work, 0, 8 * sizeof(unsigned long long)));
+  if (!h_plan) TG_HIP(hipHostMalloc((void **)&h_plan, sizeof(Plan), hipHostMallocDefault));
+  if (!h_flags) TG_HIP(hipHostMalloc((void **)&h_flags, 64 * sizeof(uint32_t), hipHostMallocDefault));
+  if (!h_work) TG_HIP(hipHostMalloc((void **)&h_work, 8 * sizeof(unsigned long long), hipHostMallocDefault));
+  cap_n = n;
+  return TG_OK;
+}
+
+// ----------------------------------------------------------------- tuning
+Tuning default_tuning() {
+  Tuning t;
+  t.min_deg[tgk::BIN_HUB] = 8192;
+  t.min_deg[tgk::BIN_BLOCK] = 512;
+  t.min_deg[tgk::BIN_WAVE] = 48;
+  t.min_deg[tgk::BIN_G16] = 12;
+  t.min_deg[tgk::BIN_G4] = 3;
+  t.hub_chunk = 4096;
+  return t;
+}
+
+static bool json_int(const char *json, const char *key, int64_t *out) {
+  std::string k = std::string("\"") + key + "\"";
+  const char *p = strstr(json, k.c_str());
+  if (!p) return false;
+  p += k.size();
+  while (*p == ' ' || *p == '\t' || *p == '\n' || *p == ':') ++p;
+  char *end = nullptr;
+  long long v = strtoll(p, &end, 10);
+  if (end == p) return false;
+  *out = v;
+  return true;
+}
+
+int parse_tuning(const char *json, Tuning *t) {
+  *t = default_tuning();
+  if (!json) return TG_OK;
+  const char *keys[5] = {"hub_min_deg", "block_min_deg", "wave_min_deg", "g16_min_deg", "g4_min_deg"};
+  for (int b = 0; b < 5; ++b) {
+    int64_t v;
+    if (json_int(json, keys[b], &v)) t->min_deg[b] = v;
+  }
+  int64_t v;
+  if (json_int(json, "hub_chunk", &v)) t->hub_chunk = v;
+  for (int b = 0; b < 5; ++b)
+    if (t->min_deg[b] < 1) return set_error(TG_EINVAL, "tuning: %s must be >= 1", keys[b]);
+  for (int b = 0; b + 1 < 5; ++b)
+    if (t->min_deg[b] < t->min_deg[b + 1])
+      return set_error(TG_EINVAL, "tuning: degree thresholds must be non-increasing");
+  if (t->hub_chunk < 256) return set_error(TG_EINVAL, "tuning: hub_chunk must be >= 256");
+  return TG_OK;
+}
+
+}  // namespace tg
+
+// ------------------------------------------------------------ graph load
+namespace {
+
+int validate_graph(const tg_graph &g, bool check_sym) {
+  const int64_t n = g.n, m = g.m;
+  if (g.off[0] != 0) return set_error(TG_EINVAL, "row_offsets[0] = %lld, expected 0", (long long)g.off[0]);
+  if (g.off[n] != m)
+    return set_error(TG_EINVAL, "row_offsets[V] = %lld, expected num_edges = %lld", (long long)g.off[n],
+                     (long long)m);
+  for (int64_t v = 0; v < n; ++v)
+    if (g.off[v + 1] < g.off[v])
+      return set_error(TG_EINVAL, "row_offsets decrease at vertex %lld", (long long)v);
+  int64_t bad = -1;
+#pragma omp parallel for schedule(static) reduction(max : bad)
+  for (int64_t e = 0; e < m; ++e)
+    if (g.col[e] < 0 || g.col[e] >= n) bad = std::max(bad, e);
+  if (bad >= 0) return set_error(TG_EINVAL, "col_indices[%lld] = %d is out of range", (long long)bad, g.col[bad]);
+  if (g.has_w) {
+    bad = -1;
+#pragma omp parallel for schedule(static) reduction(max : bad)
+    for (int64_t e = 0; e < m; ++e)
+      if (g.w[e] < 1) bad = std::max(bad, e);
+    if (bad >= 0) return set_error(TG_EINVAL, "weights[%lld] = %d must be >= 1", (long long)bad, g.w[bad]);
+  }
+  if (check_sym) {
+    // every (u, v, w) needs a (v, u, w): look it up in a sorted copy of row v
+    std::vector<int64_t> key((size_t)m);
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t u = 0; u < n; ++u) {
+      for (int64_t e = g.off[u]; e < g.off[u + 1]; ++e)
+        key[e] = ((int64_t)g.col[e] << 32) | (uint32_t)(g.has_w ? g.w[e] : 0);
+      std::sort(key.begin() + g.off[u], key.begin() + g.off[u + 1]);
+    }
+    int64_t miss = -1;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(max : miss)
+    for (int64_t u = 0; u < n; ++u) {
+      for (int64_t e = g.off[u]; e < g.off[u + 1]; ++e) {
+        const int32_t v = g.col[e];
+        const int64_t want = ((int64_t)u << 32) | (uint32_t)(g.has_w ? g.w[e] : 0);
+        if (!std::binary_search(key.begin() + g.off[v], key.begin() + g.off[v + 1], want))
+          miss = std::max(miss, e);
+      }
+    }
+    if (miss >= 0)
+      return set_error(TG_EINVAL, "graph flagged symmetric but edge %lld has no reverse edge of equal weight",
+                       (long long)miss);
+  }
+  return TG_OK;
+}
+
+}  // namespace
+
+extern "C" int graph_load_csr(int64_t num_vertices, int64_t num_edges, const int64_t *row_offsets,
+                              const int32_t *col_indices, const int32_t *weights, uint32_t flags,
+                              void *stream, tg_graph **out) {
+  clear_error();
+  if (!out) return set_error(TG_EINVAL, "graph_load_csr: out is NULL");
+  *out = nullptr;
+  if (num_vertices < 0 || num_vertices > INT32_MAX)
+    return set_error(TG_EINVAL, "num_vertices = %lld outside [0, INT32_MAX]", (long long)num_vertices);
+  if (num_edges < 0) return set_error(TG_EINVAL, "num_edges = %lld < 0", (long long)num_edges);
+  if (!row_offsets) return set_error(TG_EINVAL, "row_offsets is NULL");
+  if (num_edges > 0 && !col_indices) return set_error(TG_EINVAL, "col_indices is NULL");
+  tg_graph *g = new (std::nothrow) tg_graph();
+  if (!g) return set_error(TG_ENOMEM, "graph_load_csr: out of host memory");
+  try {
+    g->n = num_vertices;
+    g->m = num_edges;
+    g->symmetric = (flags & TG_SYMMETRIC) != 0;
+    g->has_w = weights != nullptr;
+    g->off.resize((size_t)num_vertices + 1);
+    g->col.resize((size_t)num_edges);
+    if (g->has_w) g->w.resize((size_t)num_edges);
+  } catch (...) {
+    delete g;
+    return set_error(TG_ENOMEM, "graph_load_csr: out of host memory for %lld edges", (long long)num_edges);
+  }
+  if (flags & TG_PTRS_DEVICE) {
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(g->off.data(), row_offsets, (num_vertices + 1) * sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && num_edges)
+      e = hipMemcpyAsync(g->col.data(), col_indices, num_edges * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && g->has_w && num_edges)
+      e = hipMemcpyAsync(g->w.data(), weights, num_edges * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      delete g;
+      return set_error(TG_EDEVICE, "graph_load_csr: device copy failed: %s", hipGetErrorString(e));
+    }
+  } else {
+    memcpy(g->off.data(), row_offsets, (num_vertices + 1) * sizeof(int64_t));
+    if (num_edges) memcpy(g->col.data(), col_indices, num_edges * sizeof(int32_t));
+    if (g->has_w && num_edges) memcpy(g->w.data(), weights, num_edges * sizeof(int32_t));
+  }
+  if (flags & TG_VALIDATE) {
+    int rc = validate_graph(*g, g->symmetric);
+    if (rc != TG_OK) {
+      delete g;
+      return rc;
+    }
+  } else if (g->off[0] != 0 || g->off[num_vertices] != num_edges) {
+    delete g;
+    return set_error(TG_EINVAL, "row_offsets do not span [0, num_edges]");
+  }
+  *out = g;
+  return TG_OK;
+}
+
+extern "C" void graph_free(tg_graph *g) { delete g; }
+
+// -------------------------------------------------- partition by degree
+namespace {
+
+// Stable counting sort of `ids` by key descending (keys <= maxkey).
+void sort_desc_by_key(const std::vector<int64_t> &key, std::vector<int32_t> &ids) {
+  if (ids.empty()) return;
+  int64_t maxk = 0;
+  for (int32_t v : ids) maxk = std::max(maxk, key[v]);
+  std::vector<int64_t> cnt((size_t)maxk + 2, 0);
+  for (int32_t v : ids) cnt[(size_t)(maxk - key[v]) + 1]++;
+  for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
+  std::vector<int32_t> outv(ids.size());
+  for (int32_t v : ids) outv[(size_t)cnt[(size_t)(maxk - key[v])]++] = v;
+  ids.swap(outv);
+}
+
+// Bin boundaries over a sequence whose degrees are non-increasing.
+BinBounds bins_of(const std::vector<int64_t> &deg_in_order, const Tuning &t) {
+  BinBounds bb;
+  const int64_t n = (int64_t)deg_in_order.size();
+  int64_t i = 0;
+  for (int b = 0; b < NBIN; ++b) {
+    while (i < n && bin_of_degree(deg_in_order[i], t) < b) ++i;
+    bb.bstart[b] = i;
+  }
+  bb.bstart[NBIN] = n;
+  return bb;
+}
+
+// Static plan over all positions 0..n-1 with the given bins and degrees.
+void static_plan(const BinBounds &bb, const std::vector<int64_t> &deg_in_order, const Tuning &t, Plan &work,
+                 Plan &all, std::vector<int64_t> &hubpref) {
+  const int64_t n = (int64_t)deg_in_order.size();
+  memset(&work, 0, sizeof(Plan));
+  work.count = (int32_t)n;
+  for (int b = 0; b <= NBIN; ++b) work.pos[b] = (int32_t)bb.bstart[b];
+  const int64_t nh = bb.bstart[1] - bb.bstart[0];
+  hubpref.assign((size_t)nh + 1, 0);
+  for (int64_t i = 0; i < nh; ++i)
+    hubpref[i + 1] = hubpref[i] + (deg_in_order[i] + t.hub_chunk - 1) / t.hub_chunk;
+  int64_t vb = 0;
+  work.vb[0] = 0;
+  vb += hubpref[nh];
+  work.vb[1] = vb;
+  for (int b = 1; b < NBIN; ++b) {
+    const int64_t cnt = work.pos[b + 1] - work.pos[b];
+    if (b != tgk::BIN_ZERO) vb += (cnt + tgk::verts_per_vblock(b) - 1) / tgk::verts_per_vblock(b);
+    work.vb[b + 1] = vb;
+  }
+  all = work;
+  const int64_t zc = all.pos[NBIN] - all.pos[tgk::BIN_ZERO];
+  all.vb[NBIN] = all.vb[tgk::BIN_ZERO] + (zc + 255) / 256;
+}
+
+template <typename T>
+int upload(tg::DevArena &a, T **dst, const T *src, size_t count) {
+  TG_TRY(dalloc(a, dst, count));
+  if (count) TG_HIP(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return TG_OK;
+}
+
+}  // namespace
+
+namespace tg {
+
+// Build and upload the GPU partition over the vertex subset `verts` (global
+// ids).  Edges to vertices outside the subset are boundary edges: they are
+// returned through `boundary` (per local source, the global destinations and
+// weights) instead of being stored in the local CSR.
+int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryEdges *boundary) {
+  const tg_graph &G = *p->g;
+  GpuPart &gp = p->gpu;
+  const Tuning &t = p->tune;
+  const int64_t V = G.n;
+  // order the subset by decreasing local out-degree (counting sort, stable)
+  std::vector<int32_t> order(verts);
+  std::vector<int32_t> l_of_g((size_t)V, -1);
+  for (size_t i = 0; i < verts.size(); ++i) l_of_g[verts[i]] = 0;  // membership
+  std::vector<int64_t> ldeg((size_t)V, 0);
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < (int64_t)verts.size(); ++i) {
+    const int32_t u = verts[i];
+    int64_t d = 0;
+    for (int64_t e = G.off[u]; e < G.off[u + 1]; ++e) d += (l_of_g[G.col[e]] >= 0) ? 1 : 0;
+    ldeg[u] = d;
+  }
+  sort_desc_by_key(ldeg, order);
+  const int64_t n = (int64_t)order.size();
+  for (int64_t i = 0; i < n; ++i) l_of_g[order[i]] = (int32_t)i;
+  std::vector<int64_t> off((size_t)n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + ldeg[order[i]];
+  const int64_t m = off[n];
+  std::vector<int32_t> col((size_t)m);
+  std::vector<int32_t> w(G.has_w ? (size_t)m : 0);
+  if (boundary) {
+    boundary->src_off.assign((size_t)n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      const int32_t u = order[i];
+      boundary->src_off[i + 1] = boundary->src_off[i] + (G.off[u + 1] - G.off[u]) - ldeg[u];
+    }
+    boundary->dst.resize((size_t)boundary->src_off[n]);
+    boundary->w.resize(G.has_w ? (size_t)boundary->src_off[n] : 0);
+  }
+  int fail = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(| : fail)
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t u = order[i];
+    std::vector<int64_t> tmp;
+    tmp.reserve((size_t)(off[i + 1] - off[i]));
+    int64_t bk = boundary ? boundary->src_off[i] : 0;
+    for (int64_t e = G.off[u]; e < G.off[u + 1]; ++e) {
+      const int32_t l = l_of_g[G.col[e]];
+      const uint32_t wt = G.has_w ? (uint32_t)G.w[e] : 0u;
+      if (l >= 0) {
+        tmp.push_back(((int64_t)l << 32) | wt);
+      } else if (boundary) {
+        boundary->dst[bk] = G.col[e];
+        if (G.has_w) boundary->w[bk] = G.w[e];
+        ++bk;
+      }
+    }
+    std::sort(tmp.begin(), tmp.end());
+    if ((int64_t)tmp.size() != off[i + 1] - off[i]) fail |= 1;
+    for (size_t k = 0; k < tmp.size(); ++k) {
+      col[off[i] + k] = (int32_t)(tmp[k] >> 32);
+      if (G.has_w) w[off[i] + k] = (int32_t)(uint32_t)(tmp[k] & 0xFFFFFFFFu);
+    }
+  }
+  if (fail) return set_error(TG_EINVAL, "partition: inconsistent local degree count");
+
+  gp.n = n;
+  gp.m = m;
+  gp.n_global = V;
+  std::vector<int64_t> deg_in_order((size_t)n);
+  for (int64_t i = 0; i < n; ++i) deg_in_order[i] = off[i + 1] - off[i];
+  gp.out_bins = bins_of(deg_in_order, t);
+  gp.n_dangling = 0;
+  gp.max_out_hubs = gp.out_bins.bstart[1] - gp.out_bins.bstart[0];
+  DevArena &A = p->arena;
+  TG_TRY(upload(A, &gp.out.off, off.data(), (size_t)n + 1));
+  TG_TRY(upload(A, &gp.out.col, col.data(), (size_t)m));
+  if (G.has_w) TG_TRY(upload(A, &gp.out.w, w.data(), (size_t)m));
+  gp.out.n = n;
+  gp.out.m = m;
+  gp.h_out_off = off;
+
+  // in-edges (transpose) unless the whole graph is symmetric and local
+  const bool alias = G.symmetric && !boundary;
+  std::vector<int64_t> in_deg_in_order;
+  std::vector<int32_t> pr_order;
+  if (alias) {
+    gp.in = gp.out;
+    gp.in_alias = true;
+    gp.in_bins = gp.out_bins;
+    in_deg_in_order = deg_in_order;
+    for (int64_t i = 0; i < n; ++i) gp.n_dangling += (deg_in_order[i] == 0);
+    gp.n_isolated = gp.n_dangling;
+  } else {
+    std::vector<int64_t> ioff((size_t)n + 1, 0);
+    for (int64_t e = 0; e < m; ++e) ioff[(size_t)col[e] + 1]++;
+    for (int64_t i = 0; i < n; ++i) ioff[i + 1] += ioff[i];
+    std::vector<int32_t> icol((size_t)m);
+    std::vector<int64_t> cur(ioff.begin(), ioff.end() - 1);
+    for (int64_t u = 0; u < n; ++u)  // sources in increasing order: rows come out sorted
+      for (int64_t e = off[u]; e < off[u + 1]; ++e) icol[(size_t)cur[col[e]]++] = (int32_t)u;
+    TG_TRY(upload(A, &gp.in.off, ioff.data(), (size_t)n + 1));
+    TG_TRY(upload(A, &gp.in.col, icol.data(), (size_t)m));
+    gp.in.n = n;
+    gp.in.m = m;
+    gp.in_alias = false;
+    std::vector<int64_t> indeg((size_t)n);
+    for (int64_t i = 0; i < n; ++i) indeg[i] = ioff[i + 1] - ioff[i];
+    pr_order.resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i) pr_order[i] = (int32_t)i;
+    sort_desc_by_key(indeg, pr_order);
+    in_deg_in_order.resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i) in_deg_in_order[i] = indeg[pr_order[i]];
+    gp.in_bins = bins_of(in_deg_in_order, t);
+    TG_TRY(upload(A, &gp.pr_order, pr_order.data(), (size_t)n));
+    // dangling = local out-degree 0 AND no boundary out-edges
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t bdeg = boundary ? boundary->src_off[i + 1] - boundary->src_off[i] : 0;
+      gp.n_dangling += (deg_in_order[i] == 0 && bdeg == 0);
+    }
+    gp.n_isolated = 0;
+  }
+  // static PageRank plan over in-degree bins
+  std::vector<int64_t> hubpref;
+  static_plan(gp.in_bins, in_deg_in_order, t, gp.pr.work, gp.pr.all, hubpref);
+  gp.pr.nh = (int32_t)(gp.in_bins.bstart[1] - gp.in_bins.bstart[0]);
+  TG_TRY(upload(A, &gp.pr.hubpref, hubpref.data(), hubpref.size()));
+  TG_TRY(upload(A, &gp.pr.d_work, &gp.pr.work, 1));
+  TG_TRY(upload(A, &gp.pr.d_all, &gp.pr.all, 1));
+
+  // id maps
+  p->h_g_of_l = order;
+  p->h_l_of_g = l_of_g;
+  TG_TRY(upload(A, &gp.g_of_l, order.data(), (size_t)std::max<int64_t>(n, 1)));
+  TG_TRY(upload(A, &gp.l_of_g, l_of_g.data(), (size_t)std::max<int64_t>(V, 1)));
+  return TG_OK;
+}
+
+}  // namespace tg
+
+extern "C" int partition_by_degree(const tg_graph *g, int strategy, double alpha, uint64_t seed,
+                                   const char *tuning_json, tg_partition **out) {
+  clear_error();
+  if (!out) return set_error(TG_EINVAL, "partition_by_degree: out is NULL");
+  *out = nullptr;
+  if (!g) return set_error(TG_EINVAL, "partition_by_degree: graph is NULL");
+  if (strategy != TG_PART_HIGH && strategy != TG_PART_LOW && strategy != TG_PART_RAND)
+    return set_error(TG_EINVAL, "unknown partitioning strategy %d", strategy);
+  if (!(alpha >= 0.0 && alpha < 1.0)) return set_error(TG_EINVAL, "cpu_edge_share %g outside [0, 1)", alpha);
+  tg_partition *p = new (std::nothrow) tg_partition();
+  if (!p) return set_error(TG_ENOMEM, "partition_by_degree: out of host memory");
+  p->g = g;
+  p->strategy = strategy;
+  p->alpha = alpha;
+  int rc = parse_tuning(tuning_json, &p->tune);
+  if (rc == TG_OK) rc = (hipGetDevice(&p->device) == hipSuccess) ? TG_OK : set_error(TG_EDEVICE, "no HIP device");
+  if (rc == TG_OK) {
+    try {
+      if (alpha == 0.0) {
+        std::vector<int32_t> all((size_t)g->n);
+        for (int64_t v = 0; v < g->n; ++v) all[v] = (int32_t)v;
+        rc = build_gpu_part(p, all, nullptr);
+      } else {
+        rc = build_hybrid(p, seed);
+      }
+    } catch (const std::bad_alloc &) {
+      rc = set_error(TG_ENOMEM, "partition_by_degree: out of host memory");
+    }
+  }
+  if (rc != TG_OK) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return TG_OK;
+}
+
+extern "C" void partition_free(tg_partition *p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  hybrid_free(p);
+  delete p;
+}
+
+extern "C" const char *tg_last_error(void) { return g_err.c_str(); }
+
+static int emit(const std::string &s, char *buf, size_t cap) {
+  if (buf && cap) {
+    size_t k = std::min(cap - 1, s.size());
+    memcpy(buf, s.data(), k);
+    buf[k] = 0;
+  }
+  return (int)s.size();
+}
+
+extern "C" int tg_last_stats(char *json, size_t cap) {
+  std::string s = g_stats.empty() ? std::string("{}") : g_stats + "}";
+  return emit(s, json, cap);
+}
+
+extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
+  clear_error();
+  if (!p) return set_error(TG_EINVAL, "partition_info: partition is NULL");
+  const GpuPart &g = p->gpu;
+  char buf[4096];
+  std::string s = "{";
+  snprintf(buf, sizeof(buf),
+           "\"V\":%lld,\"E\":%lld,\"strategy\":%d,\"cpu_edge_share\":%.6f,\"gpu_vertices\":%lld,"
+           "\"gpu_edges\":%lld,\"gpu_device_bytes\":%zu,\"symmetric\":%s,\"dangling\":%lld,",
+           (long long)p->g->n, (long long)p->g->m, p->strategy, p->alpha, (long long)g.n, (long long)g.m,
+           p->arena.bytes, p->g->symmetric ? "true" : "false", (long long)g.n_dangling);
+  s += buf;
+  s += "\"out_bins\":[";
+  for (int b = 0; b <= NBIN; ++b) {
+    snprintf(buf, sizeof(buf), "%s%lld", b ? "," : "", (long long)g.out_bins.bstart[b]);
+    s += buf;
+  }
+  s += "],\"in_bins\":[";
+  for (int b = 0; b <= NBIN; ++b) {
+    snprintf(buf, sizeof(buf), "%s%lld", b ? "," : "", (long long)g.in_bins.bstart[b]);
+    s += buf;
+  }
+  snprintf(buf, sizeof(buf),
+           "],\"tuning\":{\"hub_min_deg\":%lld,\"block_min_deg\":%lld,\"wave_min_deg\":%lld,"
+           "\"g16_min_deg\":%lld,\"g4_min_deg\":%lld,\"hub_chunk\":%lld}",
+           (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
+           (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk);
+  s += buf;
+  s += hybrid_info_json(p);
+  s += "}";
+  return emit(s, json, cap);
+}
+
+// ---------------------------------------------------------- algorithms
+namespace {
+
+int check_call(const tg_partition *p, const void *out, const char *name) {
+  if (!p) return set_error(TG_EINVAL, "%s: partition is NULL", name);
+  if (!out && p->g->n > 0) return set_error(TG_EINVAL, "%s: output buffer is NULL", name);
+  if (hipSetDevice(p->device) != hipSuccess) return set_error(TG_EDEVICE, "%s: hipSetDevice failed", name);
+  return TG_OK;
+}
+
+int check_roots(const tg_partition *p, const int32_t *roots, int32_t nr, const char *name) {
+  if (nr < 0) return set_error(TG_EINVAL, "%s: negative root count", name);
+  if (nr > 0 && !roots) return set_error(TG_EINVAL, "%s: roots is NULL", name);
+  for (int32_t i = 0; i < nr; ++i)
+    if (roots[i] < 0 || roots[i] >= p->g->n)
+      return set_error(TG_EINVAL, "%s: root %d out of range [0, %lld)", name, roots[i], (long long)p->g->n);
+  return TG_OK;
+}
+
+}  // namespace
+
+extern "C" int bfs(const tg_partition *pc, const int32_t *roots, int32_t num_roots, int32_t *levels,
+                   int32_t *parents, void *stream) {
+  clear_error();
+  TG_TRY(check_call(pc, levels, "bfs"));
+  TG_TRY(check_roots(pc, roots, num_roots, "bfs"));
+  tg_partition *p = const_cast<tg_partition *>(pc);
+  hipStream_t s = (hipStream_t)stream;
+  stats_reset("bfs");
+  ktimer_reset();
+  if (p->alpha > 0.0) return hybrid_bfs(p, roots, num_roots, levels, parents, s);
+  const int64_t V = p->g->n;
+  int64_t supersteps = 0;
+  TG_TRY(p->ws.ensure(p->gpu, 0));
+  TG_HIP(hipMemsetAsync(p->ws.work, 0, 8 * sizeof(unsigned long long), s));
+  for (int32_t r = 0; r < num_roots; ++r) {
+    const int32_t l = p->h_l_of_g[roots[r]];
+    int64_t depth = 0;
+    TG_TRY(gpu_bfs(p, l, s, &depth));
+    supersteps += depth + 1;
+    TG_TRY(collect_levels(p->gpu, p->ws.bits_a, p->ws.state, levels + (int64_t)r * V, s));
+    if (parents) TG_TRY(bfs_parents(p->gpu, p->ws.bits_a, p->ws.state, l, parents + (int64_t)r * V, s));
+  }
+  TG_HIP(hipMemcpyAsync(p->ws.h_work, p->ws.work, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  TG_HIP(hipStreamSynchronize(s));
+  stats_add("roots", num_roots);
+  stats_add("supersteps", (double)supersteps);
+  stats_add("edges_scanned", (double)p->ws.h_work[0]);
+  stats_add("vertices_expanded", (double)p->ws.h_work[1]);
+  ktimer_emit();
+  return TG_OK;
+}
+
+extern "C" int sssp(const tg_partition *pc, const int32_t *roots, int32_t num_roots, int32_t *dist,
+                    void *stream) {
+  clear_error();
+  TG_TRY(check_call(pc, dist, "sssp"));
+  TG_TRY(check_roots(pc, roots, num_roots, "sssp"));
+  if (!pc->g->has_w) return set_error(TG_EUNSUPPORTED, "sssp: the graph was loaded without weights");
+  tg_partition *p = const_cast<tg_partition *>(pc);
+  hipStream_t s = (hipStream_t)stream;
+  stats_reset("sssp");
+  ktimer_reset();
+  if (p->alpha > 0.0) return hybrid_sssp(p, roots, num_roots, dist, s);
+  const int64_t V = p->g->n;
+  int64_t rounds_total = 0;
+  TG_TRY(p->ws.ensure(p->gpu, 0));
+  TG_HIP(hipMemsetAsync(p->ws.work, 0, 8 * sizeof(unsigned long long), s));
+  for (int32_t r = 0; r < num_roots; ++r) {
+    int64_t rounds = 0;
+    TG_TRY(gpu_sssp(p, p->h_l_of_g[roots[r]], s, &rounds));
+    rounds_total += rounds;
+    TG_TRY(collect_i32(p->gpu, p->ws.state, dist + (int64_t)r * V, s));
+  }
+  TG_HIP(hipMemcpyAsync(p->ws.h_work, p->ws.work, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  TG_HIP(hipStreamSynchronize(s));
+  stats_add("roots", num_roots);
+  stats_add("supersteps", (double)rounds_total);
+  stats_add("relaxations", (double)p->ws.h_work[0]);
+  stats_add("activations", (double)p->ws.h_work[1]);
+  ktimer_emit();
+  return TG_OK;
+}
+
+extern "C" int pagerank(const tg_partition *pc, float damping, int32_t iterations, int32_t dangling_mode,
+                        float *rank, void *stream) {
+  clear_error();
+  TG_TRY(check_call(pc, rank, "pagerank"));
+  if (!(damping >= 0.0f && damping <= 1.0f)) return set_error(TG_EINVAL, "pagerank: damping %g outside [0, 1]", damping);
+  if (iterations < 0) return set_error(TG_EINVAL, "pagerank: iterations < 0");
+  if (dangling_mode != TG_PR_DANGLING_UNIFORM && dangling_mode != TG_PR_DANGLING_DROP)
+    return set_error(TG_EINVAL, "pagerank: unknown dangling mode %d", dangling_mode);
+  tg_partition *p = const_cast<tg_partition *>(pc);
+  hipStream_t s = (hipStream_t)stream;
+  stats_reset("pagerank");
+  ktimer_reset();
+  if (p->g->n == 0) return TG_OK;
+  if (p->alpha > 0.0) return hybrid_pagerank(p, damping, iterations, dangling_mode, rank, s);
+  TG_TRY(gpu_pagerank(p, (double)damping, iterations, dangling_mode, rank, s));
+  TG_HIP(hipStreamSynchronize(s));
+  stats_add("supersteps", iterations);
+  ktimer_emit();
+  return TG_OK;
+}
+
+extern "C" int bc(const tg_partition *pc, const int32_t *sources, int32_t num_sources, float *scores,
+                  void *stream) {
+  clear_error();
+  TG_TRY(check_call(pc, scores, "bc"));
+  TG_TRY(check_roots(pc, sources, num_sources, "bc"));
+  tg_partition *p = const_cast<tg_partition *>(pc);
+  hipStream_t s = (hipStream_t)stream;
+  stats_reset("bc");
+  ktimer_reset();
+  if (p->alpha > 0.0) return set_error(TG_EUNSUPPORTED, "bc: hybrid (cpu_edge_share > 0) partitions run bfs, sssp and pagerank only");
+  TG_TRY(p->ws.ensure(p->gpu, 0));
+  TG_TRY(fill_f64(p->ws.bc_acc, p->gpu.n, 0.0, s));
+  TG_HIP(hipMemsetAsync(p->ws.counters, 0, 64 * sizeof(uint32_t), s));
+  for (int32_t i = 0; i < num_sources; ++i) TG_TRY(gpu_bc_source(p, p->h_l_of_g[sources[i]], s));
+  TG_TRY(collect_f64_to_f32(p->gpu, p->ws.bc_acc, scores, s));
+  TG_HIP(hipMemcpyAsync(p->ws.h_flags, p->ws.counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  TG_HIP(hipStreamSynchronize(s));
+  if (p->ws.h_flags[2]) return set_error(TG_ERANGE, "bc: a shortest-path count reached 2^53");
+  stats_add("sources", num_sources);
+  ktimer_emit();
+  return TG_OK;
+}

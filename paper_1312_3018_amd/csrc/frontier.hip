@@ -1,0 +1,169 @@
+// Frontier compaction and planning.
+//
+// Each superstep's next frontier is a bitmap (one bit per local vertex).  It is
+// compacted into a queue sorted by vertex id with a block-wide prefix scan over
+// per-thread popcounts; because local ids are in decreasing-degree order, the
+// queue is also sorted by degree and each degree bin is one queue segment.  The
+// plan kernel then turns segment lengths into virtual-block counts (how many
+// 256-thread blocks each bin needs) and, for hub vertices, a prefix over their
+// edge chunks.
+#include "tg_internal.h"
+
+using namespace tgk;
+
+namespace {
+
+constexpr int WPT = 4;                     // bitmap words per thread
+constexpr int WPB = WPT * BLOCK;           // words per block (1024)
+
+__global__ __launch_bounds__(BLOCK) void k_compact_count(const uint32_t *__restrict__ bits,
+                                                         const uint32_t *__restrict__ prev,
+                                                         uint32_t *__restrict__ bcount) {
+  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // uint4 index
+  uint4 v = reinterpret_cast<const uint4 *>(bits)[q];
+  if (prev) {
+    uint4 p = reinterpret_cast<const uint4 *>(prev)[q];
+    v.x &= ~p.x; v.y &= ~p.y; v.z &= ~p.z; v.w &= ~p.w;
+  }
+  uint32_t c = __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+  c = block_sum(c);
+  if (threadIdx.x == 0) bcount[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ bits, uint32_t *__restrict__ prev,
+                                                         int mode, const uint32_t *__restrict__ bcount,
+                                                         int32_t *__restrict__ queue, int32_t *__restrict__ level,
+                                                         int32_t level_value, BinBounds bb, int64_t n,
+                                                         Plan *__restrict__ plan) {
+  // this block's offset: sum of the counts of all earlier blocks
+  uint32_t part = 0;
+  for (uint32_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) part += bcount[i];
+  const uint32_t base = block_sum(part);
+
+  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int64_t w0 = q * WPT;
+  uint4 v = reinterpret_cast<uint4 *>(bits)[q];
+  uint32_t nw[4] = {v.x, v.y, v.z, v.w};
+  if (mode == 0) {
+    uint4 p = reinterpret_cast<uint4 *>(prev)[q];
+    nw[0] &= ~p.x; nw[1] &= ~p.y; nw[2] &= ~p.z; nw[3] &= ~p.w;
+    reinterpret_cast<uint4 *>(prev)[q] = v;  // prev := visited
+  } else {
+    reinterpret_cast<uint4 *>(bits)[q] = make_uint4(0, 0, 0, 0);
+  }
+  const uint32_t cnt = __popc(nw[0]) + __popc(nw[1]) + __popc(nw[2]) + __popc(nw[3]);
+  uint32_t total;
+  const uint32_t excl = base + block_exclusive_scan(cnt, total);
+
+  // queue positions of the bin boundaries that fall inside this thread's words
+#pragma unroll
+  for (int b = 0; b < NBIN; ++b) {
+    const int64_t t = bb.bstart[b];
+    if (t < n && (t >> 5) >= w0 && (t >> 5) < w0 + WPT) {
+      const int k = (int)((t >> 5) - w0);
+      uint32_t before = 0;
+      for (int j = 0; j < k; ++j) before += __popc(nw[j]);
+      before += __popc(nw[k] & ((1u << (t & 31)) - 1u));
+      plan->pos[b] = (int32_t)(excl + before);
+    }
+  }
+  uint32_t o = excl;
+#pragma unroll
+  for (int k = 0; k < WPT; ++k) {
+    uint32_t w = nw[k];
+    while (w) {
+      const int bit = __ffs(w) - 1;
+      const int32_t vtx = (int32_t)((w0 + k) * 32 + bit);
+      queue[o++] = vtx;
+      if (level) level[vtx] = level_value;
+      w &= w - 1;
+    }
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == BLOCK - 1) plan->count = (int32_t)o;
+}
+
+// One block: fix up empty-tail positions, hub chunk prefix, virtual blocks.
+__global__ __launch_bounds__(BLOCK) void k_plan(Plan *__restrict__ plan, BinBounds bb, int64_t n,
+                                                const int32_t *__restrict__ queue,
+                                                const int64_t *__restrict__ off, int64_t hub_chunk,
+                                                int64_t *__restrict__ hubpref, int include_zero) {
+  __shared__ int32_t pos[NBIN + 1];
+  const int32_t count = plan->count;
+  if (threadIdx.x <= NBIN) {
+    const int b = threadIdx.x;
+    pos[b] = (b == NBIN || bb.bstart[b] >= n) ? count : plan->pos[b];
+  }
+  __syncthreads();
+  const int32_t nh = pos[1] - pos[0];
+  // exclusive prefix of ceil(deg / hub_chunk) over the hub segment
+  uint32_t carry = 0;  // fits: chunks <= E / hub_chunk
+  int64_t carry64 = 0;
+  for (int32_t i0 = 0; i0 < nh; i0 += BLOCK) {
+    const int32_t i = i0 + threadIdx.x;
+    uint32_t c = 0;
+    if (i < nh) {
+      const int32_t v = queue ? queue[pos[0] + i] : pos[0] + i;
+      const int64_t d = off[v + 1] - off[v];
+      c = (uint32_t)((d + hub_chunk - 1) / hub_chunk);
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(c, tot);
+    if (i < nh) hubpref[i] = carry64 + ex;
+    carry64 += tot;
+    (void)carry;
+  }
+  if (threadIdx.x == 0) {
+    hubpref[nh] = carry64;
+    int64_t vb = 0;
+    plan->vb[0] = 0;
+    vb += carry64;
+    plan->vb[1] = vb;
+    for (int b = 1; b < NBIN; ++b) {
+      const int64_t cnt = pos[b + 1] - pos[b];
+      if (b != BIN_ZERO || include_zero) vb += (cnt + verts_per_vblock(b) - 1) / verts_per_vblock(b);
+      plan->vb[b + 1] = vb;
+    }
+    for (int b = 0; b <= NBIN; ++b) plan->pos[b] = pos[b];
+  }
+}
+
+}  // namespace
+
+namespace tg {
+
+int launch_grid(int64_t vblocks) {
+  const int64_t cap = 16384;
+  if (vblocks < 1) return 1;
+  return (int)(vblocks < cap ? vblocks : cap);
+}
+
+int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, uint32_t *prev,
+                     int32_t *queue, int32_t *level, int32_t level_value, hipStream_t s) {
+  const int blocks = (int)(ws.nwords / WPB);
+  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, bits,
+                     mode == 0 ? prev : nullptr, ws.bcount);
+  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, bits, prev, mode,
+                     ws.bcount, queue, level, level_value, g.out_bins, g.n, ws.plan);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int frontier_plan(const GpuPart &g, Workspace &ws, const int32_t *queue, const Tuning &t,
+                  hipStream_t s, bool sync) {
+  return frontier_plan_off(g, ws, queue, g.out.off, t, s, sync, false);
+}
+
+int frontier_plan_off(const GpuPart &g, Workspace &ws, const int32_t *queue, const int64_t *off,
+                      const Tuning &t, hipStream_t s, bool sync, bool include_zero) {
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(BLOCK), 0, s, ws.plan, g.out_bins, g.n, queue,
+                     off, t.hub_chunk, ws.hubpref, include_zero ? 1 : 0);
+  TG_HIP(hipGetLastError());
+  if (sync) {
+    TG_HIP(hipMemcpyAsync(ws.h_plan, ws.plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
+    TG_HIP(hipStreamSynchronize(s));
+    ktimer_flush();
+  }
+  return TG_OK;
+}
+
+}  // namespace tg

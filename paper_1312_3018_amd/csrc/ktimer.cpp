@@ -1,0 +1,91 @@
+// Optional per-kernel timing with HIP events recorded on the launching
+// stream (enabled by the TG_TIMING environment variable).  Results appear in
+// tg_last_stats() as "<kernel>_ms" (summed duration) and "<kernel>_n"
+// (launches).
+#include <stdlib.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "tg_internal.h"
+
+namespace tg {
+namespace {
+
+struct Pending {
+  const char *name;
+  size_t a, b;
+};
+
+struct TimerState {
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<Pending> pending;
+  std::map<std::string, std::pair<double, long long>> acc;
+};
+
+thread_local TimerState g_t;
+
+hipEvent_t take() {
+  if (g_t.used == g_t.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_t.pool.push_back(e);
+  }
+  return g_t.pool[g_t.used++];
+}
+
+}  // namespace
+
+bool timing_enabled() {
+  static const bool on = getenv("TG_TIMING") != nullptr && getenv("TG_TIMING")[0] != '0';
+  return on;
+}
+
+int ktimer_start(hipStream_t s) {
+  if (!timing_enabled()) return -1;
+  hipEvent_t e = take();
+  if (!e) return -1;
+  (void)hipEventRecord(e, s);
+  return (int)(g_t.used - 1);
+}
+
+void ktimer_stop(int start, hipStream_t s, const char *name) {
+  if (start < 0) return;
+  hipEvent_t e = take();
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  g_t.pending.push_back({name, (size_t)start, g_t.used - 1});
+}
+
+void ktimer_flush() {
+  if (!timing_enabled()) return;
+  for (const Pending &p : g_t.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(g_t.pool[p.b]) == hipSuccess &&
+        hipEventElapsedTime(&ms, g_t.pool[p.a], g_t.pool[p.b]) == hipSuccess) {
+      auto &a = g_t.acc[p.name];
+      a.first += ms;
+      a.second += 1;
+    }
+  }
+  g_t.pending.clear();
+  g_t.used = 0;
+}
+
+void ktimer_reset() {
+  ktimer_flush();
+  g_t.acc.clear();
+}
+
+void ktimer_emit() {
+  ktimer_flush();
+  for (auto &kv : g_t.acc) {
+    stats_add((kv.first + "_ms").c_str(), kv.second.first);
+    stats_add((kv.first + "_n").c_str(), (double)kv.second.second);
+  }
+  g_t.acc.clear();
+}
+
+}  // namespace tg

@@ -1,0 +1,137 @@
+// SSSP superstep: frontier Bellman-Ford (section 7.3, Figure 20).  Every
+// active vertex relaxes its out-edges with an atomic minimum on the
+// neighbour's distance; a neighbour whose distance dropped becomes active for
+// the next superstep.  The run ends when no vertex is active.
+//
+// Activation follows the returned previous value of the atomic minimum (the
+// neighbour is activated iff the minimum actually lowered it), so an update
+// is never lost to a concurrent writer.
+//
+// Distances are int32 with INT32_MAX meaning unreachable.  A candidate
+// distance >= INT32_MAX is never stored; the vertex is marked in an overflow
+// bitmap instead, and the call fails with TG_ERANGE if such a vertex ends up
+// without a finite distance (its true distance does not fit in int32).
+#include "tg_internal.h"
+
+using namespace tgk;
+
+namespace {
+
+__global__ void k_set_i32(int32_t *p, int64_t i, int32_t v) {
+  if (threadIdx.x == 0) p[i] = v;
+}
+
+__device__ __forceinline__ void relax(int32_t *dist, uint32_t *active, uint32_t *ovf, uint32_t *flags,
+                                      int32_t dv, int32_t nb, int32_t wt) {
+  const int64_t nd = (int64_t)dv + (int64_t)wt;
+  const uint32_t bit = 1u << (nb & 31);
+  if (nd >= (int64_t)TG_INF) {
+    // cannot improve a finite distance; matters only if nb stays unreached
+    if (dist[nb] == TG_INF) {
+      atomicOr(ovf + (nb >> 5), bit);
+      flags[0] = 1u;
+    }
+    return;
+  }
+  if (nd < (int64_t)dist[nb]) {
+    const int32_t old = atomicMin(dist + nb, (int32_t)nd);
+    if (nd < (int64_t)old) atomicOr(active + (nb >> 5), bit);
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ Pp,
+                                                      const int32_t *__restrict__ queue,
+                                                      const int64_t *__restrict__ hubpref,
+                                                      const int64_t *__restrict__ off,
+                                                      const int32_t *__restrict__ col,
+                                                      const int32_t *__restrict__ wgt, int32_t *dist,
+                                                      uint32_t *active, uint32_t *ovf, uint32_t *flags,
+                                                      int64_t hub_chunk, unsigned long long *work) {
+  const Plan P = *Pp;
+  const int64_t total = P.vb[NBIN];
+  unsigned long long n_edges = 0, n_verts = 0;
+  for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    const Assign a = assign_work(vb, P, queue, nullptr, hubpref, off, hub_chunk);
+    if (!a.ok) continue;
+    if (a.lane == 0) {
+      n_edges += (unsigned long long)(a.e_end - a.e_begin);
+      n_verts += (a.bin != BIN_HUB || a.e_begin == off[a.v]) ? 1 : 0;
+    }
+    const int32_t dv = dist[a.v];
+    const int64_t st = a.stride;
+    int64_t e = a.e_begin + a.lane;
+    for (; e + st < a.e_end; e += 2 * st) {
+      const int32_t n0 = col[e], n1 = col[e + st];
+      const int32_t w0 = wgt[e], w1 = wgt[e + st];
+      relax(dist, active, ovf, flags, dv, n0, w0);
+      relax(dist, active, ovf, flags, dv, n1, w1);
+    }
+    if (e < a.e_end) relax(dist, active, ovf, flags, dv, col[e], wgt[e]);
+  }
+  n_edges = block_sum(n_edges);
+  n_verts = block_sum(n_verts);
+  if (threadIdx.x == 0 && n_edges + n_verts > 0) {
+    atomicAdd(work, n_edges);
+    atomicAdd(work + 1, n_verts);
+  }
+}
+
+// flags[1] = 1 if some vertex with an overflowing candidate stayed unreached
+__global__ __launch_bounds__(BLOCK) void k_overflow_check(const uint32_t *__restrict__ ovf,
+                                                          const int32_t *__restrict__ dist, int64_t n,
+                                                          uint32_t *flags) {
+  const int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (v >= n) return;
+  if (((ovf[v >> 5] >> (v & 31)) & 1u) && dist[v] == TG_INF) flags[1] = 1u;
+}
+
+}  // namespace
+
+namespace tg {
+
+int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) {
+  GpuPart &g = p->gpu;
+  Workspace &ws = p->ws;
+  if (!g.out.w) return set_error(TG_EUNSUPPORTED, "sssp: the graph was loaded without weights");
+  TG_TRY(ws.ensure(g, 0));
+  uint32_t *active = ws.bits_a, *ovf = ws.bits_c;
+  int32_t *dist = ws.state;
+  TG_TRY(fill_i32(dist, g.n, TG_INF, s));
+  hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, s, dist, (int64_t)root, 0);
+  TG_HIP(hipMemsetAsync(active, 0, ws.nwords * sizeof(uint32_t), s));
+  TG_HIP(hipMemsetAsync(ovf, 0, ws.nwords * sizeof(uint32_t), s));
+  TG_HIP(hipMemsetAsync(ws.counters, 0, 4 * sizeof(uint32_t), s));
+  TG_TRY(set_bit(active, root, s));
+  int64_t rounds = 0;
+  for (;; ++rounds) {
+    // a frontier Bellman-Ford settles within |V| - 1 rounds
+    if (rounds > g.n) return set_error(TG_EDEVICE, "sssp: no convergence after %lld rounds", (long long)rounds);
+    TG_TRY(frontier_compact(g, ws, 1, active, nullptr, ws.queue, nullptr, 0, s));
+    TG_TRY(frontier_plan(g, ws, ws.queue, p->tune, s, true));
+    if (ws.h_plan->count == 0) break;
+    const int64_t vbs = ws.h_plan->vb[NBIN];
+    if (vbs > 0) {
+      const int tk = ktimer_start(s);
+      hipLaunchKernelGGL(k_sssp_relax, dim3(launch_grid(vbs)), dim3(BLOCK), 0, s, ws.plan, ws.queue,
+                         ws.hubpref, g.out.off, g.out.col, g.out.w, dist, active, ovf, ws.counters,
+                         p->tune.hub_chunk, ws.work);
+      ktimer_stop(tk, s, "sssp_relax");
+      TG_HIP(hipGetLastError());
+    }
+  }
+  TG_HIP(hipMemcpyAsync(ws.h_flags, ws.counters, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  TG_HIP(hipStreamSynchronize(s));
+  if (ws.h_flags[0]) {
+    hipLaunchKernelGGL(k_overflow_check, dim3((unsigned)((g.n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s,
+                       ovf, dist, g.n, ws.counters);
+    TG_HIP(hipGetLastError());
+    TG_HIP(hipMemcpyAsync(ws.h_flags, ws.counters, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    TG_HIP(hipStreamSynchronize(s));
+    if (ws.h_flags[1])
+      return set_error(TG_ERANGE, "sssp: a shortest-path distance does not fit below INT32_MAX");
+  }
+  if (rounds_out) *rounds_out = rounds;
+  return TG_OK;
+}
+
+}  // namespace tg

@@ -1,0 +1,224 @@
+// Host-side internals of libtg: graph and partition objects, device
+// workspace, error reporting and the launchers each kernel file provides.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tg.h"
+#include "kcommon.h"
+
+using tgk::BinBounds;
+using tgk::NBIN;
+using tgk::Plan;
+
+// ------------------------------------------------------------------ errors
+namespace tg {
+// per-kernel event timing (ktimer.cpp); no-ops unless TG_TIMING is set
+bool timing_enabled();
+int ktimer_start(hipStream_t s);
+void ktimer_stop(int start, hipStream_t s, const char *name);
+void ktimer_flush();  // after a stream sync: fold pending event pairs into totals
+void ktimer_reset();
+void ktimer_emit();   // add totals to the call's stats
+int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+void stats_reset(const char *algo);
+void stats_add(const char *key, double value);
+}  // namespace tg
+
+#define TG_HIP(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return tg::set_error(TG_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define TG_TRY(expr)          \
+  do {                        \
+    int rc_ = (expr);         \
+    if (rc_ != TG_OK) return rc_; \
+  } while (0)
+
+namespace tg {
+
+// Degree thresholds of the bins (minimum degree of bins HUB..G4; G1 starts
+// at degree 1) and the edges per HUB chunk.
+struct Tuning {
+  int64_t min_deg[tgk::BIN_G1];  // HUB, BLOCK, WAVE, G16, G4
+  int64_t hub_chunk;
+};
+Tuning default_tuning();
+int parse_tuning(const char *json, Tuning *t);
+
+// Bin of a vertex with degree d.
+inline int bin_of_degree(int64_t d, const Tuning &t) {
+  if (d == 0) return tgk::BIN_ZERO;
+  for (int b = 0; b < tgk::BIN_G1; ++b)
+    if (d >= t.min_deg[b]) return b;
+  return tgk::BIN_G1;
+}
+
+// ------------------------------------------------------------ device memory
+struct DevArena {
+  std::vector<void *> ptrs;
+  size_t bytes = 0;
+  int alloc(void **p, size_t n);  // zero-size -> 256 bytes
+  void release();
+  ~DevArena() { release(); }
+};
+
+template <typename T>
+int dalloc(DevArena &a, T **p, size_t count) {
+  return a.alloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+
+// ------------------------------------------------------------ graph object
+}  // namespace tg
+
+struct tg_graph {
+  int64_t n = 0, m = 0;
+  bool symmetric = false;
+  bool has_w = false;
+  std::vector<int64_t> off;
+  std::vector<int32_t> col;
+  std::vector<int32_t> w;
+};
+
+namespace tg {
+
+// A CSR in device memory with a static plan over all of its vertices.
+struct DevCSR {
+  int64_t n = 0, m = 0;
+  int64_t *off = nullptr;
+  int32_t *col = nullptr;
+  int32_t *w = nullptr;
+};
+
+// Static plan over every vertex of a partition (PageRank walks all of them).
+struct StaticPlan {
+  Plan work;               // bins HUB..G1 (ZERO skipped)
+  Plan all;                // bins HUB..ZERO
+  int64_t *hubpref = nullptr;  // device, nh + 1 entries
+  Plan *d_work = nullptr, *d_all = nullptr;
+  int32_t nh = 0;
+};
+
+// The GPU partition: local ids 0..n-1 in decreasing out-degree order.
+struct GpuPart {
+  int64_t n = 0, m = 0;          // local vertices, local edges
+  int64_t n_global = 0;          // vertices of the whole graph
+  DevCSR out;                    // out-edges (local ids); weights if any
+  DevCSR in;                     // in-edges (aliases `out` when symmetric)
+  bool in_alias = true;
+  int32_t *pr_order = nullptr;   // positions -> vertex, by decreasing in-degree (null: identity)
+  int32_t *g_of_l = nullptr;     // local -> global id
+  int32_t *l_of_g = nullptr;     // global -> local id or -1 (size V)
+  BinBounds out_bins{};          // out-degree bins over local ids
+  BinBounds in_bins{};           // in-degree bins over pr_order positions
+  StaticPlan pr;                 // PageRank plan over in-degree bins
+  int64_t n_dangling = 0;        // vertices with out-degree 0
+  int64_t n_isolated = 0;        // out-degree 0 and in-degree 0 (ZERO bin of in_bins when symmetric)
+  int64_t max_out_hubs = 0;      // vertices in the HUB bin (out-degree)
+  std::vector<int64_t> h_out_off;  // host copy of the local out offsets
+};
+
+// Per-partition scratch, grown on demand.
+struct Workspace {
+  DevArena arena;
+  int64_t cap_n = -1;
+  int64_t nwords = 0;            // bitmap words, padded to a multiple of 1024
+  uint32_t *bits_a = nullptr, *bits_b = nullptr, *bits_c = nullptr;
+  int32_t *queue = nullptr;      // n entries (BC: all levels back to back)
+  int32_t *state = nullptr;      // levels / distances (n)
+  float *cbuf[2] = {nullptr, nullptr};
+  double *sigma = nullptr;       // BC path counts (n)
+  float *delta = nullptr;        // BC dependencies (n)
+  double *bc_acc = nullptr;      // BC scores accumulated over sources (n)
+  double *partials = nullptr;    // per-block partial sums
+  double *hub_partials = nullptr;  // per-hub-chunk partial sums
+  double *hub_dangling = nullptr;
+  double *scalars = nullptr;     // small fp64 cells (dangling sums, ...)
+  uint32_t *counters = nullptr;  // small counters and flags (zeroed)
+  unsigned long long *work = nullptr;  // [0] edges scanned, [1] vertices expanded
+  unsigned long long *h_work = nullptr;
+  uint32_t *hub_counters = nullptr;
+  uint32_t *bcount = nullptr;    // per-block counts for compaction
+  Plan *plan = nullptr;          // device frontier plan
+  int64_t *hubpref = nullptr;    // frontier hub chunk prefix
+  Plan *h_plan = nullptr;        // pinned host copy of the plan
+  uint32_t *h_flags = nullptr;   // pinned host flags
+  int64_t hub_chunks_cap = 0;
+  int64_t partials_cap = 0;
+  int ensure(const GpuPart &g, int64_t hub_chunks_needed);
+  ~Workspace();
+};
+
+struct HybridState;
+
+}  // namespace tg
+
+struct tg_partition {
+  const tg_graph *g = nullptr;
+  int strategy = TG_PART_HIGH;
+  double alpha = 0.0;
+  int device = 0;
+  tg::Tuning tune{};
+  tg::DevArena arena;
+  tg::GpuPart gpu;
+  tg::Workspace ws;
+  std::vector<int32_t> h_l_of_g;  // global -> GPU-local id (or -1)
+  std::vector<int32_t> h_g_of_l;  // GPU-local -> global id
+  tg::HybridState *hy = nullptr;  // host partition + boundary buffers (cpu_edge_share > 0)
+};
+
+namespace tg {
+
+// --------------------------------------------------------- kernel launchers
+// frontier.hip
+int frontier_init_bitmaps(Workspace &ws, hipStream_t s);
+// Compact a bitmap into a sorted queue + plan.  mode 0 (BFS): new = bits & ~prev,
+// prev |= new.  mode 1 (active set): new = bits, bits cleared.  If `level` is
+// non-null, level[v] = level_value for every new vertex.
+int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, uint32_t *prev,
+                     int32_t *queue, int32_t *level, int32_t level_value, hipStream_t s);
+// Turn the compaction result (in ws.plan) into virtual-block offsets and the
+// hub chunk prefix, then copy the plan to ws.h_plan and wait for it.
+int frontier_plan(const GpuPart &g, Workspace &ws, const int32_t *queue, const Tuning &t,
+                  hipStream_t s, bool sync);
+// As frontier_plan, with hub chunks sized by the degrees in `off`; with
+// include_zero, frontier vertices of out-degree 0 get virtual blocks too
+// (a pull over in-edges must visit them).
+int frontier_plan_off(const GpuPart &g, Workspace &ws, const int32_t *queue, const int64_t *off,
+                      const Tuning &t, hipStream_t s, bool sync, bool include_zero = false);
+int launch_grid(int64_t vblocks);
+// bfs.hip: expansion of the frontier in `queue` (plan in ws.plan) into ws.bits_a
+int bfs_expand_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks,
+                      const Tuning &t, hipStream_t s);
+int set_bit(uint32_t *bits, int32_t v, hipStream_t s);
+
+// collect.hip
+int collect_levels(const GpuPart &g, const uint32_t *visited, const int32_t *level, int32_t *out,
+                   hipStream_t s);
+int collect_i32(const GpuPart &g, const int32_t *state, int32_t *out, hipStream_t s);
+int collect_f64_to_f32(const GpuPart &g, const double *state, float *out, hipStream_t s);
+int fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+int fill_f64(double *p, int64_t n, double v, hipStream_t s);
+int fill_f32(float *p, int64_t n, float v, hipStream_t s);
+int bfs_parents(const GpuPart &g, const uint32_t *visited, const int32_t *level, int32_t root_local,
+                int32_t *out, hipStream_t s);
+
+// pagerank.hip
+int pr_init_contrib(const GpuPart &g, float *c, double N, hipStream_t s);
+int pr_write_initial(const GpuPart &g, float *rank_out, double N, hipStream_t s);
+
+// algorithms (GPU partition only)
+int gpu_bfs(tg_partition *p, int32_t root_local, hipStream_t s, int64_t *levels_out);
+int gpu_sssp(tg_partition *p, int32_t root_local, hipStream_t s, int64_t *rounds_out);
+int gpu_pagerank(tg_partition *p, double damping, int32_t iters, int mode, float *rank_out,
+                 hipStream_t s);
+int gpu_bc_source(tg_partition *p, int32_t src_local, hipStream_t s);
+
+}  // namespace tg

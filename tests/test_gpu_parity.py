@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle on the same
+seeded inputs.  BFS levels and SSSP distances are bit-exact; PageRank within
+1e-5 relative L1 of the fp64 oracle; betweenness within 1e-4 relative per
+vertex (plus 1e-6 of the largest score, for near-zero scores)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+INF = oracle.INF
+# small thresholds so that tiny graphs exercise every degree bin, including
+# multi-chunk hubs
+SMALL_BINS = {"hub_min_deg": 300, "block_min_deg": 100, "wave_min_deg": 24, "g16_min_deg": 6,
+              "g4_min_deg": 2, "hub_chunk": 256}
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def load(tg, g, weights=None, tuning=None, **kw):
+    G = tg.graph_load_csr(g.n, g.offsets, g.cols, weights, symmetric=g.symmetric)
+    return tg.partition_by_degree(G, tuning=tuning, **kw)
+
+
+def pr_rel_l1(got, ref):
+    return float(np.abs(got.astype(np.float64) - ref).sum() / np.abs(ref).sum())
+
+
+def bc_close(got, ref):
+    got = got.astype(np.float64)
+    tol = 1e-4 * np.abs(ref) + 1e-6 * max(np.abs(ref).max(), 1.0)
+    return np.all(np.abs(got - ref) <= tol)
+
+
+def six(tg, tuning=None):
+    d = json.load(open(os.path.join(GOLD, "six_vertex.json")))
+    e = np.array(d["undirected_edges"])
+    g = graphgen.from_edges(6, e[:, 0], e[:, 1], symmetrize=True)
+    wmap = {}
+    for a, b, w in d["undirected_edges"]:
+        wmap[(a, b)] = wmap[(b, a)] = w
+    w = np.array([wmap[(u, int(v))] for u in range(6) for v in g.cols[g.offsets[u]:g.offsets[u + 1]]],
+                 dtype=np.int32)
+    return d, g, w, load(tg, g, w, tuning)
+
+
+# ------------------------------------------------------------- hand-worked
+
+def test_six_vertex_example(gpu):
+    d, g, w, P = six(gpu)
+    assert gpu.bfs(P, [0]).cpu().numpy()[0].tolist() == d["bfs_from_0"]
+    assert gpu.sssp(P, [0, 3]).cpu().numpy().tolist() == [d["sssp_from_0"], d["sssp_from_3"]]
+    assert np.allclose(gpu.bc(P, [0]).cpu().numpy(), d["bc_source_0"], atol=1e-6)
+    assert np.allclose(gpu.bc(P, range(6)).cpu().numpy(), d["bc_all_sources"], atol=1e-5)
+    r1 = gpu.pagerank(P, 0.85, 1).cpu().numpy()
+    assert np.allclose(r1, [a / b for a, b in d["pagerank_r1_fraction"]], rtol=1e-6)
+
+
+# ----------------------------------------------------- RMAT-14 full parity
+
+@pytest.fixture(scope="module")
+def rmat14():
+    g = graphgen.rmat(14)
+    return g, graphgen.weights(g, seed=2)
+
+
+@pytest.mark.parametrize("tuning", [None, SMALL_BINS])
+def test_rmat14_bfs_pagerank(gpu, rmat14, tuning):
+    g, w = rmat14
+    P = load(gpu, g, w, tuning)
+    root = graphgen.max_degree_vertex(g)
+    roots = [root] + graphgen.sample_roots(g, 5, seed=3).tolist()
+    lev = gpu.bfs(P, roots).cpu().numpy()
+    for i, r in enumerate(roots):
+        assert np.array_equal(lev[i], oracle.bfs(g.offsets, g.cols, r)), f"root {r}"
+    rank = gpu.pagerank(P, 0.85, 10).cpu().numpy()
+    ref = oracle.pagerank(g.offsets, g.cols, 0.85, 10)
+    assert pr_rel_l1(rank, ref) <= 1e-5
+    assert abs(rank.astype(np.float64).sum() - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("tuning", [None, SMALL_BINS])
+def test_rmat14_sssp(gpu, rmat14, tuning):
+    g, w = rmat14
+    P = load(gpu, g, w, tuning)
+    roots = graphgen.sample_roots(g, 6, seed=5)
+    dist = gpu.sssp(P, roots).cpu().numpy()
+    for i, r in enumerate(roots):
+        assert np.array_equal(dist[i], oracle.sssp(g.offsets, g.cols, w, r)), f"root {r}"
+
+
+@pytest.mark.parametrize("tuning", [None, SMALL_BINS])
+def test_rmat12_bc(gpu, tuning):
+    g = graphgen.rmat(12)
+    P = load(gpu, g, None, tuning)
+    srcs = graphgen.sample_roots(g, 8, seed=7)
+    got = gpu.bc(P, srcs).cpu().numpy()
+    ref = oracle.bc(g.offsets, g.cols, srcs)
+    assert bc_close(got, ref)
+
+
+def test_bfs_parents_valid(gpu, rmat14):
+    g, w = rmat14
+    P = load(gpu, g, w, SMALL_BINS)
+    root = graphgen.max_degree_vertex(g)
+    lev, par = gpu.bfs(P, [root], want_parents=True)
+    lev, par = lev.cpu().numpy()[0], par.cpu().numpy()[0]
+    assert np.array_equal(lev, oracle.bfs(g.offsets, g.cols, root))
+    assert par[root] == root
+    reach = (lev != INF) & (np.arange(g.n) != root)
+    assert np.all(par[lev == INF] == -1)
+    v = np.nonzero(reach)[0]
+    p = par[v]
+    assert np.all(lev[p] == lev[v] - 1)
+    for a, b in zip(p[:2000], v[:2000]):
+        assert b in g.cols[g.offsets[a]:g.offsets[a + 1]]
+
+
+# ------------------------------------------------------------ directed graphs
+
+@pytest.mark.parametrize("tuning", [None, SMALL_BINS])
+def test_directed_rmat12_all(gpu, tuning):
+    g = graphgen.rmat(12, symmetrize=False)
+    w = graphgen.weights(g, seed=4)
+    P = load(gpu, g, w, tuning)
+    roots = graphgen.sample_roots(g, 3, seed=9)
+    lev = gpu.bfs(P, roots).cpu().numpy()
+    dist = gpu.sssp(P, roots).cpu().numpy()
+    for i, r in enumerate(roots):
+        assert np.array_equal(lev[i], oracle.bfs(g.offsets, g.cols, r))
+        assert np.array_equal(dist[i], oracle.sssp(g.offsets, g.cols, w, r))
+    for mode in ("uniform", "drop"):
+        rank = gpu.pagerank(P, 0.85, 20, mode).cpu().numpy()
+        assert pr_rel_l1(rank, oracle.pagerank(g.offsets, g.cols, 0.85, 20, mode)) <= 1e-5
+    got = gpu.bc(P, roots).cpu().numpy()
+    assert bc_close(got, oracle.bc(g.offsets, g.cols, roots))
+
+
+# ------------------------------------------------------------------ edges
+
+def test_degenerate_graphs(gpu):
+    # single vertex
+    g = graphgen.from_edges(1, [], [], symmetrize=True)
+    P = load(gpu, g, np.zeros(0, np.int32))
+    assert gpu.bfs(P, [0]).cpu().numpy().tolist() == [[0]]
+    assert gpu.sssp(P, [0]).cpu().numpy().tolist() == [[0]]
+    assert np.allclose(gpu.pagerank(P, 0.85, 5).cpu().numpy(), [1.0])
+    assert gpu.bc(P, [0]).cpu().numpy().tolist() == [0.0]
+    # isolated root, disconnected pieces
+    g = graphgen.from_edges(7, [0, 1, 4], [1, 2, 5], symmetrize=True)
+    w = graphgen.weights(g)
+    P = load(gpu, g, w)
+    assert np.array_equal(gpu.bfs(P, [3]).cpu().numpy()[0], oracle.bfs(g.offsets, g.cols, 3))
+    assert np.array_equal(gpu.bfs(P, [0]).cpu().numpy()[0], oracle.bfs(g.offsets, g.cols, 0))
+    assert np.array_equal(gpu.sssp(P, [5]).cpu().numpy()[0], oracle.sssp(g.offsets, g.cols, w, 5))
+    # zero iterations return r_0
+    assert np.allclose(gpu.pagerank(P, 0.85, 0).cpu().numpy(), 1.0 / 7)
+
+
+def test_star_hub_beyond_thresholds(gpu):
+    n = 20000  # hub degree above the default hub threshold and many chunks
+    g = graphgen.from_edges(n + 1, np.zeros(n, dtype=int), np.arange(1, n + 1), symmetrize=True)
+    P = load(gpu, g, graphgen.weights(g))
+    lev = gpu.bfs(P, [5]).cpu().numpy()[0]
+    assert lev[0] == 1 and lev[5] == 0 and np.all(np.delete(lev, [0, 5]) == 2)
+    r = gpu.pagerank(P, 0.85, 10).cpu().numpy()
+    assert pr_rel_l1(r, oracle.pagerank(g.offsets, g.cols, 0.85, 10)) <= 1e-5
+    b = gpu.bc(P, [0, 1, 2]).cpu().numpy()
+    assert bc_close(b, oracle.bc(g.offsets, g.cols, [0, 1, 2]))
+
+
+def test_long_path(gpu):
+    n = 3000  # many levels with one-vertex frontiers
+    g = graphgen.from_edges(n, np.arange(n - 1), np.arange(1, n), symmetrize=True)
+    w = graphgen.weights(g)
+    P = load(gpu, g, w)
+    assert np.array_equal(gpu.bfs(P, [17]).cpu().numpy()[0], np.abs(np.arange(n) - 17))
+    assert np.array_equal(gpu.sssp(P, [0]).cpu().numpy()[0], oracle.sssp(g.offsets, g.cols, w, 0))
+    b = gpu.bc(P, [0, n - 1]).cpu().numpy()
+    assert bc_close(b, oracle.bc(g.offsets, g.cols, [0, n - 1]))
+
+
+def test_sssp_overflow_reported(gpu):
+    g = graphgen.from_edges(3, [0, 1], [1, 2], symmetrize=False)
+    w = np.array([2**31 - 10, 2**31 - 10], dtype=np.int32)
+    P = load(gpu, g, w)
+    with pytest.raises(gpu.TGError) as ei:
+        gpu.sssp(P, [0])
+    assert ei.value.code == gpu.TG_ERANGE
+    # a large edge that is not on the shortest path is fine
+    g = graphgen.from_edges(3, [0, 0, 1], [1, 2, 2], symmetrize=False)
+    w = np.array([1, 2**31 - 2, 1], dtype=np.int32)
+    P = load(gpu, g, w)
+    assert gpu.sssp(P, [0]).cpu().numpy().tolist() == [[0, 1, 2]]
+
+
+def test_errors(gpu, rmat14):
+    g, _ = rmat14
+    P = load(gpu, g)
+    with pytest.raises(gpu.TGError) as ei:
+        gpu.sssp(P, [0])
+    assert ei.value.code == gpu.TG_EUNSUPPORTED
+    with pytest.raises(gpu.TGError) as ei:
+        gpu.bfs(P, [g.n])
+    assert ei.value.code == gpu.TG_EINVAL
+    with pytest.raises(gpu.TGError):
+        gpu.pagerank(P, 1.5, 3)
+
+
+def test_determinism(gpu, rmat14):
+    g, w = rmat14
+    P = load(gpu, g, w)
+    a = gpu.pagerank(P, 0.85, 10).cpu().numpy()
+    b = gpu.pagerank(P, 0.85, 10).cpu().numpy()
+    assert np.array_equal(a, b)
+    s1 = gpu.sssp(P, [3]).cpu().numpy()
+    s2 = gpu.sssp(P, [3]).cpu().numpy()
+    assert np.array_equal(s1, s2)
