@@ -124,8 +124,23 @@ def main():
     ap.add_argument("--roots", type=int, default=64)
     ap.add_argument("--pr-iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tuning", default=None, help="JSON tuning object for partition_by_degree")
+    ap.add_argument("--tuning", default="auto",
+                    help="JSON tuning object, 'auto' (autotuner cache if present, else built-in) or 'none'")
+    ap.add_argument("--autotune", action="store_true", help="run the autotuner (untimed) and update its cache")
+    ap.add_argument("--only", choices=["bfs", "sssp", "pagerank"], default=None,
+                    help="run one algorithm per step (for profiling); the JSON line then covers only it")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES (to scale HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(args.copy_calibration // 4, dtype=torch.int32, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4}))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
@@ -148,8 +163,25 @@ def main():
     print(f"[bench] generated {args.workload}: V={g.n} E={g.nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
     t = time.perf_counter()
     G = tg.graph_load_csr(g.n, g.offsets, g.cols, w, symmetric=g.symmetric, validate=False)
-    P = tg.partition_by_degree(G, tuning=args.tuning)
+    P = tg.partition_by_degree(G, tuning=None if args.tuning in ("auto", "none") else args.tuning)
     print(f"[bench] partitioned in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
+    from paper_1312_3018_amd import autotune
+    key = autotune.graph_key(P)
+    tuning_used = "built-in"
+    if args.autotune:
+        res = autotune.tune(P, roots[:4], roots[:2], pr_iters=5,
+                            log=lambda s: print(s, file=sys.stderr, flush=True))
+        autotune.save_cached(key, res)
+        print(f"[bench] autotuned {key}: {res['initial_ms']} -> {res['final_ms']} in {res['seconds']}s",
+              file=sys.stderr, flush=True)
+        tuning_used = "autotuned now"
+    elif args.tuning == "auto":
+        cached = autotune.load_cached(key)
+        if cached:
+            tg.partition_retune(P, cached)
+            tuning_used = "autotuner cache"
+    elif args.tuning != "none":
+        tuning_used = "given"
 
     V, E = g.n, g.nnz
     nr = len(roots)
@@ -160,15 +192,19 @@ def main():
 
     def step(stats):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        s_bfs = s_sssp = s_pr = {}
         ev[0].record(stream)
-        tg.bfs(P, roots, levels)
-        s_bfs = tg.tg_last_stats()
+        if args.only in (None, "bfs"):
+            tg.bfs(P, roots, levels)
+            s_bfs = tg.tg_last_stats()
         ev[1].record(stream)
-        tg.sssp(P, roots, dist)
-        s_sssp = tg.tg_last_stats()
+        if args.only in (None, "sssp"):
+            tg.sssp(P, roots, dist)
+            s_sssp = tg.tg_last_stats()
         ev[2].record(stream)
-        tg.pagerank(P, 0.85, args.pr_iters, "uniform", rank)
-        s_pr = tg.tg_last_stats()
+        if args.only in (None, "pagerank"):
+            tg.pagerank(P, 0.85, args.pr_iters, "uniform", rank)
+            s_pr = tg.tg_last_stats()
         ev[3].record(stream)
         stats.append((ev, s_bfs, s_sssp, s_pr))
 
@@ -192,16 +228,19 @@ def main():
 
     # traversed edges (section 5): out-degrees of reached vertices
     deg = torch.from_numpy(np.diff(g.offsets)).to("cuda")
-    bfs_edges = sum(int(deg[levels[i] != INF].sum().item()) for i in range(nr))
-    sssp_edges = sum(int(deg[dist[i] != INF].sum().item()) for i in range(nr))
-    bfs_verts = int((levels != INF).sum().item())
-    pr_edges = args.pr_iters * E
+    run_bfs = args.only in (None, "bfs")
+    run_sssp = args.only in (None, "sssp")
+    run_pr = args.only in (None, "pagerank")
+    bfs_edges = sum(int(deg[levels[i] != INF].sum().item()) for i in range(nr)) if run_bfs else 0
+    sssp_edges = sum(int(deg[dist[i] != INF].sum().item()) for i in range(nr)) if run_sssp else 0
+    bfs_verts = int((levels != INF).sum().item()) if run_bfs else 0
+    pr_edges = args.pr_iters * E if run_pr else 0
     step_edges = bfs_edges + sssp_edges + pr_edges
 
     def phase(k):
         return sum(s[0][k].elapsed_time(s[0][k + 1]) for s in stats) / len(stats)
 
-    t_bfs, t_sssp, t_pr = phase(0), phase(1), phase(2)
+    t_bfs, t_sssp, t_pr = (max(phase(k), 1e-9) for k in range(3))
     last = stats[-1]
     sb, ss, sp = last[1], last[2], last[3]
     # algorithmic bytes (int32 ids, int64 offsets)
@@ -257,6 +296,7 @@ def main():
                      "hbm_gbs_algorithmic": round(pr_bytes_iter * args.pr_iters / (t_pr / 1e3) / 1e9, 1)},
         "roofline": dict(roofs[dominant], kernel=dominant) if dominant else None,
         "kernels": roofs,
+        "tuning": {"source": tuning_used, "values": tg.partition_info(P)["tuning"]},
         "host_wall_s": round(wall, 3),
     }
     if not args.no_cpu_baseline:

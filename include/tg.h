@@ -98,11 +98,21 @@ int graph_load_csr(int64_t num_vertices, int64_t num_edges,
  *   tuning_json     NULL for the built-in degree thresholds, or a JSON object
  *                   with any of "hub_min_deg", "block_min_deg",
  *                   "wave_min_deg", "g16_min_deg", "g4_min_deg", "hub_chunk"
- *                   (as written by the autotuner).
+ *                   and the launch-shape keys of partition_retune (as written
+ *                   by the autotuner).
+ * The graph must outlive the partition (the partition reads its host CSR).
  * Errors: TG_EINVAL, TG_ENOMEM, TG_EDEVICE. */
 int partition_by_degree(const tg_graph *g, int strategy, double cpu_edge_share,
                         uint64_t seed, const char *tuning_json,
                         tg_partition **out);
+
+/* Re-derive the degree bins and launch shapes of an existing partition from
+ * a tuning object (same keys as partition_by_degree's tuning_json, plus
+ * "pr_lds_verts", "pr_grid", "bfs_lds_words", "bfs_grid",
+ * "bfs_lds_min_vblocks"; NULL restores the built-in values) without
+ * rebuilding it.  This is the autotuner's hook.  Waits for the device to be
+ * idle first.  Errors: TG_EINVAL (bad tuning), TG_ENOMEM, TG_EDEVICE. */
+int partition_retune(tg_partition *p, const char *tuning_json);
 
 /* Level-synchronous breadth-first search (section 6.3.2, Figure 11).
  *   roots     host array of num_roots original vertex ids.

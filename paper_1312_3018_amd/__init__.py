@@ -50,6 +50,7 @@ def _load():
                                    ctypes.POINTER(vp)]
     lib.partition_by_degree.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
                                         ctypes.c_char_p, ctypes.POINTER(vp)]
+    lib.partition_retune.argtypes = [vp, ctypes.c_char_p]
     lib.bfs.argtypes = [vp, _c_i32p, ctypes.c_int32, vp, vp, vp]
     lib.sssp.argtypes = [vp, _c_i32p, ctypes.c_int32, vp, vp]
     lib.pagerank.argtypes = [vp, ctypes.c_float, ctypes.c_int32, ctypes.c_int32, vp, vp]
@@ -59,7 +60,7 @@ def _load():
     lib.tg_last_error.restype = ctypes.c_char_p
     lib.partition_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     lib.tg_last_stats.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
-    for f in (lib.graph_load_csr, lib.partition_by_degree, lib.bfs, lib.sssp, lib.pagerank, lib.bc,
+    for f in (lib.graph_load_csr, lib.partition_by_degree, lib.partition_retune, lib.bfs, lib.sssp, lib.pagerank, lib.bc,
               lib.partition_info, lib.tg_last_stats):
         f.restype = ctypes.c_int
     lib.graph_free.restype = None
@@ -186,6 +187,14 @@ def partition_by_degree(graph: Graph, strategy: str = "high", cpu_edge_share: fl
     _check(lib.partition_by_degree(graph.handle, STRATEGY[strategy], float(cpu_edge_share), int(seed), tj,
                                    ctypes.byref(out)))
     return Partition(out.value, graph)
+
+
+def partition_retune(part: Partition, tuning=None) -> None:
+    """Re-derive bins and launch shapes of `part` from a tuning dict/JSON."""
+    tj = None
+    if tuning is not None:
+        tj = (tuning if isinstance(tuning, str) else json.dumps(tuning)).encode()
+    _check(_load().partition_retune(part.handle, tj))
 
 
 def partition_info(part: Partition) -> dict:

@@ -34,7 +34,23 @@ int set_error(int code, const char *fmt, ...) {
   return code;
 }
 
-void clear_error() { g_err.clear(); }
+// Also drop any HIP error left pending by an earlier unchecked runtime call
+// (so that a launch check reports only its own launch); with TG_DEBUG set,
+// name it on stderr.
+void debug_hip(hipError_t e, const char *what) {
+  static const bool dbg = getenv("TG_DEBUG") != nullptr;
+  if (e != hipSuccess) {
+    if (dbg) fprintf(stderr, "[tg] %s: %s\n", what, hipGetErrorName(e));
+    (void)hipGetLastError();
+  }
+}
+
+void clear_error() {
+  g_err.clear();
+  const hipError_t stale = hipGetLastError();
+  static const bool dbg = getenv("TG_DEBUG") != nullptr;
+  if (stale != hipSuccess && dbg) fprintf(stderr, "[tg] pending HIP error at API entry: %s\n", hipGetErrorName(stale));
+}
 
 void stats_reset(const char *algo) {
   g_stats = std::string("{\"algorithm\":\"") + algo + "\"";
@@ -63,19 +79,22 @@ int DevArena::alloc(void **p, size_t n) {
 }
 
 void DevArena::release() {
-  for (void *q : ptrs) (void)hipFree(q);
+  for (void *q : ptrs) TG_QUIET(hipFree(q));
   ptrs.clear();
   bytes = 0;
 }
 
 Workspace::~Workspace() {
-  if (h_plan) (void)hipHostFree(h_plan);
-  if (h_flags) (void)hipHostFree(h_flags);
-  if (h_work) (void)hipHostFree(h_work);
+  if (h_plan) TG_QUIET(hipHostFree(h_plan));
+  if (h_flags) TG_QUIET(hipHostFree(h_flags));
+  if (h_work) TG_QUIET(hipHostFree(h_work));
 }
 
 int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
-  if (cap_n == g.n && hub_chunks_needed <= hub_chunks_cap) return TG_OK;
+  const int64_t hubs_needed = std::max<int64_t>(g.max_out_hubs, g.pr.nh) + 1;
+  if (cap_n == g.n && hub_chunks_needed <= hub_chunks_cap && hubs_needed <= hubs_cap &&
+      g.pr.work.vb[1] + 1 <= hub_chunks_cap)
+    return TG_OK;
   arena.release();
   const int64_t n = g.n;
   nwords = ((n + 31) / 32 + 1023) / 1024 * 1024;
@@ -98,7 +117,8 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   chunks = std::max<int64_t>(chunks, g.pr.work.vb[1] + 1);
   hub_chunks_cap = chunks;
   TG_TRY(dalloc(arena, &hub_partials, chunks));
-  const int64_t hubs = std::max<int64_t>(g.max_out_hubs, g.pr.nh) + 1;
+  const int64_t hubs = hubs_needed;
+  hubs_cap = hubs;
   TG_TRY(dalloc(arena, &hub_dangling, hubs));
   TG_TRY(dalloc(arena, &hub_counters, hubs));
   TG_TRY(dalloc(arena, &hubpref, hubs + 1));
@@ -129,6 +149,11 @@ Tuning default_tuning() {
   t.min_deg[tgk::BIN_G16] = 12;
   t.min_deg[tgk::BIN_G4] = 3;
   t.hub_chunk = 4096;
+  t.pr_lds_verts = 4096;
+  t.pr_grid = 2048;
+  t.bfs_lds_words = 4096;
+  t.bfs_grid = 2048;
+  t.bfs_lds_min_vblocks = 4096;
   return t;
 }
 
@@ -155,6 +180,16 @@ int parse_tuning(const char *json, Tuning *t) {
   }
   int64_t v;
   if (json_int(json, "hub_chunk", &v)) t->hub_chunk = v;
+  if (json_int(json, "pr_lds_verts", &v)) t->pr_lds_verts = v;
+  if (json_int(json, "pr_grid", &v)) t->pr_grid = v;
+  if (json_int(json, "bfs_lds_words", &v)) t->bfs_lds_words = v;
+  if (json_int(json, "bfs_grid", &v)) t->bfs_grid = v;
+  if (json_int(json, "bfs_lds_min_vblocks", &v)) t->bfs_lds_min_vblocks = v;
+  if (t->pr_lds_verts < 0 || t->pr_lds_verts > 14336) return set_error(TG_EINVAL, "tuning: pr_lds_verts outside [0, 14336]");
+  if (t->bfs_lds_words < 0 || t->bfs_lds_words > 14336) return set_error(TG_EINVAL, "tuning: bfs_lds_words outside [0, 14336]");
+  if (t->pr_grid < 1 || t->pr_grid > 16384 || t->bfs_grid < 1 || t->bfs_grid > 16384)
+    return set_error(TG_EINVAL, "tuning: grids must be in [1, 16384]");
+  if (t->bfs_lds_min_vblocks < 0) return set_error(TG_EINVAL, "tuning: bfs_lds_min_vblocks < 0");
   for (int b = 0; b < 5; ++b)
     if (t->min_deg[b] < 1) return set_error(TG_EINVAL, "tuning: %s must be >= 1", keys[b]);
   for (int b = 0; b + 1 < 5; ++b)
@@ -342,6 +377,23 @@ int upload(tg::DevArena &a, T **dst, const T *src, size_t count) {
 
 namespace tg {
 
+// Derive the degree bins and the static PageRank plan from the tuning.
+int apply_tuning(tg_partition *p, const Tuning &t) {
+  GpuPart &gp = p->gpu;
+  p->tune = t;
+  gp.out_bins = bins_of(gp.h_deg, t);
+  gp.in_bins = gp.in_alias ? gp.out_bins : bins_of(gp.h_in_deg, t);
+  gp.max_out_hubs = gp.out_bins.bstart[1] - gp.out_bins.bstart[0];
+  std::vector<int64_t> hubpref;
+  static_plan(gp.in_bins, gp.h_in_deg, t, gp.pr.work, gp.pr.all, hubpref);
+  gp.pr.nh = (int32_t)(gp.in_bins.bstart[1] - gp.in_bins.bstart[0]);
+  gp.plan_arena.release();
+  TG_TRY(upload(gp.plan_arena, &gp.pr.hubpref, hubpref.data(), hubpref.size()));
+  TG_TRY(upload(gp.plan_arena, &gp.pr.d_work, &gp.pr.work, 1));
+  TG_TRY(upload(gp.plan_arena, &gp.pr.d_all, &gp.pr.all, 1));
+  return TG_OK;
+}
+
 // Build and upload the GPU partition over the vertex subset `verts` (global
 // ids).  Edges to vertices outside the subset are boundary edges: they are
 // returned through `boundary` (per local source, the global destinations and
@@ -412,9 +464,7 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
   gp.n_global = V;
   std::vector<int64_t> deg_in_order((size_t)n);
   for (int64_t i = 0; i < n; ++i) deg_in_order[i] = off[i + 1] - off[i];
-  gp.out_bins = bins_of(deg_in_order, t);
   gp.n_dangling = 0;
-  gp.max_out_hubs = gp.out_bins.bstart[1] - gp.out_bins.bstart[0];
   DevArena &A = p->arena;
   TG_TRY(upload(A, &gp.out.off, off.data(), (size_t)n + 1));
   TG_TRY(upload(A, &gp.out.col, col.data(), (size_t)m));
@@ -430,7 +480,6 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
   if (alias) {
     gp.in = gp.out;
     gp.in_alias = true;
-    gp.in_bins = gp.out_bins;
     in_deg_in_order = deg_in_order;
     for (int64_t i = 0; i < n; ++i) gp.n_dangling += (deg_in_order[i] == 0);
     gp.n_isolated = gp.n_dangling;
@@ -454,7 +503,6 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
     sort_desc_by_key(indeg, pr_order);
     in_deg_in_order.resize((size_t)n);
     for (int64_t i = 0; i < n; ++i) in_deg_in_order[i] = indeg[pr_order[i]];
-    gp.in_bins = bins_of(in_deg_in_order, t);
     TG_TRY(upload(A, &gp.pr_order, pr_order.data(), (size_t)n));
     // dangling = local out-degree 0 AND no boundary out-edges
     for (int64_t i = 0; i < n; ++i) {
@@ -463,13 +511,9 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
     }
     gp.n_isolated = 0;
   }
-  // static PageRank plan over in-degree bins
-  std::vector<int64_t> hubpref;
-  static_plan(gp.in_bins, in_deg_in_order, t, gp.pr.work, gp.pr.all, hubpref);
-  gp.pr.nh = (int32_t)(gp.in_bins.bstart[1] - gp.in_bins.bstart[0]);
-  TG_TRY(upload(A, &gp.pr.hubpref, hubpref.data(), hubpref.size()));
-  TG_TRY(upload(A, &gp.pr.d_work, &gp.pr.work, 1));
-  TG_TRY(upload(A, &gp.pr.d_all, &gp.pr.all, 1));
+  gp.h_deg = std::move(deg_in_order);
+  gp.h_in_deg = std::move(in_deg_in_order);
+  TG_TRY(apply_tuning(p, t));
 
   // id maps
   p->h_g_of_l = order;
@@ -518,9 +562,19 @@ extern "C" int partition_by_degree(const tg_graph *g, int strategy, double alpha
   return TG_OK;
 }
 
+extern "C" int partition_retune(tg_partition *p, const char *tuning_json) {
+  clear_error();
+  if (!p) return set_error(TG_EINVAL, "partition_retune: partition is NULL");
+  Tuning t;
+  TG_TRY(parse_tuning(tuning_json, &t));
+  if (hipSetDevice(p->device) != hipSuccess) return set_error(TG_EDEVICE, "partition_retune: hipSetDevice failed");
+  TG_HIP(hipDeviceSynchronize());
+  return apply_tuning(p, t);
+}
+
 extern "C" void partition_free(tg_partition *p) {
   if (!p) return;
-  (void)hipSetDevice(p->device);
+  TG_QUIET(hipSetDevice(p->device));
   hybrid_free(p);
   delete p;
 }
@@ -565,9 +619,12 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
   }
   snprintf(buf, sizeof(buf),
            "],\"tuning\":{\"hub_min_deg\":%lld,\"block_min_deg\":%lld,\"wave_min_deg\":%lld,"
-           "\"g16_min_deg\":%lld,\"g4_min_deg\":%lld,\"hub_chunk\":%lld}",
+           "\"g16_min_deg\":%lld,\"g4_min_deg\":%lld,\"hub_chunk\":%lld,\"pr_lds_verts\":%lld,"
+           "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld}",
            (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
-           (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk);
+           (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk,
+           (long long)p->tune.pr_lds_verts, (long long)p->tune.pr_grid, (long long)p->tune.bfs_lds_words,
+           (long long)p->tune.bfs_grid, (long long)p->tune.bfs_lds_min_vblocks);
   s += buf;
   s += hybrid_info_json(p);
   s += "}";

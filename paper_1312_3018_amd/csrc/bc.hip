@@ -20,7 +20,7 @@ __global__ void k_set_f64(double *p, int64_t i, double v) {
   if (threadIdx.x == 0) p[i] = v;
 }
 
-struct SigmaPull {
+struct SigmaPull : SumF64 {
   const int32_t *col;
   const int32_t *level;
   const double *sigma_r;
@@ -38,7 +38,7 @@ struct SigmaPull {
   }
 };
 
-struct DeltaAccum {
+struct DeltaAccum : SumF64 {
   const int32_t *col;
   const int32_t *level;
   const double *sigma;
@@ -100,7 +100,7 @@ int gpu_bc_source(tg_partition *p, int32_t src, hipStream_t s) {
       TG_TRY(frontier_plan_off(g, ws, ws.queue + noff, g.in.off, t, s, true, true));
       vbs = ws.h_plan->vb[NBIN];
     }
-    SigmaPull op{g.in.col, level, ws.sigma, ws.sigma, ws.counters, L};
+    SigmaPull op{{}, g.in.col, level, ws.sigma, ws.sigma, ws.counters, L};
     hipLaunchKernelGGL(k_gather<SigmaPull>, dim3(launch_grid(vbs)), dim3(BLOCK), 0, s, ws.plan,
                        ws.queue + noff, ws.hubpref, g.in.off, t.hub_chunk, ws.hub_partials,
                        ws.hub_counters, op);
@@ -116,7 +116,7 @@ int gpu_bc_source(tg_partition *p, int32_t src, hipStream_t s) {
   for (int32_t lv = L - 1; lv >= 1; --lv) {
     TG_HIP(hipMemcpyAsync(ws.plan, &plans[lv], sizeof(Plan), hipMemcpyHostToDevice, s));
     TG_TRY(frontier_plan_off(g, ws, ws.queue + segoff[lv], g.out.off, t, s, false));
-    DeltaAccum op{g.out.col, level, ws.sigma, ws.delta, ws.bc_acc, lv + 1};
+    DeltaAccum op{{}, g.out.col, level, ws.sigma, ws.delta, ws.bc_acc, lv + 1};
     hipLaunchKernelGGL(k_gather<DeltaAccum>, dim3(launch_grid(plans[lv].vb[NBIN])), dim3(BLOCK), 0, s,
                        ws.plan, ws.queue + segoff[lv], ws.hubpref, g.out.off, t.hub_chunk,
                        ws.hub_partials, ws.hub_counters, op);

@@ -49,6 +49,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ 
     nw[0] &= ~p.x; nw[1] &= ~p.y; nw[2] &= ~p.z; nw[3] &= ~p.w;
     reinterpret_cast<uint4 *>(prev)[q] = v;  // prev := visited
   } else {
+    if (mode == 2) reinterpret_cast<uint4 *>(prev)[q] = v;  // prev := the set taken
     reinterpret_cast<uint4 *>(bits)[q] = make_uint4(0, 0, 0, 0);
   }
   const uint32_t cnt = __popc(nw[0]) + __popc(nw[1]) + __popc(nw[2]) + __popc(nw[3]);

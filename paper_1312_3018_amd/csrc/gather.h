@@ -1,31 +1,62 @@
-// Generic degree-binned gather-reduce over a frontier queue: for each
-// frontier vertex v, s(v) = sum over edges e of v of op.term(vs, e) (fp64),
-// then op.finish(v, s(v)) once.  `vs` is op.vstate(v), loaded once per
-// vertex.  Hub vertices are split into chunks of `hub_chunk` edges; the last
-// chunk block of a hub to finish sums the chunk partials in chunk order, so
-// the result does not depend on scheduling.
+// Generic degree-binned gather-reduce over a queue of rows: for each row v,
+// r(v) = reduce over edges e of v of op.term(vs, e), then op.finish(v, r(v))
+// once, where vs = op.vstate(v) is loaded once per row.  The reduction is
+// op.combine (associative, commutative) with identity op.identity().
+//
+// Hub rows are split into chunks of `hub_chunk` edges; the last chunk block
+// of a hub to finish combines the chunk partials in chunk order, so the result
+// does not depend on scheduling.  Used for the BC sigma pull and delta
+// accumulation and for the atomic-free outbox reductions of the hybrid split.
 #pragma once
 #include "kcommon.h"
 
 namespace tgk {
 
+template <typename T, class Op>
+__device__ __forceinline__ T group_reduce(T x, int width, const Op &op) {
+  for (int o = width >> 1; o > 0; o >>= 1) x = op.combine(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+template <typename T, class Op>
+__device__ __forceinline__ T block_reduce(T x, const Op &op) {
+  __shared__ T red[BLOCK / 64];
+  x = group_reduce(x, 64, op);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = x;
+  __syncthreads();
+  T s = red[0];
+#pragma unroll
+  for (int k = 1; k < BLOCK / 64; ++k) s = op.combine(s, red[k]);
+  return s;
+}
+
+// Sum in fp64: the default reduction.
+struct SumF64 {
+  using T = double;
+  __device__ static double identity() { return 0.0; }
+  __device__ static double combine(double a, double b) { return a + b; }
+};
+
 template <class Op>
 __global__ __launch_bounds__(BLOCK) void k_gather(const Plan *__restrict__ Pp, const int32_t *__restrict__ queue,
                                                   const int64_t *__restrict__ hubpref,
                                                   const int64_t *__restrict__ off, int64_t hub_chunk,
-                                                  double *hub_partials, uint32_t *hub_counters, Op op) {
+                                                  typename Op::T *hub_partials, uint32_t *hub_counters, Op op) {
+  using T = typename Op::T;
   __shared__ int s_last;
-  const Plan P = *Pp;
+  const Plan &P = load_plan(Pp);
   const int64_t total = P.vb[NBIN];
   for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
     const Assign a = assign_work(vb, P, queue, nullptr, hubpref, off, hub_chunk);
-    double s = 0.0;
+    T s = op.identity();
     if (a.ok) {
-      const double vs = op.vstate(a.v);
-      for (int64_t e = a.e_begin + a.lane; e < a.e_end; e += a.stride) s += op.term(vs, e);
+      const auto vs = op.vstate(a.v);
+      for (int64_t e = a.e_begin + a.lane; e < a.e_end; e += a.stride) s = op.combine(s, op.term(vs, e));
     }
     if (a.bin == BIN_HUB) {
-      s = block_sum(s);
+      s = block_reduce(s, op);
       const int32_t hi = a.qi - P.pos[0];
       if (threadIdx.x == 0) {
         hub_partials[a.chunk] = s;
@@ -37,17 +68,17 @@ __global__ __launch_bounds__(BLOCK) void k_gather(const Plan *__restrict__ Pp, c
       __syncthreads();
       if (s_last && threadIdx.x == 0) {
         __threadfence();
-        double tot = 0.0;
+        T tot = op.identity();
         for (int64_t k = hubpref[hi]; k < hubpref[hi + 1]; ++k)
-          tot += __hip_atomic_load(hub_partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          tot = op.combine(tot, __hip_atomic_load(hub_partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         op.finish(a.v, tot);
         hub_counters[hi] = 0u;
       }
       __syncthreads();
       continue;
     }
-    if (a.bin == BIN_BLOCK) s = block_sum(s);
-    else s = group_sum(s, a.stride);
+    if (a.bin == BIN_BLOCK) s = block_reduce(s, op);
+    else s = group_reduce(s, a.stride, op);
     if (a.ok && a.lane == 0) op.finish(a.v, s);
   }
 }

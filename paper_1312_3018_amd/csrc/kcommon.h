@@ -46,6 +46,24 @@ struct Plan {
   int64_t vb[NBIN + 1];    // virtual blocks of bin b: [vb[b], vb[b+1])
 };
 
+// Copy the plan into LDS (it is indexed by the block's bin, so a register
+// copy would be spilled to scratch).  Every thread must call this.
+__device__ __forceinline__ const Plan &load_plan(const Plan *__restrict__ Pp) {
+  __shared__ Plan sP;
+  constexpr int words = (int)(sizeof(Plan) / sizeof(uint32_t));
+  if (threadIdx.x < words)
+    reinterpret_cast<uint32_t *>(&sP)[threadIdx.x] = reinterpret_cast<const uint32_t *>(Pp)[threadIdx.x];
+  __syncthreads();
+  return sP;
+}
+
+// Streaming read of edge data: bypass-friendly, so that the edge stream does
+// not evict the randomly accessed vertex state from the caches.
+template <typename T>
+__device__ __forceinline__ T stream_load(const T *p) {
+  return __builtin_nontemporal_load(p);
+}
+
 // Work of one thread inside a virtual block.
 struct Assign {
   int32_t v;        // vertex (local id), valid only if ok
@@ -91,8 +109,8 @@ __device__ __forceinline__ Assign assign_work(int64_t vb, const Plan &P, const i
     qi = P.pos[0] + lo;
     int32_t v = queue ? queue[qi] : (order ? order[qi] : qi);
     int64_t k = local - hubpref[lo];
-    a.e_begin = off[v] + k * hub_chunk;
-    int64_t end = off[v + 1];
+    a.e_begin = stream_load(off + v) + k * hub_chunk;
+    int64_t end = stream_load(off + v + 1);
     a.e_end = (a.e_begin + hub_chunk < end) ? a.e_begin + hub_chunk : end;
     a.v = v;
     a.qi = qi;
@@ -109,10 +127,10 @@ __device__ __forceinline__ Assign assign_work(int64_t vb, const Plan &P, const i
   a.stride = lpv;
   a.qi = qi;
   if (qi < P.pos[b + 1]) {
-    int32_t v = queue ? queue[qi] : (order ? order[qi] : qi);
+    int32_t v = queue ? stream_load(queue + qi) : (order ? stream_load(order + qi) : qi);
     a.v = v;
-    a.e_begin = off[v];
-    a.e_end = off[v + 1];
+    a.e_begin = stream_load(off + v);
+    a.e_end = stream_load(off + v + 1);
     a.ok = true;
   }
   return a;

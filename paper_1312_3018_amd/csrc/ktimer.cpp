@@ -47,7 +47,7 @@ int ktimer_start(hipStream_t s) {
   if (!timing_enabled()) return -1;
   hipEvent_t e = take();
   if (!e) return -1;
-  (void)hipEventRecord(e, s);
+  TG_QUIET(hipEventRecord(e, s));
   return (int)(g_t.used - 1);
 }
 
@@ -55,7 +55,7 @@ void ktimer_stop(int start, hipStream_t s, const char *name) {
   if (start < 0) return;
   hipEvent_t e = take();
   if (!e) return;
-  (void)hipEventRecord(e, s);
+  TG_QUIET(hipEventRecord(e, s));
   g_t.pending.push_back({name, (size_t)start, g_t.used - 1});
 }
 

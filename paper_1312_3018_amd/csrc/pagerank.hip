@@ -10,6 +10,8 @@
 // Hub vertices are split into chunks of `hub_chunk` in-edges, one block per
 // chunk; the last chunk block of a hub to finish sums the chunk partials in
 // chunk order and finalises that vertex.
+#include <algorithm>
+
 #include "tg_internal.h"
 
 using namespace tgk;
@@ -25,6 +27,7 @@ struct PRParams {
   int32_t drop;        // 1: dangling mass discarded
   int32_t last;        // 1: write ranks instead of contributions
   int32_t nh;          // hub vertices
+  int32_t lds_verts;   // contributions of vertices [0, lds_verts) are staged in LDS
 };
 
 template <bool ORDER>
@@ -35,9 +38,13 @@ __global__ __launch_bounds__(BLOCK) void k_pr_gather(
     PRParams prm, const double *__restrict__ dsum_in, double *__restrict__ dsum_out,
     double *__restrict__ partials, double *hub_partials, double *__restrict__ hub_dangling,
     uint32_t *hub_counters, uint32_t *done_counter, const int32_t *__restrict__ g_of_l,
-    float *__restrict__ rank_out) {
+    float *__restrict__ rank_out, const double *__restrict__ ghost, const int32_t *__restrict__ extra_deg) {
   __shared__ int s_last;
-  const Plan P = *Pp;
+  // The hottest gather targets (lowest local ids: highest out-degree) are
+  // staged in LDS once per block; c_in is read-only during the launch.
+  extern __shared__ float lds_c[];
+  for (int32_t i = threadIdx.x; i < prm.lds_verts; i += BLOCK) lds_c[i] = c_in[i];
+  const Plan &P = load_plan(Pp);  // (its barrier also publishes lds_c)
   const double D = prm.drop ? 0.0 : *dsum_in;
   const double add = prm.base + prm.d * D * prm.inv_n;
   double dang = 0.0;
@@ -50,12 +57,20 @@ __global__ __launch_bounds__(BLOCK) void k_pr_gather(
       const int64_t st = a.stride;
       int64_t e = a.e_begin + a.lane;
       double s1 = 0.0;
+      const int32_t H = prm.lds_verts;
       for (; e + st < a.e_end; e += 2 * st) {
-        const int32_t u0 = in_col[e], u1 = in_col[e + st];
-        s += (double)c_in[u0];
-        s1 += (double)c_in[u1];
+        const int32_t u0 = stream_load(in_col + e), u1 = stream_load(in_col + e + st);
+        // generic pointers: one load instruction for the LDS or global case
+        const float *p0 = u0 < H ? lds_c + u0 : c_in + u0;
+        const float *p1 = u1 < H ? lds_c + u1 : c_in + u1;
+        s += (double)*p0;
+        s1 += (double)*p1;
       }
-      if (e < a.e_end) s += (double)c_in[in_col[e]];
+      if (e < a.e_end) {
+        const int32_t u = stream_load(in_col + e);
+        const float *p0 = u < H ? lds_c + u : c_in + u;
+        s += (double)*p0;
+      }
       s += s1;
     }
     if (a.bin == BIN_HUB) {
@@ -75,8 +90,8 @@ __global__ __launch_bounds__(BLOCK) void k_pr_gather(
         for (int64_t k = hubpref[hi]; k < hubpref[hi + 1]; ++k)
           tot += __hip_atomic_load(hub_partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int32_t v = a.v;
-        const double r = add + prm.d * tot;
-        const int64_t od = out_off[v + 1] - out_off[v];
+        const double r = add + prm.d * (tot + (ghost ? ghost[v] : 0.0));
+        const int64_t od = out_off[v + 1] - out_off[v] + (extra_deg ? extra_deg[v] : 0);
         if (prm.last) rank_out[g_of_l[v]] = (float)r;
         else if (od > 0) c_out[v] = (float)(r / (double)od);
         hub_dangling[hi] = (od == 0) ? r : 0.0;
@@ -89,10 +104,10 @@ __global__ __launch_bounds__(BLOCK) void k_pr_gather(
     else s = group_sum(s, a.stride);
     if (a.ok && a.lane == 0) {
       const int32_t v = a.v;
-      const double r = add + prm.d * s;
-      const int64_t od = out_off[v + 1] - out_off[v];
+      const double r = add + prm.d * (s + (ghost ? ghost[v] : 0.0));
+      const int64_t od = out_off[v + 1] - out_off[v] + (extra_deg ? extra_deg[v] : 0);
       if (prm.last) rank_out[g_of_l[v]] = (float)r;
-      else if (od > 0) c_out[v] = (float)(r / (double)od);
+      else if (od > 0) __builtin_nontemporal_store((float)(r / (double)od), c_out + v);
       if (od == 0) dang += r;
     }
   }
@@ -121,10 +136,11 @@ __global__ __launch_bounds__(BLOCK) void k_pr_gather(
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pr_init(const int64_t *__restrict__ out_off, int64_t n,
-                                                   double inv_n, float *__restrict__ c) {
+                                                   double inv_n, float *__restrict__ c,
+                                                   const int32_t *__restrict__ extra_deg) {
   const int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (v >= n) return;
-  const int64_t od = out_off[v + 1] - out_off[v];
+  const int64_t od = out_off[v + 1] - out_off[v] + (extra_deg ? extra_deg[v] : 0);
   c[v] = od > 0 ? (float)(inv_n / (double)od) : 0.0f;
 }
 
@@ -138,9 +154,9 @@ __global__ __launch_bounds__(BLOCK) void k_pr_uniform(const int32_t *__restrict_
 
 namespace tg {
 
-int pr_init_contrib(const GpuPart &g, float *c, double N, hipStream_t s) {
+int pr_init_contrib(const GpuPart &g, float *c, double N, hipStream_t s, const int32_t *extra_deg) {
   hipLaunchKernelGGL(k_pr_init, dim3((unsigned)((g.n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, g.out.off,
-                     g.n, 1.0 / N, c);
+                     g.n, 1.0 / N, c, extra_deg);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
@@ -152,22 +168,29 @@ int pr_write_initial(const GpuPart &g, float *rank_out, double N, hipStream_t s)
   return TG_OK;
 }
 
-int gpu_pagerank(tg_partition *p, double damping, int32_t iters, int mode, float *rank_out,
-                 hipStream_t s) {
+int gpu_pagerank_setup(tg_partition *p, double damping, int mode, hipStream_t s, const int32_t *extra_deg,
+                       double d0) {
   GpuPart &g = p->gpu;
   Workspace &ws = p->ws;
-  const int64_t n = g.n;
-  if (n == 0) return TG_OK;
-  const int64_t chunks = g.pr.work.vb[1];
-  TG_TRY(ws.ensure(g, chunks));
+  TG_TRY(ws.ensure(g, g.pr.work.vb[1]));
   const double N = (double)g.n_global;
-  // r_0 = 1/N, so c_0(u) = 1/(N outdeg(u)) and D_0 = (#dangling)/N
-  double *dsum = ws.scalars;
-  const double d0 = (double)g.n_dangling / N;
-  TG_HIP(hipMemcpyAsync(dsum, &d0, sizeof(double), hipMemcpyHostToDevice, s));
+  TG_HIP(hipMemcpyAsync(ws.scalars, &d0, sizeof(double), hipMemcpyHostToDevice, s));
   TG_HIP(hipMemsetAsync(ws.counters, 0, 4 * sizeof(uint32_t), s));
   TG_HIP(hipMemsetAsync(ws.hub_counters, 0, (g.pr.nh + 1) * sizeof(uint32_t), s));
-  TG_TRY(pr_init_contrib(g, ws.cbuf[0], N, s));
+  TG_TRY(pr_init_contrib(g, ws.cbuf[0], N, s, extra_deg));
+  (void)damping;
+  (void)mode;
+  return TG_OK;
+}
+
+// One pull iteration k (contributions cbuf[k&1] -> cbuf[(k+1)&1], dangling
+// sum scalars[k&1] -> scalars[(k+1)&1]); `last` writes ranks instead.
+int gpu_pagerank_step(tg_partition *p, double damping, int mode, int32_t k, bool last, float *rank_out,
+                      hipStream_t s, const double *ghost, const int32_t *extra_deg) {
+  GpuPart &g = p->gpu;
+  Workspace &ws = p->ws;
+  const double N = (double)g.n_global;
+  double *dsum = ws.scalars;
   const bool ordered = g.pr_order != nullptr;
   PRParams prm;
   prm.base = (1.0 - damping) / N;
@@ -176,35 +199,47 @@ int gpu_pagerank(tg_partition *p, double damping, int32_t iters, int mode, float
   prm.hub_chunk = p->tune.hub_chunk;
   prm.drop = (mode == TG_PR_DANGLING_DROP) ? 1 : 0;
   prm.nh = g.pr.nh;
+  prm.lds_verts = (int32_t)std::min<int64_t>(p->tune.pr_lds_verts, g.n);
+  const size_t lds_bytes = (size_t)prm.lds_verts * sizeof(float);
+  // Isolated vertices (no in- or out-edges) only need walking when their
+  // rank is written; otherwise their share of the dangling mass is added
+  // analytically.  Directed graphs walk every vertex (in-degree-0 vertices
+  // may still have out-edges whose contribution must be refreshed).
+  const bool walk_all = ordered || last;
+  const Plan *plan = walk_all ? g.pr.d_all : g.pr.d_work;
+  const int64_t vbs = walk_all ? g.pr.all.vb[NBIN] : g.pr.work.vb[NBIN];
+  prm.last = last ? 1 : 0;
+  prm.iso_count = walk_all ? 0.0 : (double)g.n_isolated;
+  // one pass of blocks over the chip: each block stages lds_c once
+  const int grid = (int)std::min<int64_t>(launch_grid(vbs), p->tune.pr_grid);
+  const int tk = ktimer_start(s);
+  const float *cin = ws.cbuf[k & 1];
+  float *cout = ws.cbuf[(k + 1) & 1];
+  if (ordered)
+    hipLaunchKernelGGL(k_pr_gather<true>, dim3(grid), dim3(BLOCK), lds_bytes, s, plan, g.pr_order, g.pr.hubpref,
+                       g.in.off, g.in.col, g.out.off, cin, cout, prm, dsum + (k & 1), dsum + ((k + 1) & 1),
+                       ws.partials, ws.hub_partials, ws.hub_dangling, ws.hub_counters, ws.counters, g.g_of_l,
+                       rank_out, ghost, extra_deg);
+  else
+    hipLaunchKernelGGL(k_pr_gather<false>, dim3(grid), dim3(BLOCK), lds_bytes, s, plan, nullptr, g.pr.hubpref,
+                       g.in.off, g.in.col, g.out.off, cin, cout, prm, dsum + (k & 1), dsum + ((k + 1) & 1),
+                       ws.partials, ws.hub_partials, ws.hub_dangling, ws.hub_counters, ws.counters, g.g_of_l,
+                       rank_out, ghost, extra_deg);
+  ktimer_stop(tk, s, "pr_gather");
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int gpu_pagerank(tg_partition *p, double damping, int32_t iters, int mode, float *rank_out,
+                 hipStream_t s) {
+  GpuPart &g = p->gpu;
+  if (g.n == 0) return TG_OK;
+  const double N = (double)g.n_global;
+  // r_0 = 1/N, so c_0(u) = 1/(N outdeg(u)) and D_0 = (#dangling)/N
+  TG_TRY(gpu_pagerank_setup(p, damping, mode, s, nullptr, (double)g.n_dangling / N));
   if (iters == 0) return pr_write_initial(g, rank_out, N, s);
-  for (int32_t k = 0; k < iters; ++k) {
-    const bool last = (k == iters - 1);
-    // Isolated vertices (no in- or out-edges) only need walking when their
-    // rank is written; otherwise their share of the dangling mass is added
-    // analytically.  Directed graphs walk every vertex (in-degree-0 vertices
-    // may still have out-edges whose contribution must be refreshed).
-    const bool walk_all = ordered || last;
-    const Plan *plan = walk_all ? g.pr.d_all : g.pr.d_work;
-    const int64_t vbs = walk_all ? g.pr.all.vb[NBIN] : g.pr.work.vb[NBIN];
-    prm.last = last ? 1 : 0;
-    prm.iso_count = walk_all ? 0.0 : (double)g.n_isolated;
-    const int grid = launch_grid(vbs);
-    const int tk = ktimer_start(s);
-    const float *cin = ws.cbuf[k & 1];
-    float *cout = ws.cbuf[(k + 1) & 1];
-    if (ordered)
-      hipLaunchKernelGGL(k_pr_gather<true>, dim3(grid), dim3(BLOCK), 0, s, plan, g.pr_order, g.pr.hubpref,
-                         g.in.off, g.in.col, g.out.off, cin, cout, prm, dsum + (k & 1),
-                         dsum + ((k + 1) & 1), ws.partials, ws.hub_partials, ws.hub_dangling,
-                         ws.hub_counters, ws.counters, g.g_of_l, rank_out);
-    else
-      hipLaunchKernelGGL(k_pr_gather<false>, dim3(grid), dim3(BLOCK), 0, s, plan, nullptr, g.pr.hubpref,
-                         g.in.off, g.in.col, g.out.off, cin, cout, prm, dsum + (k & 1),
-                         dsum + ((k + 1) & 1), ws.partials, ws.hub_partials, ws.hub_dangling,
-                         ws.hub_counters, ws.counters, g.g_of_l, rank_out);
-    ktimer_stop(tk, s, "pr_gather");
-    TG_HIP(hipGetLastError());
-  }
+  for (int32_t k = 0; k < iters; ++k)
+    TG_TRY(gpu_pagerank_step(p, damping, mode, k, k == iters - 1, rank_out, s, nullptr, nullptr));
   return TG_OK;
 }
 

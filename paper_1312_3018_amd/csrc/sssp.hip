@@ -47,7 +47,7 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
                                                       const int32_t *__restrict__ wgt, int32_t *dist,
                                                       uint32_t *active, uint32_t *ovf, uint32_t *flags,
                                                       int64_t hub_chunk, unsigned long long *work) {
-  const Plan P = *Pp;
+  const Plan &P = load_plan(Pp);
   const int64_t total = P.vb[NBIN];
   unsigned long long n_edges = 0, n_verts = 0;
   for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
@@ -61,12 +61,12 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
     const int64_t st = a.stride;
     int64_t e = a.e_begin + a.lane;
     for (; e + st < a.e_end; e += 2 * st) {
-      const int32_t n0 = col[e], n1 = col[e + st];
-      const int32_t w0 = wgt[e], w1 = wgt[e + st];
+      const int32_t n0 = stream_load(col + e), n1 = stream_load(col + e + st);
+      const int32_t w0 = stream_load(wgt + e), w1 = stream_load(wgt + e + st);
       relax(dist, active, ovf, flags, dv, n0, w0);
       relax(dist, active, ovf, flags, dv, n1, w1);
     }
-    if (e < a.e_end) relax(dist, active, ovf, flags, dv, col[e], wgt[e]);
+    if (e < a.e_end) relax(dist, active, ovf, flags, dv, stream_load(col + e), stream_load(wgt + e));
   }
   n_edges = block_sum(n_edges);
   n_verts = block_sum(n_verts);
@@ -89,6 +89,33 @@ __global__ __launch_bounds__(BLOCK) void k_overflow_check(const uint32_t *__rest
 
 namespace tg {
 
+int sssp_relax_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks, const Tuning &t,
+                      hipStream_t s) {
+  if (vblocks <= 0) return TG_OK;
+  const int tk = ktimer_start(s);
+  hipLaunchKernelGGL(k_sssp_relax, dim3(launch_grid(vblocks)), dim3(BLOCK), 0, s, ws.plan, queue, ws.hubpref,
+                     g.out.off, g.out.col, g.out.w, ws.state, ws.bits_a, ws.bits_c, ws.counters, t.hub_chunk,
+                     ws.work);
+  ktimer_stop(tk, s, "sssp_relax");
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+// After the last superstep: ws.h_flags[1] = 1 iff some vertex had an
+// overflowing candidate distance and stayed unreached.  Waits on `s`.
+int sssp_overflow_check(const GpuPart &g, Workspace &ws, hipStream_t s) {
+  TG_HIP(hipMemcpyAsync(ws.h_flags, ws.counters, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  TG_HIP(hipStreamSynchronize(s));
+  if (ws.h_flags[0] && g.n > 0) {
+    hipLaunchKernelGGL(k_overflow_check, dim3((unsigned)((g.n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s,
+                       ws.bits_c, ws.state, g.n, ws.counters);
+    TG_HIP(hipGetLastError());
+    TG_HIP(hipMemcpyAsync(ws.h_flags, ws.counters, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    TG_HIP(hipStreamSynchronize(s));
+  }
+  return TG_OK;
+}
+
 int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) {
   GpuPart &g = p->gpu;
   Workspace &ws = p->ws;
@@ -109,27 +136,10 @@ int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) 
     TG_TRY(frontier_compact(g, ws, 1, active, nullptr, ws.queue, nullptr, 0, s));
     TG_TRY(frontier_plan(g, ws, ws.queue, p->tune, s, true));
     if (ws.h_plan->count == 0) break;
-    const int64_t vbs = ws.h_plan->vb[NBIN];
-    if (vbs > 0) {
-      const int tk = ktimer_start(s);
-      hipLaunchKernelGGL(k_sssp_relax, dim3(launch_grid(vbs)), dim3(BLOCK), 0, s, ws.plan, ws.queue,
-                         ws.hubpref, g.out.off, g.out.col, g.out.w, dist, active, ovf, ws.counters,
-                         p->tune.hub_chunk, ws.work);
-      ktimer_stop(tk, s, "sssp_relax");
-      TG_HIP(hipGetLastError());
-    }
+    TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s));
   }
-  TG_HIP(hipMemcpyAsync(ws.h_flags, ws.counters, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  TG_HIP(hipStreamSynchronize(s));
-  if (ws.h_flags[0]) {
-    hipLaunchKernelGGL(k_overflow_check, dim3((unsigned)((g.n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s,
-                       ovf, dist, g.n, ws.counters);
-    TG_HIP(hipGetLastError());
-    TG_HIP(hipMemcpyAsync(ws.h_flags, ws.counters, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    TG_HIP(hipStreamSynchronize(s));
-    if (ws.h_flags[1])
-      return set_error(TG_ERANGE, "sssp: a shortest-path distance does not fit below INT32_MAX");
-  }
+  TG_TRY(sssp_overflow_check(g, ws, s));
+  if (ws.h_flags[1]) return set_error(TG_ERANGE, "sssp: a shortest-path distance does not fit below INT32_MAX");
   if (rounds_out) *rounds_out = rounds;
   return TG_OK;
 }

@@ -36,6 +36,13 @@ void stats_add(const char *key, double value);
       return tg::set_error(TG_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+// A runtime call whose failure is not an error of the current call (frees,
+// timing queries): report it on stderr when TG_DEBUG is set.
+namespace tg {
+void debug_hip(hipError_t e, const char *what);
+}
+#define TG_QUIET(expr) tg::debug_hip((expr), #expr)
+
 #define TG_TRY(expr)          \
   do {                        \
     int rc_ = (expr);         \
@@ -49,6 +56,11 @@ namespace tg {
 struct Tuning {
   int64_t min_deg[tgk::BIN_G1];  // HUB, BLOCK, WAVE, G16, G4
   int64_t hub_chunk;
+  int64_t pr_lds_verts;          // PageRank: contributions staged in LDS per block
+  int64_t pr_grid;               // PageRank: blocks per launch
+  int64_t bfs_lds_words;         // BFS: visited-bitmap words staged in LDS per block
+  int64_t bfs_grid;              // BFS: blocks per launch when staging
+  int64_t bfs_lds_min_vblocks;   // BFS: stage only for frontiers at least this large
 };
 Tuning default_tuning();
 int parse_tuning(const char *json, Tuning *t);
@@ -123,6 +135,9 @@ struct GpuPart {
   int64_t n_isolated = 0;        // out-degree 0 and in-degree 0 (ZERO bin of in_bins when symmetric)
   int64_t max_out_hubs = 0;      // vertices in the HUB bin (out-degree)
   std::vector<int64_t> h_out_off;  // host copy of the local out offsets
+  std::vector<int64_t> h_deg;      // out-degree of each local id (non-increasing)
+  std::vector<int64_t> h_in_deg;   // in-degree along pr_order (non-increasing)
+  DevArena plan_arena;             // tuning-dependent plans
 };
 
 // Per-partition scratch, grown on demand.
@@ -151,6 +166,7 @@ struct Workspace {
   Plan *h_plan = nullptr;        // pinned host copy of the plan
   uint32_t *h_flags = nullptr;   // pinned host flags
   int64_t hub_chunks_cap = 0;
+  int64_t hubs_cap = 0;
   int64_t partials_cap = 0;
   int ensure(const GpuPart &g, int64_t hub_chunks_needed);
   ~Workspace();
@@ -180,7 +196,8 @@ namespace tg {
 // frontier.hip
 int frontier_init_bitmaps(Workspace &ws, hipStream_t s);
 // Compact a bitmap into a sorted queue + plan.  mode 0 (BFS): new = bits & ~prev,
-// prev |= new.  mode 1 (active set): new = bits, bits cleared.  If `level` is
+// prev |= new.  mode 1 (active set): new = bits, bits cleared.  mode 2: as 1,
+// and prev := the bits taken (membership of the current frontier).  If `level` is
 // non-null, level[v] = level_value for every new vertex.
 int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, uint32_t *prev,
                      int32_t *queue, int32_t *level, int32_t level_value, hipStream_t s);
@@ -199,6 +216,12 @@ int bfs_expand_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int
                       const Tuning &t, hipStream_t s);
 int set_bit(uint32_t *bits, int32_t v, hipStream_t s);
 
+// sssp.hip: relaxation of the frontier in `queue` (dist in ws.state, next
+// active set in ws.bits_a, overflow marks in ws.bits_c)
+int sssp_relax_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks, const Tuning &t,
+                      hipStream_t s);
+int sssp_overflow_check(const GpuPart &g, Workspace &ws, hipStream_t s);
+
 // collect.hip
 int collect_levels(const GpuPart &g, const uint32_t *visited, const int32_t *level, int32_t *out,
                    hipStream_t s);
@@ -210,8 +233,15 @@ int fill_f32(float *p, int64_t n, float v, hipStream_t s);
 int bfs_parents(const GpuPart &g, const uint32_t *visited, const int32_t *level, int32_t root_local,
                 int32_t *out, hipStream_t s);
 
+// api.cpp: derive bins and plans of p->gpu from a tuning
+int apply_tuning(tg_partition *p, const Tuning &t);
+
 // pagerank.hip
-int pr_init_contrib(const GpuPart &g, float *c, double N, hipStream_t s);
+int pr_init_contrib(const GpuPart &g, float *c, double N, hipStream_t s, const int32_t *extra_deg = nullptr);
+int gpu_pagerank_setup(tg_partition *p, double damping, int mode, hipStream_t s, const int32_t *extra_deg,
+                       double d0);
+int gpu_pagerank_step(tg_partition *p, double damping, int mode, int32_t k, bool last, float *rank_out,
+                      hipStream_t s, const double *ghost, const int32_t *extra_deg);
 int pr_write_initial(const GpuPart &g, float *rank_out, double N, hipStream_t s);
 
 // algorithms (GPU partition only)

@@ -1,0 +1,75 @@
+"""Hybrid split (one GPU partition + one host-thread partition exchanging
+reduced boundary messages each superstep) against the oracle: results must
+equal the single-partition definitions exactly (BFS, SSSP) or within the
+PageRank tolerance, for every strategy and CPU edge share."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+SMALL_BINS = {"hub_min_deg": 300, "block_min_deg": 100, "wave_min_deg": 24, "g16_min_deg": 6,
+              "g4_min_deg": 2, "hub_chunk": 256}
+
+
+def pr_rel_l1(got, ref):
+    return float(np.abs(got.astype(np.float64) - ref).sum() / np.abs(ref).sum())
+
+
+@pytest.fixture(scope="module", params=["sym", "dir"])
+def graph(request):
+    g = graphgen.rmat(12, symmetrize=(request.param == "sym"))
+    return g, graphgen.weights(g, seed=6)
+
+
+@pytest.mark.parametrize("strategy", ["high", "low", "rand"])
+@pytest.mark.parametrize("alpha", [0.1, 0.5])
+def test_hybrid_matches_oracle(gpu, graph, strategy, alpha):
+    g, w = graph
+    G = gpu.graph_load_csr(g.n, g.offsets, g.cols, w, symmetric=g.symmetric)
+    P = gpu.partition_by_degree(G, strategy, alpha, seed=11, tuning=SMALL_BINS)
+    info = P.info()
+    assert info["cpu_edges"] + info["gpu_edges"] + info["boundary_edges"] == g.nnz
+    deg = np.diff(g.offsets)
+    # a root on each side: the max-degree vertex and the min-degree non-isolated one
+    roots = [graphgen.max_degree_vertex(g), int(np.argmin(np.where(deg > 0, deg, 1 << 30)))]
+    roots += graphgen.sample_roots(g, 2, seed=4).tolist()
+    lev = gpu.bfs(P, roots).cpu().numpy()
+    dist = gpu.sssp(P, roots).cpu().numpy()
+    for i, r in enumerate(roots):
+        assert np.array_equal(lev[i], oracle.bfs(g.offsets, g.cols, r)), (strategy, alpha, r)
+        assert np.array_equal(dist[i], oracle.sssp(g.offsets, g.cols, w, r)), (strategy, alpha, r)
+    for mode in ("uniform", "drop"):
+        rank = gpu.pagerank(P, 0.85, 10, mode).cpu().numpy()
+        assert pr_rel_l1(rank, oracle.pagerank(g.offsets, g.cols, 0.85, 10, mode)) <= 1e-5
+    st = gpu.tg_last_stats()
+    assert st["supersteps"] == 10 and st["exchange_bytes"] > 0
+
+
+def test_partition_statistics(gpu):
+    g = graphgen.rmat(14)
+    G = gpu.graph_load_csr(g.n, g.offsets, g.cols, symmetric=True)
+    E = g.nnz
+    for alpha in (0.1, 0.3, 0.5):
+        hi = gpu.partition_by_degree(G, "high", alpha).info()
+        lo = gpu.partition_by_degree(G, "low", alpha).info()
+        rd = gpu.partition_by_degree(G, "rand", alpha, seed=3).info()
+        for inf in (hi, lo, rd):
+            assert inf["cpu_vertices"] + inf["gpu_vertices"] == g.n
+            assert inf["beta_reduced"] <= inf["beta_raw"]
+        # HIGH holds its edge share with far fewer vertices than LOW or RAND (section 6.3.2)
+        assert hi["cpu_vertices"] * 10 < rd["cpu_vertices"]
+        assert hi["cpu_vertices"] * 10 < lo["cpu_vertices"]
+
+
+def test_hybrid_rejects_unsupported(gpu):
+    g = graphgen.rmat(10)
+    G = gpu.graph_load_csr(g.n, g.offsets, g.cols, symmetric=True)
+    P = gpu.partition_by_degree(G, "high", 0.3)
+    with pytest.raises(gpu.TGError) as ei:
+        gpu.bc(P, [0])
+    assert ei.value.code == gpu.TG_EUNSUPPORTED
+    with pytest.raises(gpu.TGError):
+        gpu.partition_by_degree(G, "high", 0.999999)

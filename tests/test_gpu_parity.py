@@ -17,7 +17,8 @@ INF = oracle.INF
 # small thresholds so that tiny graphs exercise every degree bin, including
 # multi-chunk hubs
 SMALL_BINS = {"hub_min_deg": 300, "block_min_deg": 100, "wave_min_deg": 24, "g16_min_deg": 6,
-              "g4_min_deg": 2, "hub_chunk": 256}
+              "g4_min_deg": 2, "hub_chunk": 256, "pr_lds_verts": 100, "pr_grid": 7,
+              "bfs_lds_words": 16, "bfs_grid": 5, "bfs_lds_min_vblocks": 0}
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -220,3 +221,18 @@ def test_determinism(gpu, rmat14):
     s1 = gpu.sssp(P, [3]).cpu().numpy()
     s2 = gpu.sssp(P, [3]).cpu().numpy()
     assert np.array_equal(s1, s2)
+
+
+def test_retune_keeps_results(gpu, rmat14):
+    g, w = rmat14
+    P = load(gpu, g, w)
+    root = graphgen.max_degree_vertex(g)
+    ref_lev = oracle.bfs(g.offsets, g.cols, root)
+    ref_pr = oracle.pagerank(g.offsets, g.cols, 0.85, 10)
+    for tuning in (SMALL_BINS, {"pr_lds_verts": 0, "bfs_lds_words": 0, "bfs_lds_min_vblocks": 0}, None):
+        gpu.partition_retune(P, tuning)
+        assert np.array_equal(gpu.bfs(P, [root]).cpu().numpy()[0], ref_lev)
+        assert pr_rel_l1(gpu.pagerank(P, 0.85, 10).cpu().numpy(), ref_pr) <= 1e-5
+        assert np.array_equal(gpu.sssp(P, [root]).cpu().numpy()[0], oracle.sssp(g.offsets, g.cols, w, root))
+    with pytest.raises(gpu.TGError):
+        gpu.partition_retune(P, {"hub_min_deg": 10, "block_min_deg": 100})
