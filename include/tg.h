@@ -125,6 +125,15 @@ int partition_retune(tg_partition *p, const char *tuning_json);
 int bfs(const tg_partition *p, const int32_t *roots, int32_t num_roots,
         int32_t *levels, int32_t *parents, void *stream);
 
+/* Batched BFS: the same result as bfs() (levels only), computed for up to 64
+ * roots at a time in one chain of supersteps; every vertex carries one bit
+ * per root in its visited / frontier masks, so an edge is streamed once per
+ * superstep for all roots that have its source on their frontier.
+ * GPU-only partitions (cpu_edge_share 0).  Same buffers and errors as bfs(),
+ * plus TG_EUNSUPPORTED on a hybrid partition. */
+int bfs_batched(const tg_partition *p, const int32_t *roots, int32_t num_roots,
+                int32_t *levels, void *stream);
+
 /* Single-source shortest paths by frontier Bellman-Ford (section 7.3,
  * Figure 20) over the int32 weights given to graph_load_csr.
  *   dist      device int32 [num_roots * V] (TG_INF when unreachable).
@@ -132,6 +141,14 @@ int bfs(const tg_partition *p, const int32_t *roots, int32_t num_roots,
  * finite distance is >= INT32_MAX), TG_EINVAL, TG_ENOMEM, TG_EDEVICE. */
 int sssp(const tg_partition *p, const int32_t *roots, int32_t num_roots,
          int32_t *dist, void *stream);
+
+/* Batched SSSP: the same result as sssp(), up to 64 roots per chain of
+ * supersteps with one distance per root per vertex ([V][64] int32 scratch).
+ * If a candidate distance reaches INT32_MAX the affected roots are redone
+ * with sssp()'s exact overflow check.  GPU-only partitions.  Same buffers and
+ * errors as sssp(). */
+int sssp_batched(const tg_partition *p, const int32_t *roots, int32_t num_roots,
+                 int32_t *dist, void *stream);
 
 /* PageRank by synchronous power iteration with a pull gather over in-edges
  * (section 7.1, Figure 14): r_0 = 1/V and
@@ -155,6 +172,58 @@ int pagerank(const tg_partition *p, float damping, int32_t iterations,
  * 2^53, beyond which fp64 counts are no longer exact). */
 int bc(const tg_partition *p, const int32_t *sources, int32_t num_sources,
        float *scores, void *stream);
+
+/* ------------------------------------------------------------- serving
+ * A query server with continuous batching over resident graphs: BFS and SSSP
+ * queries are admitted into a graph's 64-slot engine (see bfs_batched) as
+ * slots and memory free up, joining at the next superstep while other
+ * queries are in flight; each query's result is the same as a solo bfs() /
+ * sssp() run.  One worker thread drives all graphs; each (graph, kind) has its
+ * own stream so different graphs' supersteps overlap on the device. */
+typedef struct tg_server tg_server;
+enum { TG_QUERY_BFS = 0, TG_QUERY_SSSP = 1 };
+
+/* opts_json: NULL or {"max_slots": 1..64 (concurrent queries per graph and
+ * kind; 1 = one query at a time), "memory_cap_bytes": N (device bytes that
+ * running queries may hold; a query over the cap waits)}.
+ * Errors: TG_EINVAL, TG_ENOMEM, TG_EDEVICE. */
+int server_create(const char *opts_json, tg_server **out);
+
+/* Register a GPU-only partition (cpu_edge_share 0); it must outlive the
+ * server.  Errors: TG_EINVAL, TG_EUNSUPPORTED (hybrid partition). */
+int server_add_graph(tg_server *s, const tg_partition *p, int32_t *graph_id);
+
+/* Queue a query.  out: device int32 [V] owned by the caller, untouched by the
+ * caller until server_wait returns for this ticket; receives levels (BFS) or
+ * distances (SSSP) in original ids.  Errors: TG_EINVAL (bad graph, kind or
+ * root), TG_EUNSUPPORTED (SSSP on an unweighted graph), TG_ENOMEM (a single
+ * query exceeds the memory cap). */
+int server_submit(tg_server *s, int32_t graph_id, int32_t kind, int32_t root,
+                  int32_t *out, uint64_t *ticket);
+
+/* Wait for a ticket (timeout_us < 0: no limit).  latency_us gets the time
+ * from submission to the result being in `out`.  A ticket can be waited for
+ * once.  Errors: TG_ETIMEOUT (not done yet; the ticket stays valid),
+ * TG_EINVAL (unknown ticket), TG_ERANGE (an SSSP candidate distance reached
+ * INT32_MAX: use sssp() for an exact verdict), or the query's own error. */
+int server_wait(tg_server *s, uint64_t ticket, int64_t timeout_us, double *latency_us);
+
+/* JSON counters (completed, supersteps, max_concurrent, waiting,
+ * memory_in_use); same return convention as partition_info. */
+int server_stats(tg_server *s, char *json, size_t cap);
+
+/* Stop the worker after running queries finish; waiting queries are
+ * dropped (their tickets are never completed). */
+void server_destroy(tg_server *s);
+
+/* Batched Brandes betweenness: the same result as bc() (within the stated
+ * tolerance), up to 64 sources per chain of supersteps with vertex state laid
+ * out [vertex][source] (sigma fp64, delta fp32, level int32: 16 B per vertex
+ * and source of scratch).  Many small graphs run in one chain by loading
+ * their disjoint union as one graph.  GPU-only partitions.  Same buffers and
+ * errors as bc(), plus TG_EUNSUPPORTED on a hybrid partition. */
+int bc_batched(const tg_partition *p, const int32_t *sources, int32_t num_sources,
+               float *scores, void *stream);
 
 void graph_free(tg_graph *g);
 void partition_free(tg_partition *p);

@@ -53,14 +53,29 @@ def _load():
     lib.partition_retune.argtypes = [vp, ctypes.c_char_p]
     lib.bfs.argtypes = [vp, _c_i32p, ctypes.c_int32, vp, vp, vp]
     lib.sssp.argtypes = [vp, _c_i32p, ctypes.c_int32, vp, vp]
+    lib.bfs_batched.argtypes = [vp, _c_i32p, ctypes.c_int32, vp, vp]
+    lib.bc_batched.argtypes = [vp, _c_i32p, ctypes.c_int32, vp, vp]
+    lib.bc_batched.restype = ctypes.c_int
+    lib.sssp_batched.argtypes = [vp, _c_i32p, ctypes.c_int32, vp, vp]
     lib.pagerank.argtypes = [vp, ctypes.c_float, ctypes.c_int32, ctypes.c_int32, vp, vp]
     lib.bc.argtypes = [vp, _c_i32p, ctypes.c_int32, vp, vp]
+    lib.server_create.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+    lib.server_add_graph.argtypes = [vp, vp, _c_i32p]
+    lib.server_submit.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+                                  ctypes.POINTER(ctypes.c_uint64)]
+    lib.server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+    lib.server_stats.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    lib.server_destroy.argtypes = [vp]
+    lib.server_destroy.restype = None
+    for f in (lib.server_create, lib.server_add_graph, lib.server_submit, lib.server_wait, lib.server_stats):
+        f.restype = ctypes.c_int
     lib.graph_free.argtypes = [vp]
     lib.partition_free.argtypes = [vp]
     lib.tg_last_error.restype = ctypes.c_char_p
     lib.partition_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     lib.tg_last_stats.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     for f in (lib.graph_load_csr, lib.partition_by_degree, lib.partition_retune, lib.bfs, lib.sssp, lib.pagerank, lib.bc,
+              lib.bfs_batched, lib.sssp_batched,
               lib.partition_info, lib.tg_last_stats):
         f.restype = ctypes.c_int
     lib.graph_free.restype = None
@@ -260,3 +275,81 @@ def bc(part: Partition, sources: Sequence[int], scores=None, stream=None):
     scores = _out(scores, (part.n,), "float32")
     _check(_load().bc(part.handle, s.ctypes.data_as(_c_i32p), s.size, scores.data_ptr(), _stream_handle(stream)))
     return scores
+
+
+def bfs_batched(part: Partition, roots: Sequence[int], levels=None, stream=None):
+    """bfs() for many roots through the 64-slot bitmask engine."""
+    r = _roots(roots)
+    levels = _out(levels, (r.size, part.n), "int32")
+    _check(_load().bfs_batched(part.handle, r.ctypes.data_as(_c_i32p), r.size, levels.data_ptr(),
+                               _stream_handle(stream)))
+    return levels
+
+
+def bc_batched(part: Partition, sources: Sequence[int], scores=None, stream=None):
+    """bc() for many sources through the 64-source [vertex][source] layout."""
+    s = _roots(sources)
+    scores = _out(scores, (part.n,), "float32")
+    _check(_load().bc_batched(part.handle, s.ctypes.data_as(_c_i32p), s.size, scores.data_ptr(),
+                              _stream_handle(stream)))
+    return scores
+
+
+def sssp_batched(part: Partition, roots: Sequence[int], dist=None, stream=None):
+    """sssp() for many roots through the 64-slot engine."""
+    r = _roots(roots)
+    dist = _out(dist, (r.size, part.n), "int32")
+    _check(_load().sssp_batched(part.handle, r.ctypes.data_as(_c_i32p), r.size, dist.data_ptr(),
+                                _stream_handle(stream)))
+    return dist
+
+
+TG_QUERY_BFS, TG_QUERY_SSSP = 0, 1
+
+
+class Server:
+    """Continuous-batching query server (server_* in the C ABI)."""
+
+    def __init__(self, max_slots: int = 64, memory_cap_bytes: Optional[int] = None):
+        lib = _load()
+        opts = {"max_slots": int(max_slots)}
+        if memory_cap_bytes is not None:
+            opts["memory_cap_bytes"] = int(memory_cap_bytes)
+        h = ctypes.c_void_p()
+        _check(lib.server_create(json.dumps(opts).encode(), ctypes.byref(h)))
+        self._h = h.value
+        self._parts = []
+
+    def add_graph(self, part: Partition) -> int:
+        gid = ctypes.c_int32()
+        _check(_load().server_add_graph(self._h, part.handle, ctypes.byref(gid)))
+        self._parts.append(part)
+        return gid.value
+
+    def submit(self, graph_id: int, kind: int, root: int, out) -> int:
+        t = ctypes.c_uint64()
+        _check(_load().server_submit(self._h, graph_id, kind, int(root), out.data_ptr(), ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> float:
+        lat = ctypes.c_double()
+        _check(_load().server_wait(self._h, ticket, int(timeout_us), ctypes.byref(lat)))
+        return lat.value
+
+    def stats(self) -> dict:
+        lib = _load()
+        n = lib.server_stats(self._h, None, 0)
+        buf = ctypes.create_string_buffer(n + 1)
+        lib.server_stats(self._h, buf, n + 1)
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if self._h:
+            _load().server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -95,7 +95,8 @@ def tune(part, roots: Sequence[int], sssp_roots: Optional[Sequence[int]] = None,
     import torch
     V = part.n
     lev = torch.empty((len(roots), V), dtype=torch.int32, device="cuda")
-    dist = torch.empty((max(len(sssp_roots or []), 1), V), dtype=torch.int32, device="cuda")
+    n_ss = 0 if sssp_roots is None else len(sssp_roots)
+    dist = torch.empty((max(n_ss, 1), V), dtype=torch.int32, device="cuda")
     rank = torch.empty((V,), dtype=torch.float32, device="cuda")
     bufs = (lev, dist, rank)
     cfg = dict(DEFAULTS)

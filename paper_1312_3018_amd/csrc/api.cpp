@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "hybrid.h"
+#include "slots.h"
 #include "tg_internal.h"
 
 using namespace tg;
@@ -576,6 +577,9 @@ extern "C" void partition_free(tg_partition *p) {
   if (!p) return;
   TG_QUIET(hipSetDevice(p->device));
   hybrid_free(p);
+  delete p->slots[0];
+  delete p->slots[1];
+  bcb_free(p);
   delete p;
 }
 
@@ -754,6 +758,65 @@ extern "C" int bc(const tg_partition *pc, const int32_t *sources, int32_t num_so
   TG_HIP(hipMemcpyAsync(p->ws.h_flags, p->ws.counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   TG_HIP(hipStreamSynchronize(s));
   if (p->ws.h_flags[2]) return set_error(TG_ERANGE, "bc: a shortest-path count reached 2^53");
+  stats_add("sources", num_sources);
+  ktimer_emit();
+  return TG_OK;
+}
+
+extern "C" int bfs_batched(const tg_partition *pc, const int32_t *roots, int32_t num_roots, int32_t *levels,
+                           void *stream) {
+  clear_error();
+  TG_TRY(check_call(pc, levels, "bfs_batched"));
+  TG_TRY(check_roots(pc, roots, num_roots, "bfs_batched"));
+  if (pc->alpha > 0.0) return set_error(TG_EUNSUPPORTED, "bfs_batched: hybrid partitions run bfs() only");
+  tg_partition *p = const_cast<tg_partition *>(pc);
+  hipStream_t s = (hipStream_t)stream;
+  stats_reset("bfs_batched");
+  ktimer_reset();
+  int64_t steps = 0;
+  TG_TRY(slots_run_batch(p, kSlotBfs, roots, num_roots, levels, s, &steps));
+  TG_HIP(hipStreamSynchronize(s));
+  stats_add("roots", num_roots);
+  stats_add("supersteps", (double)steps);
+  ktimer_emit();
+  return TG_OK;
+}
+
+extern "C" int sssp_batched(const tg_partition *pc, const int32_t *roots, int32_t num_roots, int32_t *dist,
+                            void *stream) {
+  clear_error();
+  TG_TRY(check_call(pc, dist, "sssp_batched"));
+  TG_TRY(check_roots(pc, roots, num_roots, "sssp_batched"));
+  if (!pc->g->has_w) return set_error(TG_EUNSUPPORTED, "sssp_batched: the graph was loaded without weights");
+  if (pc->alpha > 0.0) return set_error(TG_EUNSUPPORTED, "sssp_batched: hybrid partitions run sssp() only");
+  tg_partition *p = const_cast<tg_partition *>(pc);
+  hipStream_t s = (hipStream_t)stream;
+  stats_reset("sssp_batched");
+  ktimer_reset();
+  int64_t steps = 0;
+  TG_TRY(slots_run_batch(p, kSlotSssp, roots, num_roots, dist, s, &steps));
+  TG_HIP(hipStreamSynchronize(s));
+  stats_add("roots", num_roots);
+  stats_add("supersteps", (double)steps);
+  ktimer_emit();
+  return TG_OK;
+}
+
+extern "C" int bc_batched(const tg_partition *pc, const int32_t *sources, int32_t num_sources, float *scores,
+                          void *stream) {
+  clear_error();
+  TG_TRY(check_call(pc, scores, "bc_batched"));
+  TG_TRY(check_roots(pc, sources, num_sources, "bc_batched"));
+  tg_partition *p = const_cast<tg_partition *>(pc);
+  hipStream_t s = (hipStream_t)stream;
+  stats_reset("bc_batched");
+  ktimer_reset();
+  if (p->alpha > 0.0) return set_error(TG_EUNSUPPORTED, "bc_batched: hybrid partitions are not supported");
+  TG_TRY(p->ws.ensure(p->gpu, 0));
+  TG_TRY(fill_f64(p->ws.bc_acc, p->gpu.n, 0.0, s));
+  TG_TRY(gpu_bc_batched(p, sources, num_sources, s));
+  TG_TRY(collect_f64_to_f32(p->gpu, p->ws.bc_acc, scores, s));
+  TG_HIP(hipStreamSynchronize(s));
   stats_add("sources", num_sources);
   ktimer_emit();
   return TG_OK;

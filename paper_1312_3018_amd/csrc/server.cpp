@@ -1,0 +1,330 @@
+// Query server with continuous batching.  Graphs stay resident on the
+// device; BFS and SSSP queries are queued per (graph, kind) and admitted into
+// the 64-slot engine of that graph as slots and memory free up, at superstep
+// boundaries, so queries that arrive while others run join the next
+// superstep instead of waiting for the batch to drain.  One worker thread
+// enqueues one superstep on every engine that has work (each engine has its
+// own stream, so different graphs' supersteps overlap on the device), then
+// completes them, retires finished slots (results are in the caller's buffer)
+// and admits waiting queries.
+#include <hip/hip_runtime.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "slots.h"
+
+using namespace tg;
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+struct Query {
+  uint64_t ticket;
+  int32_t graph, kind, root;
+  int32_t *out;
+  clk::time_point arrival, done_at;
+  bool done = false;
+  int status = TG_OK;
+  std::string err;
+  int64_t bytes = 0;
+};
+
+struct Lane {  // one (graph, kind) engine
+  tg_partition *p = nullptr;
+  int kind = 0;
+  hipStream_t stream = nullptr;
+  std::unique_ptr<SlotEngine> eng;
+  std::deque<Query *> waiting;
+  Query *slot_q[kSlots] = {};
+  bool launched = false;
+  int64_t engine_bytes = 0;
+};
+
+bool json_num(const char *json, const char *key, double *out) {
+  if (!json) return false;
+  std::string k = std::string("\"") + key + "\"";
+  const char *p = strstr(json, k.c_str());
+  if (!p) return false;
+  p += k.size();
+  while (*p == ' ' || *p == ':' || *p == '\t' || *p == '\n') ++p;
+  char *end = nullptr;
+  const double v = strtod(p, &end);
+  if (end == p) return false;
+  *out = v;
+  return true;
+}
+
+}  // namespace
+
+struct tg_server {
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::vector<std::unique_ptr<Lane>> lanes;  // index = graph * 2 + kind
+  std::vector<tg_partition *> graphs;
+  std::unordered_map<uint64_t, std::unique_ptr<Query>> queries;
+  uint64_t next_ticket = 1;
+  int max_slots = kSlots;
+  int64_t mem_cap = INT64_MAX;
+  int64_t mem_used = 0;
+  int device = 0;
+  bool stop = false;
+  std::thread worker;
+  // statistics
+  int64_t completed = 0, supersteps = 0, max_concurrent = 0;
+
+  void run();
+};
+
+namespace {
+
+// Device bytes a query holds while it runs (the per-query share of the
+// space formula of section 4.3.3: per-vertex state for one source).
+int64_t query_bytes(const tg_partition *p, int kind) {
+  const int64_t n = p->gpu.n;
+  return kind == kSlotBfs ? (3 * n + 7) / 8 : 4 * n + (2 * n + 7) / 8;
+}
+
+void finish(tg_server *S, Query *q, int status, const std::string &err) {
+  q->status = status;
+  q->err = err;
+  q->done_at = clk::now();
+  q->done = true;
+  S->mem_used -= q->bytes;
+  ++S->completed;
+}
+
+}  // namespace
+
+void tg_server::run() {
+  TG_QUIET(hipSetDevice(device));
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    // admit waiting queries into free slots, within the memory cap
+    bool any = false;
+    for (auto &lp : lanes) {
+      Lane &L = *lp;
+      if (!L.p) continue;
+      while (!L.waiting.empty()) {
+        Query *q = L.waiting.front();
+        if (!L.eng) {
+          L.eng.reset(new SlotEngine());
+          int rc = L.eng->init(L.p, L.kind, L.stream);
+          if (rc != TG_OK) {
+            std::string e = tg_last_error();
+            for (Query *w : L.waiting) finish(this, w, rc, e);
+            L.waiting.clear();
+            L.eng.reset();
+            cv_done.notify_all();
+            break;
+          }
+        }
+        int used = 0;
+        for (int k = 0; k < kSlots; ++k) used += L.slot_q[k] != nullptr;
+        const int slot = L.eng->free_slot();
+        if (slot < 0 || used >= max_slots || mem_used + q->bytes > mem_cap) break;
+        L.waiting.pop_front();
+        mem_used += q->bytes;
+        L.slot_q[slot] = q;
+        int rc = L.eng->join(slot, L.p->h_l_of_g[q->root], L.kind == kSlotBfs ? q->out : nullptr);
+        if (rc != TG_OK) {
+          L.slot_q[slot] = nullptr;
+          L.eng->busy &= ~(1ull << slot);
+          finish(this, q, rc, tg_last_error());
+          cv_done.notify_all();
+        }
+      }
+      if (L.eng && L.eng->busy) any = true;
+    }
+    int64_t running = 0;
+    for (auto &lp : lanes)
+      if (lp->eng) running += __builtin_popcountll(lp->eng->busy);
+    if (running > max_concurrent) max_concurrent = running;
+    if (!any) {
+      if (stop) break;
+      cv_work.wait(lk);
+      continue;
+    }
+    // one superstep on every busy engine: enqueue all, then complete all
+    lk.unlock();
+    for (auto &lp : lanes) {
+      Lane &L = *lp;
+      L.launched = false;
+      if (L.eng && L.eng->busy && L.eng->launch_step() == TG_OK) L.launched = true;
+    }
+    std::vector<std::pair<Lane *, unsigned long long>> fin;
+    for (auto &lp : lanes) {
+      Lane &L = *lp;
+      if (!L.launched) continue;
+      unsigned long long f = 0;
+      if (L.eng->finish_step(&f) == TG_OK && f) {
+        if (L.kind == kSlotSssp)
+          for (int k = 0; k < kSlots; ++k)
+            if ((f >> k) & 1ull) L.eng->tab.out[k] = L.slot_q[k]->out;
+        bool ovf = false;
+        const int rc = L.eng->retire(f, &ovf);
+        fin.emplace_back(&L, f);
+        if (rc != TG_OK || ovf) {
+          for (int k = 0; k < kSlots; ++k)
+            if ((f >> k) & 1ull) L.slot_q[k]->status = rc != TG_OK ? rc : TG_ERANGE;
+        }
+      }
+    }
+    lk.lock();
+    ++supersteps;
+    for (auto &pr : fin) {
+      Lane &L = *pr.first;
+      for (int k = 0; k < kSlots; ++k)
+        if ((pr.second >> k) & 1ull) {
+          Query *q = L.slot_q[k];
+          L.slot_q[k] = nullptr;
+          const int st = q->status;
+          finish(this, q, st, st == TG_ERANGE ? "sssp: a candidate distance reached INT32_MAX" : "");
+        }
+    }
+    if (!fin.empty()) cv_done.notify_all();
+  }
+}
+
+extern "C" int server_create(const char *opts_json, tg_server **out) {
+  clear_error();
+  if (!out) return set_error(TG_EINVAL, "server_create: out is NULL");
+  auto *S = new (std::nothrow) tg_server();
+  if (!S) return set_error(TG_ENOMEM, "server_create: out of host memory");
+  double v;
+  if (json_num(opts_json, "max_slots", &v)) S->max_slots = (int)v;
+  if (json_num(opts_json, "memory_cap_bytes", &v)) S->mem_cap = (int64_t)v;
+  if (S->max_slots < 1 || S->max_slots > kSlots) {
+    delete S;
+    return set_error(TG_EINVAL, "server_create: max_slots must be in [1, 64]");
+  }
+  if (S->mem_cap < 0) {
+    delete S;
+    return set_error(TG_EINVAL, "server_create: memory_cap_bytes < 0");
+  }
+  if (hipGetDevice(&S->device) != hipSuccess) {
+    delete S;
+    return set_error(TG_EDEVICE, "server_create: no HIP device");
+  }
+  S->worker = std::thread([S] { S->run(); });
+  *out = S;
+  return TG_OK;
+}
+
+extern "C" int server_add_graph(tg_server *S, const tg_partition *p, int32_t *graph_id) {
+  clear_error();
+  if (!S || !p || !graph_id) return set_error(TG_EINVAL, "server_add_graph: NULL argument");
+  if (p->alpha > 0.0) return set_error(TG_EUNSUPPORTED, "server_add_graph: hybrid partitions are not served");
+  std::lock_guard<std::mutex> lk(S->mu);
+  const int32_t id = (int32_t)S->graphs.size();
+  S->graphs.push_back(const_cast<tg_partition *>(p));
+  for (int kind = 0; kind < 2; ++kind) {
+    std::unique_ptr<Lane> L(new Lane());
+    L->p = const_cast<tg_partition *>(p);
+    L->kind = kind;
+    TG_HIP(hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking));
+    S->lanes.push_back(std::move(L));
+  }
+  *graph_id = id;
+  return TG_OK;
+}
+
+extern "C" int server_submit(tg_server *S, int32_t graph_id, int32_t kind, int32_t root, int32_t *out,
+                             uint64_t *ticket) {
+  clear_error();
+  if (!S || !out || !ticket) return set_error(TG_EINVAL, "server_submit: NULL argument");
+  if (kind != TG_QUERY_BFS && kind != TG_QUERY_SSSP) return set_error(TG_EINVAL, "server_submit: unknown kind %d", kind);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (graph_id < 0 || graph_id >= (int32_t)S->graphs.size())
+    return set_error(TG_EINVAL, "server_submit: unknown graph %d", graph_id);
+  tg_partition *p = S->graphs[graph_id];
+  if (root < 0 || root >= p->g->n) return set_error(TG_EINVAL, "server_submit: root %d out of range", root);
+  if (kind == TG_QUERY_SSSP && !p->g->has_w)
+    return set_error(TG_EUNSUPPORTED, "server_submit: graph %d has no weights", graph_id);
+  const int k = kind == TG_QUERY_BFS ? kSlotBfs : kSlotSssp;
+  const int64_t bytes = query_bytes(p, k);
+  if (bytes > S->mem_cap)
+    return set_error(TG_ENOMEM, "server_submit: a query needs %lld bytes, above the cap", (long long)bytes);
+  std::unique_ptr<Query> q(new Query());
+  q->ticket = S->next_ticket++;
+  q->graph = graph_id;
+  q->kind = k;
+  q->root = root;
+  q->out = out;
+  q->arrival = clk::now();
+  q->bytes = bytes;
+  S->lanes[(size_t)graph_id * 2 + k]->waiting.push_back(q.get());
+  *ticket = q->ticket;
+  S->queries.emplace(q->ticket, std::move(q));
+  S->cv_work.notify_one();
+  return TG_OK;
+}
+
+extern "C" int server_wait(tg_server *S, uint64_t ticket, int64_t timeout_us, double *latency_us) {
+  clear_error();
+  if (!S) return set_error(TG_EINVAL, "server_wait: server is NULL");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->queries.find(ticket);
+  if (it == S->queries.end()) return set_error(TG_EINVAL, "server_wait: unknown ticket %llu", (unsigned long long)ticket);
+  Query *q = it->second.get();
+  auto ready = [q] { return q->done; };
+  if (timeout_us < 0) {
+    S->cv_done.wait(lk, ready);
+  } else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+    return set_error(TG_ETIMEOUT, "server_wait: ticket %llu not done within %lld us", (unsigned long long)ticket,
+                     (long long)timeout_us);
+  }
+  if (latency_us) *latency_us = std::chrono::duration<double, std::micro>(q->done_at - q->arrival).count();
+  const int st = q->status;
+  const std::string err = q->err;
+  S->queries.erase(it);
+  if (st != TG_OK) return set_error(st, "%s", err.c_str());
+  return TG_OK;
+}
+
+extern "C" int server_stats(tg_server *S, char *json, size_t cap) {
+  clear_error();
+  if (!S) return set_error(TG_EINVAL, "server_stats: server is NULL");
+  std::lock_guard<std::mutex> lk(S->mu);
+  int64_t waiting = 0;
+  for (auto &lp : S->lanes) waiting += (int64_t)lp->waiting.size();
+  char buf[512];
+  const int n = snprintf(buf, sizeof(buf),
+                         "{\"completed\":%lld,\"supersteps\":%lld,\"max_concurrent\":%lld,\"waiting\":%lld,"
+                         "\"memory_in_use\":%lld,\"max_slots\":%d}",
+                         (long long)S->completed, (long long)S->supersteps, (long long)S->max_concurrent,
+                         (long long)waiting, (long long)S->mem_used, S->max_slots);
+  if (json && cap) {
+    const size_t k = std::min(cap - 1, (size_t)n);
+    memcpy(json, buf, k);
+    json[k] = 0;
+  }
+  return n;
+}
+
+extern "C" void server_destroy(tg_server *S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    // queries still waiting are abandoned; running ones finish first
+    for (auto &lp : S->lanes) lp->waiting.clear();
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  for (auto &lp : S->lanes) {
+    lp->eng.reset();
+    if (lp->stream) TG_QUIET(hipStreamDestroy(lp->stream));
+  }
+  delete S;
+}

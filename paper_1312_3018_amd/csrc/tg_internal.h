@@ -173,6 +173,8 @@ struct Workspace {
 };
 
 struct HybridState;
+struct SlotEngine;
+struct BcBatchState;
 
 }  // namespace tg
 
@@ -188,6 +190,8 @@ struct tg_partition {
   std::vector<int32_t> h_l_of_g;  // global -> GPU-local id (or -1)
   std::vector<int32_t> h_g_of_l;  // GPU-local -> global id
   tg::HybridState *hy = nullptr;  // host partition + boundary buffers (cpu_edge_share > 0)
+  tg::SlotEngine *slots[2] = {nullptr, nullptr};  // batched BFS / SSSP engines (lazy)
+  tg::BcBatchState *bcb = nullptr;                 // batched BC scratch (lazy)
 };
 
 namespace tg {
@@ -250,5 +254,8 @@ int gpu_sssp(tg_partition *p, int32_t root_local, hipStream_t s, int64_t *rounds
 int gpu_pagerank(tg_partition *p, double damping, int32_t iters, int mode, float *rank_out,
                  hipStream_t s);
 int gpu_bc_source(tg_partition *p, int32_t src_local, hipStream_t s);
+// bcb.hip: adds the dependencies of `sources` (original ids) into ws.bc_acc
+int gpu_bc_batched(tg_partition *p, const int32_t *sources, int32_t ns, hipStream_t s);
+void bcb_free(tg_partition *p);
 
 }  // namespace tg

@@ -1,0 +1,88 @@
+"""Batched (64-slot bitmask) BFS and SSSP: every root's result equals its
+single-source run and the oracle (bit-exact)."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+SMALL_BINS = {"hub_min_deg": 300, "block_min_deg": 100, "wave_min_deg": 24, "g16_min_deg": 6,
+              "g4_min_deg": 2, "hub_chunk": 256}
+
+
+@pytest.mark.parametrize("sym", [True, False])
+@pytest.mark.parametrize("tuning", [None, SMALL_BINS])
+def test_batched_equals_oracle(gpu, sym, tuning):
+    g = graphgen.rmat(12, symmetrize=sym)
+    w = graphgen.weights(g, seed=8)
+    G = gpu.graph_load_csr(g.n, g.offsets, g.cols, w, symmetric=sym)
+    P = gpu.partition_by_degree(G, tuning=tuning)
+    # 70 roots: one full chunk of 64 and a ragged one; a repeated root; an isolated one
+    roots = graphgen.sample_roots(g, 68, seed=2).tolist()
+    roots += [roots[3], int(np.argmin(np.diff(g.offsets)))]
+    lev = gpu.bfs_batched(P, roots).cpu().numpy()
+    dist = gpu.sssp_batched(P, roots).cpu().numpy()
+    single = gpu.bfs(P, roots[:5]).cpu().numpy()
+    assert np.array_equal(single, lev[:5])
+    for i, r in enumerate(roots):
+        assert np.array_equal(lev[i], oracle.bfs(g.offsets, g.cols, r)), (i, r)
+        assert np.array_equal(dist[i], oracle.sssp(g.offsets, g.cols, w, r)), (i, r)
+    # reuse of the engine after a run gives the same answers
+    lev2 = gpu.bfs_batched(P, roots[:7]).cpu().numpy()
+    assert np.array_equal(lev2, lev[:7])
+
+
+def test_batched_overflow_falls_back_exactly(gpu):
+    g = graphgen.from_edges(4, [0, 1, 0], [1, 2, 3], symmetrize=False)
+    w = np.array([2**31 - 10, 2**31 - 10, 5], dtype=np.int32)
+    G = gpu.graph_load_csr(g.n, g.offsets, g.cols, w)
+    P = gpu.partition_by_degree(G)
+    with pytest.raises(gpu.TGError) as ei:
+        gpu.sssp_batched(P, [0])
+    assert ei.value.code == gpu.TG_ERANGE
+    assert gpu.sssp_batched(P, [3, 2]).cpu().numpy().tolist() == [[2**31 - 1] * 3 + [0],
+                                                                  [2**31 - 1, 2**31 - 1, 0, 2**31 - 1]]
+
+
+@pytest.mark.parametrize("sym", [True, False])
+def test_bc_batched_equals_oracle(gpu, sym):
+    g = graphgen.rmat(11, symmetrize=sym)
+    G = gpu.graph_load_csr(g.n, g.offsets, g.cols, symmetric=sym)
+    P = gpu.partition_by_degree(G, tuning=SMALL_BINS)
+    srcs = graphgen.sample_roots(g, 70, seed=12).tolist() + [5, 5]
+    got = gpu.bc_batched(P, srcs).cpu().numpy().astype(np.float64)
+    ref = oracle.bc(g.offsets, g.cols, srcs)
+    tol = 1e-4 * np.abs(ref) + 1e-6 * max(np.abs(ref).max(), 1.0)
+    assert np.all(np.abs(got - ref) <= tol)
+    single = gpu.bc(P, srcs[:3]).cpu().numpy().astype(np.float64)
+    ref3 = oracle.bc(g.offsets, g.cols, srcs[:3])
+    assert np.all(np.abs(single - ref3) <= 1e-4 * np.abs(ref3) + 1e-6 * max(ref3.max(), 1.0))
+
+
+def test_bc_batched_many_graphs_in_one_chain(gpu):
+    """Uneven graphs as one disjoint union: each graph's scores equal its solo run."""
+    parts = [graphgen.rmat(s, seed=100 + i) for i, s in enumerate((7, 9, 8, 10, 7))]
+    offs, cols, base = [np.zeros(1, dtype=np.int64)], [], 0
+    edge_base = 0
+    for g in parts:
+        offs.append(g.offsets[1:] + edge_base)
+        cols.append(g.cols + base)
+        base += g.n
+        edge_base += g.nnz
+    U_off, U_col = np.concatenate(offs), np.concatenate(cols)
+    G = gpu.graph_load_csr(base, U_off, U_col, symmetric=True)
+    P = gpu.partition_by_degree(G)
+    srcs, vbase = [], 0
+    for g in parts:
+        srcs += (graphgen.sample_roots(g, 6, seed=1) + vbase).tolist()
+        vbase += g.n
+    got = gpu.bc_batched(P, srcs).cpu().numpy().astype(np.float64)
+    vbase = 0
+    for g in parts:
+        mine = [s - vbase for s in srcs if vbase <= s < vbase + g.n]
+        ref = oracle.bc(g.offsets, g.cols, mine)
+        sub = got[vbase:vbase + g.n]
+        assert np.all(np.abs(sub - ref) <= 1e-4 * np.abs(ref) + 1e-6 * max(ref.max(), 1.0))
+        vbase += g.n
