@@ -22,7 +22,7 @@ from . import bfs, pagerank, partition_info, partition_retune, sssp
 DEFAULTS = {
     "hub_min_deg": 8192, "block_min_deg": 512, "wave_min_deg": 48, "g16_min_deg": 12, "g4_min_deg": 3,
     "hub_chunk": 4096, "pr_lds_verts": 4096, "pr_grid": 2048, "bfs_lds_words": 4096, "bfs_grid": 2048,
-    "bfs_lds_min_vblocks": 4096,
+    "bfs_lds_min_vblocks": 4096, "sssp_delta": 0, "sssp_lds_verts": 0, "sssp_grid": 2048,
 }
 
 SPACE = {
@@ -37,12 +37,16 @@ SPACE = {
     "bfs_lds_words": [0, 1024, 4096, 8192],
     "bfs_grid": [1024, 2048, 4096, 16384],
     "bfs_lds_min_vblocks": [1024, 4096, 16384, 1 << 40],
+    "sssp_delta": [0, 64, 128, 256, 512, 1024, 4096],
+    "sssp_lds_verts": [0, 2048, 4096, 8192],
+    "sssp_grid": [1024, 2048, 4096, 16384],
 }
 
 FAMILY = {k: "all" for k in ("hub_min_deg", "block_min_deg", "wave_min_deg", "g16_min_deg", "g4_min_deg",
                              "hub_chunk")}
 FAMILY.update({"pr_lds_verts": "pr", "pr_grid": "pr", "bfs_lds_words": "bfs", "bfs_grid": "bfs",
-               "bfs_lds_min_vblocks": "bfs"})
+               "bfs_lds_min_vblocks": "bfs", "sssp_delta": "sssp", "sssp_lds_verts": "sssp",
+               "sssp_grid": "sssp"})
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
@@ -81,7 +85,7 @@ def measure(part, cfg, roots, sssp_roots, pr_iters, family: str, bufs, repeats: 
         ms = 0.0
         if family in ("all", "bfs"):
             ms += _timed(lambda: bfs(part, roots, lev))
-        if family == "all" and sssp_roots is not None and len(sssp_roots):
+        if family in ("all", "sssp") and sssp_roots is not None and len(sssp_roots):
             ms += _timed(lambda: sssp(part, sssp_roots, dist))
         if family in ("all", "pr"):
             ms += _timed(lambda: pagerank(part, 0.85, pr_iters, "uniform", rank))
@@ -104,7 +108,8 @@ def tune(part, roots: Sequence[int], sssp_roots: Optional[Sequence[int]] = None,
         cfg.update(start)
     trials: List[dict] = []
     t0 = time.perf_counter()
-    base = {f: measure(part, cfg, roots, sssp_roots, pr_iters, f, bufs) for f in ("all", "bfs", "pr")}
+    fams = ("all", "bfs", "pr", "sssp")
+    base = {f: measure(part, cfg, roots, sssp_roots, pr_iters, f, bufs) for f in fams}
     initial = dict(base)
     for r in range(rounds):
         for key, values in SPACE.items():
@@ -123,8 +128,8 @@ def tune(part, roots: Sequence[int], sssp_roots: Optional[Sequence[int]] = None,
                     base[fam] = ms
                     # a shared key changes the per-family baselines too
                     if fam == "all":
-                        base["bfs"] = measure(part, cfg, roots, sssp_roots, pr_iters, "bfs", bufs)
-                        base["pr"] = measure(part, cfg, roots, sssp_roots, pr_iters, "pr", bufs)
+                        for f in fams[1:]:
+                            base[f] = measure(part, cfg, roots, sssp_roots, pr_iters, f, bufs)
     partition_retune(part, cfg)
     return {"config": cfg, "initial_ms": initial, "final_ms": base, "trials": len(trials),
             "seconds": round(time.perf_counter() - t0, 1), "log": trials}

@@ -126,6 +126,7 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   TG_TRY(dalloc(arena, &scalars, 16));
   TG_TRY(dalloc(arena, &counters, 64));
   TG_TRY(dalloc(arena, &work, 8));
+  TG_TRY(dalloc(arena, &rest, 2));
   TG_TRY(dalloc(arena, &bcount, nwords / 1024 + 1));
   TG_TRY(dalloc(arena, &plan, 1));
   TG_HIP(hipMemset(bits_a, 0, nwords * sizeof(uint32_t)));
@@ -155,6 +156,9 @@ Tuning default_tuning() {
   t.bfs_lds_words = 4096;
   t.bfs_grid = 2048;
   t.bfs_lds_min_vblocks = 4096;
+  t.sssp_delta = 0;
+  t.sssp_lds_verts = 0;
+  t.sssp_grid = 2048;
   return t;
 }
 
@@ -186,6 +190,12 @@ int parse_tuning(const char *json, Tuning *t) {
   if (json_int(json, "bfs_lds_words", &v)) t->bfs_lds_words = v;
   if (json_int(json, "bfs_grid", &v)) t->bfs_grid = v;
   if (json_int(json, "bfs_lds_min_vblocks", &v)) t->bfs_lds_min_vblocks = v;
+  if (json_int(json, "sssp_delta", &v)) t->sssp_delta = v;
+  if (json_int(json, "sssp_lds_verts", &v)) t->sssp_lds_verts = v;
+  if (json_int(json, "sssp_grid", &v)) t->sssp_grid = v;
+  if (t->sssp_delta < 0 || t->sssp_delta > INT32_MAX / 2) return set_error(TG_EINVAL, "tuning: sssp_delta outside [0, 2^30]");
+  if (t->sssp_lds_verts < 0 || t->sssp_lds_verts > 14336) return set_error(TG_EINVAL, "tuning: sssp_lds_verts outside [0, 14336]");
+  if (t->sssp_grid < 1 || t->sssp_grid > 16384) return set_error(TG_EINVAL, "tuning: sssp_grid outside [1, 16384]");
   if (t->pr_lds_verts < 0 || t->pr_lds_verts > 14336) return set_error(TG_EINVAL, "tuning: pr_lds_verts outside [0, 14336]");
   if (t->bfs_lds_words < 0 || t->bfs_lds_words > 14336) return set_error(TG_EINVAL, "tuning: bfs_lds_words outside [0, 14336]");
   if (t->pr_grid < 1 || t->pr_grid > 16384 || t->bfs_grid < 1 || t->bfs_grid > 16384)
@@ -367,6 +377,35 @@ void static_plan(const BinBounds &bb, const std::vector<int64_t> &deg_in_order, 
   all.vb[NBIN] = all.vb[tgk::BIN_ZERO] + (zc + 255) / 256;
 }
 
+}  // namespace
+
+namespace tg {
+
+// In-edges of a CSR over n vertices: rows sorted ascending (deterministic).
+void transpose_csr(int64_t n, const std::vector<int64_t> &off, const std::vector<int32_t> &col,
+                   std::vector<int64_t> &ioff, std::vector<int32_t> &icol) {
+  const int64_t m = off[n];
+  std::vector<int64_t> cnt((size_t)n + 1, 0);
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < m; ++e) __atomic_fetch_add(&cnt[(size_t)col[e] + 1], (int64_t)1, __ATOMIC_RELAXED);
+  ioff.assign((size_t)n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) ioff[i + 1] = ioff[i] + cnt[i + 1];
+  icol.resize((size_t)m);
+  std::vector<int64_t> cur(ioff.begin(), ioff.end() - 1);
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t u = 0; u < n; ++u)
+    for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+      const int64_t k = __atomic_fetch_add(&cur[col[e]], (int64_t)1, __ATOMIC_RELAXED);
+      icol[(size_t)k] = (int32_t)u;
+    }
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t v = 0; v < n; ++v) std::sort(icol.begin() + ioff[v], icol.begin() + ioff[v + 1]);
+}
+
+}  // namespace tg
+
+namespace {
+
 template <typename T>
 int upload(tg::DevArena &a, T **dst, const T *src, size_t count) {
   TG_TRY(dalloc(a, dst, count));
@@ -485,13 +524,9 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
     for (int64_t i = 0; i < n; ++i) gp.n_dangling += (deg_in_order[i] == 0);
     gp.n_isolated = gp.n_dangling;
   } else {
-    std::vector<int64_t> ioff((size_t)n + 1, 0);
-    for (int64_t e = 0; e < m; ++e) ioff[(size_t)col[e] + 1]++;
-    for (int64_t i = 0; i < n; ++i) ioff[i + 1] += ioff[i];
-    std::vector<int32_t> icol((size_t)m);
-    std::vector<int64_t> cur(ioff.begin(), ioff.end() - 1);
-    for (int64_t u = 0; u < n; ++u)  // sources in increasing order: rows come out sorted
-      for (int64_t e = off[u]; e < off[u + 1]; ++e) icol[(size_t)cur[col[e]]++] = (int32_t)u;
+    std::vector<int64_t> ioff;
+    std::vector<int32_t> icol;
+    transpose_csr(n, off, col, ioff, icol);
     TG_TRY(upload(A, &gp.in.off, ioff.data(), (size_t)n + 1));
     TG_TRY(upload(A, &gp.in.col, icol.data(), (size_t)m));
     gp.in.n = n;
@@ -624,11 +659,13 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
   snprintf(buf, sizeof(buf),
            "],\"tuning\":{\"hub_min_deg\":%lld,\"block_min_deg\":%lld,\"wave_min_deg\":%lld,"
            "\"g16_min_deg\":%lld,\"g4_min_deg\":%lld,\"hub_chunk\":%lld,\"pr_lds_verts\":%lld,"
-           "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld}",
+           "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld,"
+           "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld}",
            (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
            (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk,
            (long long)p->tune.pr_lds_verts, (long long)p->tune.pr_grid, (long long)p->tune.bfs_lds_words,
-           (long long)p->tune.bfs_grid, (long long)p->tune.bfs_lds_min_vblocks);
+           (long long)p->tune.bfs_grid, (long long)p->tune.bfs_lds_min_vblocks, (long long)p->tune.sssp_delta,
+           (long long)p->tune.sssp_lds_verts, (long long)p->tune.sssp_grid);
   s += buf;
   s += hybrid_info_json(p);
   s += "}";

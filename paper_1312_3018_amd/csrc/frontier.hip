@@ -16,14 +16,49 @@ namespace {
 constexpr int WPT = 4;                     // bitmap words per thread
 constexpr int WPB = WPT * BLOCK;           // words per block (1024)
 
+// Distance filter (near set): keep only the set bits whose vertex has
+// dist < thresh; count and find the least distance of the rest.
+__device__ __forceinline__ uint32_t near_bits(uint32_t w, int64_t word, const int32_t *__restrict__ dist,
+                                              int32_t thresh, uint32_t &rest, int32_t &rest_min) {
+  uint32_t keep = 0;
+  while (w) {
+    const int bit = __ffs(w) - 1;
+    w &= w - 1;
+    const int32_t d = dist[word * 32 + bit];
+    if (d < thresh) keep |= 1u << bit;
+    else {
+      ++rest;
+      rest_min = d < rest_min ? d : rest_min;
+    }
+  }
+  return keep;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_compact_count(const uint32_t *__restrict__ bits,
                                                          const uint32_t *__restrict__ prev,
-                                                         uint32_t *__restrict__ bcount) {
+                                                         uint32_t *__restrict__ bcount,
+                                                         const int32_t *__restrict__ dist, int32_t thresh,
+                                                         unsigned long long *rest) {
   const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // uint4 index
   uint4 v = reinterpret_cast<const uint4 *>(bits)[q];
   if (prev) {
     uint4 p = reinterpret_cast<const uint4 *>(prev)[q];
     v.x &= ~p.x; v.y &= ~p.y; v.z &= ~p.z; v.w &= ~p.w;
+  }
+  if (dist) {
+    uint32_t r = 0;
+    int32_t rmin = TG_INF;
+    v.x = near_bits(v.x, q * 4 + 0, dist, thresh, r, rmin);
+    v.y = near_bits(v.y, q * 4 + 1, dist, thresh, r, rmin);
+    v.z = near_bits(v.z, q * 4 + 2, dist, thresh, r, rmin);
+    v.w = near_bits(v.w, q * 4 + 3, dist, thresh, r, rmin);
+    r = block_sum(r);
+    for (int o = 32; o > 0; o >>= 1) {
+      const int32_t y = __shfl_xor(rmin, o, 64);
+      rmin = y < rmin ? y : rmin;
+    }
+    if ((threadIdx.x & 63) == 0 && rmin < TG_INF) atomicMin(reinterpret_cast<int32_t *>(rest + 1), rmin);
+    if (threadIdx.x == 0 && r) atomicAdd(rest, (unsigned long long)r);
   }
   uint32_t c = __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
   c = block_sum(c);
@@ -34,7 +69,8 @@ __global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ 
                                                          int mode, const uint32_t *__restrict__ bcount,
                                                          int32_t *__restrict__ queue, int32_t *__restrict__ level,
                                                          int32_t level_value, BinBounds bb, int64_t n,
-                                                         Plan *__restrict__ plan) {
+                                                         Plan *__restrict__ plan, const int32_t *__restrict__ dist,
+                                                         int32_t thresh) {
   // this block's offset: sum of the counts of all earlier blocks
   uint32_t part = 0;
   for (uint32_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) part += bcount[i];
@@ -48,6 +84,12 @@ __global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ 
     uint4 p = reinterpret_cast<uint4 *>(prev)[q];
     nw[0] &= ~p.x; nw[1] &= ~p.y; nw[2] &= ~p.z; nw[3] &= ~p.w;
     reinterpret_cast<uint4 *>(prev)[q] = v;  // prev := visited
+  } else if (mode == 3) {
+    // near set only: take the bits with dist < thresh, leave the rest active
+    uint32_t r = 0;
+    int32_t rmin = TG_INF;
+    for (int k = 0; k < 4; ++k) nw[k] = near_bits(nw[k], q * 4 + k, dist, thresh, r, rmin);
+    reinterpret_cast<uint4 *>(bits)[q] = make_uint4(v.x & ~nw[0], v.y & ~nw[1], v.z & ~nw[2], v.w & ~nw[3]);
   } else {
     if (mode == 2) reinterpret_cast<uint4 *>(prev)[q] = v;  // prev := the set taken
     reinterpret_cast<uint4 *>(bits)[q] = make_uint4(0, 0, 0, 0);
@@ -142,9 +184,23 @@ int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, 
                      int32_t *queue, int32_t *level, int32_t level_value, hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
   hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, bits,
-                     mode == 0 ? prev : nullptr, ws.bcount);
+                     mode == 0 ? prev : nullptr, ws.bcount, nullptr, 0, nullptr);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, bits, prev, mode,
-                     ws.bcount, queue, level, level_value, g.out_bins, g.n, ws.plan);
+                     ws.bcount, queue, level, level_value, g.out_bins, g.n, ws.plan, nullptr, 0);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int frontier_compact_near(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
+                          int32_t thresh, hipStream_t s) {
+  const int blocks = (int)(ws.nwords / WPB);
+  // rest[0] = active vertices left behind, rest[1] (low word) = their least distance
+  const unsigned long long init[2] = {0ull, (unsigned long long)(uint32_t)TG_INF};
+  TG_HIP(hipMemcpyAsync(ws.rest, init, sizeof(init), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, bits, nullptr, ws.bcount, dist, thresh,
+                     ws.rest);
+  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, bits, nullptr, 3, ws.bcount, queue, nullptr,
+                     0, g.out_bins, g.n, ws.plan, dist, thresh);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }

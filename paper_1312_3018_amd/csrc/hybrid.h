@@ -21,6 +21,8 @@ struct BoundaryEdges {
 
 struct HybridState;
 
+void transpose_csr(int64_t n, const std::vector<int64_t> &off, const std::vector<int32_t> &col,
+                   std::vector<int64_t> &ioff, std::vector<int32_t> &icol);
 int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryEdges *boundary);
 int build_hybrid(tg_partition *p, uint64_t seed);
 void hybrid_free(tg_partition *p);

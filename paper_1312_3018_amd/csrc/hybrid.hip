@@ -229,15 +229,7 @@ int build_hybrid(tg_partition *p, uint64_t seed) {
     C.bdeg[i] = (int32_t)(cb_off[i + 1] - cb_off[i]);
   }
   // host in-edges
-  C.ioff.assign((size_t)C.n + 1, 0);
-  for (int64_t e = 0; e < C.m; ++e) C.ioff[(size_t)C.col[e] + 1]++;
-  for (int64_t i = 0; i < C.n; ++i) C.ioff[i + 1] += C.ioff[i];
-  C.icol.resize((size_t)C.m);
-  {
-    std::vector<int64_t> cur(C.ioff.begin(), C.ioff.end() - 1);
-    for (int64_t u = 0; u < C.n; ++u)
-      for (int64_t e = C.off[u]; e < C.off[u + 1]; ++e) C.icol[(size_t)cur[C.col[e]]++] = (int32_t)u;
-  }
+  transpose_csr(C.n, C.off, C.col, C.ioff, C.icol);
   for (int64_t i = 0; i < C.n; ++i) C.n_dangling += (C.off[i + 1] == C.off[i] && C.bdeg[i] == 0);
 
   // channels: GPU -> host uses the GPU's boundary edges, host -> GPU the host's

@@ -11,6 +11,8 @@
 // distance >= INT32_MAX is never stored; the vertex is marked in an overflow
 // bitmap instead, and the call fails with TG_ERANGE if such a vertex ends up
 // without a finite distance (its true distance does not fit in int32).
+#include <algorithm>
+
 #include "tg_internal.h"
 
 using namespace tgk;
@@ -21,8 +23,11 @@ __global__ void k_set_i32(int32_t *p, int64_t i, int32_t v) {
   if (threadIdx.x == 0) p[i] = v;
 }
 
-__device__ __forceinline__ void relax(int32_t *dist, uint32_t *active, uint32_t *ovf, uint32_t *flags,
-                                      int32_t dv, int32_t nb, int32_t wt) {
+// Relax one edge.  `cur` is the neighbour's distance as this block knows it:
+// an LDS snapshot for the hottest vertices (never below the true value, since
+// distances only decrease) or the global value.
+__device__ __forceinline__ void relax(int32_t *dist, int32_t *lds_d, int32_t hot, uint32_t *active, uint32_t *ovf,
+                                      uint32_t *flags, int32_t dv, int32_t nb, int32_t wt, int32_t cur) {
   const int64_t nd = (int64_t)dv + (int64_t)wt;
   const uint32_t bit = 1u << (nb & 31);
   if (nd >= (int64_t)TG_INF) {
@@ -33,10 +38,15 @@ __device__ __forceinline__ void relax(int32_t *dist, uint32_t *active, uint32_t 
     }
     return;
   }
-  if (nd < (int64_t)dist[nb]) {
+  if (nd < (int64_t)cur) {
     const int32_t old = atomicMin(dist + nb, (int32_t)nd);
+    if (nb < hot) atomicMin(lds_d + nb, (int32_t)nd);
     if (nd < (int64_t)old) atomicOr(active + (nb >> 5), bit);
   }
+}
+
+__device__ __forceinline__ const int32_t *dist_ptr(const int32_t *dist, const int32_t *lds_d, int32_t hot, int32_t nb) {
+  return nb < hot ? lds_d + nb : dist + nb;  // generic pointer: one load for LDS or HBM
 }
 
 __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ Pp,
@@ -46,8 +56,10 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
                                                       const int32_t *__restrict__ col,
                                                       const int32_t *__restrict__ wgt, int32_t *dist,
                                                       uint32_t *active, uint32_t *ovf, uint32_t *flags,
-                                                      int64_t hub_chunk, unsigned long long *work) {
-  const Plan &P = load_plan(Pp);
+                                                      int64_t hub_chunk, unsigned long long *work, int32_t hot) {
+  extern __shared__ int32_t lds_d[];
+  for (int32_t i = threadIdx.x; i < hot; i += BLOCK) lds_d[i] = dist[i];
+  const Plan &P = load_plan(Pp);  // (its barrier also publishes lds_d)
   const int64_t total = P.vb[NBIN];
   unsigned long long n_edges = 0, n_verts = 0;
   for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
@@ -63,10 +75,15 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
     for (; e + st < a.e_end; e += 2 * st) {
       const int32_t n0 = stream_load(col + e), n1 = stream_load(col + e + st);
       const int32_t w0 = stream_load(wgt + e), w1 = stream_load(wgt + e + st);
-      relax(dist, active, ovf, flags, dv, n0, w0);
-      relax(dist, active, ovf, flags, dv, n1, w1);
+      const int32_t c0 = *dist_ptr(dist, lds_d, hot, n0);
+      const int32_t c1 = *dist_ptr(dist, lds_d, hot, n1);
+      relax(dist, lds_d, hot, active, ovf, flags, dv, n0, w0, c0);
+      relax(dist, lds_d, hot, active, ovf, flags, dv, n1, w1, c1);
     }
-    if (e < a.e_end) relax(dist, active, ovf, flags, dv, stream_load(col + e), stream_load(wgt + e));
+    if (e < a.e_end) {
+      const int32_t n0 = stream_load(col + e);
+      relax(dist, lds_d, hot, active, ovf, flags, dv, n0, stream_load(wgt + e), *dist_ptr(dist, lds_d, hot, n0));
+    }
   }
   n_edges = block_sum(n_edges);
   n_verts = block_sum(n_verts);
@@ -92,10 +109,12 @@ namespace tg {
 int sssp_relax_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks, const Tuning &t,
                       hipStream_t s) {
   if (vblocks <= 0) return TG_OK;
+  const int32_t hot = (int32_t)std::min<int64_t>(t.sssp_lds_verts, g.n);
+  const int grid = hot > 0 ? (int)std::min<int64_t>(launch_grid(vblocks), t.sssp_grid) : launch_grid(vblocks);
   const int tk = ktimer_start(s);
-  hipLaunchKernelGGL(k_sssp_relax, dim3(launch_grid(vblocks)), dim3(BLOCK), 0, s, ws.plan, queue, ws.hubpref,
-                     g.out.off, g.out.col, g.out.w, ws.state, ws.bits_a, ws.bits_c, ws.counters, t.hub_chunk,
-                     ws.work);
+  hipLaunchKernelGGL(k_sssp_relax, dim3(grid), dim3(BLOCK), (size_t)hot * sizeof(int32_t), s, ws.plan, queue,
+                     ws.hubpref, g.out.off, g.out.col, g.out.w, ws.state, ws.bits_a, ws.bits_c, ws.counters,
+                     t.hub_chunk, ws.work, hot);
   ktimer_stop(tk, s, "sssp_relax");
   TG_HIP(hipGetLastError());
   return TG_OK;
@@ -130,12 +149,26 @@ int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) 
   TG_HIP(hipMemsetAsync(ws.counters, 0, 4 * sizeof(uint32_t), s));
   TG_TRY(set_bit(active, root, s));
   int64_t rounds = 0;
+  const int64_t delta = p->tune.sssp_delta;
+  int64_t thresh = delta;  // near/far: only active vertices below thresh relax
   for (;; ++rounds) {
-    // a frontier Bellman-Ford settles within |V| - 1 rounds
-    if (rounds > g.n) return set_error(TG_EDEVICE, "sssp: no convergence after %lld rounds", (long long)rounds);
-    TG_TRY(frontier_compact(g, ws, 1, active, nullptr, ws.queue, nullptr, 0, s));
-    TG_TRY(frontier_plan(g, ws, ws.queue, p->tune, s, true));
-    if (ws.h_plan->count == 0) break;
+    // a frontier Bellman-Ford settles within |V| - 1 rounds (per threshold step)
+    if (rounds > 2 * g.n + 2) return set_error(TG_EDEVICE, "sssp: no convergence after %lld rounds", (long long)rounds);
+    if (delta <= 0) {
+      TG_TRY(frontier_compact(g, ws, 1, active, nullptr, ws.queue, nullptr, 0, s));
+      TG_TRY(frontier_plan(g, ws, ws.queue, p->tune, s, true));
+      if (ws.h_plan->count == 0) break;
+    } else {
+      TG_TRY(frontier_compact_near(g, ws, active, ws.queue, dist, (int32_t)std::min<int64_t>(thresh, TG_INF), s));
+      TG_HIP(hipMemcpyAsync(ws.h_work + 4, ws.rest, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+      TG_TRY(frontier_plan(g, ws, ws.queue, p->tune, s, true));
+      if (ws.h_plan->count == 0) {
+        if (ws.h_work[4] == 0) break;  // nothing left beyond the threshold either
+        // jump to the least distance still waiting
+        thresh = (int64_t)(int32_t)(ws.h_work[5] & 0xFFFFFFFFull) + delta;
+        continue;
+      }
+    }
     TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s));
   }
   TG_TRY(sssp_overflow_check(g, ws, s));

@@ -61,6 +61,9 @@ struct Tuning {
   int64_t bfs_lds_words;         // BFS: visited-bitmap words staged in LDS per block
   int64_t bfs_grid;              // BFS: blocks per launch when staging
   int64_t bfs_lds_min_vblocks;   // BFS: stage only for frontiers at least this large
+  int64_t sssp_delta;            // SSSP: near/far distance step (0 = plain frontier Bellman-Ford)
+  int64_t sssp_lds_verts;        // SSSP: distances of vertices [0, n) snapshotted in LDS per block
+  int64_t sssp_grid;             // SSSP: blocks per launch when snapshotting
 };
 Tuning default_tuning();
 int parse_tuning(const char *json, Tuning *t);
@@ -158,6 +161,7 @@ struct Workspace {
   double *scalars = nullptr;     // small fp64 cells (dangling sums, ...)
   uint32_t *counters = nullptr;  // small counters and flags (zeroed)
   unsigned long long *work = nullptr;  // [0] edges scanned, [1] vertices expanded
+  unsigned long long *rest = nullptr;  // near/far compaction: [0] left active, [1] their least distance
   unsigned long long *h_work = nullptr;
   uint32_t *hub_counters = nullptr;
   uint32_t *bcount = nullptr;    // per-block counts for compaction
@@ -209,6 +213,10 @@ int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, 
 // hub chunk prefix, then copy the plan to ws.h_plan and wait for it.
 int frontier_plan(const GpuPart &g, Workspace &ws, const int32_t *queue, const Tuning &t,
                   hipStream_t s, bool sync);
+// Active-set compaction restricted to vertices with dist < thresh (the rest
+// stay active); ws.rest gets the count and least distance of the rest.
+int frontier_compact_near(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
+                          int32_t thresh, hipStream_t s);
 // As frontier_plan, with hub chunks sized by the degrees in `off`; with
 // include_zero, frontier vertices of out-degree 0 get virtual blocks too
 // (a pull over in-edges must visit them).

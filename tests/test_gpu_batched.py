@@ -36,14 +36,16 @@ def test_batched_equals_oracle(gpu, sym, tuning):
 
 def test_batched_overflow_falls_back_exactly(gpu):
     g = graphgen.from_edges(4, [0, 1, 0], [1, 2, 3], symmetrize=False)
-    w = np.array([2**31 - 10, 2**31 - 10, 5], dtype=np.int32)
+    # CSR edge order: (0,1), (0,3), (1,2)
+    assert g.cols.tolist() == [1, 3, 2]
+    w = np.array([2**31 - 10, 5, 2**31 - 10], dtype=np.int32)
     G = gpu.graph_load_csr(g.n, g.offsets, g.cols, w)
     P = gpu.partition_by_degree(G)
     with pytest.raises(gpu.TGError) as ei:
         gpu.sssp_batched(P, [0])
     assert ei.value.code == gpu.TG_ERANGE
-    assert gpu.sssp_batched(P, [3, 2]).cpu().numpy().tolist() == [[2**31 - 1] * 3 + [0],
-                                                                  [2**31 - 1, 2**31 - 1, 0, 2**31 - 1]]
+    assert gpu.sssp_batched(P, [3, 2, 1]).cpu().numpy().tolist() == [
+        [2**31 - 1] * 3 + [0], [2**31 - 1, 2**31 - 1, 0, 2**31 - 1], [2**31 - 1, 0, 2**31 - 10, 2**31 - 1]]
 
 
 @pytest.mark.parametrize("sym", [True, False])

@@ -18,7 +18,8 @@ INF = oracle.INF
 # multi-chunk hubs
 SMALL_BINS = {"hub_min_deg": 300, "block_min_deg": 100, "wave_min_deg": 24, "g16_min_deg": 6,
               "g4_min_deg": 2, "hub_chunk": 256, "pr_lds_verts": 100, "pr_grid": 7,
-              "bfs_lds_words": 16, "bfs_grid": 5, "bfs_lds_min_vblocks": 0}
+              "bfs_lds_words": 16, "bfs_grid": 5, "bfs_lds_min_vblocks": 0,
+              "sssp_delta": 64, "sssp_lds_verts": 100, "sssp_grid": 6}
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -102,6 +103,16 @@ def test_rmat12_bc(gpu, tuning):
     got = gpu.bc(P, srcs).cpu().numpy()
     ref = oracle.bc(g.offsets, g.cols, srcs)
     assert bc_close(got, ref)
+
+
+@pytest.mark.parametrize("delta", [1, 300, 1 << 20])
+def test_sssp_near_far_thresholds(gpu, rmat14, delta):
+    g, w = rmat14
+    P = load(gpu, g, w, {"sssp_delta": delta, "sssp_lds_verts": 4096})
+    roots = graphgen.sample_roots(g, 3, seed=15)
+    dist = gpu.sssp(P, roots).cpu().numpy()
+    for i, r in enumerate(roots):
+        assert np.array_equal(dist[i], oracle.sssp(g.offsets, g.cols, w, r))
 
 
 def test_bfs_parents_valid(gpu, rmat14):
