@@ -43,7 +43,7 @@ def kernel_sources_digest(files):
 # Sources each timed kernel is built from (a traffic figure is only reused
 # while these are unchanged).
 KERNEL_FILES = {
-    "pr_gather": ["pagerank.hip", "kcommon.h"],
+    "pr_gather": ["pagerank.hip", "pr_sliced.hip", "kcommon.h"],
     "bfs_expand": ["bfs.hip", "kcommon.h"],
     "sssp_relax": ["sssp.hip", "kcommon.h"],
 }
@@ -510,6 +510,10 @@ def main():
     kernels = {}
     if "pr_gather_ms" in sp:
         kernels["pr_gather"] = dict(ms=sp["pr_gather_ms"], n=sp["pr_gather_n"], bytes=pr_bytes_iter * sp["pr_gather_n"])
+    elif "pr_slice_gather_ms" in sp:
+        # the XCD-split gather: one iteration = class gathers + their combine
+        kernels["pr_gather"] = dict(ms=sp["pr_slice_gather_ms"] + sp["pr_combine_ms"], n=sp["pr_slice_gather_n"],
+                                    bytes=pr_bytes_iter * sp["pr_slice_gather_n"])
     if "bfs_expand_ms" in sb:
         exp_bytes = 4.125 * sb["edges_scanned"] + 12.0 * sb["vertices_expanded"]
         kernels["bfs_expand"] = dict(ms=sb["bfs_expand_ms"], n=sb["bfs_expand_n"], bytes=exp_bytes)

@@ -22,7 +22,7 @@ from . import bfs, pagerank, partition_info, partition_retune, sssp
 DEFAULTS = {
     "hub_min_deg": 8192, "block_min_deg": 512, "wave_min_deg": 48, "g16_min_deg": 12, "g4_min_deg": 3,
     "hub_chunk": 4096, "pr_lds_verts": 4096, "pr_grid": 2048, "bfs_lds_words": 4096, "bfs_grid": 2048,
-    "bfs_lds_min_vblocks": 4096, "sssp_delta": 0, "sssp_lds_verts": 0, "sssp_grid": 2048,
+    "bfs_lds_min_vblocks": 4096, "sssp_delta": 0, "sssp_lds_verts": 0, "sssp_grid": 2048, "pr_xcd": 1,
 }
 
 SPACE = {
@@ -32,6 +32,7 @@ SPACE = {
     "g16_min_deg": [6, 12, 24],
     "g4_min_deg": [2, 3, 5],
     "hub_chunk": [1024, 2048, 4096, 8192],
+    "pr_xcd": [0, 1],
     "pr_lds_verts": [0, 2048, 4096, 8192, 14336],
     "pr_grid": [1024, 2048, 4096, 8192, 16384],
     "bfs_lds_words": [0, 1024, 4096, 8192],
@@ -44,7 +45,7 @@ SPACE = {
 
 FAMILY = {k: "all" for k in ("hub_min_deg", "block_min_deg", "wave_min_deg", "g16_min_deg", "g4_min_deg",
                              "hub_chunk")}
-FAMILY.update({"pr_lds_verts": "pr", "pr_grid": "pr", "bfs_lds_words": "bfs", "bfs_grid": "bfs",
+FAMILY.update({"pr_xcd": "pr", "pr_lds_verts": "pr", "pr_grid": "pr", "bfs_lds_words": "bfs", "bfs_grid": "bfs",
                "bfs_lds_min_vblocks": "bfs", "sssp_delta": "sssp", "sssp_lds_verts": "sssp",
                "sssp_grid": "sssp"})
 

@@ -238,8 +238,12 @@ int gpu_pagerank(tg_partition *p, double damping, int32_t iters, int mode, float
   // r_0 = 1/N, so c_0(u) = 1/(N outdeg(u)) and D_0 = (#dangling)/N
   TG_TRY(gpu_pagerank_setup(p, damping, mode, s, nullptr, (double)g.n_dangling / N));
   if (iters == 0) return pr_write_initial(g, rank_out, N, s);
-  for (int32_t k = 0; k < iters; ++k)
-    TG_TRY(gpu_pagerank_step(p, damping, mode, k, k == iters - 1, rank_out, s, nullptr, nullptr));
+  for (int32_t k = 0; k < iters; ++k) {
+    if (p->tune.pr_xcd)
+      TG_TRY(gpu_pagerank_sliced_step(p, damping, mode, k, k == iters - 1, rank_out, s));
+    else
+      TG_TRY(gpu_pagerank_step(p, damping, mode, k, k == iters - 1, rank_out, s, nullptr, nullptr));
+  }
   return TG_OK;
 }
 

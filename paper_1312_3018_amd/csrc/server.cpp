@@ -80,7 +80,7 @@ struct tg_server {
   int device = 0;
   bool stop = false;
   std::thread worker;
-  // statistics
+  // statistics (supersteps: completion passes of the worker)
   int64_t completed = 0, supersteps = 0, max_concurrent = 0;
 
   void run();
@@ -110,11 +110,16 @@ void tg_server::run() {
   TG_QUIET(hipSetDevice(device));
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    // admit waiting queries into free slots, within the memory cap
-    bool any = false;
+    // 1. every idle lane: admit waiting queries into free slots (within the
+    //    memory cap), then start its next superstep if it has running slots
+    bool in_flight = false;
     for (auto &lp : lanes) {
       Lane &L = *lp;
       if (!L.p) continue;
+      if (L.launched) {
+        in_flight = true;
+        continue;
+      }
       while (!L.waiting.empty()) {
         Query *q = L.waiting.front();
         if (!L.eng) {
@@ -144,28 +149,33 @@ void tg_server::run() {
           cv_done.notify_all();
         }
       }
-      if (L.eng && L.eng->busy) any = true;
+      if (L.eng && L.eng->busy) {
+        if (L.eng->launch_step() == TG_OK) {
+          L.launched = true;
+          in_flight = true;
+        }
+      }
     }
     int64_t running = 0;
     for (auto &lp : lanes)
       if (lp->eng) running += __builtin_popcountll(lp->eng->busy);
     if (running > max_concurrent) max_concurrent = running;
-    if (!any) {
+    if (!in_flight) {
       if (stop) break;
       cv_work.wait(lk);
       continue;
     }
-    // one superstep on every busy engine: enqueue all, then complete all
+    // 2. complete whichever lanes' supersteps are done; lanes advance
+    //    independently, so a slow graph does not hold back the others
     lk.unlock();
-    for (auto &lp : lanes) {
-      Lane &L = *lp;
-      L.launched = false;
-      if (L.eng && L.eng->busy && L.eng->launch_step() == TG_OK) L.launched = true;
-    }
     std::vector<std::pair<Lane *, unsigned long long>> fin;
+    bool progressed = false;
     for (auto &lp : lanes) {
       Lane &L = *lp;
-      if (!L.launched) continue;
+      if (!L.launched || hipStreamQuery(L.stream) != hipSuccess) continue;
+      (void)hipGetLastError();  // hipStreamQuery reports "not ready" through the error state
+      L.launched = false;
+      progressed = true;
       unsigned long long f = 0;
       if (L.eng->finish_step(&f) == TG_OK && f) {
         if (L.kind == kSlotSssp)
@@ -174,14 +184,15 @@ void tg_server::run() {
         bool ovf = false;
         const int rc = L.eng->retire(f, &ovf);
         fin.emplace_back(&L, f);
-        if (rc != TG_OK || ovf) {
+        if (rc != TG_OK || ovf)
           for (int k = 0; k < kSlots; ++k)
             if ((f >> k) & 1ull) L.slot_q[k]->status = rc != TG_OK ? rc : TG_ERANGE;
-        }
       }
     }
+    (void)hipGetLastError();
+    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
     lk.lock();
-    ++supersteps;
+    if (progressed) ++supersteps;
     for (auto &pr : fin) {
       Lane &L = *pr.first;
       for (int k = 0; k < kSlots; ++k)

@@ -64,6 +64,7 @@ struct Tuning {
   int64_t sssp_delta;            // SSSP: near/far distance step (0 = plain frontier Bellman-Ford)
   int64_t sssp_lds_verts;        // SSSP: distances of vertices [0, n) snapshotted in LDS per block
   int64_t sssp_grid;             // SSSP: blocks per launch when snapshotting
+  int64_t pr_xcd;                // PageRank: 1 = gather split by source class per XCD
 };
 Tuning default_tuning();
 int parse_tuning(const char *json, Tuning *t);
@@ -82,6 +83,7 @@ struct DevArena {
   size_t bytes = 0;
   int alloc(void **p, size_t n);  // zero-size -> 256 bytes
   void release();
+  void release_one(void *p);       // free one allocation early
   ~DevArena() { release(); }
 };
 
@@ -121,6 +123,8 @@ struct StaticPlan {
   int32_t nh = 0;
 };
 
+struct PrSlices;
+
 // The GPU partition: local ids 0..n-1 in decreasing out-degree order.
 struct GpuPart {
   int64_t n = 0, m = 0;          // local vertices, local edges
@@ -141,6 +145,7 @@ struct GpuPart {
   std::vector<int64_t> h_deg;      // out-degree of each local id (non-increasing)
   std::vector<int64_t> h_in_deg;   // in-degree along pr_order (non-increasing)
   DevArena plan_arena;             // tuning-dependent plans
+  PrSlices *slices = nullptr;      // PageRank in-edges split by source class (lazy)
 };
 
 // Per-partition scratch, grown on demand.
@@ -254,6 +259,10 @@ int gpu_pagerank_setup(tg_partition *p, double damping, int mode, hipStream_t s,
                        double d0);
 int gpu_pagerank_step(tg_partition *p, double damping, int mode, int32_t k, bool last, float *rank_out,
                       hipStream_t s, const double *ghost, const int32_t *extra_deg);
+// pr_sliced.hip: the same step through the per-XCD source classes
+int gpu_pagerank_sliced_step(tg_partition *p, double damping, int mode, int32_t k, bool last, float *rank_out,
+                             hipStream_t s);
+void pr_slices_free(GpuPart &g);
 int pr_write_initial(const GpuPart &g, float *rank_out, double N, hipStream_t s);
 
 // algorithms (GPU partition only)

@@ -240,7 +240,8 @@ def test_retune_keeps_results(gpu, rmat14):
     root = graphgen.max_degree_vertex(g)
     ref_lev = oracle.bfs(g.offsets, g.cols, root)
     ref_pr = oracle.pagerank(g.offsets, g.cols, 0.85, 10)
-    for tuning in (SMALL_BINS, {"pr_lds_verts": 0, "bfs_lds_words": 0, "bfs_lds_min_vblocks": 0}, None):
+    for tuning in (SMALL_BINS, {"pr_lds_verts": 0, "bfs_lds_words": 0, "bfs_lds_min_vblocks": 0},
+                   dict(SMALL_BINS, pr_xcd=0), {"pr_xcd": 0}, None):
         gpu.partition_retune(P, tuning)
         assert np.array_equal(gpu.bfs(P, [root]).cpu().numpy()[0], ref_lev)
         assert pr_rel_l1(gpu.pagerank(P, 0.85, 10).cpu().numpy(), ref_pr) <= 1e-5
