@@ -169,6 +169,7 @@ Tuning default_tuning() {
   t.sssp_lds_verts = 0;
   t.sssp_grid = 2048;
   t.pr_xcd = 1;
+  t.pr_rows = 2048;
   return t;
 }
 
@@ -204,7 +205,10 @@ int parse_tuning(const char *json, Tuning *t) {
   if (json_int(json, "sssp_lds_verts", &v)) t->sssp_lds_verts = v;
   if (json_int(json, "sssp_grid", &v)) t->sssp_grid = v;
   if (json_int(json, "pr_xcd", &v)) t->pr_xcd = v;
+  if (json_int(json, "pr_rows", &v)) t->pr_rows = v;
   if (t->pr_xcd != 0 && t->pr_xcd != 1) return set_error(TG_EINVAL, "tuning: pr_xcd must be 0 or 1");
+  if (t->pr_rows != 0 && (t->pr_rows < 256 || t->pr_rows > 4096 || t->pr_rows % 256 != 0))
+    return set_error(TG_EINVAL, "tuning: pr_rows must be 0 or a multiple of 256 in [256, 4096]");
   if (t->sssp_delta < 0 || t->sssp_delta > INT32_MAX / 2) return set_error(TG_EINVAL, "tuning: sssp_delta outside [0, 2^30]");
   if (t->sssp_lds_verts < 0 || t->sssp_lds_verts > 14336) return set_error(TG_EINVAL, "tuning: sssp_lds_verts outside [0, 14336]");
   if (t->sssp_grid < 1 || t->sssp_grid > 16384) return set_error(TG_EINVAL, "tuning: sssp_grid outside [1, 16384]");
@@ -628,6 +632,7 @@ extern "C" void partition_free(tg_partition *p) {
   delete p->slots[1];
   bcb_free(p);
   pr_slices_free(p->gpu);
+  pr_rows_free(p->gpu);
   delete p;
 }
 
@@ -673,12 +678,13 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            "],\"tuning\":{\"hub_min_deg\":%lld,\"block_min_deg\":%lld,\"wave_min_deg\":%lld,"
            "\"g16_min_deg\":%lld,\"g4_min_deg\":%lld,\"hub_chunk\":%lld,\"pr_lds_verts\":%lld,"
            "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld,"
-           "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld,\"pr_xcd\":%lld}",
+           "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld,\"pr_xcd\":%lld,\"pr_rows\":%lld}",
            (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
            (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk,
            (long long)p->tune.pr_lds_verts, (long long)p->tune.pr_grid, (long long)p->tune.bfs_lds_words,
            (long long)p->tune.bfs_grid, (long long)p->tune.bfs_lds_min_vblocks, (long long)p->tune.sssp_delta,
-           (long long)p->tune.sssp_lds_verts, (long long)p->tune.sssp_grid, (long long)p->tune.pr_xcd);
+           (long long)p->tune.sssp_lds_verts, (long long)p->tune.sssp_grid, (long long)p->tune.pr_xcd,
+           (long long)p->tune.pr_rows);
   s += buf;
   s += hybrid_info_json(p);
   s += "}";

@@ -187,6 +187,7 @@ int gpu_pagerank_setup(tg_partition *p, double damping, int mode, hipStream_t s,
 // sum scalars[k&1] -> scalars[(k+1)&1]); `last` writes ranks instead.
 int gpu_pagerank_step(tg_partition *p, double damping, int mode, int32_t k, bool last, float *rank_out,
                       hipStream_t s, const double *ghost, const int32_t *extra_deg) {
+  if (p->tune.pr_rows) return gpu_pagerank_rows_step(p, damping, mode, k, last, rank_out, s, ghost, extra_deg);
   GpuPart &g = p->gpu;
   Workspace &ws = p->ws;
   const double N = (double)g.n_global;

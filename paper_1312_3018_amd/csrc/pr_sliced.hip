@@ -200,14 +200,14 @@ struct CombineParams {
 };
 
 // r(v) = (1-d)/N + d (sum of the 8 partials + D/N); contribution, rank and
-// the dangling mass as in the plain gather.
+// the dangling mass as in the plain gather.  Each block leaves its dangling
+// partial in partials[blockIdx]; a one-block launch adds them.
 __global__ __launch_bounds__(BLOCK) void k_pr_combine(CombineParams prm, const float *__restrict__ ps,
                                                       const int64_t *__restrict__ out_off,
-                                                      const double *__restrict__ dsum_in, double *__restrict__ dsum_out,
-                                                      double *__restrict__ partials, uint32_t *done_counter,
-                                                      float *__restrict__ c_out, const int32_t *__restrict__ g_of_l,
+                                                      const double *__restrict__ dsum_in,
+                                                      double *__restrict__ partials, float *__restrict__ c_out,
+                                                      const int32_t *__restrict__ g_of_l,
                                                       float *__restrict__ rank_out) {
-  __shared__ int s_last;
   const double D = prm.drop ? 0.0 : *dsum_in;
   const double add = prm.base + prm.d * D * prm.inv_n;
   double dang = 0.0;
@@ -222,22 +222,7 @@ __global__ __launch_bounds__(BLOCK) void k_pr_combine(CombineParams prm, const f
     if (od == 0) dang += r;
   }
   dang = block_sum(dang);
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = dang;
-    __threadfence();
-    s_last = (atomicAdd(done_counter, 1u) == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  double acc = 0.0;
-  for (uint32_t i = threadIdx.x; i < gridDim.x; i += BLOCK)
-    acc += __hip_atomic_load(partials + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  acc = block_sum(acc);
-  if (threadIdx.x == 0) {
-    *dsum_out = acc + prm.iso_count * add;
-    *done_counter = 0u;
-  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = dang;
 }
 
 }  // namespace
@@ -252,6 +237,9 @@ struct PrSlices {
   Plan plans[NS];
   SliceArgs sa{};
   int32_t nh_max = 0;
+  RowsDev rows;             // per-class row blocks (when tuned for row blocks)
+  int64_t rb_base[NS] = {}, nb[NS] = {};
+  int64_t nrows = 0;
   Tuning built_for{};
   bool built = false;
 };
@@ -261,12 +249,14 @@ void pr_slices_free(GpuPart &g) {
   g.slices = nullptr;
 }
 
-// Build the class CSRs on the device (once per partition and hub chunk).
+static int build_class_plans(tg_partition *p, PrSlices &S, const std::vector<int32_t> &hc);
+
+// Build the class CSRs on the device (once per partition and tuning).
 static int build_slices(tg_partition *p, hipStream_t s) {
   GpuPart &g = p->gpu;
   const Tuning &t = p->tune;
   if (g.slices && g.slices->built && memcmp(g.slices->built_for.min_deg, t.min_deg, sizeof(t.min_deg)) == 0 &&
-      g.slices->built_for.hub_chunk == t.hub_chunk)
+      g.slices->built_for.hub_chunk == t.hub_chunk && g.slices->built_for.pr_rows == t.pr_rows)
     return TG_OK;
   pr_slices_free(g);
   g.slices = new (std::nothrow) PrSlices();
@@ -284,7 +274,8 @@ static int build_slices(tg_partition *p, hipStream_t s) {
   TG_HIP(hipMemcpyAsync(hc.data(), cnt, hc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   TG_HIP(hipStreamSynchronize(s));
   std::vector<int32_t> hsoff((size_t)NS * (n + 1));
-  int64_t base = 0;
+  int64_t tot[NS];
+#pragma omp parallel for schedule(static, 1)
   for (int k = 0; k < NS; ++k) {
     int64_t acc = 0;
     for (int64_t v = 0; v < n; ++v) {
@@ -292,9 +283,13 @@ static int build_slices(tg_partition *p, hipStream_t s) {
       acc += hc[(size_t)k * n + v];
     }
     hsoff[(size_t)k * (n + 1) + n] = (int32_t)acc;
-    if (acc >= ((int64_t)1 << 31)) return set_error(TG_EUNSUPPORTED, "pagerank: a source class exceeds 2^31 edges");
+    tot[k] = acc;
+  }
+  int64_t base = 0;
+  for (int k = 0; k < NS; ++k) {
+    if (tot[k] >= ((int64_t)1 << 31)) return set_error(TG_EUNSUPPORTED, "pagerank: a source class exceeds 2^31 edges");
     S.sa.base[k] = base;
-    base += acc;
+    base += tot[k];
   }
   TG_TRY(dalloc(S.arena, &S.soff, hsoff.size()));
   TG_HIP(hipMemcpyAsync(S.soff, hsoff.data(), hsoff.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
@@ -302,9 +297,48 @@ static int build_slices(tg_partition *p, hipStream_t s) {
   hipLaunchKernelGGL(k_slice_fill, dim3(std::max(grid, 1u)), dim3(BLOCK), 0, s, g.in.off, g.in.col, n, S.soff, S.sa,
                      S.scol);
   TG_HIP(hipGetLastError());
-  // per-class plans over the same positions as the plain gather (decreasing
-  // in-degree); bins follow the expected class row length ceil(indeg / 8),
-  // hub chunks the actual class rows
+  if (t.pr_rows) {
+    // row blocks of every class over rows [0, nrows) (a symmetric whole-graph
+    // partition leaves out its isolated tail, whose partials stay 0)
+    S.nrows = g.in_alias ? g.in_bins.bstart[BIN_ZERO] : n;
+    RowBlocksHost all, hk;
+    int64_t nlr = 0;
+    for (int k = 0; k < NS; ++k) {
+      S.rb_base[k] = (int64_t)all.rb.size();
+      build_row_blocks(S.nrows, nullptr, hsoff.data() + (size_t)k * (n + 1), (int32_t)t.pr_rows, S.rb_base[k],
+                       (int64_t)k * n, hk);
+      S.nb[k] = (int64_t)hk.rb.size() - 1;
+      for (RowBlk &b : hk.rb)
+        if (b.lr >= 0) b.lr += (int32_t)nlr;
+      all.rb.insert(all.rb.end(), hk.rb.begin(), hk.rb.end());
+      all.lr_b0.insert(all.lr_b0.end(), hk.lr_b0.begin(), hk.lr_b0.end());
+      all.lr_nch.insert(all.lr_nch.end(), hk.lr_nch.begin(), hk.lr_nch.end());
+      all.lr_pos.insert(all.lr_pos.end(), hk.lr_pos.begin(), hk.lr_pos.end());
+      nlr += (int64_t)hk.lr_b0.size();
+    }
+    if ((int64_t)all.rb.size() >= ((int64_t)1 << 31))
+      return set_error(TG_EUNSUPPORTED, "pagerank: too many row blocks");
+    TG_TRY(rows_upload(S.rows, all));
+  } else {
+    TG_TRY(build_class_plans(p, S, hc));
+  }
+  TG_TRY(dalloc(S.arena, &S.ps, (size_t)NS * std::max<int64_t>(n, 1)));
+  // rows that are never walked keep partial 0
+  TG_HIP(hipMemset(S.ps, 0, (size_t)NS * std::max<int64_t>(n, 1) * sizeof(float)));
+  TG_HIP(hipStreamSynchronize(s));
+  S.arena.release_one(cnt);
+  S.built_for = t;
+  S.built = true;
+  return TG_OK;
+}
+
+// Per-class plans over the same positions as the plain gather (decreasing
+// in-degree) for the degree-bin walk; bins follow the expected class row
+// length ceil(indeg / 8), hub chunks the actual class rows.
+static int build_class_plans(tg_partition *p, PrSlices &S, const std::vector<int32_t> &hc) {
+  GpuPart &g = p->gpu;
+  const Tuning &t = p->tune;
+  const int64_t n = g.n;
   std::vector<int64_t> d8((size_t)n);
   for (int64_t i = 0; i < n; ++i) d8[i] = (g.h_in_deg[i] + NS - 1) / NS;
   BinBounds cb{};
@@ -357,13 +391,6 @@ static int build_slices(tg_partition *p, hipStream_t s) {
   TG_TRY(dalloc(S.arena, &S.hub_partials, (size_t)std::max<int64_t>(chunks, 1)));
   TG_TRY(dalloc(S.arena, &S.hub_counters, (size_t)NS * S.nh_max));
   TG_HIP(hipMemset(S.hub_counters, 0, (size_t)NS * S.nh_max * sizeof(uint32_t)));
-  TG_TRY(dalloc(S.arena, &S.ps, (size_t)NS * std::max<int64_t>(n, 1)));
-  // rows of in-degree 0 are never walked: their partials stay 0
-  TG_HIP(hipMemset(S.ps, 0, (size_t)NS * std::max<int64_t>(n, 1) * sizeof(float)));
-  TG_HIP(hipStreamSynchronize(s));
-  S.arena.release_one(cnt);
-  S.built_for = t;
-  S.built = true;
   return TG_OK;
 }
 
@@ -376,25 +403,55 @@ int gpu_pagerank_sliced_step(tg_partition *p, double damping, int mode, int32_t 
   const Tuning &t = p->tune;
   const double N = (double)g.n_global;
   const bool ordered = g.pr_order != nullptr;
-  int64_t vbmax = 0;
-  for (int c = 0; c < NS; ++c) vbmax = std::max<int64_t>(vbmax, S.plans[c].vb[NBIN]);
-  const int64_t per = std::max<int64_t>(1, std::min<int64_t>(vbmax, std::max<int64_t>(t.pr_grid / NS, 1)));
-  const int grid = (int)(per * NS);
   // whole lines only, and no more than the class holds
   const int64_t lines = std::min<int64_t>(t.pr_lds_verts / LINE, (g.n + (int64_t)LINE * NS - 1) / ((int64_t)LINE * NS));
-  const int32_t lds = (int32_t)(lines * LINE);
+  int32_t lds = (int32_t)(lines * LINE);
   const int tk = ktimer_start(s);
   const float *cin = ws.cbuf[k & 1];
-  if (ordered)
+  if (t.pr_rows) {
+    RowsArgs A;
+    memset(&A, 0, sizeof(A));
+    int64_t nbmax = 0;
+    for (int c = 0; c < NS; ++c) {
+      A.rb_base[c] = S.rb_base[c];
+      A.nb[c] = S.nb[c];
+      A.ebase[c] = S.sa.base[c];
+      nbmax = std::max<int64_t>(nbmax, S.nb[c]);
+    }
+    A.rb = S.rows.rb;
+    A.off = S.soff;
+    A.off_stride = g.n + 1;
+    A.col = S.scol;
+    A.lr_b0 = S.rows.lr_b0;
+    A.lr_nch = S.rows.lr_nch;
+    A.chunk_part = S.rows.chunk_part;
+    A.lr_pos = S.rows.lr_pos;
+    A.long_part = S.rows.long_part;
+    A.nlr = (int32_t)S.rows.nlr;
+    A.nnz = (int32_t)t.pr_rows;
+    while (lds > 0 && rows_lds_bytes(lds, A.nnz, false) > 65536) lds -= LINE;
+    A.lds_verts = lds;
+    A.c_in = cin;
+    A.n = g.n;
+    A.ps = S.ps;
+    const int64_t per = std::max<int64_t>(1, std::min<int64_t>(nbmax, std::max<int64_t>(t.pr_grid / NS, 1)));
+    TG_TRY(rows_launch(A, true, true, (int)(per * NS), s));
+  } else {
+    int64_t vbmax = 0;
+    for (int c = 0; c < NS; ++c) vbmax = std::max<int64_t>(vbmax, S.plans[c].vb[NBIN]);
+    const int64_t per = std::max<int64_t>(1, std::min<int64_t>(vbmax, std::max<int64_t>(t.pr_grid / NS, 1)));
+    const int grid = (int)(per * NS);
+    if (ordered)
     hipLaunchKernelGGL(k_pr_slice<true>, dim3(grid), dim3(BLOCK), (size_t)lds * sizeof(float), s, S.d_plans,
                        g.pr_order, S.hubpref, S.sa, S.soff, S.scol, g.n, cin, S.ps, S.hub_partials, S.hub_counters,
                        S.nh_max, t.hub_chunk, lds);
-  else
-    hipLaunchKernelGGL(k_pr_slice<false>, dim3(grid), dim3(BLOCK), (size_t)lds * sizeof(float), s, S.d_plans,
-                       nullptr, S.hubpref, S.sa, S.soff, S.scol, g.n, cin, S.ps, S.hub_partials, S.hub_counters,
-                       S.nh_max, t.hub_chunk, lds);
+    else
+      hipLaunchKernelGGL(k_pr_slice<false>, dim3(grid), dim3(BLOCK), (size_t)lds * sizeof(float), s, S.d_plans,
+                         nullptr, S.hubpref, S.sa, S.soff, S.scol, g.n, cin, S.ps, S.hub_partials, S.hub_counters,
+                         S.nh_max, t.hub_chunk, lds);
+    TG_HIP(hipGetLastError());
+  }
   ktimer_stop(tk, s, "pr_slice_gather");
-  TG_HIP(hipGetLastError());
   CombineParams cp;
   cp.base = (1.0 - damping) / N;
   cp.d = damping;
@@ -410,9 +467,11 @@ int gpu_pagerank_sliced_step(tg_partition *p, double damping, int mode, int32_t 
   const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>((cp.n_walk + BLOCK - 1) / BLOCK, 4096));
   const int tk2 = ktimer_start(s);
   hipLaunchKernelGGL(k_pr_combine, dim3(cgrid), dim3(BLOCK), 0, s, cp, S.ps, g.out.off, ws.scalars + (k & 1),
-                     ws.scalars + ((k + 1) & 1), ws.partials, ws.counters, ws.cbuf[(k + 1) & 1], g.g_of_l, rank_out);
-  ktimer_stop(tk2, s, "pr_combine");
+                     ws.partials, ws.cbuf[(k + 1) & 1], g.g_of_l, rank_out);
   TG_HIP(hipGetLastError());
+  TG_TRY(pr_dsum_launch(ws.partials, cgrid, nullptr, 0, cp.iso_count, cp.base, cp.d, cp.inv_n, cp.drop,
+                        ws.scalars + (k & 1), ws.scalars + ((k + 1) & 1), s));
+  ktimer_stop(tk2, s, "pr_combine");
   return TG_OK;
 }
 

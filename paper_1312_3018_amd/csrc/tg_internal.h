@@ -65,6 +65,7 @@ struct Tuning {
   int64_t sssp_lds_verts;        // SSSP: distances of vertices [0, n) snapshotted in LDS per block
   int64_t sssp_grid;             // SSSP: blocks per launch when snapshotting
   int64_t pr_xcd;                // PageRank: 1 = gather split by source class per XCD
+  int64_t pr_rows;               // PageRank: edges per row block (0 = degree-bin walk)
 };
 Tuning default_tuning();
 int parse_tuning(const char *json, Tuning *t);
@@ -124,6 +125,77 @@ struct StaticPlan {
 };
 
 struct PrSlices;
+struct PrRows;
+
+// Row blocks of a CSR for the PageRank gather (pr_rows.hip).
+struct RowBlk {
+  int64_t e0;  // first edge, relative to the CSR's own first edge
+  int32_t r0;  // first row
+  int32_t lr;  // -1: whole rows [r0, next block's r0); else this block is a chunk of long row `lr`
+};
+struct RowBlocksHost {
+  std::vector<RowBlk> rb;       // blocks, then a sentinel {E, nrows, -1}
+  std::vector<int32_t> lr_b0;   // long row -> index of its first chunk block (first_block-based)
+  std::vector<int32_t> lr_nch;  // long row -> number of chunks
+  std::vector<int64_t> lr_pos;  // long row -> where its result goes (pos_base + row)
+};
+// Pack rows [0, nrows) (offsets off64 or off32) into blocks of at most nnz
+// edges and nnz rows; longer rows become chunks of nnz edges.
+void build_row_blocks(int64_t nrows, const int64_t *off64, const int32_t *off32, int32_t nnz, int64_t first_block,
+                      int64_t pos_base, RowBlocksHost &out);
+struct RowsDev {
+  DevArena arena;
+  RowBlk *rb = nullptr;
+  int32_t *lr_b0 = nullptr, *lr_nch = nullptr;
+  int64_t *lr_pos = nullptr;
+  double *chunk_part = nullptr;  // per block: chunk partial sums
+  double *long_part = nullptr;   // per long-row block: dangling partials (LONG_GRID)
+  int64_t nb_total = 0, nlr = 0;
+};
+constexpr int LONG_GRID = 1024;  // blocks of the long-row launch, at most
+int rows_upload(RowsDev &D, const RowBlocksHost &h);
+int long_grid(int64_t nlr);
+// One block: *dsum_out = sum(pa[0..na)) + sum(pb[0..nb)) + iso_count * ((1-d)/N + d D/N)
+int pr_dsum_launch(const double *pa, int32_t na, const double *pb, int32_t nb, double iso_count, double base,
+                   double d, double inv_n, int32_t drop, const double *dsum_in, double *dsum_out, hipStream_t s);
+// Kernel arguments.  Class mode: class k's blocks are rb[rb_base[k] ..
+// rb_base[k] + nb[k]] (sentinel included), its rows' offsets are
+// off + k * off_stride (int32, relative) and its edges col + ebase[k]; rows
+// write partial sums into ps[k * n + v].  Single mode: class 0 only, and rows
+// are finished as in the degree-bin gather.
+struct RowsArgs {
+  const RowBlk *rb;
+  int64_t rb_base[8];
+  int64_t nb[8];
+  const void *off;
+  int64_t off_stride;
+  int64_t ebase[8];
+  const int32_t *col;
+  const int32_t *lr_b0, *lr_nch;
+  const int64_t *lr_pos;
+  double *chunk_part;
+  double *long_part;
+  int32_t nlr;
+  int32_t nnz;
+  int32_t lds_verts;
+  const float *c_in;
+  int64_t n;
+  float *ps;
+  double base, d, inv_n, iso_count;
+  int32_t drop, last;
+  int32_t od_rows;  // single mode: out-degree of a row = its length (symmetric whole graph)
+  const double *dsum_in;
+  double *dsum_out;
+  double *partials;
+  const int64_t *out_off;
+  float *c_out;
+  const int32_t *g_of_l;
+  float *rank_out;
+  const double *ghost;
+  const int32_t *extra_deg;
+};
+size_t rows_lds_bytes(int32_t lds_verts, int32_t nnz, bool stage_od);
+int rows_launch(const RowsArgs &A, bool classes, bool off32, int grid, hipStream_t s);
 
 // The GPU partition: local ids 0..n-1 in decreasing out-degree order.
 struct GpuPart {
@@ -146,6 +218,7 @@ struct GpuPart {
   std::vector<int64_t> h_in_deg;   // in-degree along pr_order (non-increasing)
   DevArena plan_arena;             // tuning-dependent plans
   PrSlices *slices = nullptr;      // PageRank in-edges split by source class (lazy)
+  PrRows *rows = nullptr;          // PageRank row blocks of the in-edges (lazy)
 };
 
 // Per-partition scratch, grown on demand.
@@ -263,6 +336,10 @@ int gpu_pagerank_step(tg_partition *p, double damping, int mode, int32_t k, bool
 int gpu_pagerank_sliced_step(tg_partition *p, double damping, int mode, int32_t k, bool last, float *rank_out,
                              hipStream_t s);
 void pr_slices_free(GpuPart &g);
+// pr_rows.hip: the step over row blocks of the in-edges
+int gpu_pagerank_rows_step(tg_partition *p, double damping, int mode, int32_t k, bool last, float *rank_out,
+                           hipStream_t s, const double *ghost, const int32_t *extra_deg);
+void pr_rows_free(GpuPart &g);
 int pr_write_initial(const GpuPart &g, float *rank_out, double N, hipStream_t s);
 
 // algorithms (GPU partition only)

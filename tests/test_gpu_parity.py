@@ -19,7 +19,7 @@ INF = oracle.INF
 SMALL_BINS = {"hub_min_deg": 300, "block_min_deg": 100, "wave_min_deg": 24, "g16_min_deg": 6,
               "g4_min_deg": 2, "hub_chunk": 256, "pr_lds_verts": 100, "pr_grid": 7,
               "bfs_lds_words": 16, "bfs_grid": 5, "bfs_lds_min_vblocks": 0,
-              "sssp_delta": 64, "sssp_lds_verts": 100, "sssp_grid": 6}
+              "sssp_delta": 64, "sssp_lds_verts": 100, "sssp_grid": 6, "pr_rows": 256}
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -152,6 +152,26 @@ def test_directed_rmat12_all(gpu, tuning):
     assert bc_close(got, oracle.bc(g.offsets, g.cols, roots))
 
 
+@pytest.mark.parametrize("xcd", [0, 1])
+@pytest.mark.parametrize("rows", [0, 256, 1024, 4096])
+def test_pagerank_variants(gpu, rmat14, xcd, rows):
+    """Every PageRank gather (degree bins or row blocks, whole CSR or per-XCD
+    source classes) on a symmetric and a directed graph; row blocks of 256
+    edges split the hubs into many chunks."""
+    g, w = rmat14
+    gd = graphgen.rmat(12, symmetrize=False)
+    for graph, iters in ((g, 10), (gd, 20)):
+        for lds in (0, 100, 4096):
+            tuning = {"pr_xcd": xcd, "pr_rows": rows, "pr_lds_verts": lds, "pr_grid": 64}
+            P = load(gpu, graph, None, tuning)
+            for mode in ("uniform", "drop"):
+                rank = gpu.pagerank(P, 0.85, iters, mode).cpu().numpy()
+                ref = oracle.pagerank(graph.offsets, graph.cols, 0.85, iters, mode)
+                assert pr_rel_l1(rank, ref) <= 1e-5, (tuning, mode)
+            again = gpu.pagerank(P, 0.85, iters, "drop").cpu().numpy()
+            assert np.array_equal(again, rank)  # deterministic
+
+
 # ------------------------------------------------------------------ edges
 
 def test_degenerate_graphs(gpu):
@@ -241,7 +261,8 @@ def test_retune_keeps_results(gpu, rmat14):
     ref_lev = oracle.bfs(g.offsets, g.cols, root)
     ref_pr = oracle.pagerank(g.offsets, g.cols, 0.85, 10)
     for tuning in (SMALL_BINS, {"pr_lds_verts": 0, "bfs_lds_words": 0, "bfs_lds_min_vblocks": 0},
-                   dict(SMALL_BINS, pr_xcd=0), {"pr_xcd": 0}, None):
+                   dict(SMALL_BINS, pr_xcd=0), {"pr_xcd": 0}, {"pr_rows": 0}, {"pr_rows": 512, "pr_xcd": 0},
+                   None):
         gpu.partition_retune(P, tuning)
         assert np.array_equal(gpu.bfs(P, [root]).cpu().numpy()[0], ref_lev)
         assert pr_rel_l1(gpu.pagerank(P, 0.85, 10).cpu().numpy(), ref_pr) <= 1e-5
