@@ -21,9 +21,9 @@ from . import bfs, pagerank, partition_info, partition_retune, sssp
 
 DEFAULTS = {
     "hub_min_deg": 8192, "block_min_deg": 512, "wave_min_deg": 48, "g16_min_deg": 12, "g4_min_deg": 3,
-    "hub_chunk": 4096, "pr_lds_verts": 4096, "pr_grid": 2048, "bfs_lds_words": 4096, "bfs_grid": 2048,
+    "hub_chunk": 4096, "pr_lds_verts": 40960, "pr_grid": 256, "bfs_lds_words": 4096, "bfs_grid": 2048,
     "bfs_lds_min_vblocks": 4096, "sssp_delta": 0, "sssp_lds_verts": 0, "sssp_grid": 2048, "pr_xcd": 1,
-    "pr_rows": 2048,
+    "pr_rows": 512,
 }
 
 SPACE = {
@@ -34,9 +34,9 @@ SPACE = {
     "g4_min_deg": [2, 3, 5],
     "hub_chunk": [1024, 2048, 4096, 8192],
     "pr_xcd": [0, 1],
-    "pr_rows": [0, 1024, 2048, 4096],
-    "pr_lds_verts": [0, 2048, 4096, 8192, 14336],
-    "pr_grid": [1024, 2048, 4096, 8192, 16384],
+    "pr_rows": [256, 512],
+    "pr_lds_verts": [0, 8192, 16384, 24576, 32768, 40960],
+    "pr_grid": [256, 512, 1024],
     "bfs_lds_words": [0, 1024, 4096, 8192],
     "bfs_grid": [1024, 2048, 4096, 16384],
     "bfs_lds_min_vblocks": [1024, 4096, 16384, 1 << 40],

@@ -101,10 +101,8 @@ Workspace::~Workspace() {
 }
 
 int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
-  const int64_t hubs_needed = std::max<int64_t>(g.max_out_hubs, g.pr.nh) + 1;
-  if (cap_n == g.n && hub_chunks_needed <= hub_chunks_cap && hubs_needed <= hubs_cap &&
-      g.pr.work.vb[1] + 1 <= hub_chunks_cap)
-    return TG_OK;
+  const int64_t hubs_needed = g.max_out_hubs + 1;
+  if (cap_n == g.n && hub_chunks_needed <= hub_chunks_cap && hubs_needed <= hubs_cap) return TG_OK;
   arena.release();
   const int64_t n = g.n;
   nwords = ((n + 31) / 32 + 1023) / 1024 * 1024;
@@ -124,12 +122,10 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   // frontier hub chunks are bounded by E / chunk + (hub vertices)
   // (hub_chunk >= 256, so a frontier has at most E/256 + hubs chunks)
   int64_t chunks = std::max<int64_t>(hub_chunks_needed, g.m / 256 + g.max_out_hubs + 1);
-  chunks = std::max<int64_t>(chunks, g.pr.work.vb[1] + 1);
   hub_chunks_cap = chunks;
   TG_TRY(dalloc(arena, &hub_partials, chunks));
   const int64_t hubs = hubs_needed;
   hubs_cap = hubs;
-  TG_TRY(dalloc(arena, &hub_dangling, hubs));
   TG_TRY(dalloc(arena, &hub_counters, hubs));
   TG_TRY(dalloc(arena, &hubpref, hubs + 1));
   TG_TRY(dalloc(arena, &scalars, 16));
@@ -160,8 +156,8 @@ Tuning default_tuning() {
   t.min_deg[tgk::BIN_G16] = 12;
   t.min_deg[tgk::BIN_G4] = 3;
   t.hub_chunk = 4096;
-  t.pr_lds_verts = 4096;
-  t.pr_grid = 2048;
+  t.pr_lds_verts = 40960;  // as many as fit next to the row blocks
+  t.pr_grid = 256;         // one workgroup per CU
   t.bfs_lds_words = 4096;
   t.bfs_grid = 2048;
   t.bfs_lds_min_vblocks = 4096;
@@ -169,7 +165,7 @@ Tuning default_tuning() {
   t.sssp_lds_verts = 0;
   t.sssp_grid = 2048;
   t.pr_xcd = 1;
-  t.pr_rows = 2048;
+  t.pr_rows = 512;
   return t;
 }
 
@@ -207,12 +203,11 @@ int parse_tuning(const char *json, Tuning *t) {
   if (json_int(json, "pr_xcd", &v)) t->pr_xcd = v;
   if (json_int(json, "pr_rows", &v)) t->pr_rows = v;
   if (t->pr_xcd != 0 && t->pr_xcd != 1) return set_error(TG_EINVAL, "tuning: pr_xcd must be 0 or 1");
-  if (t->pr_rows != 0 && (t->pr_rows < 256 || t->pr_rows > 4096 || t->pr_rows % 256 != 0))
-    return set_error(TG_EINVAL, "tuning: pr_rows must be 0 or a multiple of 256 in [256, 4096]");
+  if (t->pr_rows != 256 && t->pr_rows != 512) return set_error(TG_EINVAL, "tuning: pr_rows must be 256 or 512");
   if (t->sssp_delta < 0 || t->sssp_delta > INT32_MAX / 2) return set_error(TG_EINVAL, "tuning: sssp_delta outside [0, 2^30]");
   if (t->sssp_lds_verts < 0 || t->sssp_lds_verts > 14336) return set_error(TG_EINVAL, "tuning: sssp_lds_verts outside [0, 14336]");
   if (t->sssp_grid < 1 || t->sssp_grid > 16384) return set_error(TG_EINVAL, "tuning: sssp_grid outside [1, 16384]");
-  if (t->pr_lds_verts < 0 || t->pr_lds_verts > 14336) return set_error(TG_EINVAL, "tuning: pr_lds_verts outside [0, 14336]");
+  if (t->pr_lds_verts < 0 || t->pr_lds_verts > 40960) return set_error(TG_EINVAL, "tuning: pr_lds_verts outside [0, 40960]");
   if (t->bfs_lds_words < 0 || t->bfs_lds_words > 14336) return set_error(TG_EINVAL, "tuning: bfs_lds_words outside [0, 14336]");
   if (t->pr_grid < 1 || t->pr_grid > 16384 || t->bfs_grid < 1 || t->bfs_grid > 16384)
     return set_error(TG_EINVAL, "tuning: grids must be in [1, 16384]");
@@ -368,29 +363,19 @@ BinBounds bins_of(const std::vector<int64_t> &deg_in_order, const Tuning &t) {
   return bb;
 }
 
-// Static plan over all positions 0..n-1 with the given bins and degrees.
-void static_plan(const BinBounds &bb, const std::vector<int64_t> &deg_in_order, const Tuning &t, Plan &work,
-                 Plan &all, std::vector<int64_t> &hubpref) {
-  const int64_t n = (int64_t)deg_in_order.size();
-  memset(&work, 0, sizeof(Plan));
-  work.count = (int32_t)n;
-  for (int b = 0; b <= NBIN; ++b) work.pos[b] = (int32_t)bb.bstart[b];
-  const int64_t nh = bb.bstart[1] - bb.bstart[0];
-  hubpref.assign((size_t)nh + 1, 0);
-  for (int64_t i = 0; i < nh; ++i)
-    hubpref[i + 1] = hubpref[i] + (deg_in_order[i] + t.hub_chunk - 1) / t.hub_chunk;
-  int64_t vb = 0;
-  work.vb[0] = 0;
-  vb += hubpref[nh];
-  work.vb[1] = vb;
-  for (int b = 1; b < NBIN; ++b) {
-    const int64_t cnt = work.pos[b + 1] - work.pos[b];
-    if (b != tgk::BIN_ZERO) vb += (cnt + tgk::verts_per_vblock(b) - 1) / tgk::verts_per_vblock(b);
-    work.vb[b + 1] = vb;
+// The same boundaries from unsorted degrees (positions they would have after
+// a sort by decreasing degree).
+BinBounds bins_of_unsorted(const std::vector<int64_t> &deg, const Tuning &t) {
+  int64_t cnt[NBIN] = {};
+  for (int64_t d : deg) cnt[bin_of_degree(d, t)]++;
+  BinBounds bb;
+  int64_t acc = 0;
+  for (int b = 0; b < NBIN; ++b) {
+    bb.bstart[b] = acc;
+    acc += cnt[b];
   }
-  all = work;
-  const int64_t zc = all.pos[NBIN] - all.pos[tgk::BIN_ZERO];
-  all.vb[NBIN] = all.vb[tgk::BIN_ZERO] + (zc + 255) / 256;
+  bb.bstart[NBIN] = acc;
+  return bb;
 }
 
 }  // namespace
@@ -438,15 +423,8 @@ int apply_tuning(tg_partition *p, const Tuning &t) {
   GpuPart &gp = p->gpu;
   p->tune = t;
   gp.out_bins = bins_of(gp.h_deg, t);
-  gp.in_bins = gp.in_alias ? gp.out_bins : bins_of(gp.h_in_deg, t);
+  gp.in_bins = gp.in_alias ? gp.out_bins : bins_of_unsorted(gp.h_in_deg, t);
   gp.max_out_hubs = gp.out_bins.bstart[1] - gp.out_bins.bstart[0];
-  std::vector<int64_t> hubpref;
-  static_plan(gp.in_bins, gp.h_in_deg, t, gp.pr.work, gp.pr.all, hubpref);
-  gp.pr.nh = (int32_t)(gp.in_bins.bstart[1] - gp.in_bins.bstart[0]);
-  gp.plan_arena.release();
-  TG_TRY(upload(gp.plan_arena, &gp.pr.hubpref, hubpref.data(), hubpref.size()));
-  TG_TRY(upload(gp.plan_arena, &gp.pr.d_work, &gp.pr.work, 1));
-  TG_TRY(upload(gp.plan_arena, &gp.pr.d_all, &gp.pr.all, 1));
   return TG_OK;
 }
 
@@ -532,7 +510,6 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
   // in-edges (transpose) unless the whole graph is symmetric and local
   const bool alias = G.symmetric && !boundary;
   std::vector<int64_t> in_deg_in_order;
-  std::vector<int32_t> pr_order;
   if (alias) {
     gp.in = gp.out;
     gp.in_alias = true;
@@ -548,14 +525,8 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
     gp.in.n = n;
     gp.in.m = m;
     gp.in_alias = false;
-    std::vector<int64_t> indeg((size_t)n);
-    for (int64_t i = 0; i < n; ++i) indeg[i] = ioff[i + 1] - ioff[i];
-    pr_order.resize((size_t)n);
-    for (int64_t i = 0; i < n; ++i) pr_order[i] = (int32_t)i;
-    sort_desc_by_key(indeg, pr_order);
-    in_deg_in_order.resize((size_t)n);
-    for (int64_t i = 0; i < n; ++i) in_deg_in_order[i] = indeg[pr_order[i]];
-    TG_TRY(upload(A, &gp.pr_order, pr_order.data(), (size_t)n));
+    in_deg_in_order.resize((size_t)n);  // (by local id: only binned for reporting)
+    for (int64_t i = 0; i < n; ++i) in_deg_in_order[i] = ioff[i + 1] - ioff[i];
     // dangling = local out-degree 0 AND no boundary out-edges
     for (int64_t i = 0; i < n; ++i) {
       const int64_t bdeg = boundary ? boundary->src_off[i + 1] - boundary->src_off[i] : 0;

@@ -1,15 +1,16 @@
 // PageRank pull gather over row blocks (section 7.1, Figure 14).
 //
 // The in-edge CSR is cut once into row blocks: runs of consecutive
-// destination rows holding at most `nnz` in-edges and at most `nnz` rows; a
-// row longer than `nnz` becomes a run of chunk blocks of `nnz` edges each.  A
-// workgroup takes one row block at a time.  Its lanes first stream the block's
-// source ids (coalesced) and gather the contributions c(u) into LDS, up to
-// eight independent gathers in flight per lane; then groups of 1 to 64 lanes,
-// sized to the block's mean row length, sum the rows out of LDS.  The number
-// of dependent memory round trips per block is fixed, however the block's
-// edges are spread over its rows, which is what bounds the degree-bin walk on
-// low-degree rows.
+// destination rows holding at most `nnz` in-edges and fewer than `nnz` rows;
+// a row longer than `nnz` becomes a run of chunk blocks of `nnz` edges each.
+// A workgroup takes one row block at a time.  Its lanes stream the block's
+// row offsets and source ids (coalesced) and gather the contributions c(u)
+// into LDS, nnz/256 independent loads per lane in flight; then groups of 1 to
+// 64 lanes, sized to the block's mean row length, sum the rows out of LDS.
+// The loads of the next block are issued while the current block's gathers
+// are in flight, so a block costs one memory round trip whatever the spread
+// of its edges over its rows -- the latency chain (offsets, then ids, then
+// gathers) is what bounds a degree-bin walk on low-degree rows.
 //
 // The same kernel serves the per-XCD source classes: there every class has
 // its own CSR and row blocks, workgroup i takes class i mod 8, and rows yield
@@ -63,7 +64,7 @@ void build_row_blocks(int64_t nrows, const int64_t *off64, const int32_t *off32,
         continue;
       }
       // close the open block if row v does not fit in it
-      if (start < v && (off(v + 1) - off(start) > nnz || v - start >= nnz)) {
+      if (start < v && (off(v + 1) - off(start) > nnz || v - start >= nnz - 1)) {
         rb.push_back(RowBlk{off(start), (int32_t)start, -1});
         start = v;
       }
@@ -90,7 +91,7 @@ namespace {
 
 constexpr int NS = 8;     // source classes (XCDs)
 constexpr int LINE = 32;  // contributions per 128-byte line
-constexpr int U = 8;      // edges per lane per pass
+constexpr int WB = 1024;  // threads per workgroup of the row-block gather
 
 template <bool CLASSES>
 __device__ __forceinline__ const float *contrib_ptr(const float *hot, const float *c_in, int64_t H, int32_t u) {
@@ -99,21 +100,69 @@ __device__ __forceinline__ const float *contrib_ptr(const float *hot, const floa
   return u < H ? hot + u : c_in + u;
 }
 
-template <bool CLASSES, typename OffT>
-__global__ __launch_bounds__(BLOCK) void k_pr_rows(const RowsArgs A) {
+// Loads of one row block (its row offsets, out-degrees when staged, and
+// source ids) by one wave, issued without a branch: lanes past an end re-read
+// the last element, and a chunk block re-reads its row's offset.
+template <typename OffT, int U>
+struct BlockLoads {
+  OffT o[U];
+  int32_t od[U];
+  int32_t u[U];
+};
+
+template <typename OffT, int U>
+__device__ __forceinline__ void issue_loads(BlockLoads<OffT, U> &L, const RowBlk &me, const RowBlk &nx,
+                                            const OffT *off, const int32_t *col, const int32_t *od32,
+                                            bool stage_od, int lane) {
+  const bool chunk = me.lr >= 0;
+  const int32_t R = chunk ? 1 : nx.r0 - me.r0;
+  const int32_t nr = chunk ? 1 : R + 1;
+  const int32_t ne = (int32_t)(nx.e0 - me.e0);
+  const int64_t elast = ne > 0 ? me.e0 + ne - 1 : 0;
+#pragma unroll
+  for (int q = 0; q < U; ++q) {
+    const int32_t i = q * 64 + lane;
+    L.o[q] = off[me.r0 + min(i, nr - 1)];
+    if (stage_od) L.od[q] = od32[me.r0 + min(i, R - 1)];
+    L.u[q] = stream_load(col + min(me.e0 + i, elast));
+  }
+}
+
+// Keeps the compiler from moving LDS accesses across this point; the LDS
+// unit serves one wave's accesses in order, so lanes then see each other's
+// writes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// One workgroup of WB threads per CU.  Its waves share one table of hot
+// contributions in LDS (in class mode every workgroup of an XCD serves the
+// same class, so the table covers 8x as many sources) and each wave walks its
+// own row blocks of at most 64*U edges and 64*U - 1 rows, with no workgroup
+// barrier.  Per wave the loads of block j+1 are issued right after the
+// gathers of block j, so one memory round trip covers both.
+template <bool CLASSES, typename OffT, int U>
+__global__ __launch_bounds__(WB) void k_pr_rows(const RowsArgs A) {
+  constexpr int NNZ = 64 * U;
+  // all LDS is dynamic (sized by rows_lds_bytes): hot table, then one
+  // region per wave, then (single mode) the waves' dangling partials
   extern __shared__ float lds[];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const bool stage_od = !CLASSES && !A.od_rows;
   float *hot = lds;
-  float *vals = lds + A.lds_verts;
-  int32_t *loff = reinterpret_cast<int32_t *>(vals + A.nnz);
-  int32_t *lod = loff + A.nnz + 1;  // out-degrees of the rows (single mode, unless they equal the row lengths)
-  const int t = threadIdx.x;
+  double *s_dang = reinterpret_cast<double *>(lds + A.lds_verts + (int64_t)(WB / 64) * NNZ * (stage_od ? 3 : 2));
+  float *vals = lds + A.lds_verts + (int64_t)w * NNZ * (stage_od ? 3 : 2);
+  int32_t *loff = reinterpret_cast<int32_t *>(vals + NNZ);
+  int32_t *lod = loff + NNZ;  // out-degrees of the rows (single mode, unless they equal the row lengths)
   const int k = CLASSES ? (int)(blockIdx.x & (NS - 1)) : 0;
-  const int64_t j0 = CLASSES ? (int64_t)(blockIdx.x >> 3) : (int64_t)blockIdx.x;
-  const int64_t js = CLASSES ? (int64_t)(gridDim.x >> 3) : (int64_t)gridDim.x;
+  const int64_t nwg = CLASSES ? (int64_t)(gridDim.x >> 3) : (int64_t)gridDim.x;
+  const int64_t j0 = (CLASSES ? (int64_t)(blockIdx.x >> 3) : (int64_t)blockIdx.x) * (WB / 64) + w;
+  const int64_t js = nwg * (WB / 64);
   // hottest contributions: sources [0, lds_verts); in class mode the first
   // lds_verts/32 lines of class k (lines k, k+8, ...), so that every source
   // below H has its line in LDS
-  for (int32_t i = t; i < A.lds_verts; i += BLOCK) {
+  for (int32_t i = t; i < A.lds_verts; i += WB) {
     const int64_t u = CLASSES ? ((int64_t)(i / LINE) * NS + k) * LINE + (i % LINE) : (int64_t)i;
     hot[i] = u < A.n ? A.c_in[u] : 0.0f;
   }
@@ -124,107 +173,92 @@ __global__ __launch_bounds__(BLOCK) void k_pr_rows(const RowsArgs A) {
   const int32_t *col = A.col + A.ebase[k];
   float *psk = CLASSES ? A.ps + (int64_t)k * A.n : nullptr;
   const double add = CLASSES ? 0.0 : A.base + A.d * (A.drop ? 0.0 : *A.dsum_in) * A.inv_n;
-  const bool stage_od = !CLASSES && !A.od_rows;
   double dang = 0.0;
 
   const int64_t nbk = A.nb[k];
-  RowBlk me{}, nx{};
   if (j0 < nbk) {
-    me = rb[j0];
-    nx = rb[j0 + 1];
-  }
-  for (int64_t j = j0; j < nbk; j += js) {
-    // next block's descriptor, fetched while this one is processed
-    RowBlk me2{}, nx2{};
-    if (j + js < nbk) {
-      me2 = rb[j + js];
-      nx2 = rb[j + js + 1];
-    }
-    const int32_t ne = (int32_t)(nx.e0 - me.e0);
-    const bool chunk = me.lr >= 0;
-    const int32_t R = chunk ? 1 : nx.r0 - me.r0;
-    const int32_t nr = chunk ? 0 : R + 1;  // row offsets to stage
-    // One round stages up to BLOCK*U row offsets (and out-degrees) and
-    // BLOCK*U edges.  Every load of a round is issued before the first use and
-    // without a branch: lanes past an end re-read the last element, and a
-    // part with nothing left reads the arrays' first element.
-    for (int32_t b0 = 0; b0 < nr || b0 < ne; b0 += BLOCK * U) {
-      const bool do_r = b0 < nr, do_e = b0 < ne;
-      OffT o[U];
-      int64_t p0[U], p1[U];
-      int32_t u[U];
+    // descriptors of the current and the next block (past the end the last
+    // block's is re-read: its loads are issued but never used)
+    RowBlk cur = rb[j0], cur_nx = rb[j0 + 1];
+    const int64_t i1 = min(j0 + js, nbk - 1);
+    RowBlk nxt = rb[i1], nxt_nx = rb[i1 + 1];
+    BlockLoads<OffT, U> L;
+    issue_loads<OffT, U>(L, cur, cur_nx, off, col, A.od32, stage_od, lane);
+    for (int64_t j = j0; j < nbk; j += js) {
+      const int64_t i2 = min(j + 2 * js, nbk - 1);
+      const RowBlk nn = rb[i2], nn_nx = rb[i2 + 1];
       float x[U];
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int32_t i = b0 + q * BLOCK + t;
-        o[q] = *(do_r ? off + me.r0 + min(i, nr - 1) : off);
-        if (stage_od) {
-          const int64_t v = do_r ? me.r0 + min(i, R - 1) : 0;
-          p0[q] = stream_load(A.out_off + v);
-          p1[q] = stream_load(A.out_off + v + 1) + (A.extra_deg ? A.extra_deg[v] : 0);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < U; ++q) u[q] = stream_load(do_e ? col + me.e0 + min(b0 + q * BLOCK + t, ne - 1) : A.col);
-#pragma unroll
-      for (int q = 0; q < U; ++q) x[q] = *contrib_ptr<CLASSES>(hot, A.c_in, H, u[q]);
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int32_t i = b0 + q * BLOCK + t;
-        if (i < nr) loff[i] = (int32_t)((int64_t)o[q] - me.e0);
-        if (stage_od && i < R) lod[i] = (int32_t)(p1[q] - p0[q]);
-        if (i < ne) vals[i] = x[q];
-      }
-    }
-    __syncthreads();
+      for (int q = 0; q < U; ++q) x[q] = *contrib_ptr<CLASSES>(hot, A.c_in, H, L.u[q]);
+      BlockLoads<OffT, U> L2;
+      issue_loads<OffT, U>(L2, nxt, nxt_nx, off, col, A.od32, stage_od, lane);
 
-    if (chunk) {
-      // partial sum of one chunk of a long row, finished by k_pr_long
-      double cs = 0.0;
-      for (int32_t i = t; i < ne; i += BLOCK) cs += (double)vals[i];
-      cs = block_sum(cs);
-      if (t == 0) A.chunk_part[A.rb_base[k] + j] = cs;
-      __syncthreads();
-      me = me2;
-      nx = nx2;
-      continue;
-    }
-
-    // rows of this block, L lanes each (L about the mean row length)
-    const int32_t avg = R > 0 ? ne / R : 0;
-    const int lg = avg >= 48 ? 6 : avg >= 24 ? 5 : avg >= 12 ? 4 : avg >= 6 ? 3 : avg >= 3 ? 2 : avg >= 2 ? 1 : 0;
-    const int L = 1 << lg;
-    const int32_t grp = t >> lg, lane = t & (L - 1);
-    for (int32_t rbase = 0; rbase < R; rbase += (BLOCK >> lg)) {
-      const int32_t r = rbase + grp;
-      double s = 0.0;
-      int32_t lo = 0, hi = 0;
-      if (r < R) {
-        lo = loff[r];
-        hi = loff[r + 1];
-        for (int32_t i = lo + lane; i < hi; i += L) s += (double)vals[i];
-      }
-      s = group_sum(s, L);
-      if (r < R && lane == 0) {
-        const int32_t v = me.r0 + r;
-        if (CLASSES) {
-          __builtin_nontemporal_store((float)s, psk + v);
-        } else {
-          const double rv = add + A.d * (s + (A.ghost ? A.ghost[v] : 0.0));
-          const int32_t od = stage_od ? lod[r] : hi - lo;
-          if (A.last) A.rank_out[A.g_of_l[v]] = (float)rv;
-          else if (od > 0) __builtin_nontemporal_store((float)(rv / (double)od), A.c_out + v);
-          if (od == 0) dang += rv;
+      const int32_t ne = (int32_t)(cur_nx.e0 - cur.e0);
+      const bool chunk = cur.lr >= 0;
+      if (chunk) {
+        // partial sum of one chunk of a long row, finished by k_pr_long
+        double cs = 0.0;
+#pragma unroll
+        for (int q = 0; q < U; ++q) cs += (q * 64 + lane < ne) ? (double)x[q] : 0.0;
+        cs = wave_sum(cs);
+        if (lane == 0) A.chunk_part[A.rb_base[k] + j] = cs;
+      } else {
+        const int32_t R = cur_nx.r0 - cur.r0;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          const int32_t i = q * 64 + lane;
+          if (i <= R) loff[i] = (int32_t)((int64_t)L.o[q] - cur.e0);
+          if (stage_od && i < R) lod[i] = L.od[q];
+          if (i < ne) vals[i] = x[q];
         }
+        wave_lds_sync();
+        // rows of this block, Lw lanes each (Lw about the mean row length)
+        const int32_t avg = ne / R;
+        const int lg = avg >= 48 ? 6 : avg >= 24 ? 5 : avg >= 12 ? 4 : avg >= 6 ? 3 : avg >= 3 ? 2 : avg >= 2 ? 1 : 0;
+        const int Lw = 1 << lg;
+        const int32_t grp = lane >> lg, sub = lane & (Lw - 1);
+        for (int32_t rbase = 0; rbase < R; rbase += (64 >> lg)) {
+          const int32_t r = rbase + grp;
+          double sm = 0.0;
+          int32_t lo = 0, hi = 0;
+          if (r < R) {
+            lo = loff[r];
+            hi = loff[r + 1];
+            for (int32_t i = lo + sub; i < hi; i += Lw) sm += (double)vals[i];
+          }
+          sm = group_sum(sm, Lw);
+          if (r < R && sub == 0) {
+            const int32_t v = cur.r0 + r;
+            if (CLASSES) {
+              __builtin_nontemporal_store((float)sm, psk + v);
+            } else {
+              const double rv = add + A.d * (sm + (A.ghost ? A.ghost[v] : 0.0));
+              const int32_t od = stage_od ? lod[r] : hi - lo;
+              if (A.last) A.rank_out[A.g_of_l[v]] = (float)rv;
+              else if (od > 0) __builtin_nontemporal_store((float)(rv / (double)od), A.c_out + v);
+              if (od == 0) dang += rv;
+            }
+          }
+        }
+        wave_lds_sync();
       }
+      cur = nxt;
+      cur_nx = nxt_nx;
+      nxt = nn;
+      nxt_nx = nn_nx;
+      L = L2;
     }
-    __syncthreads();
-    me = me2;
-    nx = nx2;
   }
   if (CLASSES) return;
-  dang = block_sum(dang);
-  if (t == 0) A.partials[blockIdx.x] = dang;
+  // dangling partial of this workgroup, waves added in order
+  dang = wave_sum(dang);
+  if (lane == 0) s_dang[w] = dang;
+  __syncthreads();
+  if (t == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < WB / 64; ++i) acc += s_dang[i];
+    A.partials[blockIdx.x] = acc;
+  }
 }
 
 // Long rows: one wave per row sums the row's chunk partials (lane-strided,
@@ -250,7 +284,7 @@ __global__ __launch_bounds__(BLOCK) void k_pr_long(const RowsArgs A) {
       } else {
         const int64_t v = pos;
         const double r = add + A.d * (s + (A.ghost ? A.ghost[v] : 0.0));
-        const int64_t od = A.out_off[v + 1] - A.out_off[v] + (A.extra_deg ? A.extra_deg[v] : 0);
+        const int64_t od = A.od_rows ? A.out_off[v + 1] - A.out_off[v] : A.od32[v];
         if (A.last) A.rank_out[A.g_of_l[v]] = (float)r;
         else if (od > 0) A.c_out[v] = (float)(r / (double)od);
         if (od == 0) dang += r;
@@ -260,6 +294,14 @@ __global__ __launch_bounds__(BLOCK) void k_pr_long(const RowsArgs A) {
   if (CLASSES) return;
   dang = block_sum(dang);
   if (threadIdx.x == 0) A.long_part[blockIdx.x] = dang;
+}
+
+// od32[v] = out-degree of v, boundary out-edges included
+__global__ __launch_bounds__(BLOCK) void k_pr_od(const int64_t *__restrict__ out_off,
+                                                 const int32_t *__restrict__ extra_deg, int64_t n,
+                                                 int32_t *__restrict__ od32) {
+  const int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (v < n) od32[v] = (int32_t)(out_off[v + 1] - out_off[v]) + (extra_deg ? extra_deg[v] : 0);
 }
 
 // D' = sum of the dangling partials (a then b, each in block order) + the
@@ -311,18 +353,39 @@ int rows_upload(RowsDev &D, const RowBlocksHost &h) {
 }
 
 size_t rows_lds_bytes(int32_t lds_verts, int32_t nnz, bool stage_od) {
-  return (size_t)lds_verts * sizeof(float) + (size_t)nnz * sizeof(float) + (size_t)(nnz + 1) * sizeof(int32_t) +
-         (stage_od ? (size_t)nnz * sizeof(int32_t) : 0);
+  // (lds_verts is even, so the trailing doubles stay 8-byte aligned)
+  return (size_t)lds_verts * sizeof(float) + (size_t)(WB / 64) * nnz * sizeof(int32_t) * (stage_od ? 3 : 2) +
+         (size_t)(WB / 64) * sizeof(double);
+}
+
+int rows_lds_limit() {
+  static int limit[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+  if (!limit[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
+    limit[dev] = v;
+  }
+  return limit[dev];
 }
 
 int rows_launch(const RowsArgs &A, bool classes, bool off32, int grid, hipStream_t s) {
   const size_t lds = rows_lds_bytes(A.lds_verts, A.nnz, !classes && !A.od_rows);
-  if (lds > 65536) return set_error(TG_EINVAL, "pagerank: row blocks need %zu bytes of LDS (limit 65536)", lds);
+  if (lds > (size_t)rows_lds_limit())
+    return set_error(TG_EINVAL, "pagerank: row blocks need %zu bytes of LDS (limit %d)", lds, rows_lds_limit());
   if (classes != (bool)off32) return set_error(TG_EINVAL, "pagerank: row offset width does not match the mode");
-  if (classes)
-    hipLaunchKernelGGL((k_pr_rows<true, int32_t>), dim3(grid), dim3(BLOCK), lds, s, A);
-  else
-    hipLaunchKernelGGL((k_pr_rows<false, int64_t>), dim3(grid), dim3(BLOCK), lds, s, A);
+  if (A.nnz != 256 && A.nnz != 512) return set_error(TG_EINVAL, "pagerank: row blocks of %d edges (256 or 512)", A.nnz);
+  if (A.lds_verts % 2) return set_error(TG_EINVAL, "pagerank: odd hot-table size");
+#define TG_ROWS_LAUNCH(C, T, UU) hipLaunchKernelGGL((k_pr_rows<C, T, UU>), dim3(grid), dim3(WB), lds, s, A)
+  if (classes) {
+    if (A.nnz == 256) TG_ROWS_LAUNCH(true, int32_t, 4);
+    else TG_ROWS_LAUNCH(true, int32_t, 8);
+  } else {
+    if (A.nnz == 256) TG_ROWS_LAUNCH(false, int64_t, 4);
+    else TG_ROWS_LAUNCH(false, int64_t, 8);
+  }
+#undef TG_ROWS_LAUNCH
   TG_HIP(hipGetLastError());
   if (A.nlr > 0 || !classes) {
     // single mode always runs it: it writes the long rows' dangling partials
@@ -352,6 +415,7 @@ int pr_dsum_launch(const double *pa, int32_t na, const double *pb, int32_t nb, d
 // except that a symmetric whole-graph partition leaves out its isolated tail.
 struct PrRows {
   RowsDev dev;
+  int32_t *od32 = nullptr;  // out-degrees (incl. boundary edges) when they differ from the row lengths
   int64_t nrows = 0;
   int32_t nnz = 0;
 };
@@ -375,6 +439,7 @@ static int build_rows(tg_partition *p) {
   RowBlocksHost h;
   build_row_blocks(R.nrows, hoff.data(), nullptr, nnz, 0, 0, h);
   TG_TRY(rows_upload(R.dev, h));
+  if (!g.in_alias) TG_TRY(dalloc(R.dev.arena, &R.od32, (size_t)std::max<int64_t>(g.n, 1)));
   R.nnz = nnz;
   return TG_OK;
 }
@@ -399,10 +464,17 @@ int gpu_pagerank_rows_step(tg_partition *p, double damping, int mode, int32_t k,
   A.long_part = R.dev.long_part;
   A.nlr = (int32_t)R.dev.nlr;
   A.nnz = R.nnz;
-  A.lds_verts = (int32_t)std::min<int64_t>(p->tune.pr_lds_verts, g.n);
+  A.lds_verts = (int32_t)std::min<int64_t>(p->tune.pr_lds_verts, g.n) & ~1;
   // symmetric whole graph: out-degree = in-degree = row length
   A.od_rows = g.in_alias ? 1 : 0;
-  while (A.lds_verts > 0 && rows_lds_bytes(A.lds_verts, A.nnz, !A.od_rows) > 65536) A.lds_verts -= 256;
+  A.od32 = R.od32;
+  if (!g.in_alias && k == 0 && g.n > 0) {
+    hipLaunchKernelGGL(k_pr_od, dim3((unsigned)((g.n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, g.out.off, extra_deg,
+                       g.n, R.od32);
+    TG_HIP(hipGetLastError());
+  }
+  while (A.lds_verts > 0 && rows_lds_bytes(A.lds_verts, A.nnz, !A.od_rows) > (size_t)rows_lds_limit())
+    A.lds_verts -= 256;
   if (A.lds_verts < 0) A.lds_verts = 0;
   A.c_in = ws.cbuf[k & 1];
   A.n = g.n;
@@ -421,7 +493,8 @@ int gpu_pagerank_rows_step(tg_partition *p, double damping, int mode, int32_t k,
   A.rank_out = rank_out;
   A.ghost = ghost;
   A.extra_deg = extra_deg;
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(A.nb[0], p->tune.pr_grid));
+  // workgroups: enough for every wave to get a block, at most pr_grid
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((A.nb[0] + 15) / 16, p->tune.pr_grid));
   const int tk = ktimer_start(s);
   TG_TRY(rows_launch(A, false, false, grid, s));
   TG_TRY(pr_dsum_launch(ws.partials, grid, R.dev.long_part, long_grid(A.nlr), A.iso_count, A.base, A.d, A.inv_n,

@@ -56,8 +56,8 @@ namespace tg {
 struct Tuning {
   int64_t min_deg[tgk::BIN_G1];  // HUB, BLOCK, WAVE, G16, G4
   int64_t hub_chunk;
-  int64_t pr_lds_verts;          // PageRank: contributions staged in LDS per block
-  int64_t pr_grid;               // PageRank: blocks per launch
+  int64_t pr_lds_verts;          // PageRank: hot contributions staged in LDS per workgroup (at most)
+  int64_t pr_grid;               // PageRank: workgroups per launch (at most)
   int64_t bfs_lds_words;         // BFS: visited-bitmap words staged in LDS per block
   int64_t bfs_grid;              // BFS: blocks per launch when staging
   int64_t bfs_lds_min_vblocks;   // BFS: stage only for frontiers at least this large
@@ -65,7 +65,7 @@ struct Tuning {
   int64_t sssp_lds_verts;        // SSSP: distances of vertices [0, n) snapshotted in LDS per block
   int64_t sssp_grid;             // SSSP: blocks per launch when snapshotting
   int64_t pr_xcd;                // PageRank: 1 = gather split by source class per XCD
-  int64_t pr_rows;               // PageRank: edges per row block (0 = degree-bin walk)
+  int64_t pr_rows;               // PageRank: edges per row block (one wave's block)
 };
 Tuning default_tuning();
 int parse_tuning(const char *json, Tuning *t);
@@ -115,15 +115,6 @@ struct DevCSR {
   int32_t *w = nullptr;
 };
 
-// Static plan over every vertex of a partition (PageRank walks all of them).
-struct StaticPlan {
-  Plan work;               // bins HUB..G1 (ZERO skipped)
-  Plan all;                // bins HUB..ZERO
-  int64_t *hubpref = nullptr;  // device, nh + 1 entries
-  Plan *d_work = nullptr, *d_all = nullptr;
-  int32_t nh = 0;
-};
-
 struct PrSlices;
 struct PrRows;
 
@@ -140,7 +131,7 @@ struct RowBlocksHost {
   std::vector<int64_t> lr_pos;  // long row -> where its result goes (pos_base + row)
 };
 // Pack rows [0, nrows) (offsets off64 or off32) into blocks of at most nnz
-// edges and nnz rows; longer rows become chunks of nnz edges.
+// edges and nnz - 1 rows; longer rows become chunks of nnz edges.
 void build_row_blocks(int64_t nrows, const int64_t *off64, const int32_t *off32, int32_t nnz, int64_t first_block,
                       int64_t pos_base, RowBlocksHost &out);
 struct RowsDev {
@@ -188,6 +179,7 @@ struct RowsArgs {
   double *dsum_out;
   double *partials;
   const int64_t *out_off;
+  const int32_t *od32;      // single mode, od_rows == 0: out-degree of each row
   float *c_out;
   const int32_t *g_of_l;
   float *rank_out;
@@ -195,6 +187,7 @@ struct RowsArgs {
   const int32_t *extra_deg;
 };
 size_t rows_lds_bytes(int32_t lds_verts, int32_t nnz, bool stage_od);
+int rows_lds_limit();  // LDS bytes a workgroup may use on the current device
 int rows_launch(const RowsArgs &A, bool classes, bool off32, int grid, hipStream_t s);
 
 // The GPU partition: local ids 0..n-1 in decreasing out-degree order.
@@ -204,19 +197,16 @@ struct GpuPart {
   DevCSR out;                    // out-edges (local ids); weights if any
   DevCSR in;                     // in-edges (aliases `out` when symmetric)
   bool in_alias = true;
-  int32_t *pr_order = nullptr;   // positions -> vertex, by decreasing in-degree (null: identity)
   int32_t *g_of_l = nullptr;     // local -> global id
   int32_t *l_of_g = nullptr;     // global -> local id or -1 (size V)
   BinBounds out_bins{};          // out-degree bins over local ids
-  BinBounds in_bins{};           // in-degree bins over pr_order positions
-  StaticPlan pr;                 // PageRank plan over in-degree bins
+  BinBounds in_bins{};           // in-degree bins as positions in decreasing in-degree order (symmetric whole graph: out_bins)
   int64_t n_dangling = 0;        // vertices with out-degree 0
   int64_t n_isolated = 0;        // out-degree 0 and in-degree 0 (ZERO bin of in_bins when symmetric)
   int64_t max_out_hubs = 0;      // vertices in the HUB bin (out-degree)
   std::vector<int64_t> h_out_off;  // host copy of the local out offsets
   std::vector<int64_t> h_deg;      // out-degree of each local id (non-increasing)
-  std::vector<int64_t> h_in_deg;   // in-degree along pr_order (non-increasing)
-  DevArena plan_arena;             // tuning-dependent plans
+  std::vector<int64_t> h_in_deg;   // in-degree of each local id
   PrSlices *slices = nullptr;      // PageRank in-edges split by source class (lazy)
   PrRows *rows = nullptr;          // PageRank row blocks of the in-edges (lazy)
 };
