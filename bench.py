@@ -45,6 +45,7 @@ def kernel_sources_digest(files):
 KERNEL_FILES = {
     "pr_gather": ["pagerank.hip", "pr_sliced.hip", "pr_rows.hip", "kcommon.h"],
     "bfs_expand": ["bfs.hip", "kcommon.h"],
+    "bfs_bottom_up": ["bfs.hip", "kcommon.h"],
     "sssp_relax": ["sssp.hip", "kcommon.h"],
 }
 
@@ -524,6 +525,10 @@ def main():
     if "bfs_expand_ms" in sb:
         exp_bytes = 4.125 * sb["edges_scanned"] + 12.0 * sb["vertices_expanded"]
         kernels["bfs_expand"] = dict(ms=sb["bfs_expand_ms"], n=sb["bfs_expand_n"], bytes=exp_bytes)
+    if "bfs_bottom_up_ms" in sb:
+        # bottom-up steps: an in-neighbour id (4 B) and a frontier bit per edge checked
+        kernels["bfs_bottom_up"] = dict(ms=sb["bfs_bottom_up_ms"], n=sb["bfs_bottom_up_n"],
+                                        bytes=4.125 * sb.get("bottom_up_edges_checked", 0))
     if "sssp_relax_ms" in ss:
         kernels["sssp_relax"] = dict(ms=ss["sssp_relax_ms"], n=ss["sssp_relax_n"], bytes=sssp_bytes)
     roofs = {}
@@ -557,7 +562,10 @@ def main():
                    "global_batch": nr, "parallelism": "none (1 GPU)"},
         "bfs": {"gteps": round(bfs_edges / (t_bfs / 1e3) / 1e9, 2), "ms_per_root": round(t_bfs / nr, 4),
                 "hbm_gbs_algorithmic": round(bfs_bytes / (t_bfs / 1e3) / 1e9, 1),
-                "graph500_undirected_gteps": round(bfs_edges / 2 / (t_bfs / 1e3) / 1e9, 2)},
+                "graph500_undirected_gteps": round(bfs_edges / 2 / (t_bfs / 1e3) / 1e9, 2),
+                "top_down_edges_per_root": round(sb.get("edges_scanned", 0) / nr),
+                "bottom_up_edges_checked_per_root": round(sb.get("bottom_up_edges_checked", 0) / nr),
+                "bottom_up_steps_per_root": round(sb.get("bottom_up_steps", 0) / nr, 2)},
         "sssp": {"gteps": round(sssp_edges / (t_sssp / 1e3) / 1e9, 2), "ms_per_root": round(t_sssp / nr, 4),
                  "supersteps_per_root": round(ss.get("supersteps", 0) / nr, 1),
                  "work_efficiency": round(ss.get("relaxations", 0) / max(sssp_edges, 1), 3)},

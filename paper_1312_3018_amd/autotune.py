@@ -23,7 +23,7 @@ DEFAULTS = {
     "hub_min_deg": 8192, "block_min_deg": 512, "wave_min_deg": 48, "g16_min_deg": 12, "g4_min_deg": 3,
     "hub_chunk": 4096, "pr_lds_verts": 40960, "pr_grid": 256, "bfs_lds_words": 4096, "bfs_grid": 2048,
     "bfs_lds_min_vblocks": 4096, "sssp_delta": 0, "sssp_lds_verts": 0, "sssp_grid": 2048, "pr_xcd": 1,
-    "pr_rows": 512,
+    "pr_rows": 512, "bfs_do": 1, "bfs_alpha": 14, "bfs_beta": 24,
 }
 
 SPACE = {
@@ -40,6 +40,8 @@ SPACE = {
     "bfs_lds_words": [0, 1024, 4096, 8192],
     "bfs_grid": [1024, 2048, 4096, 16384],
     "bfs_lds_min_vblocks": [1024, 4096, 16384, 1 << 40],
+    "bfs_alpha": [4, 14, 32, 64],
+    "bfs_beta": [8, 24, 64],
     "sssp_delta": [0, 64, 128, 256, 512, 1024, 4096],
     "sssp_lds_verts": [0, 2048, 4096, 8192],
     "sssp_grid": [1024, 2048, 4096, 16384],
@@ -48,6 +50,7 @@ SPACE = {
 FAMILY = {k: "all" for k in ("hub_min_deg", "block_min_deg", "wave_min_deg", "g16_min_deg", "g4_min_deg",
                              "hub_chunk")}
 FAMILY.update({"pr_xcd": "pr", "pr_rows": "pr", "pr_lds_verts": "pr", "pr_grid": "pr", "bfs_lds_words": "bfs", "bfs_grid": "bfs",
+               "bfs_alpha": "bfs", "bfs_beta": "bfs",
                "bfs_lds_min_vblocks": "bfs", "sssp_delta": "sssp", "sssp_lds_verts": "sssp",
                "sssp_grid": "sssp"})
 

@@ -112,6 +112,7 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   TG_TRY(dalloc(arena, &bits_c, nwords));
   TG_TRY(dalloc(arena, &queue, n + 1));
   TG_TRY(dalloc(arena, &state, n + 1));
+  TG_TRY(dalloc(arena, &settled, n + 1));
   TG_TRY(dalloc(arena, &cbuf[0], n + 1));
   TG_TRY(dalloc(arena, &cbuf[1], n + 1));
   TG_TRY(dalloc(arena, &sigma, n + 1));
@@ -166,6 +167,9 @@ Tuning default_tuning() {
   t.sssp_grid = 2048;
   t.pr_xcd = 1;
   t.pr_rows = 512;
+  t.bfs_do = 1;
+  t.bfs_alpha = 14;
+  t.bfs_beta = 24;
   return t;
 }
 
@@ -202,6 +206,12 @@ int parse_tuning(const char *json, Tuning *t) {
   if (json_int(json, "sssp_grid", &v)) t->sssp_grid = v;
   if (json_int(json, "pr_xcd", &v)) t->pr_xcd = v;
   if (json_int(json, "pr_rows", &v)) t->pr_rows = v;
+  if (json_int(json, "bfs_do", &v)) t->bfs_do = v;
+  if (json_int(json, "bfs_alpha", &v)) t->bfs_alpha = v;
+  if (json_int(json, "bfs_beta", &v)) t->bfs_beta = v;
+  if (t->bfs_do != 0 && t->bfs_do != 1) return set_error(TG_EINVAL, "tuning: bfs_do must be 0 or 1");
+  if (t->bfs_alpha < 1 || t->bfs_alpha > 1000000 || t->bfs_beta < 1 || t->bfs_beta > 1000000)
+    return set_error(TG_EINVAL, "tuning: bfs_alpha and bfs_beta must be in [1, 10^6]");
   if (t->pr_xcd != 0 && t->pr_xcd != 1) return set_error(TG_EINVAL, "tuning: pr_xcd must be 0 or 1");
   if (t->pr_rows != 256 && t->pr_rows != 512) return set_error(TG_EINVAL, "tuning: pr_rows must be 256 or 512");
   if (t->sssp_delta < 0 || t->sssp_delta > INT32_MAX / 2) return set_error(TG_EINVAL, "tuning: sssp_delta outside [0, 2^30]");
@@ -649,13 +659,15 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            "],\"tuning\":{\"hub_min_deg\":%lld,\"block_min_deg\":%lld,\"wave_min_deg\":%lld,"
            "\"g16_min_deg\":%lld,\"g4_min_deg\":%lld,\"hub_chunk\":%lld,\"pr_lds_verts\":%lld,"
            "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld,"
-           "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld,\"pr_xcd\":%lld,\"pr_rows\":%lld}",
+           "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld,\"pr_xcd\":%lld,\"pr_rows\":%lld,"
+           "\"bfs_do\":%lld,\"bfs_alpha\":%lld,\"bfs_beta\":%lld}",
            (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
            (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk,
            (long long)p->tune.pr_lds_verts, (long long)p->tune.pr_grid, (long long)p->tune.bfs_lds_words,
            (long long)p->tune.bfs_grid, (long long)p->tune.bfs_lds_min_vblocks, (long long)p->tune.sssp_delta,
            (long long)p->tune.sssp_lds_verts, (long long)p->tune.sssp_grid, (long long)p->tune.pr_xcd,
-           (long long)p->tune.pr_rows);
+           (long long)p->tune.pr_rows, (long long)p->tune.bfs_do, (long long)p->tune.bfs_alpha,
+           (long long)p->tune.bfs_beta);
   s += buf;
   s += hybrid_info_json(p);
   s += "}";
@@ -705,12 +717,14 @@ extern "C" int bfs(const tg_partition *pc, const int32_t *roots, int32_t num_roo
     TG_TRY(collect_levels(p->gpu, p->ws.bits_a, p->ws.state, levels + (int64_t)r * V, s));
     if (parents) TG_TRY(bfs_parents(p->gpu, p->ws.bits_a, p->ws.state, l, parents + (int64_t)r * V, s));
   }
-  TG_HIP(hipMemcpyAsync(p->ws.h_work, p->ws.work, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  TG_HIP(hipMemcpyAsync(p->ws.h_work, p->ws.work, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   TG_HIP(hipStreamSynchronize(s));
   stats_add("roots", num_roots);
   stats_add("supersteps", (double)supersteps);
   stats_add("edges_scanned", (double)p->ws.h_work[0]);
   stats_add("vertices_expanded", (double)p->ws.h_work[1]);
+  stats_add("bottom_up_edges_checked", (double)p->ws.h_work[2]);
+  stats_add("bottom_up_steps", (double)p->ws.h_work[3]);
   ktimer_emit();
   return TG_OK;
 }

@@ -4,6 +4,13 @@
 // turns it into the next (sorted, degree-binned) queue and writes level L+1.
 // A superstep ends when the new frontier is empty (the termination vote of
 // section 4.1).
+//
+// Direction optimisation (the bottom-up step the paper's BFS leaves for
+// later work): when the frontier's edges outnumber the unexplored edges by a
+// factor (m_f > m_u / alpha), a superstep instead lets every unvisited vertex
+// look through its in-neighbours for one in the frontier bitmap and stop at
+// the first; it returns to top-down steps once the frontier is small again
+// (n_f < n / beta).  Both directions produce the same levels.
 #include <algorithm>
 
 #include "tg_internal.h"
@@ -14,6 +21,10 @@ namespace {
 
 __global__ void k_set_bit(uint32_t *bits, int32_t v) {
   if (threadIdx.x == 0) atomicOr(bits + (v >> 5), 1u << (v & 31));
+}
+
+__global__ void k_count_step(unsigned long long *c) {
+  if (threadIdx.x == 0) *c += 1ull;
 }
 
 // Test-then-set on the visited bitmap.  A plain load filters out neighbours
@@ -88,6 +99,64 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_expand(const Plan *__restrict__ P
   }
 }
 
+// Bottom-up step, one thread per vertex in [v0, v1): an unvisited vertex
+// looks at its in-neighbours four at a time and joins the next frontier at
+// the first one found in `fbits` (the level-L set).
+__global__ __launch_bounds__(BLOCK) void k_bfs_bottom_up_thread(const int64_t *__restrict__ ioff,
+                                                                const int32_t *__restrict__ icol,
+                                                                const uint32_t *__restrict__ fbits, uint32_t *visited,
+                                                                int64_t v0, int64_t v1, unsigned long long *work) {
+  unsigned long long checked = 0;
+  for (int64_t v = v0 + (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < v1; v += (int64_t)gridDim.x * BLOCK) {
+    const uint32_t bit = 1u << (v & 31);
+    if (visited[v >> 5] & bit) continue;
+    const int64_t e1 = ioff[v + 1];
+    for (int64_t e = ioff[v]; e < e1; e += 4) {
+      int32_t u[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) u[k] = icol[e + k < e1 ? e + k : e1 - 1];
+      bool hit = false;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) hit |= (e + k < e1) && ((fbits[u[k] >> 5] >> (u[k] & 31)) & 1u);
+      checked += (unsigned long long)(e1 - e < 4 ? e1 - e : 4);
+      if (hit) {
+        atomicOr(visited + (v >> 5), bit);
+        break;
+      }
+    }
+  }
+  checked = block_sum(checked);
+  if (threadIdx.x == 0 && checked) atomicAdd(work, checked);
+}
+
+// The same with one wave per vertex in [v0, v1) (high in-degree): the wave
+// checks 64 in-neighbours per round and stops at the first round with a hit.
+__global__ __launch_bounds__(BLOCK) void k_bfs_bottom_up_wave(const int64_t *__restrict__ ioff,
+                                                              const int32_t *__restrict__ icol,
+                                                              const uint32_t *__restrict__ fbits, uint32_t *visited,
+                                                              int64_t v0, int64_t v1, unsigned long long *work) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = ((int64_t)gridDim.x * BLOCK) >> 6;
+  unsigned long long checked = 0;
+  for (int64_t v = v0 + (((int64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6); v < v1; v += nw) {
+    const uint32_t bit = 1u << (v & 31);
+    if (visited[v >> 5] & bit) continue;
+    const int64_t e1 = ioff[v + 1];
+    for (int64_t e = ioff[v]; e < e1; e += 64) {
+      const bool live = e + lane < e1;
+      const int32_t u = live ? icol[e + lane] : 0;
+      const bool hit = live && ((fbits[u >> 5] >> (u & 31)) & 1u);
+      if (lane == 0) checked += (unsigned long long)(e1 - e < 64 ? e1 - e : 64);
+      if (__ballot(hit)) {
+        if (lane == 0) atomicOr(visited + (v >> 5), bit);
+        break;
+      }
+    }
+  }
+  checked = block_sum(checked);
+  if (threadIdx.x == 0 && checked) atomicAdd(work, checked);
+}
+
 }  // namespace
 
 namespace tg {
@@ -114,24 +183,72 @@ int bfs_expand_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int
   return TG_OK;
 }
 
+// One bottom-up step over the in-edges: vertices [0, wave_end) one wave each,
+// [wave_end, n_end) one thread each.
+static int bfs_bottom_up_launch(const GpuPart &g, Workspace &ws, const uint32_t *fbits, int64_t wave_end,
+                                int64_t n_end, hipStream_t s) {
+  const int tk = ktimer_start(s);
+  if (wave_end > 0) {
+    const int grid = (int)std::min<int64_t>((wave_end * 64 + BLOCK - 1) / BLOCK, 8192);
+    hipLaunchKernelGGL(k_bfs_bottom_up_wave, dim3(grid), dim3(BLOCK), 0, s, g.in.off, g.in.col, fbits, ws.bits_a,
+                       (int64_t)0, wave_end, ws.work + 2);
+  }
+  if (n_end > wave_end) {
+    const int grid = (int)std::min<int64_t>((n_end - wave_end + BLOCK - 1) / BLOCK, 16384);
+    hipLaunchKernelGGL(k_bfs_bottom_up_thread, dim3(grid), dim3(BLOCK), 0, s, g.in.off, g.in.col, fbits, ws.bits_a,
+                       wave_end, n_end, ws.work + 2);
+  }
+  ktimer_stop(tk, s, "bfs_bottom_up");
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
 // BFS from local vertex `root` over the GPU partition.  Leaves the visited
 // bitmap in ws.bits_a and levels in ws.state (valid where visited).
 int gpu_bfs(tg_partition *p, int32_t root, hipStream_t s, int64_t *levels_out) {
   GpuPart &g = p->gpu;
   Workspace &ws = p->ws;
+  const Tuning &t = p->tune;
   TG_TRY(ws.ensure(g, 0));
-  uint32_t *visited = ws.bits_a, *prev = ws.bits_b;
+  uint32_t *visited = ws.bits_a, *prev = ws.bits_b, *fbits = ws.bits_c;
   TG_HIP(hipMemsetAsync(visited, 0, ws.nwords * sizeof(uint32_t), s));
   TG_HIP(hipMemsetAsync(prev, 0, ws.nwords * sizeof(uint32_t), s));
   TG_TRY(set_bit(visited, root, s));
-  TG_TRY(frontier_compact(g, ws, 0, visited, prev, ws.queue, ws.state, 0, s));
+  unsigned long long *degsum = ws.work + 4;
+  TG_TRY(frontier_compact_bfs(g, ws, visited, prev, fbits, ws.queue, ws.state, 0, degsum, s));
+  // vertices with in-edges: a symmetric whole graph ends them at its
+  // degree-0 tail and has its in-degrees sorted, so its head (HUB and BLOCK
+  // bins) gets a wave per vertex; most vertices find a parent among their
+  // first few in-neighbours, so everything else takes a thread each
+  const int64_t n_end = g.in_alias ? g.out_bins.bstart[BIN_ZERO] : g.n;
+  const int64_t wave_end = g.in_alias ? g.out_bins.bstart[BIN_WAVE] : 0;
+  int64_t m_u = g.m;  // edges of vertices not yet in a frontier
+  bool bottom_up = false;
   int32_t L = 0;
   for (;; ++L) {
     if (L > g.n) return set_error(TG_EDEVICE, "bfs: more supersteps than vertices");
-    TG_TRY(frontier_plan(g, ws, ws.queue, p->tune, s, true));
-    if (ws.h_plan->count == 0) break;
-    TG_TRY(bfs_expand_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s));
-    TG_TRY(frontier_compact(g, ws, 0, visited, prev, ws.queue, ws.state, L + 1, s));
+    TG_TRY(frontier_plan(g, ws, ws.queue, t, s, false));
+    TG_HIP(hipMemcpyAsync(ws.h_plan, ws.plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
+    TG_HIP(hipMemcpyAsync(ws.h_work + 6, degsum, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    TG_HIP(hipStreamSynchronize(s));
+    ktimer_flush();
+    const int64_t n_f = ws.h_plan->count;
+    if (n_f == 0) break;
+    const int64_t m_f = (int64_t)ws.h_work[6];
+    m_u -= m_f;
+    if (t.bfs_do) {
+      // Beamer's switch: bottom-up while the frontier is heavy, back once it is small
+      if (!bottom_up && m_f > m_u / t.bfs_alpha) bottom_up = true;
+      else if (bottom_up && n_f < g.n / t.bfs_beta) bottom_up = false;
+    }
+    if (bottom_up) {
+      TG_TRY(bfs_bottom_up_launch(g, ws, fbits, wave_end, n_end, s));
+      hipLaunchKernelGGL(k_count_step, dim3(1), dim3(64), 0, s, ws.work + 3);
+      TG_HIP(hipGetLastError());
+    } else {
+      TG_TRY(bfs_expand_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], t, s));
+    }
+    TG_TRY(frontier_compact_bfs(g, ws, visited, prev, fbits, ws.queue, ws.state, L + 1, degsum, s));
   }
   if (levels_out) *levels_out = L;
   return TG_OK;

@@ -16,16 +16,22 @@ namespace {
 constexpr int WPT = 4;                     // bitmap words per thread
 constexpr int WPB = WPT * BLOCK;           // words per block (1024)
 
-// Distance filter (near set): keep only the set bits whose vertex has
-// dist < thresh; count and find the least distance of the rest.
-__device__ __forceinline__ uint32_t near_bits(uint32_t w, int64_t word, const int32_t *__restrict__ dist,
-                                              int32_t thresh, uint32_t &rest, int32_t &rest_min) {
+// SSSP filter over the set bits of one word.  With `settled` (the distance
+// each vertex had when it last relaxed its edges), a bit whose vertex has
+// dist >= settled is dropped: an attempt to lower it set the bit but found it
+// already as low.  Of the rest, bits with dist < thresh are kept (the near
+// set); the others are counted, with their least distance, and stay active.
+__device__ __forceinline__ uint32_t sssp_bits(uint32_t w, int64_t word, const int32_t *__restrict__ dist,
+                                              const int32_t *__restrict__ settled, int32_t thresh,
+                                              uint32_t &dropped, uint32_t &rest, int32_t &rest_min) {
   uint32_t keep = 0;
   while (w) {
     const int bit = __ffs(w) - 1;
     w &= w - 1;
-    const int32_t d = dist[word * 32 + bit];
-    if (d < thresh) keep |= 1u << bit;
+    const int64_t v = word * 32 + bit;
+    const int32_t d = dist[v];
+    if (settled && d >= settled[v]) dropped |= 1u << bit;
+    else if (d < thresh) keep |= 1u << bit;
     else {
       ++rest;
       rest_min = d < rest_min ? d : rest_min;
@@ -37,7 +43,8 @@ __device__ __forceinline__ uint32_t near_bits(uint32_t w, int64_t word, const in
 __global__ __launch_bounds__(BLOCK) void k_compact_count(const uint32_t *__restrict__ bits,
                                                          const uint32_t *__restrict__ prev,
                                                          uint32_t *__restrict__ bcount,
-                                                         const int32_t *__restrict__ dist, int32_t thresh,
+                                                         const int32_t *__restrict__ dist,
+                                                         const int32_t *__restrict__ settled, int32_t thresh,
                                                          unsigned long long *rest) {
   const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // uint4 index
   uint4 v = reinterpret_cast<const uint4 *>(bits)[q];
@@ -46,19 +53,21 @@ __global__ __launch_bounds__(BLOCK) void k_compact_count(const uint32_t *__restr
     v.x &= ~p.x; v.y &= ~p.y; v.z &= ~p.z; v.w &= ~p.w;
   }
   if (dist) {
-    uint32_t r = 0;
+    uint32_t r = 0, dropped = 0;
     int32_t rmin = TG_INF;
-    v.x = near_bits(v.x, q * 4 + 0, dist, thresh, r, rmin);
-    v.y = near_bits(v.y, q * 4 + 1, dist, thresh, r, rmin);
-    v.z = near_bits(v.z, q * 4 + 2, dist, thresh, r, rmin);
-    v.w = near_bits(v.w, q * 4 + 3, dist, thresh, r, rmin);
-    r = block_sum(r);
-    for (int o = 32; o > 0; o >>= 1) {
-      const int32_t y = __shfl_xor(rmin, o, 64);
-      rmin = y < rmin ? y : rmin;
+    v.x = sssp_bits(v.x, q * 4 + 0, dist, settled, thresh, dropped, r, rmin);
+    v.y = sssp_bits(v.y, q * 4 + 1, dist, settled, thresh, dropped, r, rmin);
+    v.z = sssp_bits(v.z, q * 4 + 2, dist, settled, thresh, dropped, r, rmin);
+    v.w = sssp_bits(v.w, q * 4 + 3, dist, settled, thresh, dropped, r, rmin);
+    if (rest) {
+      r = block_sum(r);
+      for (int o = 32; o > 0; o >>= 1) {
+        const int32_t y = __shfl_xor(rmin, o, 64);
+        rmin = y < rmin ? y : rmin;
+      }
+      if ((threadIdx.x & 63) == 0 && rmin < TG_INF) atomicMin(reinterpret_cast<int32_t *>(rest + 1), rmin);
+      if (threadIdx.x == 0 && r) atomicAdd(rest, (unsigned long long)r);
     }
-    if ((threadIdx.x & 63) == 0 && rmin < TG_INF) atomicMin(reinterpret_cast<int32_t *>(rest + 1), rmin);
-    if (threadIdx.x == 0 && r) atomicAdd(rest, (unsigned long long)r);
   }
   uint32_t c = __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
   c = block_sum(c);
@@ -70,7 +79,9 @@ __global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ 
                                                          int32_t *__restrict__ queue, int32_t *__restrict__ level,
                                                          int32_t level_value, BinBounds bb, int64_t n,
                                                          Plan *__restrict__ plan, const int32_t *__restrict__ dist,
-                                                         int32_t thresh) {
+                                                         int32_t *__restrict__ settled, int32_t thresh,
+                                                         uint32_t *__restrict__ fbits, const int64_t *__restrict__ off,
+                                                         unsigned long long *degsum) {
   // this block's offset: sum of the counts of all earlier blocks
   uint32_t part = 0;
   for (uint32_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) part += bcount[i];
@@ -84,12 +95,16 @@ __global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ 
     uint4 p = reinterpret_cast<uint4 *>(prev)[q];
     nw[0] &= ~p.x; nw[1] &= ~p.y; nw[2] &= ~p.z; nw[3] &= ~p.w;
     reinterpret_cast<uint4 *>(prev)[q] = v;  // prev := visited
+    if (fbits) reinterpret_cast<uint4 *>(fbits)[q] = make_uint4(nw[0], nw[1], nw[2], nw[3]);  // the new frontier
   } else if (mode == 3) {
-    // near set only: take the bits with dist < thresh, leave the rest active
+    // SSSP: take the bits with dist < thresh (and below their settled
+    // distance), drop the stale ones, leave the rest active
     uint32_t r = 0;
     int32_t rmin = TG_INF;
-    for (int k = 0; k < 4; ++k) nw[k] = near_bits(nw[k], q * 4 + k, dist, thresh, r, rmin);
-    reinterpret_cast<uint4 *>(bits)[q] = make_uint4(v.x & ~nw[0], v.y & ~nw[1], v.z & ~nw[2], v.w & ~nw[3]);
+    uint32_t dr[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k) nw[k] = sssp_bits(nw[k], q * 4 + k, dist, settled, thresh, dr[k], r, rmin);
+    reinterpret_cast<uint4 *>(bits)[q] =
+        make_uint4(v.x & ~(nw[0] | dr[0]), v.y & ~(nw[1] | dr[1]), v.z & ~(nw[2] | dr[2]), v.w & ~(nw[3] | dr[3]));
   } else {
     if (mode == 2) reinterpret_cast<uint4 *>(prev)[q] = v;  // prev := the set taken
     reinterpret_cast<uint4 *>(bits)[q] = make_uint4(0, 0, 0, 0);
@@ -111,6 +126,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ 
     }
   }
   uint32_t o = excl;
+  unsigned long long deg = 0;
 #pragma unroll
   for (int k = 0; k < WPT; ++k) {
     uint32_t w = nw[k];
@@ -119,8 +135,14 @@ __global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ 
       const int32_t vtx = (int32_t)((w0 + k) * 32 + bit);
       queue[o++] = vtx;
       if (level) level[vtx] = level_value;
+      if (settled) settled[vtx] = dist[vtx];  // the distance it relaxes with (at least)
+      if (degsum) deg += (unsigned long long)(off[vtx + 1] - off[vtx]);
       w &= w - 1;
     }
+  }
+  if (degsum) {
+    deg = block_sum(deg);
+    if (threadIdx.x == 0 && deg) atomicAdd(degsum, deg);
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == BLOCK - 1) plan->count = (int32_t)o;
 }
@@ -184,23 +206,39 @@ int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, 
                      int32_t *queue, int32_t *level, int32_t level_value, hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
   hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, bits,
-                     mode == 0 ? prev : nullptr, ws.bcount, nullptr, 0, nullptr);
+                     mode == 0 ? prev : nullptr, ws.bcount, nullptr, nullptr, 0, nullptr);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, bits, prev, mode,
-                     ws.bcount, queue, level, level_value, g.out_bins, g.n, ws.plan, nullptr, 0);
+                     ws.bcount, queue, level, level_value, g.out_bins, g.n, ws.plan, nullptr, nullptr, 0, nullptr,
+                     nullptr, nullptr);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
 
-int frontier_compact_near(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
-                          int32_t thresh, hipStream_t s) {
+int frontier_compact_bfs(const GpuPart &g, Workspace &ws, uint32_t *visited, uint32_t *prev, uint32_t *fbits,
+                         int32_t *queue, int32_t *level, int32_t level_value, unsigned long long *degsum,
+                         hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
-  // rest[0] = active vertices left behind, rest[1] (low word) = their least distance
-  const unsigned long long init[2] = {0ull, (unsigned long long)(uint32_t)TG_INF};
-  TG_HIP(hipMemcpyAsync(ws.rest, init, sizeof(init), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, bits, nullptr, ws.bcount, dist, thresh,
-                     ws.rest);
+  TG_HIP(hipMemsetAsync(degsum, 0, sizeof(unsigned long long), s));
+  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, visited, prev, ws.bcount, nullptr, nullptr, 0,
+                     nullptr);
+  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, visited, prev, 0, ws.bcount, queue, level,
+                     level_value, g.out_bins, g.n, ws.plan, nullptr, nullptr, 0, fbits, g.out.off, degsum);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
+                          int32_t *settled, int32_t thresh, bool near, hipStream_t s) {
+  const int blocks = (int)(ws.nwords / WPB);
+  if (near) {
+    // rest[0] = active vertices left behind, rest[1] (low word) = their least distance
+    const unsigned long long init[2] = {0ull, (unsigned long long)(uint32_t)TG_INF};
+    TG_HIP(hipMemcpyAsync(ws.rest, init, sizeof(init), hipMemcpyHostToDevice, s));
+  }
+  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, bits, nullptr, ws.bcount, dist, settled,
+                     near ? thresh : TG_INF, near ? ws.rest : nullptr);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, bits, nullptr, 3, ws.bcount, queue, nullptr,
-                     0, g.out_bins, g.n, ws.plan, dist, thresh);
+                     0, g.out_bins, g.n, ws.plan, dist, settled, near ? thresh : TG_INF, nullptr, nullptr, nullptr);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }

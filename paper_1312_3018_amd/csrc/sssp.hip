@@ -3,9 +3,12 @@
 // neighbour's distance; a neighbour whose distance dropped becomes active for
 // the next superstep.  The run ends when no vertex is active.
 //
-// Activation follows the returned previous value of the atomic minimum (the
-// neighbour is activated iff the minimum actually lowered it), so an update
-// is never lost to a concurrent writer.
+// The atomic minimum returns nothing, so a lane never waits on it: a lane
+// whose candidate beats the distance it read marks the neighbour active,
+// whether or not its own minimum was the one that won.  The compaction keeps
+// a marked vertex only if its distance is below the one it last relaxed with
+// (`settled`), so every real improvement is expanded exactly as with a
+// returned previous value, and stale marks are dropped.
 //
 // Distances are int32 with INT32_MAX meaning unreachable.  A candidate
 // distance >= INT32_MAX is never stored; the vertex is marked in an overflow
@@ -39,9 +42,9 @@ __device__ __forceinline__ void relax(int32_t *dist, int32_t *lds_d, int32_t hot
     return;
   }
   if (nd < (int64_t)cur) {
-    const int32_t old = atomicMin(dist + nb, (int32_t)nd);
+    atomicMin(dist + nb, (int32_t)nd);  // no return value: nothing waits on it
     if (nb < hot) atomicMin(lds_d + nb, (int32_t)nd);
-    if (nd < (int64_t)old) atomicOr(active + (nb >> 5), bit);
+    atomicOr(active + (nb >> 5), bit);
   }
 }
 
@@ -72,15 +75,21 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
     const int32_t dv = dist[a.v];
     const int64_t st = a.stride;
     int64_t e = a.e_begin + a.lane;
-    for (; e + st < a.e_end; e += 2 * st) {
-      const int32_t n0 = stream_load(col + e), n1 = stream_load(col + e + st);
-      const int32_t w0 = stream_load(wgt + e), w1 = stream_load(wgt + e + st);
-      const int32_t c0 = *dist_ptr(dist, lds_d, hot, n0);
-      const int32_t c1 = *dist_ptr(dist, lds_d, hot, n1);
-      relax(dist, lds_d, hot, active, ovf, flags, dv, n0, w0, c0);
-      relax(dist, lds_d, hot, active, ovf, flags, dv, n1, w1, c1);
+    // four edges per lane in flight: ids and weights, then the neighbours'
+    // distances, then the (non-returning) atomics
+    for (; e + 3 * st < a.e_end; e += 4 * st) {
+      int32_t nb[4], wt[4], cur[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        nb[k] = stream_load(col + e + k * st);
+        wt[k] = stream_load(wgt + e + k * st);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) cur[k] = *dist_ptr(dist, lds_d, hot, nb[k]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) relax(dist, lds_d, hot, active, ovf, flags, dv, nb[k], wt[k], cur[k]);
     }
-    if (e < a.e_end) {
+    for (; e < a.e_end; e += st) {
       const int32_t n0 = stream_load(col + e);
       relax(dist, lds_d, hot, active, ovf, flags, dv, n0, stream_load(wgt + e), *dist_ptr(dist, lds_d, hot, n0));
     }
@@ -143,6 +152,7 @@ int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) 
   uint32_t *active = ws.bits_a, *ovf = ws.bits_c;
   int32_t *dist = ws.state;
   TG_TRY(fill_i32(dist, g.n, TG_INF, s));
+  TG_TRY(fill_i32(ws.settled, g.n, TG_INF, s));
   hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, s, dist, (int64_t)root, 0);
   TG_HIP(hipMemsetAsync(active, 0, ws.nwords * sizeof(uint32_t), s));
   TG_HIP(hipMemsetAsync(ovf, 0, ws.nwords * sizeof(uint32_t), s));
@@ -155,11 +165,12 @@ int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) 
     // a frontier Bellman-Ford settles within |V| - 1 rounds (per threshold step)
     if (rounds > 2 * g.n + 2) return set_error(TG_EDEVICE, "sssp: no convergence after %lld rounds", (long long)rounds);
     if (delta <= 0) {
-      TG_TRY(frontier_compact(g, ws, 1, active, nullptr, ws.queue, nullptr, 0, s));
+      TG_TRY(frontier_compact_sssp(g, ws, active, ws.queue, dist, ws.settled, TG_INF, false, s));
       TG_TRY(frontier_plan(g, ws, ws.queue, p->tune, s, true));
       if (ws.h_plan->count == 0) break;
     } else {
-      TG_TRY(frontier_compact_near(g, ws, active, ws.queue, dist, (int32_t)std::min<int64_t>(thresh, TG_INF), s));
+      TG_TRY(frontier_compact_sssp(g, ws, active, ws.queue, dist, ws.settled,
+                                   (int32_t)std::min<int64_t>(thresh, TG_INF), true, s));
       TG_HIP(hipMemcpyAsync(ws.h_work + 4, ws.rest, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
       TG_TRY(frontier_plan(g, ws, ws.queue, p->tune, s, true));
       if (ws.h_plan->count == 0) {

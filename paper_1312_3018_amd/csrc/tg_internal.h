@@ -66,6 +66,8 @@ struct Tuning {
   int64_t sssp_grid;             // SSSP: blocks per launch when snapshotting
   int64_t pr_xcd;                // PageRank: 1 = gather split by source class per XCD
   int64_t pr_rows;               // PageRank: edges per row block (one wave's block)
+  int64_t bfs_do;                // BFS: 1 = switch to bottom-up steps on large frontiers
+  int64_t bfs_alpha, bfs_beta;   // BFS: top-down -> bottom-up when m_f > m_u / alpha; back when n_f < n / beta
 };
 Tuning default_tuning();
 int parse_tuning(const char *json, Tuning *t);
@@ -219,6 +221,7 @@ struct Workspace {
   uint32_t *bits_a = nullptr, *bits_b = nullptr, *bits_c = nullptr;
   int32_t *queue = nullptr;      // n entries (BC: all levels back to back)
   int32_t *state = nullptr;      // levels / distances (n)
+  int32_t *settled = nullptr;    // SSSP: distance each vertex last relaxed with (n)
   float *cbuf[2] = {nullptr, nullptr};
   double *sigma = nullptr;       // BC path counts (n)
   float *delta = nullptr;        // BC dependencies (n)
@@ -281,10 +284,17 @@ int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, 
 // hub chunk prefix, then copy the plan to ws.h_plan and wait for it.
 int frontier_plan(const GpuPart &g, Workspace &ws, const int32_t *queue, const Tuning &t,
                   hipStream_t s, bool sync);
-// Active-set compaction restricted to vertices with dist < thresh (the rest
-// stay active); ws.rest gets the count and least distance of the rest.
-int frontier_compact_near(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
-                          int32_t thresh, hipStream_t s);
+// BFS compaction (mode 0) that also writes the new frontier as a bitmap into
+// `fbits` and adds the frontier's out-degree sum into *degsum (zeroed first).
+int frontier_compact_bfs(const GpuPart &g, Workspace &ws, uint32_t *visited, uint32_t *prev, uint32_t *fbits,
+                         int32_t *queue, int32_t *level, int32_t level_value, unsigned long long *degsum,
+                         hipStream_t s);
+// SSSP compaction of the active bitmap: a vertex is taken if dist < settled
+// (it really got lower since it last relaxed; settled := dist when taken) and,
+// with `near`, dist < thresh; stale bits are dropped; with `near` the others
+// stay active and ws.rest gets their count and least distance.
+int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
+                          int32_t *settled, int32_t thresh, bool near, hipStream_t s);
 // As frontier_plan, with hub chunks sized by the degrees in `off`; with
 // include_zero, frontier vertices of out-degree 0 get virtual blocks too
 // (a pull over in-edges must visit them).

@@ -172,6 +172,32 @@ def test_pagerank_variants(gpu, rmat14, xcd, rows):
             assert np.array_equal(again, rank)  # deterministic
 
 
+DO_VARIANTS = [{"bfs_do": 0},                                   # top-down only
+               {"bfs_alpha": 1000000, "bfs_beta": 1000000},     # bottom-up from the second step on
+               {"bfs_alpha": 1000000, "bfs_beta": 1},           # alternate bottom-up and top-down
+               {}]                                              # the default switch
+
+
+@pytest.mark.parametrize("tuning", DO_VARIANTS)
+def test_bfs_direction_optimizing(gpu, rmat14, tuning):
+    """Bottom-up steps give the same levels as top-down ones, on a symmetric
+    graph (wave and thread bottom-up kernels), a directed one (in-edges) and
+    graphs with isolated and unreachable vertices."""
+    g, _ = rmat14
+    cases = [(g, [graphgen.max_degree_vertex(g)] + graphgen.sample_roots(g, 3, seed=11).tolist())]
+    gd = graphgen.rmat(12, symmetrize=False)
+    cases.append((gd, graphgen.sample_roots(gd, 3, seed=12).tolist()))
+    gp = graphgen.from_edges(9, [0, 1, 2, 5, 6], [1, 2, 3, 6, 7], symmetrize=True)
+    cases.append((gp, [0, 4, 5]))
+    gs = graphgen.from_edges(3001, np.zeros(3000, dtype=int), np.arange(1, 3001), symmetrize=True)
+    cases.append((gs, [0, 7]))
+    for graph, roots in cases:
+        P = load(gpu, graph, None, tuning)
+        lev = gpu.bfs(P, roots).cpu().numpy()
+        for i, r in enumerate(roots):
+            assert np.array_equal(lev[i], oracle.bfs(graph.offsets, graph.cols, r)), (tuning, graph.n, r)
+
+
 # ------------------------------------------------------------------ edges
 
 def test_degenerate_graphs(gpu):
