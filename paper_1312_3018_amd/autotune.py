@@ -23,7 +23,7 @@ DEFAULTS = {
     "hub_min_deg": 8192, "block_min_deg": 512, "wave_min_deg": 48, "g16_min_deg": 12, "g4_min_deg": 3,
     "hub_chunk": 4096, "pr_lds_verts": 40960, "pr_grid": 256, "bfs_lds_words": 4096, "bfs_grid": 2048,
     "bfs_lds_min_vblocks": 4096, "sssp_delta": 0, "sssp_lds_verts": 0, "sssp_grid": 2048, "pr_xcd": 1,
-    "pr_rows": 512, "bfs_do": 1, "bfs_alpha": 14, "bfs_beta": 24,
+    "pr_rows": 512, "bfs_do": 1, "bfs_alpha": 14, "bfs_beta": 24, "sssp_xcd": 0,
 }
 
 SPACE = {
@@ -45,6 +45,7 @@ SPACE = {
     "sssp_delta": [0, 64, 128, 256, 512, 1024, 4096],
     "sssp_lds_verts": [0, 2048, 4096, 8192],
     "sssp_grid": [1024, 2048, 4096, 16384],
+    "sssp_xcd": [0, 1],
 }
 
 FAMILY = {k: "all" for k in ("hub_min_deg", "block_min_deg", "wave_min_deg", "g16_min_deg", "g4_min_deg",
@@ -52,7 +53,7 @@ FAMILY = {k: "all" for k in ("hub_min_deg", "block_min_deg", "wave_min_deg", "g1
 FAMILY.update({"pr_xcd": "pr", "pr_rows": "pr", "pr_lds_verts": "pr", "pr_grid": "pr", "bfs_lds_words": "bfs", "bfs_grid": "bfs",
                "bfs_alpha": "bfs", "bfs_beta": "bfs",
                "bfs_lds_min_vblocks": "bfs", "sssp_delta": "sssp", "sssp_lds_verts": "sssp",
-               "sssp_grid": "sssp"})
+               "sssp_grid": "sssp", "sssp_xcd": "sssp"})
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 

@@ -127,7 +127,6 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   TG_TRY(dalloc(arena, &hub_partials, chunks));
   const int64_t hubs = hubs_needed;
   hubs_cap = hubs;
-  TG_TRY(dalloc(arena, &hub_counters, hubs));
   TG_TRY(dalloc(arena, &hubpref, hubs + 1));
   TG_TRY(dalloc(arena, &scalars, 16));
   TG_TRY(dalloc(arena, &counters, 64));
@@ -138,7 +137,6 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   TG_HIP(hipMemset(bits_a, 0, nwords * sizeof(uint32_t)));
   TG_HIP(hipMemset(bits_b, 0, nwords * sizeof(uint32_t)));
   TG_HIP(hipMemset(bits_c, 0, nwords * sizeof(uint32_t)));
-  TG_HIP(hipMemset(hub_counters, 0, hubs * sizeof(uint32_t)));
   TG_HIP(hipMemset(counters, 0, 64 * sizeof(uint32_t)));
   TG_HIP(hipMemset(work, 0, 8 * sizeof(unsigned long long)));
   if (!h_plan) TG_HIP(hipHostMalloc((void **)&h_plan, sizeof(Plan), hipHostMallocDefault));
@@ -170,6 +168,7 @@ Tuning default_tuning() {
   t.bfs_do = 1;
   t.bfs_alpha = 14;
   t.bfs_beta = 24;
+  t.sssp_xcd = 0;  // measured slower than the plain relax (8 x the per-vertex work)
   return t;
 }
 
@@ -209,6 +208,8 @@ int parse_tuning(const char *json, Tuning *t) {
   if (json_int(json, "bfs_do", &v)) t->bfs_do = v;
   if (json_int(json, "bfs_alpha", &v)) t->bfs_alpha = v;
   if (json_int(json, "bfs_beta", &v)) t->bfs_beta = v;
+  if (json_int(json, "sssp_xcd", &v)) t->sssp_xcd = v;
+  if (t->sssp_xcd != 0 && t->sssp_xcd != 1) return set_error(TG_EINVAL, "tuning: sssp_xcd must be 0 or 1");
   if (t->bfs_do != 0 && t->bfs_do != 1) return set_error(TG_EINVAL, "tuning: bfs_do must be 0 or 1");
   if (t->bfs_alpha < 1 || t->bfs_alpha > 1000000 || t->bfs_beta < 1 || t->bfs_beta > 1000000)
     return set_error(TG_EINVAL, "tuning: bfs_alpha and bfs_beta must be in [1, 10^6]");
@@ -614,6 +615,7 @@ extern "C" void partition_free(tg_partition *p) {
   bcb_free(p);
   pr_slices_free(p->gpu);
   pr_rows_free(p->gpu);
+  sssp_slices_free(p->gpu);
   delete p;
 }
 
@@ -660,14 +662,14 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            "\"g16_min_deg\":%lld,\"g4_min_deg\":%lld,\"hub_chunk\":%lld,\"pr_lds_verts\":%lld,"
            "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld,"
            "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld,\"pr_xcd\":%lld,\"pr_rows\":%lld,"
-           "\"bfs_do\":%lld,\"bfs_alpha\":%lld,\"bfs_beta\":%lld}",
+           "\"bfs_do\":%lld,\"bfs_alpha\":%lld,\"bfs_beta\":%lld,\"sssp_xcd\":%lld}",
            (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
            (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk,
            (long long)p->tune.pr_lds_verts, (long long)p->tune.pr_grid, (long long)p->tune.bfs_lds_words,
            (long long)p->tune.bfs_grid, (long long)p->tune.bfs_lds_min_vblocks, (long long)p->tune.sssp_delta,
            (long long)p->tune.sssp_lds_verts, (long long)p->tune.sssp_grid, (long long)p->tune.pr_xcd,
            (long long)p->tune.pr_rows, (long long)p->tune.bfs_do, (long long)p->tune.bfs_alpha,
-           (long long)p->tune.bfs_beta);
+           (long long)p->tune.bfs_beta, (long long)p->tune.sssp_xcd);
   s += buf;
   s += hybrid_info_json(p);
   s += "}";

@@ -102,8 +102,9 @@ int gpu_bc_source(tg_partition *p, int32_t src, hipStream_t s) {
     }
     SigmaPull op{{}, g.in.col, level, ws.sigma, ws.sigma, ws.counters, L};
     hipLaunchKernelGGL(k_gather<SigmaPull>, dim3(launch_grid(vbs)), dim3(BLOCK), 0, s, ws.plan,
-                       ws.queue + noff, ws.hubpref, g.in.off, t.hub_chunk, ws.hub_partials,
-                       ws.hub_counters, op);
+                       ws.queue + noff, ws.hubpref, g.in.off, t.hub_chunk, ws.hub_partials, op);
+    hipLaunchKernelGGL(k_gather_hubs<SigmaPull>, dim3(64), dim3(BLOCK), 0, s, ws.plan, ws.queue + noff, ws.hubpref,
+                       ws.hub_partials, op);
     TG_HIP(hipGetLastError());
     if (!g.in_alias) {
       // restore the out-degree plan for the next expansion
@@ -118,8 +119,9 @@ int gpu_bc_source(tg_partition *p, int32_t src, hipStream_t s) {
     TG_TRY(frontier_plan_off(g, ws, ws.queue + segoff[lv], g.out.off, t, s, false));
     DeltaAccum op{{}, g.out.col, level, ws.sigma, ws.delta, ws.bc_acc, lv + 1};
     hipLaunchKernelGGL(k_gather<DeltaAccum>, dim3(launch_grid(plans[lv].vb[NBIN])), dim3(BLOCK), 0, s,
-                       ws.plan, ws.queue + segoff[lv], ws.hubpref, g.out.off, t.hub_chunk,
-                       ws.hub_partials, ws.hub_counters, op);
+                       ws.plan, ws.queue + segoff[lv], ws.hubpref, g.out.off, t.hub_chunk, ws.hub_partials, op);
+    hipLaunchKernelGGL(k_gather_hubs<DeltaAccum>, dim3(64), dim3(BLOCK), 0, s, ws.plan, ws.queue + segoff[lv],
+                       ws.hubpref, ws.hub_partials, op);
     TG_HIP(hipGetLastError());
   }
   return TG_OK;

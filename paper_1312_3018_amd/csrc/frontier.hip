@@ -151,7 +151,8 @@ __global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ 
 __global__ __launch_bounds__(BLOCK) void k_plan(Plan *__restrict__ plan, BinBounds bb, int64_t n,
                                                 const int32_t *__restrict__ queue,
                                                 const int64_t *__restrict__ off, int64_t hub_chunk,
-                                                int64_t *__restrict__ hubpref, int include_zero) {
+                                                int64_t *__restrict__ hubpref, int include_zero,
+                                                const int32_t *__restrict__ len) {
   __shared__ int32_t pos[NBIN + 1];
   const int32_t count = plan->count;
   if (threadIdx.x <= NBIN) {
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(BLOCK) void k_plan(Plan *__restrict__ plan, BinBoun
     uint32_t c = 0;
     if (i < nh) {
       const int32_t v = queue ? queue[pos[0] + i] : pos[0] + i;
-      const int64_t d = off[v + 1] - off[v];
+      const int64_t d = len ? (int64_t)len[v] : off[v + 1] - off[v];  // edges to chunk
       c = (uint32_t)((d + hub_chunk - 1) / hub_chunk);
     }
     uint32_t tot;
@@ -228,7 +229,7 @@ int frontier_compact_bfs(const GpuPart &g, Workspace &ws, uint32_t *visited, uin
 }
 
 int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
-                          int32_t *settled, int32_t thresh, bool near, hipStream_t s) {
+                          int32_t *settled, int32_t thresh, bool near, const BinBounds &bb, hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
   if (near) {
     // rest[0] = active vertices left behind, rest[1] (low word) = their least distance
@@ -238,8 +239,21 @@ int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32
   hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, bits, nullptr, ws.bcount, dist, settled,
                      near ? thresh : TG_INF, near ? ws.rest : nullptr);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, bits, nullptr, 3, ws.bcount, queue, nullptr,
-                     0, g.out_bins, g.n, ws.plan, dist, settled, near ? thresh : TG_INF, nullptr, nullptr, nullptr);
+                     0, bb, g.n, ws.plan, dist, settled, near ? thresh : TG_INF, nullptr, nullptr, nullptr);
   TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int frontier_plan_bins(const GpuPart &g, Workspace &ws, const int32_t *queue, const BinBounds &bb,
+                       const int32_t *len, const Tuning &t, hipStream_t s, bool sync) {
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(BLOCK), 0, s, ws.plan, bb, g.n, queue, g.out.off, t.hub_chunk,
+                     ws.hubpref, 0, len);
+  TG_HIP(hipGetLastError());
+  if (sync) {
+    TG_HIP(hipMemcpyAsync(ws.h_plan, ws.plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
+    TG_HIP(hipStreamSynchronize(s));
+    ktimer_flush();
+  }
   return TG_OK;
 }
 
@@ -251,7 +265,7 @@ int frontier_plan(const GpuPart &g, Workspace &ws, const int32_t *queue, const T
 int frontier_plan_off(const GpuPart &g, Workspace &ws, const int32_t *queue, const int64_t *off,
                       const Tuning &t, hipStream_t s, bool sync, bool include_zero) {
   hipLaunchKernelGGL(k_plan, dim3(1), dim3(BLOCK), 0, s, ws.plan, g.out_bins, g.n, queue,
-                     off, t.hub_chunk, ws.hubpref, include_zero ? 1 : 0);
+                     off, t.hub_chunk, ws.hubpref, include_zero ? 1 : 0, nullptr);
   TG_HIP(hipGetLastError());
   if (sync) {
     TG_HIP(hipMemcpyAsync(ws.h_plan, ws.plan, sizeof(Plan), hipMemcpyDeviceToHost, s));

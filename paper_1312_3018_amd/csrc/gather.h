@@ -3,10 +3,13 @@
 // once, where vs = op.vstate(v) is loaded once per row.  The reduction is
 // op.combine (associative, commutative) with identity op.identity().
 //
-// Hub rows are split into chunks of `hub_chunk` edges; the last chunk block
-// of a hub to finish combines the chunk partials in chunk order, so the result
-// does not depend on scheduling.  Used for the BC sigma pull and delta
-// accumulation and for the atomic-free outbox reductions of the hybrid split.
+// Hub rows are split into chunks of `hub_chunk` edges, one block each; a chunk
+// block stores its partial and a second launch (k_gather_hubs, one wave per
+// hub) combines each hub's partials with a fixed reduction tree, so the
+// result does not depend on scheduling.  (A "last block to finish combines"
+// scheme would need device-scope fences, which write back and invalidate the
+// XCD's L2 on this part.)  Used for the BC sigma pull and delta accumulation
+// and for the atomic-free outbox reductions of the hybrid split.
 #pragma once
 #include "kcommon.h"
 
@@ -43,9 +46,8 @@ template <class Op>
 __global__ __launch_bounds__(BLOCK) void k_gather(const Plan *__restrict__ Pp, const int32_t *__restrict__ queue,
                                                   const int64_t *__restrict__ hubpref,
                                                   const int64_t *__restrict__ off, int64_t hub_chunk,
-                                                  typename Op::T *hub_partials, uint32_t *hub_counters, Op op) {
+                                                  typename Op::T *hub_partials, Op op) {
   using T = typename Op::T;
-  __shared__ int s_last;
   const Plan &P = load_plan(Pp);
   const int64_t total = P.vb[NBIN];
   for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
@@ -57,29 +59,30 @@ __global__ __launch_bounds__(BLOCK) void k_gather(const Plan *__restrict__ Pp, c
     }
     if (a.bin == BIN_HUB) {
       s = block_reduce(s, op);
-      const int32_t hi = a.qi - P.pos[0];
-      if (threadIdx.x == 0) {
-        hub_partials[a.chunk] = s;
-        __threadfence();
-        const uint32_t nchunks = (uint32_t)(hubpref[hi + 1] - hubpref[hi]);
-        const uint32_t prev = atomicAdd(hub_counters + hi, 1u);
-        s_last = (prev == nchunks - 1) ? 1 : 0;
-      }
-      __syncthreads();
-      if (s_last && threadIdx.x == 0) {
-        __threadfence();
-        T tot = op.identity();
-        for (int64_t k = hubpref[hi]; k < hubpref[hi + 1]; ++k)
-          tot = op.combine(tot, __hip_atomic_load(hub_partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        op.finish(a.v, tot);
-        hub_counters[hi] = 0u;
-      }
-      __syncthreads();
+      if (threadIdx.x == 0) hub_partials[a.chunk] = s;  // finished by k_gather_hubs
       continue;
     }
     if (a.bin == BIN_BLOCK) s = block_reduce(s, op);
     else s = group_reduce(s, a.stride, op);
     if (a.ok && a.lane == 0) op.finish(a.v, s);
+  }
+}
+
+// One wave per hub of the plan: combine its chunk partials (lane-strided,
+// then a fixed butterfly) and finish the row.
+template <class Op>
+__global__ __launch_bounds__(BLOCK) void k_gather_hubs(const Plan *__restrict__ Pp, const int32_t *__restrict__ queue,
+                                                       const int64_t *__restrict__ hubpref,
+                                                       const typename Op::T *__restrict__ hub_partials, Op op) {
+  using T = typename Op::T;
+  const int32_t p0 = Pp->pos[0], nh = Pp->pos[1] - p0;
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = ((int64_t)gridDim.x * BLOCK) >> 6;
+  for (int64_t i = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6; i < nh; i += nw) {
+    T s = op.identity();
+    for (int64_t c = hubpref[i] + lane; c < hubpref[i + 1]; c += 64) s = op.combine(s, hub_partials[c]);
+    s = group_reduce(s, 64, op);
+    if (lane == 0) op.finish(queue ? queue[p0 + i] : p0 + (int32_t)i, s);
   }
 }
 

@@ -65,7 +65,6 @@ struct HybridState {
   int64_t *d_shubpref = nullptr;
   double *d_shub_partials_f = nullptr;
   int64_t *d_shub_partials_i = nullptr;
-  uint32_t *d_shub_counters = nullptr;
   // messages
   int64_t *d_out_i = nullptr;   // GPU outbox (int64: level or distance)
   double *d_out_f = nullptr;    // GPU outbox (PageRank sums)
@@ -280,8 +279,6 @@ int build_hybrid(tg_partition *p, uint64_t seed) {
     TG_TRY(up(A, &hy->d_splan, &P, 1));
     TG_TRY(dalloc(A, &hy->d_shub_partials_f, (size_t)hubpref[nh] + 1));
     TG_TRY(dalloc(A, &hy->d_shub_partials_i, (size_t)hubpref[nh] + 1));
-    TG_TRY(dalloc(A, &hy->d_shub_counters, (size_t)nh + 1));
-    TG_HIP(hipMemset(hy->d_shub_counters, 0, ((size_t)nh + 1) * sizeof(uint32_t)));
   }
   const size_t no = (size_t)std::max<int64_t>(o.nslots, 1), ni = (size_t)std::max<int64_t>(hy->c2g.nslots, 1);
   TG_TRY(dalloc(A, &hy->d_out_i, no));
@@ -431,7 +428,10 @@ template <class Op>
 int launch_outbox(HybridState &h, const Tuning &t, hipStream_t s, Op op, typename Op::T *partials) {
   if (h.g2c.nslots == 0) return TG_OK;
   hipLaunchKernelGGL(k_gather<Op>, dim3(launch_grid(h.h_splan.vb[NBIN])), dim3(BLOCK), 0, s, h.d_splan,
-                     h.d_slot_order, h.d_shubpref, h.d_roff, t.hub_chunk, partials, h.d_shub_counters, op);
+                     h.d_slot_order, h.d_shubpref, h.d_roff, t.hub_chunk, partials, op);
+  if (h.h_splan.pos[1] > h.h_splan.pos[0])
+    hipLaunchKernelGGL(k_gather_hubs<Op>, dim3(64), dim3(BLOCK), 0, s, h.d_splan, h.d_slot_order, h.d_shubpref,
+                       partials, op);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }

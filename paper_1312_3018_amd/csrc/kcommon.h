@@ -88,9 +88,11 @@ __device__ __forceinline__ int segment_of(int64_t vb, const Plan &P) {
 
 // Map virtual block `vb` to this thread's work.  `queue == nullptr` means the
 // identity frontier (every vertex, in id order) optionally through `order`.
-__device__ __forceinline__ Assign assign_work(int64_t vb, const Plan &P, const int32_t *queue,
-                                              const int32_t *order, const int64_t *hubpref,
-                                              const int64_t *off, int64_t hub_chunk) {
+// `row(i)` returns the offset of row i (rows v and v+1 bound vertex v's edges).
+template <typename RowF>
+__device__ __forceinline__ Assign assign_work_rows(int64_t vb, const Plan &P, const int32_t *queue,
+                                                   const int32_t *order, const int64_t *hubpref, RowF row,
+                                                   int64_t hub_chunk) {
   Assign a;
   a.ok = false;
   a.chunk = -1;
@@ -109,8 +111,8 @@ __device__ __forceinline__ Assign assign_work(int64_t vb, const Plan &P, const i
     qi = P.pos[0] + lo;
     int32_t v = queue ? queue[qi] : (order ? order[qi] : qi);
     int64_t k = local - hubpref[lo];
-    a.e_begin = stream_load(off + v) + k * hub_chunk;
-    int64_t end = stream_load(off + v + 1);
+    a.e_begin = row(v) + k * hub_chunk;
+    int64_t end = row(v + 1);
     a.e_end = (a.e_begin + hub_chunk < end) ? a.e_begin + hub_chunk : end;
     a.v = v;
     a.qi = qi;
@@ -129,11 +131,18 @@ __device__ __forceinline__ Assign assign_work(int64_t vb, const Plan &P, const i
   if (qi < P.pos[b + 1]) {
     int32_t v = queue ? stream_load(queue + qi) : (order ? stream_load(order + qi) : qi);
     a.v = v;
-    a.e_begin = stream_load(off + v);
-    a.e_end = stream_load(off + v + 1);
+    a.e_begin = row(v);
+    a.e_end = row(v + 1);
     a.ok = true;
   }
   return a;
+}
+
+__device__ __forceinline__ Assign assign_work(int64_t vb, const Plan &P, const int32_t *queue,
+                                              const int32_t *order, const int64_t *hubpref,
+                                              const int64_t *off, int64_t hub_chunk) {
+  return assign_work_rows(vb, P, queue, order, hubpref, [off](int64_t i) { return stream_load(off + i); },
+                          hub_chunk);
 }
 
 // ------------------------------------------------------------ reductions

@@ -27,61 +27,6 @@ namespace {
 constexpr int NS = 8;     // source classes = XCDs
 constexpr int LINE = 32;  // contributions per 128-byte cache line
 
-__host__ __device__ __forceinline__ int class_of(int32_t u) { return (u >> 5) & (NS - 1); }
-
-struct SliceArgs {
-  int64_t base[NS];  // first edge of class k in scol
-};
-
-// Row of destination v in class k: [base[k] + soff[k][v], base[k] + soff[k][v+1]).
-// Both set-up kernels take one wave per destination; the wave walks the row
-// 64 edges at a time and counts (or places) each class with a ballot, so the
-// sources keep their ascending order within each class.
-__global__ __launch_bounds__(BLOCK) void k_slice_count(const int64_t *__restrict__ ioff, const int32_t *__restrict__ icol,
-                                                       int64_t n, int32_t *__restrict__ cnt) {
-  const int lane = threadIdx.x & 63;
-  const int64_t nw = ((int64_t)gridDim.x * BLOCK) >> 6;
-  for (int64_t v = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6; v < n; v += nw) {
-    const int64_t e0 = ioff[v], e1 = ioff[v + 1];
-    int32_t mine = 0;  // lane j < 8 keeps the count of class j
-    for (int64_t e = e0; e < e1; e += 64) {
-      const int k = e + lane < e1 ? class_of(icol[e + lane]) : -1;
-#pragma unroll
-      for (int j = 0; j < NS; ++j) {
-        const int c = __popcll(__ballot(k == j));
-        if (lane == j) mine += c;
-      }
-    }
-    if (lane < NS) cnt[(int64_t)lane * n + v] = mine;
-  }
-}
-
-__global__ __launch_bounds__(BLOCK) void k_slice_fill(const int64_t *__restrict__ ioff, const int32_t *__restrict__ icol,
-                                                      int64_t n, const int32_t *__restrict__ soff, SliceArgs sa,
-                                                      int32_t *__restrict__ scol) {
-  const int lane = threadIdx.x & 63;
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes under this one
-  const int64_t nw = ((int64_t)gridDim.x * BLOCK) >> 6;
-  for (int64_t v = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6; v < n; v += nw) {
-    const int64_t e0 = ioff[v], e1 = ioff[v + 1];
-    int64_t pos = lane < NS ? sa.base[lane] + soff[(int64_t)lane * (n + 1) + v] : 0;  // lane j: next slot of class j
-    for (int64_t e = e0; e < e1; e += 64) {
-      const bool live = e + lane < e1;
-      const int32_t u = live ? icol[e + lane] : 0;
-      const int k = live ? class_of(u) : -1;
-      int64_t dst = 0;
-#pragma unroll
-      for (int j = 0; j < NS; ++j) {
-        const uint64_t m = __ballot(k == j);
-        const int64_t pj = __shfl(pos, j, 64);
-        if (k == j) dst = pj + __popcll(m & below);
-        if (lane == j) pos += __popcll(m);
-      }
-      if (live) scol[dst] = u;
-    }
-  }
-}
-
 struct CombineParams {
   double base, d, inv_n, iso_count;
   int32_t drop, last;
@@ -119,9 +64,8 @@ __global__ __launch_bounds__(BLOCK) void k_pr_combine(CombineParams prm, const f
 
 struct PrSlices {
   DevArena arena;
-  int32_t *soff = nullptr, *scol = nullptr;
+  ClassCsr cc;              // in-edges by source class
   float *ps = nullptr;      // partial sums, class k at ps + k * n
-  SliceArgs sa{};
   RowsDev rows;             // per-class row blocks
   int64_t rb_base[NS] = {}, nb[NS] = {};
   int64_t nrows = 0;
@@ -144,41 +88,8 @@ static int build_slices(tg_partition *p, hipStream_t s) {
   if (!g.slices) return set_error(TG_ENOMEM, "pagerank: out of host memory");
   PrSlices &S = *g.slices;
   const int64_t n = g.n, m = g.in.m;
-  if (m >= ((int64_t)1 << 31) * NS / 2)
-    return set_error(TG_EUNSUPPORTED, "pagerank: too many edges for the sliced gather");
-  int32_t *cnt = nullptr;
-  TG_TRY(dalloc(S.arena, &cnt, (size_t)NS * n));
-  const unsigned grid = (unsigned)std::min<int64_t>((n * 64 + BLOCK - 1) / BLOCK, 8192);  // a wave per row
-  hipLaunchKernelGGL(k_slice_count, dim3(std::max(grid, 1u)), dim3(BLOCK), 0, s, g.in.off, g.in.col, n, cnt);
-  TG_HIP(hipGetLastError());
-  std::vector<int32_t> hc((size_t)NS * n);
-  TG_HIP(hipMemcpyAsync(hc.data(), cnt, hc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  TG_HIP(hipStreamSynchronize(s));
-  std::vector<int32_t> hsoff((size_t)NS * (n + 1));
-  int64_t tot[NS];
-#pragma omp parallel for schedule(static, 1)
-  for (int k = 0; k < NS; ++k) {
-    int64_t acc = 0;
-    for (int64_t v = 0; v < n; ++v) {
-      hsoff[(size_t)k * (n + 1) + v] = (int32_t)acc;
-      acc += hc[(size_t)k * n + v];
-    }
-    hsoff[(size_t)k * (n + 1) + n] = (int32_t)acc;
-    tot[k] = acc;
-  }
-  int64_t base = 0;
-  for (int k = 0; k < NS; ++k) {
-    if (tot[k] >= ((int64_t)1 << 31)) return set_error(TG_EUNSUPPORTED, "pagerank: a source class exceeds 2^31 edges");
-    S.sa.base[k] = base;
-    base += tot[k];
-  }
-  TG_TRY(dalloc(S.arena, &S.soff, hsoff.size()));
-  TG_HIP(hipMemcpyAsync(S.soff, hsoff.data(), hsoff.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  // padded: a block of a class without edges re-reads the class's first slot
-  TG_TRY(dalloc(S.arena, &S.scol, (size_t)m + 64));
-  hipLaunchKernelGGL(k_slice_fill, dim3(std::max(grid, 1u)), dim3(BLOCK), 0, s, g.in.off, g.in.col, n, S.soff, S.sa,
-                     S.scol);
-  TG_HIP(hipGetLastError());
+  std::vector<int32_t> hsoff, hc;
+  TG_TRY(build_class_csr(g.in.off, g.in.col, nullptr, n, m, S.cc, hsoff, hc, s));
   {
     // row blocks of every class over rows [0, nrows) (a symmetric whole-graph
     // partition leaves out its isolated tail, whose partials stay 0)
@@ -206,7 +117,6 @@ static int build_slices(tg_partition *p, hipStream_t s) {
   // rows that are never walked keep partial 0
   TG_HIP(hipMemset(S.ps, 0, (size_t)NS * std::max<int64_t>(n, 1) * sizeof(float)));
   TG_HIP(hipStreamSynchronize(s));
-  S.arena.release_one(cnt);
   S.built_nnz = t.pr_rows;
   S.built = true;
   return TG_OK;
@@ -226,13 +136,13 @@ int gpu_pagerank_sliced_step(tg_partition *p, double damping, int mode, int32_t 
   for (int c = 0; c < NS; ++c) {
     A.rb_base[c] = S.rb_base[c];
     A.nb[c] = S.nb[c];
-    A.ebase[c] = S.sa.base[c];
+    A.ebase[c] = S.cc.cb.base[c];
     nbmax = std::max<int64_t>(nbmax, S.nb[c]);
   }
   A.rb = S.rows.rb;
-  A.off = S.soff;
+  A.off = S.cc.soff;
   A.off_stride = g.n + 1;
-  A.col = S.scol;
+  A.col = S.cc.scol;
   A.lr_b0 = S.rows.lr_b0;
   A.lr_nch = S.rows.lr_nch;
   A.chunk_part = S.rows.chunk_part;

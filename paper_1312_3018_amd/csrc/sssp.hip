@@ -10,11 +10,21 @@
 // (`settled`), so every real improvement is expanded exactly as with a
 // returned previous value, and stale marks are dropped.
 //
+// Per-XCD destination classes (tuning `sssp_xcd`): the out-edges are split by the
+// 128-byte line of the destination's distance (class_csr.hip) and workgroups
+// of XCD k relax only class k, so each XCD's L2 serves an eighth of the
+// distance array.  Frontier vertices take lanes by the degree bin of
+// ceil(deg / 8) (about one class row), hubs are chunked by their longest
+// class row.
+//
 // Distances are int32 with INT32_MAX meaning unreachable.  A candidate
 // distance >= INT32_MAX is never stored; the vertex is marked in an overflow
 // bitmap instead, and the call fails with TG_ERANGE if such a vertex ends up
 // without a finite distance (its true distance does not fit in int32).
+#include <string.h>
+
 #include <algorithm>
+#include <vector>
 
 #include "tg_internal.h"
 
@@ -102,6 +112,60 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
   }
 }
 
+// One class per XCD: workgroup i relaxes class (i mod 8) of every frontier
+// vertex's out-edges.
+__global__ __launch_bounds__(BLOCK) void k_sssp_relax_cls(const Plan *__restrict__ Pp,
+                                                          const int32_t *__restrict__ queue,
+                                                          const int64_t *__restrict__ hubpref,
+                                                          const int32_t *__restrict__ soff, tg::ClassBase cb,
+                                                          const int32_t *__restrict__ scol,
+                                                          const int32_t *__restrict__ sw, int64_t n, int32_t *dist,
+                                                          uint32_t *active, uint32_t *ovf, uint32_t *flags,
+                                                          int64_t hub_chunk, unsigned long long *work) {
+  const Plan &P = load_plan(Pp);
+  const int k = (int)(blockIdx.x & 7);
+  const int64_t jb = blockIdx.x >> 3, nb = gridDim.x >> 3;
+  const int32_t *so = soff + (int64_t)k * (n + 1);
+  const int64_t base = cb.base[k];
+  const int64_t total = P.vb[NBIN];
+  unsigned long long n_edges = 0, n_verts = 0;
+  for (int64_t vb = jb; vb < total; vb += nb) {
+    const Assign a = assign_work_rows(vb, P, queue, nullptr, hubpref,
+                                      [so, base](int64_t i) { return base + (int64_t)stream_load(so + i); },
+                                      hub_chunk);
+    if (!a.ok || a.e_begin >= a.e_end) continue;
+    if (a.lane == 0) {
+      n_edges += (unsigned long long)(a.e_end - a.e_begin);
+      n_verts += (k == 0 && (a.bin != BIN_HUB || a.e_begin == base + so[a.v])) ? 1 : 0;
+    }
+    const int32_t dv = dist[a.v];
+    const int64_t st = a.stride;
+    int64_t e = a.e_begin + a.lane;
+    for (; e + 3 * st < a.e_end; e += 4 * st) {
+      int32_t nb4[4], wt[4], cur[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        nb4[q] = stream_load(scol + e + q * st);
+        wt[q] = stream_load(sw + e + q * st);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cur[q] = dist[nb4[q]];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) relax(dist, nullptr, 0, active, ovf, flags, dv, nb4[q], wt[q], cur[q]);
+    }
+    for (; e < a.e_end; e += st) {
+      const int32_t n0 = stream_load(scol + e);
+      relax(dist, nullptr, 0, active, ovf, flags, dv, n0, stream_load(sw + e), dist[n0]);
+    }
+  }
+  n_edges = block_sum(n_edges);
+  n_verts = block_sum(n_verts);
+  if (threadIdx.x == 0 && n_edges + n_verts > 0) {
+    atomicAdd(work, n_edges);
+    atomicAdd(work + 1, n_verts);
+  }
+}
+
 // flags[1] = 1 if some vertex with an overflowing candidate stayed unreached
 __global__ __launch_bounds__(BLOCK) void k_overflow_check(const uint32_t *__restrict__ ovf,
                                                           const int32_t *__restrict__ dist, int64_t n,
@@ -144,6 +208,79 @@ int sssp_overflow_check(const GpuPart &g, Workspace &ws, hipStream_t s) {
   return TG_OK;
 }
 
+struct SsspSlices {
+  ClassCsr cc;               // out-edges and weights by destination class
+  int32_t *maxlen = nullptr; // per vertex: its longest class row (hub chunking)
+  DevArena arena;
+  BinBounds bins{};          // bins of ceil(deg / 8) over the degree-sorted ids
+  Tuning built_for{};
+  bool built = false;
+};
+
+void sssp_slices_free(GpuPart &g) {
+  delete g.sslices;
+  g.sslices = nullptr;
+}
+
+static int build_sssp_slices(tg_partition *p, hipStream_t s) {
+  GpuPart &g = p->gpu;
+  const Tuning &t = p->tune;
+  if (g.sslices && g.sslices->built) {
+    // the bins follow the tuning's thresholds
+    if (memcmp(g.sslices->built_for.min_deg, t.min_deg, sizeof(t.min_deg)) != 0) {
+      g.sslices->bins = BinBounds{};
+      const int64_t n = g.n;
+      int64_t i = 0;
+      for (int b = 0; b < NBIN; ++b) {
+        while (i < n && bin_of_degree((g.h_deg[i] + 7) / 8, t) < b) ++i;
+        g.sslices->bins.bstart[b] = i;
+      }
+      g.sslices->bins.bstart[NBIN] = n;
+      g.sslices->built_for = t;
+    }
+    return TG_OK;
+  }
+  sssp_slices_free(g);
+  g.sslices = new (std::nothrow) SsspSlices();
+  if (!g.sslices) return set_error(TG_ENOMEM, "sssp: out of host memory");
+  SsspSlices &S = *g.sslices;
+  const int64_t n = g.n;
+  std::vector<int32_t> hsoff, hcnt;
+  TG_TRY(build_class_csr(g.out.off, g.out.col, g.out.w, n, g.m, S.cc, hsoff, hcnt, s));
+  std::vector<int32_t> ml((size_t)std::max<int64_t>(n, 1), 0);
+#pragma omp parallel for schedule(static)
+  for (int64_t v = 0; v < n; ++v) {
+    int32_t m = 0;
+    for (int k = 0; k < 8; ++k) m = std::max(m, hcnt[(size_t)k * n + v]);
+    ml[v] = m;
+  }
+  TG_TRY(dalloc(S.arena, &S.maxlen, ml.size()));
+  TG_HIP(hipMemcpy(S.maxlen, ml.data(), ml.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  int64_t i = 0;
+  for (int b = 0; b < NBIN; ++b) {
+    while (i < n && bin_of_degree((g.h_deg[i] + 7) / 8, t) < b) ++i;
+    S.bins.bstart[b] = i;
+  }
+  S.bins.bstart[NBIN] = n;
+  S.built_for = t;
+  S.built = true;
+  return TG_OK;
+}
+
+static int sssp_relax_cls_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks,
+                                 const Tuning &t, hipStream_t s) {
+  if (vblocks <= 0) return TG_OK;
+  const SsspSlices &S = *g.sslices;
+  // every class walks every virtual block: up to sssp_grid blocks per class
+  const int grid = (int)(8 * std::min<int64_t>(vblocks, std::max<int64_t>(t.sssp_grid, 1)));
+  const int tk = ktimer_start(s);
+  hipLaunchKernelGGL(k_sssp_relax_cls, dim3(grid), dim3(BLOCK), 0, s, ws.plan, queue, ws.hubpref, S.cc.soff, S.cc.cb,
+                     S.cc.scol, S.cc.sw, g.n, ws.state, ws.bits_a, ws.bits_c, ws.counters, t.hub_chunk, ws.work);
+  ktimer_stop(tk, s, "sssp_relax");
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
 int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) {
   GpuPart &g = p->gpu;
   Workspace &ws = p->ws;
@@ -160,19 +297,23 @@ int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) 
   TG_TRY(set_bit(active, root, s));
   int64_t rounds = 0;
   const int64_t delta = p->tune.sssp_delta;
+  const bool cls = p->tune.sssp_xcd != 0;
+  if (cls) TG_TRY(build_sssp_slices(p, s));
+  const BinBounds &bb = cls ? g.sslices->bins : g.out_bins;
+  const int32_t *len = cls ? g.sslices->maxlen : nullptr;
   int64_t thresh = delta;  // near/far: only active vertices below thresh relax
   for (;; ++rounds) {
     // a frontier Bellman-Ford settles within |V| - 1 rounds (per threshold step)
     if (rounds > 2 * g.n + 2) return set_error(TG_EDEVICE, "sssp: no convergence after %lld rounds", (long long)rounds);
     if (delta <= 0) {
-      TG_TRY(frontier_compact_sssp(g, ws, active, ws.queue, dist, ws.settled, TG_INF, false, s));
-      TG_TRY(frontier_plan(g, ws, ws.queue, p->tune, s, true));
+      TG_TRY(frontier_compact_sssp(g, ws, active, ws.queue, dist, ws.settled, TG_INF, false, bb, s));
+      TG_TRY(frontier_plan_bins(g, ws, ws.queue, bb, len, p->tune, s, true));
       if (ws.h_plan->count == 0) break;
     } else {
       TG_TRY(frontier_compact_sssp(g, ws, active, ws.queue, dist, ws.settled,
-                                   (int32_t)std::min<int64_t>(thresh, TG_INF), true, s));
+                                   (int32_t)std::min<int64_t>(thresh, TG_INF), true, bb, s));
       TG_HIP(hipMemcpyAsync(ws.h_work + 4, ws.rest, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-      TG_TRY(frontier_plan(g, ws, ws.queue, p->tune, s, true));
+      TG_TRY(frontier_plan_bins(g, ws, ws.queue, bb, len, p->tune, s, true));
       if (ws.h_plan->count == 0) {
         if (ws.h_work[4] == 0) break;  // nothing left beyond the threshold either
         // jump to the least distance still waiting
@@ -180,7 +321,8 @@ int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) 
         continue;
       }
     }
-    TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s));
+    if (cls) TG_TRY(sssp_relax_cls_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s));
+    else TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s));
   }
   TG_TRY(sssp_overflow_check(g, ws, s));
   if (ws.h_flags[1]) return set_error(TG_ERANGE, "sssp: a shortest-path distance does not fit below INT32_MAX");

@@ -68,6 +68,7 @@ struct Tuning {
   int64_t pr_rows;               // PageRank: edges per row block (one wave's block)
   int64_t bfs_do;                // BFS: 1 = switch to bottom-up steps on large frontiers
   int64_t bfs_alpha, bfs_beta;   // BFS: top-down -> bottom-up when m_f > m_u / alpha; back when n_f < n / beta
+  int64_t sssp_xcd;              // SSSP: 1 = relaxation split by destination class per XCD
 };
 Tuning default_tuning();
 int parse_tuning(const char *json, Tuning *t);
@@ -119,6 +120,26 @@ struct DevCSR {
 
 struct PrSlices;
 struct PrRows;
+struct SsspSlices;
+
+// Per-XCD edge classes (class_csr.hip): class = 128-byte line of the 4-byte
+// state of the vertex an edge points at, mod 8.
+__host__ __device__ inline int line_class(int32_t u) { return (u >> 5) & 7; }
+struct ClassBase {
+  int64_t base[8];  // first edge of class k in scol / sw
+};
+struct ClassCsr {
+  DevArena arena;
+  int32_t *soff = nullptr;  // [8][n+1] row offsets relative to base[k]
+  int32_t *scol = nullptr;  // [m + 64] targets, class by class (padded)
+  int32_t *sw = nullptr;    // [m + 64] weights in the same order, or null
+  ClassBase cb{};
+  int64_t n = 0, m = 0;
+};
+// Build C from a CSR (off, col, optional w).  hsoff gets the host copy of
+// soff and hcnt the class row lengths [8][n].  Waits on s.
+int build_class_csr(const int64_t *off, const int32_t *col, const int32_t *w, int64_t n, int64_t m, ClassCsr &C,
+                    std::vector<int32_t> &hsoff, std::vector<int32_t> &hcnt, hipStream_t s);
 
 // Row blocks of a CSR for the PageRank gather (pr_rows.hip).
 struct RowBlk {
@@ -211,6 +232,7 @@ struct GpuPart {
   std::vector<int64_t> h_in_deg;   // in-degree of each local id
   PrSlices *slices = nullptr;      // PageRank in-edges split by source class (lazy)
   PrRows *rows = nullptr;          // PageRank row blocks of the in-edges (lazy)
+  SsspSlices *sslices = nullptr;   // SSSP out-edges split by destination class (lazy)
 };
 
 // Per-partition scratch, grown on demand.
@@ -234,7 +256,6 @@ struct Workspace {
   unsigned long long *work = nullptr;  // [0] edges scanned, [1] vertices expanded
   unsigned long long *rest = nullptr;  // near/far compaction: [0] left active, [1] their least distance
   unsigned long long *h_work = nullptr;
-  uint32_t *hub_counters = nullptr;
   uint32_t *bcount = nullptr;    // per-block counts for compaction
   Plan *plan = nullptr;          // device frontier plan
   int64_t *hubpref = nullptr;    // frontier hub chunk prefix
@@ -294,7 +315,11 @@ int frontier_compact_bfs(const GpuPart &g, Workspace &ws, uint32_t *visited, uin
 // with `near`, dist < thresh; stale bits are dropped; with `near` the others
 // stay active and ws.rest gets their count and least distance.
 int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
-                          int32_t *settled, int32_t thresh, bool near, hipStream_t s);
+                          int32_t *settled, int32_t thresh, bool near, const BinBounds &bb, hipStream_t s);
+// Plan over the queue with bins `bb` (queue positions set by a compaction
+// with the same bins) and hub chunks sized by len[v] edges.
+int frontier_plan_bins(const GpuPart &g, Workspace &ws, const int32_t *queue, const BinBounds &bb,
+                       const int32_t *len, const Tuning &t, hipStream_t s, bool sync);
 // As frontier_plan, with hub chunks sized by the degrees in `off`; with
 // include_zero, frontier vertices of out-degree 0 get virtual blocks too
 // (a pull over in-edges must visit them).
@@ -306,6 +331,7 @@ int bfs_expand_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int
                       const Tuning &t, hipStream_t s);
 int set_bit(uint32_t *bits, int32_t v, hipStream_t s);
 
+void sssp_slices_free(GpuPart &g);
 // sssp.hip: relaxation of the frontier in `queue` (dist in ws.state, next
 // active set in ws.bits_a, overflow marks in ws.bits_c)
 int sssp_relax_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks, const Tuning &t,

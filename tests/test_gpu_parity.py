@@ -172,6 +172,30 @@ def test_pagerank_variants(gpu, rmat14, xcd, rows):
             assert np.array_equal(again, rank)  # deterministic
 
 
+@pytest.mark.parametrize("xcd", [0, 1])
+@pytest.mark.parametrize("delta", [0, 64])
+def test_sssp_variants(gpu, rmat14, xcd, delta):
+    """SSSP with and without the per-XCD destination classes and the near/far
+    step, with small degree thresholds (multi-chunk hubs whose class rows
+    differ in length) and the defaults, on symmetric, directed, star and path
+    graphs."""
+    g, w = rmat14
+    gd = graphgen.rmat(12, symmetrize=False)
+    gs = graphgen.from_edges(20001, np.zeros(20000, dtype=int), np.arange(1, 20001), symmetrize=True)
+    gp = graphgen.from_edges(700, np.arange(699), np.arange(1, 700), symmetrize=True)
+    cases = [(g, w, graphgen.sample_roots(g, 3, seed=21).tolist()),
+             (gd, graphgen.weights(gd, seed=4), graphgen.sample_roots(gd, 3, seed=22).tolist()),
+             (gs, graphgen.weights(gs, seed=5), [0, 3]),
+             (gp, graphgen.weights(gp, seed=6), [0, 350])]
+    for tuning in ({"sssp_xcd": xcd, "sssp_delta": delta},
+                   dict(SMALL_BINS, sssp_xcd=xcd, sssp_delta=delta, sssp_grid=3)):
+        for graph, wt, roots in cases:
+            P = load(gpu, graph, wt, tuning)
+            dist = gpu.sssp(P, roots).cpu().numpy()
+            for i, r in enumerate(roots):
+                assert np.array_equal(dist[i], oracle.sssp(graph.offsets, graph.cols, wt, r)), (tuning, graph.n, r)
+
+
 DO_VARIANTS = [{"bfs_do": 0},                                   # top-down only
                {"bfs_alpha": 1000000, "bfs_beta": 1000000},     # bottom-up from the second step on
                {"bfs_alpha": 1000000, "bfs_beta": 1},           # alternate bottom-up and top-down
