@@ -1,8 +1,8 @@
 """The oracle — TEST INFRASTRUCTURE ONLY.
 
-Plain CPU reference results for BFS levels, SSSP distances, PageRank and
-Brandes betweenness centrality, computed in C (``oracle.c``) from their plain
-definitions in fp64 / int64.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+Plain CPU reference results for BFS levels, SSSP distances, PageRank,
+Brandes betweenness centrality and connected components, computed in C
+(``oracle.c``) from their plain definitions in fp64 / int64.  Only ``tests/``, ``__graft_entry__.smoke()`` and
 the CPU-baseline leg of ``bench.py`` may import this package.  It shares no
 code with the GPU library and never imports it.
 
@@ -71,6 +71,7 @@ def _load():
                                                  ctypes.c_int32, _i64p]
         lib.oracle_pagerank.argtypes = [ctypes.c_int64, _i64p, _i32p, ctypes.c_double,
                                         ctypes.c_int32, ctypes.c_int32, _f64p]
+        lib.oracle_cc.argtypes = [ctypes.c_int64, _i64p, _i32p, _i32p]
         lib.oracle_bc.argtypes = [ctypes.c_int64, _i64p, _i32p, _i32p, ctypes.c_int32,
                                   _f64p, _f64p]
         for f in (lib.oracle_bfs, lib.oracle_sssp_dijkstra, lib.oracle_sssp_bellman_ford,
@@ -146,3 +147,12 @@ def bc(offsets, cols, sources: Sequence[int], return_sigma: bool = False):
                              sig.ctypes.data_as(_f64p) if return_sigma else None))
     return (out, sig) if return_sigma else out
 
+
+
+def cc(offsets, cols) -> np.ndarray:
+    """Connected components of the undirected graph (edge direction ignored):
+    labels[v] = smallest vertex id in v's component."""
+    n, off, col = _csr(offsets, cols)
+    lab = np.empty(n, dtype=np.int32)
+    _check(_load().oracle_cc(n, off.ctypes.data_as(_i64p), col.ctypes.data_as(_i32p), lab.ctypes.data_as(_i32p)))
+    return lab

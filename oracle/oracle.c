@@ -18,6 +18,12 @@
  *     section 7.1 (Figure 14), in fp64, with the contribution of u divided by
  *     its out-degree and the rank of out-degree-0 vertices spread uniformly
  *     (or dropped, as Figure 14 read literally does).
+ *   - Connected components (section 9.4; the algorithm runs on the undirected
+ *     graph, section 9.4 / Table 5): two vertices share a component iff an
+ *     undirected path joins them; each vertex is labelled with the smallest
+ *     vertex id of its component (the fixed point of minimum-label
+ *     propagation).  Union-find with path halving over every edge, then the
+ *     minimum id per root.
  *   - Betweenness centrality: Brandes' algorithm cited in section 7.2
  *     (Figure 18): a BFS from each source counting shortest paths sigma, then
  *     dependencies delta(v) = sum over successors w of sigma_v/sigma_w *
@@ -222,5 +228,38 @@ int oracle_bc(int64_t n, const int64_t *off, const int32_t *col,
       memcpy(sigma_out, sigma, (size_t)n * sizeof(double));
   }
   free(order); free(dist); free(sigma); free(delta);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ CC */
+
+static int32_t uf_find(int32_t *parent, int32_t x) {
+  while (parent[x] != x) {
+    parent[x] = parent[parent[x]]; /* path halving */
+    x = parent[x];
+  }
+  return x;
+}
+
+/* labels[v] = smallest vertex id in v's (weakly) connected component; the
+ * edge direction is ignored. */
+int oracle_cc(int64_t n, const int64_t *off, const int32_t *col, int32_t *labels) {
+  if (n < 0 || !off || (n > 0 && (!col || !labels))) return OR_EINVAL;
+  int32_t *parent = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int32_t *minid = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  if (!parent || !minid) { free(parent); free(minid); return OR_ENOMEM; }
+  for (int64_t v = 0; v < n; ++v) parent[v] = (int32_t)v;
+  for (int64_t u = 0; u < n; ++u)
+    for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+      int32_t a = uf_find(parent, (int32_t)u), b = uf_find(parent, col[e]);
+      if (a != b) parent[a < b ? b : a] = a < b ? a : b; /* union: smaller root wins */
+    }
+  for (int64_t v = 0; v < n; ++v) minid[v] = INT32_MAX;
+  for (int64_t v = 0; v < n; ++v) {
+    int32_t r = uf_find(parent, (int32_t)v);
+    if ((int32_t)v < minid[r]) minid[r] = (int32_t)v;
+  }
+  for (int64_t v = 0; v < n; ++v) labels[v] = minid[uf_find(parent, (int32_t)v)];
+  free(parent); free(minid);
   return OR_OK;
 }

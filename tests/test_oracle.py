@@ -359,3 +359,65 @@ def test_bc_sum_equals_interior_count():
         fin = lev[lev != INF]
         total += int(np.sum(fin[fin > 0] - 1))
     assert abs(got.sum() - total) < 1e-6 * max(total, 1)
+
+
+# ----------------------------------------------------------------- CC pins
+
+
+def test_cc_hand_worked():
+    # components {0, 1, 2}, {3, 4}, {5}, {6, 7} (edge 7 -> 6 directed: weak)
+    g = graphgen.from_edges(8, [1, 2, 4, 7], [0, 1, 3, 6], symmetrize=False)
+    assert oracle.cc(g.offsets, g.cols).tolist() == [0, 0, 0, 3, 3, 5, 6, 6]
+
+
+def _components_brute(g):
+    # undirected reachability by repeated relaxation of an adjacency matrix
+    a = np.zeros((g.n, g.n), dtype=bool)
+    for u in range(g.n):
+        for v in g.cols[g.offsets[u]:g.offsets[u + 1]]:
+            a[u, v] = a[v, u] = True
+    reach = a | np.eye(g.n, dtype=bool)
+    while True:
+        nxt = reach | ((reach.astype(np.int32) @ reach.astype(np.int32)) > 0)
+        if np.array_equal(nxt, reach):
+            break
+        reach = nxt
+    return np.array([np.flatnonzero(reach[v]).min() for v in range(g.n)], dtype=np.int32)
+
+
+@pytest.mark.parametrize("seed,sym", [(1, True), (2, False), (3, True), (4, False)])
+def test_cc_brute_force(seed, sym):
+    g = random_graph(40, 30, seed, sym)  # sparse: many components
+    assert np.array_equal(oracle.cc(g.offsets, g.cols), _components_brute(g))
+
+
+@pytest.mark.parametrize("seed,sym", [(5, True), (6, False)])
+def test_cc_vs_scipy(seed, sym):
+    g = random_graph(500, 420, seed, sym)
+    k, comp = csg.connected_components(to_scipy(g), directed=True, connection="weak")
+    lab = oracle.cc(g.offsets, g.cols)
+    assert len(np.unique(lab)) == k
+    # same partition, and the label is the smallest member
+    for c in range(k):
+        members = np.flatnonzero(comp == c)
+        assert np.all(lab[members] == members.min())
+
+
+def test_cc_invariants_rmat():
+    g = graphgen.rmat(12, symmetrize=False, seed=3)
+    lab = oracle.cc(g.offsets, g.cols)
+    v = np.arange(g.n)
+    assert np.all(lab <= v) and np.array_equal(lab[lab], lab)
+    src = np.repeat(v, np.diff(g.offsets))
+    assert np.array_equal(lab[src], lab[g.cols])  # every edge inside one component
+    iso = np.diff(g.offsets) == 0
+    indeg = np.bincount(g.cols, minlength=g.n)
+    alone = iso & (indeg == 0)
+    assert np.array_equal(lab[alone], v[alone])
+
+
+def test_cc_empty_and_single():
+    g = graphgen.from_edges(1, [], [], symmetrize=True)
+    assert oracle.cc(g.offsets, g.cols).tolist() == [0]
+    g = graphgen.from_edges(4, [], [], symmetrize=True)
+    assert oracle.cc(g.offsets, g.cols).tolist() == [0, 1, 2, 3]
