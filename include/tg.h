@@ -173,6 +173,18 @@ int pagerank(const tg_partition *p, float damping, int32_t iterations,
 int bc(const tg_partition *p, const int32_t *sources, int32_t num_sources,
        float *scores, void *stream);
 
+/* Connected components by minimum-label propagation (the fifth algorithm of
+ * section 9.4, run on the undirected graph; labels are reduced by minimum,
+ * section 3.4): every vertex starts with its own id and pushes any lower
+ * label it receives to its neighbours until no label drops.
+ *   labels    device int32 [V]: the smallest original vertex id of the
+ *             vertex's component.  On a directed graph the components are
+ *             the weak ones (labels cross edges in both directions).
+ * GPU-only partitions (cpu_edge_share 0).
+ * Errors: TG_EINVAL, TG_EUNSUPPORTED (hybrid partition), TG_ENOMEM,
+ * TG_EDEVICE. */
+int cc(const tg_partition *p, int32_t *labels, void *stream);
+
 /* ------------------------------------------------------------- serving
  * A query server with continuous batching over resident graphs: BFS and SSSP
  * queries are admitted into a graph's 64-slot engine (see bfs_batched) as

@@ -59,6 +59,7 @@ def _load():
     lib.sssp_batched.argtypes = [vp, _c_i32p, ctypes.c_int32, vp, vp]
     lib.pagerank.argtypes = [vp, ctypes.c_float, ctypes.c_int32, ctypes.c_int32, vp, vp]
     lib.bc.argtypes = [vp, _c_i32p, ctypes.c_int32, vp, vp]
+    lib.cc.argtypes = [vp, vp, vp]
     lib.server_create.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
     lib.server_add_graph.argtypes = [vp, vp, _c_i32p]
     lib.server_submit.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
@@ -275,6 +276,14 @@ def bc(part: Partition, sources: Sequence[int], scores=None, stream=None):
     scores = _out(scores, (part.n,), "float32")
     _check(_load().bc(part.handle, s.ctypes.data_as(_c_i32p), s.size, scores.data_ptr(), _stream_handle(stream)))
     return scores
+
+
+def cc(part: Partition, labels=None, stream=None):
+    """Connected components: labels[v] = smallest original id in v's component
+    (weak components of a directed graph)."""
+    labels = _out(labels, (part.n,), "int32")
+    _check(_load().cc(part.handle, labels.data_ptr(), _stream_handle(stream)))
+    return labels
 
 
 def bfs_batched(part: Partition, roots: Sequence[int], levels=None, stream=None):

@@ -762,6 +762,27 @@ extern "C" int sssp(const tg_partition *pc, const int32_t *roots, int32_t num_ro
   return TG_OK;
 }
 
+extern "C" int cc(const tg_partition *pc, int32_t *labels, void *stream) {
+  clear_error();
+  TG_TRY(check_call(pc, labels, "cc"));
+  if (pc->alpha > 0.0) return set_error(TG_EUNSUPPORTED, "cc: hybrid partitions are not supported");
+  tg_partition *p = const_cast<tg_partition *>(pc);
+  hipStream_t s = (hipStream_t)stream;
+  stats_reset("cc");
+  ktimer_reset();
+  TG_TRY(p->ws.ensure(p->gpu, 0));
+  TG_HIP(hipMemsetAsync(p->ws.work, 0, 8 * sizeof(unsigned long long), s));
+  int64_t rounds = 0;
+  TG_TRY(gpu_cc(p, s, &rounds));
+  if (p->gpu.n > 0) TG_TRY(collect_i32(p->gpu, p->ws.state, labels, s));
+  TG_HIP(hipMemcpyAsync(p->ws.h_work, p->ws.work, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  TG_HIP(hipStreamSynchronize(s));
+  stats_add("supersteps", (double)rounds);
+  stats_add("edges_pushed", (double)p->ws.h_work[0]);
+  ktimer_emit();
+  return TG_OK;
+}
+
 extern "C" int pagerank(const tg_partition *pc, float damping, int32_t iterations, int32_t dangling_mode,
                         float *rank, void *stream) {
   clear_error();

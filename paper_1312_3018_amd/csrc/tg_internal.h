@@ -374,6 +374,8 @@ int gpu_sssp(tg_partition *p, int32_t root_local, hipStream_t s, int64_t *rounds
 int gpu_pagerank(tg_partition *p, double damping, int32_t iters, int mode, float *rank_out,
                  hipStream_t s);
 int gpu_bc_source(tg_partition *p, int32_t src_local, hipStream_t s);
+// cc.hip: component labels (original ids) into ws.state
+int gpu_cc(tg_partition *p, hipStream_t s, int64_t *rounds_out);
 // bcb.hip: adds the dependencies of `sources` (original ids) into ws.bc_acc
 int gpu_bc_batched(tg_partition *p, const int32_t *sources, int32_t ns, hipStream_t s);
 void bcb_free(tg_partition *p);
