@@ -69,13 +69,15 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
                                                       const int32_t *__restrict__ col,
                                                       const int32_t *__restrict__ wgt, int32_t *dist,
                                                       uint32_t *active, uint32_t *ovf, uint32_t *flags,
-                                                      int64_t hub_chunk, unsigned long long *work, int32_t hot) {
+                                                      int64_t hub_chunk, unsigned long long *work, int32_t hot,
+                                                      int vb_bin_lo) {
   extern __shared__ int32_t lds_d[];
   for (int32_t i = threadIdx.x; i < hot; i += BLOCK) lds_d[i] = dist[i];
   const Plan &P = load_plan(Pp);  // (its barrier also publishes lds_d)
   const int64_t total = P.vb[NBIN];
   unsigned long long n_edges = 0, n_verts = 0;
-  for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
+  // virtual blocks of bins vb_bin_lo.. only
+  for (int64_t vb = P.vb[vb_bin_lo] + blockIdx.x; vb < total; vb += gridDim.x) {
     const Assign a = assign_work(vb, P, queue, nullptr, hubpref, off, hub_chunk);
     if (!a.ok) continue;
     if (a.lane == 0) {
@@ -121,13 +123,14 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax_cls(const Plan *__restrict
                                                           const int32_t *__restrict__ scol,
                                                           const int32_t *__restrict__ sw, int64_t n, int32_t *dist,
                                                           uint32_t *active, uint32_t *ovf, uint32_t *flags,
-                                                          int64_t hub_chunk, unsigned long long *work) {
+                                                          int64_t hub_chunk, unsigned long long *work,
+                                                          int vb_bin_hi) {
   const Plan &P = load_plan(Pp);
   const int k = (int)(blockIdx.x & 7);
   const int64_t jb = blockIdx.x >> 3, nb = gridDim.x >> 3;
   const int32_t *so = soff + (int64_t)k * (n + 1);
   const int64_t base = cb.base[k];
-  const int64_t total = P.vb[NBIN];
+  const int64_t total = P.vb[vb_bin_hi];  // virtual blocks of bins ..vb_bin_hi-1 only
   unsigned long long n_edges = 0, n_verts = 0;
   for (int64_t vb = jb; vb < total; vb += nb) {
     const Assign a = assign_work_rows(vb, P, queue, nullptr, hubpref,
@@ -187,7 +190,7 @@ int sssp_relax_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int
   const int tk = ktimer_start(s);
   hipLaunchKernelGGL(k_sssp_relax, dim3(grid), dim3(BLOCK), (size_t)hot * sizeof(int32_t), s, ws.plan, queue,
                      ws.hubpref, g.out.off, g.out.col, g.out.w, ws.state, ws.bits_a, ws.bits_c, ws.counters,
-                     t.hub_chunk, ws.work, hot);
+                     t.hub_chunk, ws.work, hot, 0);
   ktimer_stop(tk, s, "sssp_relax");
   TG_HIP(hipGetLastError());
   return TG_OK;
@@ -267,15 +270,25 @@ static int build_sssp_slices(tg_partition *p, hipStream_t s) {
   return TG_OK;
 }
 
-static int sssp_relax_cls_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks,
+// Class mode: vertices of the HUB, BLOCK and WAVE bins (about a wave or more
+// per class row) relax through the per-XCD classes; the lower bins, whose
+// rows are too short to split eight ways, relax their whole rows in one pass.
+static int sssp_relax_cls_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, const Plan &hp,
                                  const Tuning &t, hipStream_t s) {
-  if (vblocks <= 0) return TG_OK;
   const SsspSlices &S = *g.sslices;
-  // every class walks every virtual block: up to sssp_grid blocks per class
-  const int grid = (int)(8 * std::min<int64_t>(vblocks, std::max<int64_t>(t.sssp_grid, 1)));
+  const int64_t vb_hi = hp.vb[BIN_G16], vb_lo_n = hp.vb[NBIN] - hp.vb[BIN_G16];
   const int tk = ktimer_start(s);
-  hipLaunchKernelGGL(k_sssp_relax_cls, dim3(grid), dim3(BLOCK), 0, s, ws.plan, queue, ws.hubpref, S.cc.soff, S.cc.cb,
-                     S.cc.scol, S.cc.sw, g.n, ws.state, ws.bits_a, ws.bits_c, ws.counters, t.hub_chunk, ws.work);
+  if (vb_hi > 0) {
+    // every class walks every virtual block: up to sssp_grid blocks per class
+    const int grid = (int)(8 * std::min<int64_t>(vb_hi, std::max<int64_t>(t.sssp_grid, 1)));
+    hipLaunchKernelGGL(k_sssp_relax_cls, dim3(grid), dim3(BLOCK), 0, s, ws.plan, queue, ws.hubpref, S.cc.soff,
+                       S.cc.cb, S.cc.scol, S.cc.sw, g.n, ws.state, ws.bits_a, ws.bits_c, ws.counters, t.hub_chunk,
+                       ws.work, (int)BIN_G16);
+  }
+  if (vb_lo_n > 0)
+    hipLaunchKernelGGL(k_sssp_relax, dim3(launch_grid(vb_lo_n)), dim3(BLOCK), 0, s, ws.plan, queue, ws.hubpref,
+                       g.out.off, g.out.col, g.out.w, ws.state, ws.bits_a, ws.bits_c, ws.counters, t.hub_chunk,
+                       ws.work, 0, (int)BIN_G16);
   ktimer_stop(tk, s, "sssp_relax");
   TG_HIP(hipGetLastError());
   return TG_OK;
@@ -321,7 +334,7 @@ int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) 
         continue;
       }
     }
-    if (cls) TG_TRY(sssp_relax_cls_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s));
+    if (cls) TG_TRY(sssp_relax_cls_launch(g, ws, ws.queue, *ws.h_plan, p->tune, s));
     else TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s));
   }
   TG_TRY(sssp_overflow_check(g, ws, s));
