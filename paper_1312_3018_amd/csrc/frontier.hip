@@ -16,58 +16,91 @@ namespace {
 constexpr int WPT = 4;                     // bitmap words per thread
 constexpr int WPB = WPT * BLOCK;           // words per block (1024)
 
-// SSSP filter over the set bits of one word.  With `settled` (the distance
-// each vertex had when it last relaxed its edges), a bit whose vertex has
-// dist >= settled is dropped: an attempt to lower it set the bit but found it
-// already as low.  Of the rest, bits with dist < thresh are kept (the near
-// set); the others are counted, with their least distance, and stay active.
-__device__ __forceinline__ uint32_t sssp_bits(uint32_t w, int64_t word, const int32_t *__restrict__ dist,
-                                              const int32_t *__restrict__ settled, int32_t thresh,
-                                              uint32_t &dropped, uint32_t &rest, int32_t &rest_min) {
-  uint32_t keep = 0;
-  while (w) {
-    const int bit = __ffs(w) - 1;
-    w &= w - 1;
-    const int64_t v = word * 32 + bit;
-    const int32_t d = dist[v];
-    if (settled && d >= settled[v]) dropped |= 1u << bit;
-    else if (d < thresh) keep |= 1u << bit;
-    else {
-      ++rest;
-      rest_min = d < rest_min ? d : rest_min;
+// SSSP filter over the set bits of a thread's four words.  A bit whose
+// vertex has dist >= settled (the distance it had when it last relaxed its
+// edges) is dropped: an attempt to lower it set the bit but found it already
+// as low.  Of the rest, bits with dist < thresh are kept (the near set; their
+// settled distance is updated here) and the others are counted, with their
+// least distance, and stay active.  Eight set bits are handled at a time so
+// that their distance loads are in flight together.
+__device__ __forceinline__ void sssp_filter4(uint32_t (&w)[4], int64_t word0, const int32_t *__restrict__ dist,
+                                             int32_t *__restrict__ settled, int32_t thresh, uint32_t (&keep)[4],
+                                             uint32_t (&dropped)[4], uint32_t &rest, int32_t &rest_min) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    keep[k] = 0;
+    dropped[k] = 0;
+    uint32_t x = w[k];
+    const int64_t base = (word0 + k) * 32;
+    while (x) {
+      int b[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        b[j] = x ? __ffs(x) - 1 : -1;
+        x &= x - 1;
+      }
+      int32_t d[8], st[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t v = base + (b[j] >= 0 ? b[j] : b[0]);
+        d[j] = dist[v];
+        st[j] = settled[v];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (b[j] < 0) continue;
+        const uint32_t bit = 1u << b[j];
+        if (d[j] >= st[j]) dropped[k] |= bit;
+        else if (d[j] < thresh) {
+          keep[k] |= bit;
+          settled[base + b[j]] = d[j];  // the distance it relaxes with (at least)
+        } else {
+          ++rest;
+          rest_min = d[j] < rest_min ? d[j] : rest_min;
+        }
+      }
     }
   }
-  return keep;
+}
+
+// SSSP compaction, first pass: filter the active bitmap (sssp_filter4),
+// leave the untaken active bits in `bits`, the taken ones in `keep_out`, and
+// each block's count in bcount.
+__global__ __launch_bounds__(BLOCK) void k_sssp_filter(uint32_t *__restrict__ bits, uint32_t *__restrict__ keep_out,
+                                                       uint32_t *__restrict__ bcount, const int32_t *__restrict__ dist,
+                                                       int32_t *__restrict__ settled, int32_t thresh,
+                                                       unsigned long long *rest_out) {
+  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // uint4 index
+  const uint4 v = reinterpret_cast<const uint4 *>(bits)[q];
+  uint32_t w[4] = {v.x, v.y, v.z, v.w}, keep[4], dr[4];
+  uint32_t r = 0;
+  int32_t rmin = TG_INF;
+  sssp_filter4(w, q * 4, dist, settled, thresh, keep, dr, r, rmin);
+  reinterpret_cast<uint4 *>(bits)[q] =
+      make_uint4(v.x & ~(keep[0] | dr[0]), v.y & ~(keep[1] | dr[1]), v.z & ~(keep[2] | dr[2]), v.w & ~(keep[3] | dr[3]));
+  reinterpret_cast<uint4 *>(keep_out)[q] = make_uint4(keep[0], keep[1], keep[2], keep[3]);
+  if (rest_out) {
+    r = block_sum(r);
+    for (int o = 32; o > 0; o >>= 1) {
+      const int32_t y = __shfl_xor(rmin, o, 64);
+      rmin = y < rmin ? y : rmin;
+    }
+    if ((threadIdx.x & 63) == 0 && rmin < TG_INF) atomicMin(reinterpret_cast<int32_t *>(rest_out + 1), rmin);
+    if (threadIdx.x == 0 && r) atomicAdd(rest_out, (unsigned long long)r);
+  }
+  uint32_t c = __popc(keep[0]) + __popc(keep[1]) + __popc(keep[2]) + __popc(keep[3]);
+  c = block_sum(c);
+  if (threadIdx.x == 0) bcount[blockIdx.x] = c;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_compact_count(const uint32_t *__restrict__ bits,
                                                          const uint32_t *__restrict__ prev,
-                                                         uint32_t *__restrict__ bcount,
-                                                         const int32_t *__restrict__ dist,
-                                                         const int32_t *__restrict__ settled, int32_t thresh,
-                                                         unsigned long long *rest) {
+                                                         uint32_t *__restrict__ bcount) {
   const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // uint4 index
   uint4 v = reinterpret_cast<const uint4 *>(bits)[q];
   if (prev) {
     uint4 p = reinterpret_cast<const uint4 *>(prev)[q];
     v.x &= ~p.x; v.y &= ~p.y; v.z &= ~p.z; v.w &= ~p.w;
-  }
-  if (dist) {
-    uint32_t r = 0, dropped = 0;
-    int32_t rmin = TG_INF;
-    v.x = sssp_bits(v.x, q * 4 + 0, dist, settled, thresh, dropped, r, rmin);
-    v.y = sssp_bits(v.y, q * 4 + 1, dist, settled, thresh, dropped, r, rmin);
-    v.z = sssp_bits(v.z, q * 4 + 2, dist, settled, thresh, dropped, r, rmin);
-    v.w = sssp_bits(v.w, q * 4 + 3, dist, settled, thresh, dropped, r, rmin);
-    if (rest) {
-      r = block_sum(r);
-      for (int o = 32; o > 0; o >>= 1) {
-        const int32_t y = __shfl_xor(rmin, o, 64);
-        rmin = y < rmin ? y : rmin;
-      }
-      if ((threadIdx.x & 63) == 0 && rmin < TG_INF) atomicMin(reinterpret_cast<int32_t *>(rest + 1), rmin);
-      if (threadIdx.x == 0 && r) atomicAdd(rest, (unsigned long long)r);
-    }
   }
   uint32_t c = __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
   c = block_sum(c);
@@ -78,10 +111,8 @@ __global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ 
                                                          int mode, const uint32_t *__restrict__ bcount,
                                                          int32_t *__restrict__ queue, int32_t *__restrict__ level,
                                                          int32_t level_value, BinBounds bb, int64_t n,
-                                                         Plan *__restrict__ plan, const int32_t *__restrict__ dist,
-                                                         int32_t *__restrict__ settled, int32_t thresh,
-                                                         uint32_t *__restrict__ fbits, const int64_t *__restrict__ off,
-                                                         unsigned long long *degsum) {
+                                                         Plan *__restrict__ plan, uint32_t *__restrict__ fbits,
+                                                         const int64_t *__restrict__ off, unsigned long long *degsum) {
   // this block's offset: sum of the counts of all earlier blocks
   uint32_t part = 0;
   for (uint32_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) part += bcount[i];
@@ -96,15 +127,8 @@ __global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ 
     nw[0] &= ~p.x; nw[1] &= ~p.y; nw[2] &= ~p.z; nw[3] &= ~p.w;
     reinterpret_cast<uint4 *>(prev)[q] = v;  // prev := visited
     if (fbits) reinterpret_cast<uint4 *>(fbits)[q] = make_uint4(nw[0], nw[1], nw[2], nw[3]);  // the new frontier
-  } else if (mode == 3) {
-    // SSSP: take the bits with dist < thresh (and below their settled
-    // distance), drop the stale ones, leave the rest active
-    uint32_t r = 0;
-    int32_t rmin = TG_INF;
-    uint32_t dr[4] = {0, 0, 0, 0};
-    for (int k = 0; k < 4; ++k) nw[k] = sssp_bits(nw[k], q * 4 + k, dist, settled, thresh, dr[k], r, rmin);
-    reinterpret_cast<uint4 *>(bits)[q] =
-        make_uint4(v.x & ~(nw[0] | dr[0]), v.y & ~(nw[1] | dr[1]), v.z & ~(nw[2] | dr[2]), v.w & ~(nw[3] | dr[3]));
+  } else if (mode == 4) {
+    // a bitmap already filtered (k_sssp_filter): take it as it is
   } else {
     if (mode == 2) reinterpret_cast<uint4 *>(prev)[q] = v;  // prev := the set taken
     reinterpret_cast<uint4 *>(bits)[q] = make_uint4(0, 0, 0, 0);
@@ -135,7 +159,6 @@ __global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ 
       const int32_t vtx = (int32_t)((w0 + k) * 32 + bit);
       queue[o++] = vtx;
       if (level) level[vtx] = level_value;
-      if (settled) settled[vtx] = dist[vtx];  // the distance it relaxes with (at least)
       if (degsum) deg += (unsigned long long)(off[vtx + 1] - off[vtx]);
       w &= w - 1;
     }
@@ -206,11 +229,9 @@ int launch_grid(int64_t vblocks) {
 int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, uint32_t *prev,
                      int32_t *queue, int32_t *level, int32_t level_value, hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
-  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, bits,
-                     mode == 0 ? prev : nullptr, ws.bcount, nullptr, nullptr, 0, nullptr);
-  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, bits, prev, mode,
-                     ws.bcount, queue, level, level_value, g.out_bins, g.n, ws.plan, nullptr, nullptr, 0, nullptr,
-                     nullptr, nullptr);
+  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, bits, mode == 0 ? prev : nullptr, ws.bcount);
+  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, bits, prev, mode, ws.bcount, queue, level,
+                     level_value, g.out_bins, g.n, ws.plan, nullptr, nullptr, nullptr);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
@@ -220,10 +241,9 @@ int frontier_compact_bfs(const GpuPart &g, Workspace &ws, uint32_t *visited, uin
                          hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
   TG_HIP(hipMemsetAsync(degsum, 0, sizeof(unsigned long long), s));
-  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, visited, prev, ws.bcount, nullptr, nullptr, 0,
-                     nullptr);
+  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, visited, prev, ws.bcount);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, visited, prev, 0, ws.bcount, queue, level,
-                     level_value, g.out_bins, g.n, ws.plan, nullptr, nullptr, 0, fbits, g.out.off, degsum);
+                     level_value, g.out_bins, g.n, ws.plan, fbits, g.out.off, degsum);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
@@ -236,10 +256,11 @@ int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32
     const unsigned long long init[2] = {0ull, (unsigned long long)(uint32_t)TG_INF};
     TG_HIP(hipMemcpyAsync(ws.rest, init, sizeof(init), hipMemcpyHostToDevice, s));
   }
-  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, bits, nullptr, ws.bcount, dist, settled,
+  // the taken bits go to bits_b (free during SSSP and connected components)
+  hipLaunchKernelGGL(k_sssp_filter, dim3(blocks), dim3(BLOCK), 0, s, bits, ws.bits_b, ws.bcount, dist, settled,
                      near ? thresh : TG_INF, near ? ws.rest : nullptr);
-  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, bits, nullptr, 3, ws.bcount, queue, nullptr,
-                     0, bb, g.n, ws.plan, dist, settled, near ? thresh : TG_INF, nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, ws.bits_b, nullptr, 4, ws.bcount, queue,
+                     nullptr, 0, bb, g.n, ws.plan, nullptr, nullptr, nullptr);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
