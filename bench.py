@@ -385,16 +385,21 @@ def bench_hybrid(args):
         sp = tg.tg_last_stats()
         rows.append({"strategy": strategy, "alpha": alpha, "cpu_vertices": info.get("cpu_vertices", 0),
                      "cpu_edges": info.get("cpu_edges", 0), "boundary_edges": info.get("boundary_edges", 0),
+                     "cpu_boundary_edges": info.get("cpu_boundary_edges", 0),
+                     "bfs_ms": round(bfs_ms, 2), "bfs_edges": edges,
                      "beta_raw": info.get("beta_raw", 0), "beta_reduced": info.get("beta_reduced", 0),
                      "bfs_gteps": round(edges / (bfs_ms / 1e3) / 1e9, 3),
                      "bfs_gpu_ms": round(sum(s.get("gpu_ms", 0) for s in st_b), 2),
                      "bfs_cpu_ms": round(sum(s.get("cpu_ms", 0) for s in st_b), 2),
                      "bfs_exchange_ms": round(sum(s.get("exchange_ms", 0) for s in st_b), 2),
                      "bfs_exchange_bytes": int(sum(s.get("exchange_bytes", 0) for s in st_b)),
+                     "bfs_h2d_bytes": int(sum(s.get("exchange_h2d_bytes", 0) for s in st_b)),
+                     "bfs_cpu_edges": int(sum(s.get("cpu_edges", 0) for s in st_b)),
                      "pr_ms_per_iter": round(pr_ms / args.pr_iters, 2),
                      "pr_gteps": round(g.nnz * args.pr_iters / (pr_ms / 1e3) / 1e9, 3),
                      "pr_gpu_ms": round(sp.get("gpu_ms", 0), 2), "pr_cpu_ms": round(sp.get("cpu_ms", 0), 2),
-                     "pr_exchange_bytes": int(sp.get("exchange_bytes", 0))})
+                     "pr_exchange_bytes": int(sp.get("exchange_bytes", 0)),
+                     "pr_cpu_edges": int(sp.get("cpu_edges", 0))})
         log(f"[hybrid] {rows[-1]}")
         del P
     out = {"metric": "hybrid split: GTEPS of BFS and PageRank with host-thread partition",
@@ -403,7 +408,63 @@ def bench_hybrid(args):
            "config": {"workload": f"rmat{args.hybrid_scale} directed: V={g.n}, E={g.nnz}; {len(roots)} BFS roots, "
                                   f"{args.pr_iters} PageRank iterations; host threads = OMP_NUM_THREADS"},
            "rows": rows}
+    out["model"] = hybrid_model(rows, g.nnz, log)
     print(json.dumps(out), flush=True)
+
+
+def pearson(x, y):
+    import numpy as np
+    x, y = np.asarray(x, dtype=np.float64), np.asarray(y, dtype=np.float64)
+    if len(x) < 2 or x.std() == 0 or y.std() == 0:
+        return None
+    return round(float(np.corrcoef(x, y)[0, 1]), 4)
+
+
+def hybrid_model(rows, num_edges, log):
+    """The performance model of section 3 (Equations 1-4) against the measured
+    splits.  Inputs, all measured in the same run:
+      r_cpu  the host threads' rate (their edges / their compute time) at the
+             split that gives them the most edges (HIGH, largest alpha): the
+             stand-in for a host-only run, which this engine does not make;
+      c      messages per second over PCIe: the host-to-GPU bytes of the BFS
+             exchange over its timed window, divided by 8-byte messages;
+      alpha  the share of edges whose source is on the host;
+      beta   messages per edge after the reduction of section 3.4 (one per
+             distinct remote vertex and direction).
+    Predicted speedup over the host alone (Equation 4):
+    1 / (beta r_cpu / c + alpha).  Achieved: (edges traversed / r_cpu) over
+    the measured hybrid time, the BFS over the same roots and one PageRank
+    iteration."""
+    pts_rows = [r for r in rows if r["alpha"] > 0 and r.get("bfs_cpu_ms", 0) > 0]
+    if not pts_rows:
+        return None
+    ref = max((r for r in pts_rows if r["strategy"] == "high"), key=lambda r: r["alpha"], default=pts_rows[0])
+    rate = lambda r, alg: r[f"{alg}_cpu_edges"] / (r[f"{alg}_cpu_ms"] / 1e3)
+    r_cpu = {"bfs": rate(ref, "bfs"), "pagerank": rate(ref, "pr")}
+    cs = sorted(r["bfs_h2d_bytes"] / (r["bfs_exchange_ms"] / 1e3) for r in pts_rows if r["bfs_exchange_ms"] > 0)
+    c_bytes = cs[len(cs) // 2]
+    c = c_bytes / 8.0
+    pts = []
+    for r in pts_rows:
+        a = (r["cpu_edges"] + r["cpu_boundary_edges"]) / num_edges
+        b = r["beta_reduced"]
+        pt = {"strategy": r["strategy"], "alpha_set": r["alpha"], "alpha": round(a, 4), "beta": b,
+              "r_cpu_bfs": round(rate(r, "bfs")), "r_cpu_pagerank": round(rate(r, "pr"))}
+        for alg, e_trav, t_hyb in (("bfs", r["bfs_edges"], r["bfs_ms"] / 1e3),
+                                   ("pagerank", num_edges, r["pr_ms_per_iter"] / 1e3)):
+            pred = 1.0 / (b * r_cpu[alg] / c + a)
+            ach = (e_trav / r_cpu[alg]) / t_hyb
+            pt[alg] = {"predicted": round(pred, 3), "achieved": round(ach, 3), "error": round((ach - pred) / pred, 4)}
+        pts.append(pt)
+    model = {"r_cpu_eps": {k: round(v) for k, v in r_cpu.items()}, "r_cpu_from": f"{ref['strategy']} alpha={ref['alpha']}",
+             "c_bytes_per_s": round(c_bytes), "c_msgs_per_s": round(c), "points": pts}
+    for alg in ("bfs", "pagerank"):
+        high = [p for p in pts if p["strategy"] == "high"]
+        model[alg] = {"correlation_high": pearson([p[alg]["predicted"] for p in high], [p[alg]["achieved"] for p in high]),
+                      "correlation_all": pearson([p[alg]["predicted"] for p in pts], [p[alg]["achieved"] for p in pts]),
+                      "mean_error": round(sum(p[alg]["error"] for p in pts) / len(pts), 4)}
+    log(f"[hybrid] model: {model}")
+    return model
 
 
 def main():

@@ -348,19 +348,6 @@ extern "C" void graph_free(tg_graph *g) { delete g; }
 // -------------------------------------------------- partition by degree
 namespace {
 
-// Stable counting sort of `ids` by key descending (keys <= maxkey).
-void sort_desc_by_key(const std::vector<int64_t> &key, std::vector<int32_t> &ids) {
-  if (ids.empty()) return;
-  int64_t maxk = 0;
-  for (int32_t v : ids) maxk = std::max(maxk, key[v]);
-  std::vector<int64_t> cnt((size_t)maxk + 2, 0);
-  for (int32_t v : ids) cnt[(size_t)(maxk - key[v]) + 1]++;
-  for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
-  std::vector<int32_t> outv(ids.size());
-  for (int32_t v : ids) outv[(size_t)cnt[(size_t)(maxk - key[v])]++] = v;
-  ids.swap(outv);
-}
-
 // Bin boundaries over a sequence whose degrees are non-increasing.
 BinBounds bins_of(const std::vector<int64_t> &deg_in_order, const Tuning &t) {
   BinBounds bb;
@@ -392,6 +379,19 @@ BinBounds bins_of_unsorted(const std::vector<int64_t> &deg, const Tuning &t) {
 }  // namespace
 
 namespace tg {
+
+// Stable counting sort of `ids` by key descending (keys >= 0).
+void sort_desc_by_key(const std::vector<int64_t> &key, std::vector<int32_t> &ids) {
+  if (ids.empty()) return;
+  int64_t maxk = 0;
+  for (int32_t v : ids) maxk = std::max(maxk, key[v]);
+  std::vector<int64_t> cnt((size_t)maxk + 2, 0);
+  for (int32_t v : ids) cnt[(size_t)(maxk - key[v]) + 1]++;
+  for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
+  std::vector<int32_t> outv(ids.size());
+  for (int32_t v : ids) outv[(size_t)cnt[(size_t)(maxk - key[v])]++] = v;
+  ids.swap(outv);
+}
 
 // In-edges of a CSR over n vertices: rows sorted ascending (deterministic).
 void transpose_csr(int64_t n, const std::vector<int64_t> &off, const std::vector<int32_t> &col,

@@ -21,6 +21,8 @@ struct BoundaryEdges {
 
 struct HybridState;
 
+// Stable counting sort of `ids` by decreasing key[id] (keys >= 0).
+void sort_desc_by_key(const std::vector<int64_t> &key, std::vector<int32_t> &ids);
 void transpose_csr(int64_t n, const std::vector<int64_t> &off, const std::vector<int32_t> &col,
                    std::vector<int64_t> &ioff, std::vector<int32_t> &icol);
 int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryEdges *boundary);

