@@ -207,6 +207,7 @@ def bench_serve(args):
                 "queries_per_s": round(len(lat) / span, 1), "max_concurrent": st["max_concurrent"],
                 "supersteps": st["supersteps"]}
 
+    capacity = serve_capacity(tg, parts, log)
     n_b, warm_b = args.serve_queries, args.serve_queries // 10
     stream = make_stream(n_b + warm_b, args.serve_rate)
     log(f"[serve] continuous batching: {len(stream)} queries at {args.serve_rate}/s")
@@ -236,9 +237,43 @@ def bench_serve(args):
            "data": "synthetic", "config": {"workload": "serve: 8 resident graphs (" + ", ".join(SERVE_GRAPHS) +
                                            f"), Poisson {args.serve_rate}/s, 50% BFS / 50% SSSP, roots uniform "
                                            "among degree >= 1"},
-           "continuous_batching": batched, "one_per_launch": single,
+           "continuous_batching": batched, "one_per_launch": single, "capacity": capacity,
            "sampled_equal_to_solo": f"{checked - mism}/{checked}"}
     print(json.dumps(out), flush=True)
+
+
+def serve_capacity(tg, parts, log, batch=64):
+    """GPU time per query of each (graph, kind) lane when its engine is full:
+    one batch of `batch` queries through the slot engine, and a few queries
+    one at a time, each after a warm-up.  The mix's capacity is the inverse of
+    the mean batched time per query over the lanes (the queries are spread
+    evenly over graphs and kinds)."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    lanes, per_query = [], []
+    for gi, (g, P) in enumerate(parts):
+        roots = graphgen.sample_roots(g, batch, seed=5)
+        out = torch.empty((batch, g.n), dtype=torch.int32, device="cuda")
+        for kind, batched, solo in (("bfs", tg.bfs_batched, tg.bfs), ("sssp", tg.sssp_batched, tg.sssp)):
+            batched(P, roots[:8], out[:8])
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            batched(P, roots, out)
+            torch.cuda.synchronize()
+            tb = (time.perf_counter() - t) / batch
+            t = time.perf_counter()
+            solo(P, roots[:8], out[:8])
+            torch.cuda.synchronize()
+            ts = (time.perf_counter() - t) / 8
+            lanes.append({"graph": SERVE_GRAPHS[gi], "kind": kind, "ms_per_query_batched": round(tb * 1e3, 3),
+                          "ms_per_query_solo": round(ts * 1e3, 3)})
+            per_query.append(tb)
+        del out
+    cap = round(1.0 / float(np.mean(per_query)), 1)
+    log(f"[serve] capacity of the mix with full engines: {cap} queries/s")
+    return {"queries_per_s_full_engines": cap, "batch": batch, "lanes": lanes}
 
 
 def bench_bc(args):
