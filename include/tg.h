@@ -107,14 +107,28 @@ int partition_by_degree(const tg_graph *g, int strategy, double cpu_edge_share,
                         tg_partition **out);
 
 /* Re-derive the degree bins and launch shapes of an existing partition from
- * a tuning object (same keys as partition_by_degree's tuning_json, plus
- * "pr_lds_verts", "pr_grid", "bfs_lds_words", "bfs_grid",
- * "bfs_lds_min_vblocks"; NULL restores the built-in values) without
- * rebuilding it.  This is the autotuner's hook.  Waits for the device to be
- * idle first.  Errors: TG_EINVAL (bad tuning), TG_ENOMEM, TG_EDEVICE. */
+ * a tuning object without rebuilding it (NULL restores the built-in values).
+ * This is the autotuner's hook.  Keys (all optional, integers):
+ *   degree bins  "hub_min_deg", "block_min_deg", "wave_min_deg",
+ *                "g16_min_deg", "g4_min_deg" (decreasing), "hub_chunk"
+ *                (edges per block of a hub);
+ *   BFS          "bfs_do" (1: direction-optimizing steps), "bfs_alpha",
+ *                "bfs_beta" (the switch thresholds), "bfs_lds_words",
+ *                "bfs_grid", "bfs_lds_min_vblocks";
+ *   SSSP         "sssp_delta" (0: plain frontier; > 0: near/far step),
+ *                "sssp_grid", "sssp_lds_verts", "sssp_xcd" (per-XCD
+ *                destination classes);
+ *   PageRank     "pr_xcd" (per-XCD source classes), "pr_rows" (256 or 512
+ *                edges per row block), "pr_lds_verts" (hot-table entries,
+ *                <= 40960), "pr_grid" (workgroups).
+ * Results do not depend on the tuning.  Waits for the device to be idle
+ * first.  Errors: TG_EINVAL (bad tuning), TG_ENOMEM, TG_EDEVICE. */
 int partition_retune(tg_partition *p, const char *tuning_json);
 
-/* Level-synchronous breadth-first search (section 6.3.2, Figure 11).
+/* Level-synchronous breadth-first search (section 6.3.2, Figure 11).  With
+ * "bfs_do" (the default) a superstep whose frontier holds many edges runs
+ * bottom-up instead: every unvisited vertex looks for an in-neighbour on the
+ * frontier.  Levels are the same either way.
  *   roots     host array of num_roots original vertex ids.
  *   levels    device int32 [num_roots * V]; row r holds the level of every
  *             vertex from roots[r] (TG_INF when unreachable).
@@ -250,8 +264,11 @@ const char *tg_last_error(void);
 int partition_info(const tg_partition *p, char *json, size_t cap);
 
 /* JSON statistics of the last algorithm call on this thread: supersteps,
- * per-phase milliseconds (GPU compute, host compute, exchange), bytes
- * exchanged, relaxations.  Same return convention as partition_info. */
+ * edges scanned or relaxations, and on hybrid partitions per-phase
+ * milliseconds (gpu_ms, cpu_ms, exchange_ms), bytes exchanged
+ * (exchange_bytes, of which exchange_h2d_bytes host-to-GPU) and the host
+ * vertices' out-edges processed (cpu_edges).  Same return convention as
+ * partition_info. */
 int tg_last_stats(char *json, size_t cap);
 
 #ifdef __cplusplus
