@@ -66,6 +66,38 @@ def load_traffic(kernel: str, workload: str):
     return None
 
 
+def gather_reference(n, cols, count=1 << 27, reps=3):
+    """A reference for the SSSP relaxation's access pattern, measured
+    with torch.index_select (not this library's kernels) on an n-element int32
+    array (the distance vector): (a) `count` uniformly random indices; (b) the
+    graph's own column array as the index stream, i.e. one read of the
+    destination's distance per edge in CSR order -- the relaxation's reads
+    without its weights, comparisons and atomics."""
+    import torch
+
+    def rate(idx):
+        out = torch.empty(idx.numel(), dtype=torch.int32, device="cuda")
+        torch.index_select(src, 0, idx, out=out)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            torch.index_select(src, 0, idx, out=out)
+        b.record()
+        torch.cuda.synchronize()
+        return idx.numel() / (a.elapsed_time(b) / 1e3 / reps)
+
+    src = torch.zeros(n, dtype=torch.int32, device="cuda")
+    uniform = rate(torch.randint(0, n, (count,), dtype=torch.int64, device="cuda"))
+    edge = rate(torch.from_numpy(cols).to("cuda"))
+    del src
+    torch.cuda.empty_cache()
+    return {"uniform_gathers_per_s": round(uniform), "edge_order_gathers_per_s": round(edge),
+            "array_elems": n, "edges": int(cols.size),
+            "how": "torch.index_select over an n-element int32 array: uniformly random int64 indices, "
+                   "and the CSR column array (int32) as indices"}
+
+
 def cpu_baseline(g, w, roots, iters, step_units):
     """The oracle on the host cores over a bounded sample of the same work."""
     import concurrent.futures as cf
@@ -705,6 +737,7 @@ def main():
         "sssp": {"gteps": round(sssp_edges / (t_sssp / 1e3) / 1e9, 2), "ms_per_root": round(t_sssp / nr, 4),
                  "supersteps_per_root": round(ss.get("supersteps", 0) / nr, 1),
                  "work_efficiency": round(ss.get("relaxations", 0) / max(sssp_edges, 1), 3)},
+        "gather_reference": None,
         "pagerank": {"gteps": round(pr_edges / (t_pr / 1e3) / 1e9, 2),
                      "ms_per_iter": round(t_pr / args.pr_iters, 4),
                      "hbm_gbs_algorithmic": round(pr_bytes_iter * args.pr_iters / (t_pr / 1e3) / 1e9, 1)},
@@ -713,6 +746,12 @@ def main():
         "tuning": {"source": tuning_used, "values": tg.partition_info(P)["tuning"]},
         "host_wall_s": round(wall, 3),
     }
+    if run_sssp and "sssp_relax_ms" in ss:
+        gc = gather_reference(V, g.cols)
+        relax_rate = ss.get("relaxations", 0) / (ss["sssp_relax_ms"] / 1e3)
+        gc["sssp_relaxations_per_s"] = round(relax_rate)
+        gc["sssp_relax_vs_edge_order"] = round(relax_rate / gc["edge_order_gathers_per_s"], 3)
+        out["gather_reference"] = gc
     if not args.no_cpu_baseline:
         units = {"bfs": bfs_edges, "sssp": sssp_edges, "pr": pr_edges}
         print("[bench] timing the oracle on the host (bounded sample)", file=sys.stderr, flush=True)
