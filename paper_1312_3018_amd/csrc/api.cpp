@@ -98,6 +98,7 @@ Workspace::~Workspace() {
   if (h_plan) TG_QUIET(hipHostFree(h_plan));
   if (h_flags) TG_QUIET(hipHostFree(h_flags));
   if (h_work) TG_QUIET(hipHostFree(h_work));
+  if (h_stat) TG_QUIET(hipHostFree(h_stat));
 }
 
 int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
@@ -130,7 +131,7 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   TG_TRY(dalloc(arena, &hubpref, hubs + 1));
   TG_TRY(dalloc(arena, &scalars, 16));
   TG_TRY(dalloc(arena, &counters, 64));
-  TG_TRY(dalloc(arena, &work, 8));
+  TG_TRY(dalloc(arena, &work, (size_t)tgk::STAT_COUNTERS * tgk::STAT_SPAN));
   TG_TRY(dalloc(arena, &rest, 2));
   TG_TRY(dalloc(arena, &bcount, nwords / 1024 + 1));
   TG_TRY(dalloc(arena, &plan, 1));
@@ -138,12 +139,38 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   TG_HIP(hipMemset(bits_b, 0, nwords * sizeof(uint32_t)));
   TG_HIP(hipMemset(bits_c, 0, nwords * sizeof(uint32_t)));
   TG_HIP(hipMemset(counters, 0, 64 * sizeof(uint32_t)));
-  TG_HIP(hipMemset(work, 0, 8 * sizeof(unsigned long long)));
+  TG_HIP(hipMemset(work, 0, (size_t)tgk::STAT_COUNTERS * tgk::STAT_SPAN * sizeof(unsigned long long)));
   if (!h_plan) TG_HIP(hipHostMalloc((void **)&h_plan, sizeof(Plan), hipHostMallocDefault));
   if (!h_flags) TG_HIP(hipHostMalloc((void **)&h_flags, 64 * sizeof(uint32_t), hipHostMallocDefault));
   if (!h_work) TG_HIP(hipHostMalloc((void **)&h_work, 8 * sizeof(unsigned long long), hipHostMallocDefault));
+  if (!h_stat)
+    TG_HIP(hipHostMalloc((void **)&h_stat, (size_t)tgk::STAT_COUNTERS * tgk::STAT_SPAN * sizeof(unsigned long long),
+                         hipHostMallocDefault));
   cap_n = n;
   return TG_OK;
+}
+
+int stat_zero(Workspace &ws, int k, hipStream_t s) {
+  TG_HIP(hipMemsetAsync(tgk::stat_counter(ws.work, k), 0, tgk::STAT_SPAN * sizeof(unsigned long long), s));
+  return TG_OK;
+}
+
+int stat_zero_all(Workspace &ws, hipStream_t s) {
+  TG_HIP(hipMemsetAsync(ws.work, 0, (size_t)tgk::STAT_COUNTERS * tgk::STAT_SPAN * sizeof(unsigned long long), s));
+  return TG_OK;
+}
+
+int stat_fetch(Workspace &ws, int k, hipStream_t s) {
+  TG_HIP(hipMemcpyAsync(tgk::stat_counter(ws.h_stat, k), tgk::stat_counter(ws.work, k), tgk::STAT_SPAN * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, s));
+  return TG_OK;
+}
+
+unsigned long long stat_sum(const Workspace &ws, int k) {
+  const unsigned long long *c = tgk::stat_counter(ws.h_stat, k);
+  unsigned long long t = 0;
+  for (int i = 0; i < tgk::STAT_SLOTS; ++i) t += c[(size_t)i * tgk::STAT_STRIDE];
+  return t;
 }
 
 // ----------------------------------------------------------------- tuning
@@ -710,7 +737,7 @@ extern "C" int bfs(const tg_partition *pc, const int32_t *roots, int32_t num_roo
   const int64_t V = p->g->n;
   int64_t supersteps = 0;
   TG_TRY(p->ws.ensure(p->gpu, 0));
-  TG_HIP(hipMemsetAsync(p->ws.work, 0, 8 * sizeof(unsigned long long), s));
+  TG_TRY(stat_zero_all(p->ws, s));
   for (int32_t r = 0; r < num_roots; ++r) {
     const int32_t l = p->h_l_of_g[roots[r]];
     int64_t depth = 0;
@@ -719,14 +746,14 @@ extern "C" int bfs(const tg_partition *pc, const int32_t *roots, int32_t num_roo
     TG_TRY(collect_levels(p->gpu, p->ws.bits_a, p->ws.state, levels + (int64_t)r * V, s));
     if (parents) TG_TRY(bfs_parents(p->gpu, p->ws.bits_a, p->ws.state, l, parents + (int64_t)r * V, s));
   }
-  TG_HIP(hipMemcpyAsync(p->ws.h_work, p->ws.work, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  for (int k = 0; k < 4; ++k) TG_TRY(stat_fetch(p->ws, k, s));
   TG_HIP(hipStreamSynchronize(s));
   stats_add("roots", num_roots);
   stats_add("supersteps", (double)supersteps);
-  stats_add("edges_scanned", (double)p->ws.h_work[0]);
-  stats_add("vertices_expanded", (double)p->ws.h_work[1]);
-  stats_add("bottom_up_edges_checked", (double)p->ws.h_work[2]);
-  stats_add("bottom_up_steps", (double)p->ws.h_work[3]);
+  stats_add("edges_scanned", (double)stat_sum(p->ws, 0));
+  stats_add("vertices_expanded", (double)stat_sum(p->ws, 1));
+  stats_add("bottom_up_edges_checked", (double)stat_sum(p->ws, 2));
+  stats_add("bottom_up_steps", (double)stat_sum(p->ws, 3));
   ktimer_emit();
   return TG_OK;
 }
@@ -745,19 +772,19 @@ extern "C" int sssp(const tg_partition *pc, const int32_t *roots, int32_t num_ro
   const int64_t V = p->g->n;
   int64_t rounds_total = 0;
   TG_TRY(p->ws.ensure(p->gpu, 0));
-  TG_HIP(hipMemsetAsync(p->ws.work, 0, 8 * sizeof(unsigned long long), s));
+  TG_TRY(stat_zero_all(p->ws, s));
   for (int32_t r = 0; r < num_roots; ++r) {
     int64_t rounds = 0;
     TG_TRY(gpu_sssp(p, p->h_l_of_g[roots[r]], s, &rounds));
     rounds_total += rounds;
     TG_TRY(collect_i32(p->gpu, p->ws.state, dist + (int64_t)r * V, s));
   }
-  TG_HIP(hipMemcpyAsync(p->ws.h_work, p->ws.work, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  for (int k = 0; k < 2; ++k) TG_TRY(stat_fetch(p->ws, k, s));
   TG_HIP(hipStreamSynchronize(s));
   stats_add("roots", num_roots);
   stats_add("supersteps", (double)rounds_total);
-  stats_add("relaxations", (double)p->ws.h_work[0]);
-  stats_add("activations", (double)p->ws.h_work[1]);
+  stats_add("relaxations", (double)stat_sum(p->ws, 0));
+  stats_add("activations", (double)stat_sum(p->ws, 1));
   ktimer_emit();
   return TG_OK;
 }
@@ -771,14 +798,14 @@ extern "C" int cc(const tg_partition *pc, int32_t *labels, void *stream) {
   stats_reset("cc");
   ktimer_reset();
   TG_TRY(p->ws.ensure(p->gpu, 0));
-  TG_HIP(hipMemsetAsync(p->ws.work, 0, 8 * sizeof(unsigned long long), s));
+  TG_TRY(stat_zero_all(p->ws, s));
   int64_t rounds = 0;
   TG_TRY(gpu_cc(p, s, &rounds));
   if (p->gpu.n > 0) TG_TRY(collect_i32(p->gpu, p->ws.state, labels, s));
-  TG_HIP(hipMemcpyAsync(p->ws.h_work, p->ws.work, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  TG_TRY(stat_fetch(p->ws, 0, s));
   TG_HIP(hipStreamSynchronize(s));
   stats_add("supersteps", (double)rounds);
-  stats_add("edges_pushed", (double)p->ws.h_work[0]);
+  stats_add("edges_pushed", (double)stat_sum(p->ws, 0));
   ktimer_emit();
   return TG_OK;
 }

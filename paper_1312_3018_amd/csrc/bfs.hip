@@ -94,24 +94,34 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_expand(const Plan *__restrict__ P
   n_edges = block_sum(n_edges);
   n_verts = block_sum(n_verts);
   if (threadIdx.x == 0 && n_edges + n_verts > 0) {
-    atomicAdd(work, n_edges);
-    atomicAdd(work + 1, n_verts);
+    stat_add(stat_counter(work, 0), n_edges);
+    stat_add(stat_counter(work, 1), n_verts);
   }
+}
+
+// Out-degree of a vertex that joins the next frontier: from the in-edge
+// offsets already loaded when in- and out-edges are the same (`ooff` null),
+// else from the out-edge offsets.
+__device__ __forceinline__ unsigned long long joined_degree(const int64_t *ooff, int64_t v, int64_t e0, int64_t e1) {
+  return (unsigned long long)(ooff ? ooff[v + 1] - ooff[v] : e1 - e0);
 }
 
 // Bottom-up step, one thread per vertex in [v0, v1): an unvisited vertex
 // looks at its in-neighbours four at a time and joins the next frontier at
-// the first one found in `fbits` (the level-L set).
+// the first one found in `fbits` (the level-L set).  The out-degrees of the
+// vertices that join are summed into `degsum` (the direction switch's m_f).
 __global__ __launch_bounds__(BLOCK) void k_bfs_bottom_up_thread(const int64_t *__restrict__ ioff,
                                                                 const int32_t *__restrict__ icol,
                                                                 const uint32_t *__restrict__ fbits, uint32_t *visited,
-                                                                int64_t v0, int64_t v1, unsigned long long *work) {
-  unsigned long long checked = 0;
+                                                                int64_t v0, int64_t v1, unsigned long long *work,
+                                                                const int64_t *__restrict__ ooff,
+                                                                unsigned long long *degsum) {
+  unsigned long long checked = 0, joined = 0;
   for (int64_t v = v0 + (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < v1; v += (int64_t)gridDim.x * BLOCK) {
     const uint32_t bit = 1u << (v & 31);
     if (visited[v >> 5] & bit) continue;
-    const int64_t e1 = ioff[v + 1];
-    for (int64_t e = ioff[v]; e < e1; e += 4) {
+    const int64_t e0 = ioff[v], e1 = ioff[v + 1];
+    for (int64_t e = e0; e < e1; e += 4) {
       int32_t u[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) u[k] = icol[e + k < e1 ? e + k : e1 - 1];
@@ -121,12 +131,15 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_bottom_up_thread(const int64_t *_
       checked += (unsigned long long)(e1 - e < 4 ? e1 - e : 4);
       if (hit) {
         atomicOr(visited + (v >> 5), bit);
+        joined += joined_degree(ooff, v, e0, e1);
         break;
       }
     }
   }
   checked = block_sum(checked);
-  if (threadIdx.x == 0 && checked) atomicAdd(work, checked);
+  joined = block_sum(joined);
+  if (threadIdx.x == 0 && checked) stat_add(work, checked);
+  if (threadIdx.x == 0 && joined) stat_add(degsum, joined);
 }
 
 // The same with one wave per vertex in [v0, v1) (high in-degree): the wave
@@ -134,27 +147,34 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_bottom_up_thread(const int64_t *_
 __global__ __launch_bounds__(BLOCK) void k_bfs_bottom_up_wave(const int64_t *__restrict__ ioff,
                                                               const int32_t *__restrict__ icol,
                                                               const uint32_t *__restrict__ fbits, uint32_t *visited,
-                                                              int64_t v0, int64_t v1, unsigned long long *work) {
+                                                              int64_t v0, int64_t v1, unsigned long long *work,
+                                                              const int64_t *__restrict__ ooff,
+                                                              unsigned long long *degsum) {
   const int lane = threadIdx.x & 63;
   const int64_t nw = ((int64_t)gridDim.x * BLOCK) >> 6;
-  unsigned long long checked = 0;
+  unsigned long long checked = 0, joined = 0;
   for (int64_t v = v0 + (((int64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6); v < v1; v += nw) {
     const uint32_t bit = 1u << (v & 31);
     if (visited[v >> 5] & bit) continue;
-    const int64_t e1 = ioff[v + 1];
-    for (int64_t e = ioff[v]; e < e1; e += 64) {
+    const int64_t e0 = ioff[v], e1 = ioff[v + 1];
+    for (int64_t e = e0; e < e1; e += 64) {
       const bool live = e + lane < e1;
       const int32_t u = live ? icol[e + lane] : 0;
       const bool hit = live && ((fbits[u >> 5] >> (u & 31)) & 1u);
       if (lane == 0) checked += (unsigned long long)(e1 - e < 64 ? e1 - e : 64);
       if (__ballot(hit)) {
-        if (lane == 0) atomicOr(visited + (v >> 5), bit);
+        if (lane == 0) {
+          atomicOr(visited + (v >> 5), bit);
+          joined += joined_degree(ooff, v, e0, e1);
+        }
         break;
       }
     }
   }
   checked = block_sum(checked);
-  if (threadIdx.x == 0 && checked) atomicAdd(work, checked);
+  joined = block_sum(joined);
+  if (threadIdx.x == 0 && checked) stat_add(work, checked);
+  if (threadIdx.x == 0 && joined) stat_add(degsum, joined);
 }
 
 }  // namespace
@@ -186,17 +206,20 @@ int bfs_expand_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int
 // One bottom-up step over the in-edges: vertices [0, wave_end) one wave each,
 // [wave_end, n_end) one thread each.
 static int bfs_bottom_up_launch(const GpuPart &g, Workspace &ws, const uint32_t *fbits, int64_t wave_end,
-                                int64_t n_end, hipStream_t s) {
+                                int64_t n_end, unsigned long long *degsum, hipStream_t s) {
+  // the joining vertices' out-degrees: in-edge rows are out-edge rows on a
+  // symmetric whole graph
+  const int64_t *ooff = g.in_alias ? nullptr : g.out.off;
   const int tk = ktimer_start(s);
   if (wave_end > 0) {
     const int grid = (int)std::min<int64_t>((wave_end * 64 + BLOCK - 1) / BLOCK, 8192);
     hipLaunchKernelGGL(k_bfs_bottom_up_wave, dim3(grid), dim3(BLOCK), 0, s, g.in.off, g.in.col, fbits, ws.bits_a,
-                       (int64_t)0, wave_end, ws.work + 2);
+                       (int64_t)0, wave_end, stat_counter(ws.work, 2), ooff, degsum);
   }
   if (n_end > wave_end) {
     const int grid = (int)std::min<int64_t>((n_end - wave_end + BLOCK - 1) / BLOCK, 16384);
     hipLaunchKernelGGL(k_bfs_bottom_up_thread, dim3(grid), dim3(BLOCK), 0, s, g.in.off, g.in.col, fbits, ws.bits_a,
-                       wave_end, n_end, ws.work + 2);
+                       wave_end, n_end, stat_counter(ws.work, 2), ooff, degsum);
   }
   ktimer_stop(tk, s, "bfs_bottom_up");
   TG_HIP(hipGetLastError());
@@ -214,8 +237,8 @@ int gpu_bfs(tg_partition *p, int32_t root, hipStream_t s, int64_t *levels_out) {
   TG_HIP(hipMemsetAsync(visited, 0, ws.nwords * sizeof(uint32_t), s));
   TG_HIP(hipMemsetAsync(prev, 0, ws.nwords * sizeof(uint32_t), s));
   TG_TRY(set_bit(visited, root, s));
-  unsigned long long *degsum = ws.work + 4;
-  TG_TRY(frontier_compact_bfs(g, ws, visited, prev, fbits, ws.queue, ws.state, 0, degsum, s));
+  unsigned long long *degsum = stat_counter(ws.work, 4);
+  TG_TRY(frontier_compact_bfs(g, ws, visited, prev, fbits, ws.queue, ws.state, 0, degsum, true, s));
   // vertices with in-edges: a symmetric whole graph ends them at its
   // degree-0 tail and has its in-degrees sorted, so its head (HUB and BLOCK
   // bins) gets a wave per vertex; most vertices find a parent among their
@@ -229,12 +252,12 @@ int gpu_bfs(tg_partition *p, int32_t root, hipStream_t s, int64_t *levels_out) {
     if (L > g.n) return set_error(TG_EDEVICE, "bfs: more supersteps than vertices");
     TG_TRY(frontier_plan(g, ws, ws.queue, t, s, false));
     TG_HIP(hipMemcpyAsync(ws.h_plan, ws.plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
-    TG_HIP(hipMemcpyAsync(ws.h_work + 6, degsum, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    TG_TRY(stat_fetch(ws, 4, s));
     TG_HIP(hipStreamSynchronize(s));
     ktimer_flush();
     const int64_t n_f = ws.h_plan->count;
     if (n_f == 0) break;
-    const int64_t m_f = (int64_t)ws.h_work[6];
+    const int64_t m_f = (int64_t)stat_sum(ws, 4);
     m_u -= m_f;
     if (t.bfs_do) {
       // Beamer's switch: bottom-up while the frontier is heavy, back once it is small
@@ -242,13 +265,15 @@ int gpu_bfs(tg_partition *p, int32_t root, hipStream_t s, int64_t *levels_out) {
       else if (bottom_up && n_f < g.n / t.bfs_beta) bottom_up = false;
     }
     if (bottom_up) {
-      TG_TRY(bfs_bottom_up_launch(g, ws, fbits, wave_end, n_end, s));
-      hipLaunchKernelGGL(k_count_step, dim3(1), dim3(64), 0, s, ws.work + 3);
+      // the bottom-up kernels sum the new frontier's out-degrees themselves
+      TG_TRY(stat_zero(ws, 4, s));
+      TG_TRY(bfs_bottom_up_launch(g, ws, fbits, wave_end, n_end, degsum, s));
+      hipLaunchKernelGGL(k_count_step, dim3(1), dim3(64), 0, s, stat_counter(ws.work, 3));
       TG_HIP(hipGetLastError());
     } else {
       TG_TRY(bfs_expand_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], t, s));
     }
-    TG_TRY(frontier_compact_bfs(g, ws, visited, prev, fbits, ws.queue, ws.state, L + 1, degsum, s));
+    TG_TRY(frontier_compact_bfs(g, ws, visited, prev, fbits, ws.queue, ws.state, L + 1, degsum, !bottom_up, s));
   }
   if (levels_out) *levels_out = L;
   return TG_OK;

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(BLOCK) void k_cc_push(const Plan *__restrict__ Pp, 
     }
   }
   n_edges = block_sum(n_edges);
-  if (threadIdx.x == 0 && n_edges > 0) atomicAdd(work, n_edges);
+  if (threadIdx.x == 0 && n_edges > 0) stat_add(work, n_edges);
 }
 
 }  // namespace

@@ -165,7 +165,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ 
   }
   if (degsum) {
     deg = block_sum(deg);
-    if (threadIdx.x == 0 && deg) atomicAdd(degsum, deg);
+    if (threadIdx.x == 0 && deg) stat_add(degsum, deg);
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == BLOCK - 1) plan->count = (int32_t)o;
 }
@@ -238,12 +238,12 @@ int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, 
 
 int frontier_compact_bfs(const GpuPart &g, Workspace &ws, uint32_t *visited, uint32_t *prev, uint32_t *fbits,
                          int32_t *queue, int32_t *level, int32_t level_value, unsigned long long *degsum,
-                         hipStream_t s) {
+                         bool count_degrees, hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
-  TG_HIP(hipMemsetAsync(degsum, 0, sizeof(unsigned long long), s));
+  if (count_degrees) TG_HIP(hipMemsetAsync(degsum, 0, STAT_SPAN * sizeof(unsigned long long), s));
   hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, visited, prev, ws.bcount);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, visited, prev, 0, ws.bcount, queue, level,
-                     level_value, g.out_bins, g.n, ws.plan, fbits, g.out.off, degsum);
+                     level_value, g.out_bins, g.n, ws.plan, fbits, g.out.off, count_degrees ? degsum : nullptr);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }

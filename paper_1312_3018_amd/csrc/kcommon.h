@@ -161,6 +161,24 @@ __device__ __forceinline__ T wave_sum(T x) {
 }
 
 // Sum over the 256-thread block; every thread gets the result.
+// Per-call counters that every block of a large grid adds to.  Atomics from
+// thousands of blocks on one address serialize (device-scope atomics are
+// resolved beyond the L2): a counter is STAT_SLOTS slots on separate
+// 128-byte lines, block b adds into slot b mod STAT_SLOTS, and the host sums
+// the slots.  Counter k starts at stat_counter(base, k).
+constexpr int STAT_SLOTS = 64;
+constexpr int STAT_STRIDE = 16;  // unsigned long longs between slots (128 bytes)
+constexpr int STAT_SPAN = STAT_SLOTS * STAT_STRIDE;
+constexpr int STAT_COUNTERS = 8;
+
+__host__ __device__ __forceinline__ unsigned long long *stat_counter(unsigned long long *base, int k) {
+  return base + (size_t)k * STAT_SPAN;
+}
+
+__device__ __forceinline__ void stat_add(unsigned long long *counter, unsigned long long x) {
+  atomicAdd(counter + (size_t)(blockIdx.x & (STAT_SLOTS - 1)) * STAT_STRIDE, x);
+}
+
 template <typename T>
 __device__ __forceinline__ T block_sum(T x) {
   __shared__ T red[BLOCK / 64];

@@ -109,8 +109,8 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
   n_edges = block_sum(n_edges);
   n_verts = block_sum(n_verts);
   if (threadIdx.x == 0 && n_edges + n_verts > 0) {
-    atomicAdd(work, n_edges);
-    atomicAdd(work + 1, n_verts);
+    stat_add(stat_counter(work, 0), n_edges);
+    stat_add(stat_counter(work, 1), n_verts);
   }
 }
 
@@ -164,8 +164,8 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax_cls(const Plan *__restrict
   n_edges = block_sum(n_edges);
   n_verts = block_sum(n_verts);
   if (threadIdx.x == 0 && n_edges + n_verts > 0) {
-    atomicAdd(work, n_edges);
-    atomicAdd(work + 1, n_verts);
+    stat_add(stat_counter(work, 0), n_edges);
+    stat_add(stat_counter(work, 1), n_verts);
   }
 }
 

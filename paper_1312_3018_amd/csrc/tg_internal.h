@@ -253,9 +253,14 @@ struct Workspace {
   double *hub_dangling = nullptr;
   double *scalars = nullptr;     // small fp64 cells (dangling sums, ...)
   uint32_t *counters = nullptr;  // small counters and flags (zeroed)
-  unsigned long long *work = nullptr;  // [0] edges scanned, [1] vertices expanded
+  // per-call counters, STAT_COUNTERS of them, each spread over STAT_SLOTS
+  // slots (stat_counter / stat_add): 0 edges scanned or relaxations, 1
+  // vertices expanded or activations, 2 bottom-up edges checked, 3
+  // bottom-up steps, 4 the BFS frontier's out-degree sum
+  unsigned long long *work = nullptr;
   unsigned long long *rest = nullptr;  // near/far compaction: [0] left active, [1] their least distance
-  unsigned long long *h_work = nullptr;
+  unsigned long long *h_work = nullptr;  // small pinned scratch
+  unsigned long long *h_stat = nullptr;  // pinned mirror of `work`
   uint32_t *bcount = nullptr;    // per-block counts for compaction
   Plan *plan = nullptr;          // device frontier plan
   int64_t *hubpref = nullptr;    // frontier hub chunk prefix
@@ -267,6 +272,13 @@ struct Workspace {
   int ensure(const GpuPart &g, int64_t hub_chunks_needed);
   ~Workspace();
 };
+
+// Spread counters (see `work`): zero counter k (or all), copy it to h_stat
+// (asynchronously on s), and sum its slots on the host after a wait.
+int stat_zero(Workspace &ws, int k, hipStream_t s);
+int stat_zero_all(Workspace &ws, hipStream_t s);
+int stat_fetch(Workspace &ws, int k, hipStream_t s);
+unsigned long long stat_sum(const Workspace &ws, int k);
 
 struct HybridState;
 struct SlotEngine;
@@ -306,10 +318,11 @@ int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, 
 int frontier_plan(const GpuPart &g, Workspace &ws, const int32_t *queue, const Tuning &t,
                   hipStream_t s, bool sync);
 // BFS compaction (mode 0) that also writes the new frontier as a bitmap into
-// `fbits` and adds the frontier's out-degree sum into *degsum (zeroed first).
+// `fbits` and, with count_degrees, sets *degsum to the frontier's out-degree
+// sum (otherwise *degsum is left as it is).
 int frontier_compact_bfs(const GpuPart &g, Workspace &ws, uint32_t *visited, uint32_t *prev, uint32_t *fbits,
                          int32_t *queue, int32_t *level, int32_t level_value, unsigned long long *degsum,
-                         hipStream_t s);
+                         bool count_degrees, hipStream_t s);
 // SSSP compaction of the active bitmap: a vertex is taken if dist < settled
 // (it really got lower since it last relaxed; settled := dist when taken) and,
 // with `near`, dist < thresh; stale bits are dropped; with `near` the others
