@@ -132,7 +132,6 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   TG_TRY(dalloc(arena, &scalars, 16));
   TG_TRY(dalloc(arena, &counters, 64));
   TG_TRY(dalloc(arena, &work, (size_t)tgk::STAT_COUNTERS * tgk::STAT_SPAN));
-  TG_TRY(dalloc(arena, &rest, 2));
   TG_TRY(dalloc(arena, &bcount, nwords / 1024 + 1));
   TG_TRY(dalloc(arena, &plan, 1));
   TG_HIP(hipMemset(bits_a, 0, nwords * sizeof(uint32_t)));

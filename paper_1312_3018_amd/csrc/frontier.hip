@@ -65,11 +65,13 @@ __device__ __forceinline__ void sssp_filter4(uint32_t (&w)[4], int64_t word0, co
 
 // SSSP compaction, first pass: filter the active bitmap (sssp_filter4),
 // leave the untaken active bits in `bits`, the taken ones in `keep_out`, and
-// each block's count in bcount.
+// each block's count in bcount.  With rest_cnt, the vertices left active
+// beyond the threshold are counted into it and their least distance goes
+// into rest_min (both spread counters; rest_min's slots start all ones).
 __global__ __launch_bounds__(BLOCK) void k_sssp_filter(uint32_t *__restrict__ bits, uint32_t *__restrict__ keep_out,
                                                        uint32_t *__restrict__ bcount, const int32_t *__restrict__ dist,
                                                        int32_t *__restrict__ settled, int32_t thresh,
-                                                       unsigned long long *rest_out) {
+                                                       unsigned long long *rest_cnt, unsigned long long *rest_min) {
   const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // uint4 index
   const uint4 v = reinterpret_cast<const uint4 *>(bits)[q];
   uint32_t w[4] = {v.x, v.y, v.z, v.w}, keep[4], dr[4];
@@ -79,14 +81,15 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_filter(uint32_t *__restrict__ bi
   reinterpret_cast<uint4 *>(bits)[q] =
       make_uint4(v.x & ~(keep[0] | dr[0]), v.y & ~(keep[1] | dr[1]), v.z & ~(keep[2] | dr[2]), v.w & ~(keep[3] | dr[3]));
   reinterpret_cast<uint4 *>(keep_out)[q] = make_uint4(keep[0], keep[1], keep[2], keep[3]);
-  if (rest_out) {
+  if (rest_cnt) {
     r = block_sum(r);
     for (int o = 32; o > 0; o >>= 1) {
       const int32_t y = __shfl_xor(rmin, o, 64);
       rmin = y < rmin ? y : rmin;
     }
-    if ((threadIdx.x & 63) == 0 && rmin < TG_INF) atomicMin(reinterpret_cast<int32_t *>(rest_out + 1), rmin);
-    if (threadIdx.x == 0 && r) atomicAdd(rest_out, (unsigned long long)r);
+    if ((threadIdx.x & 63) == 0 && rmin < TG_INF)
+      atomicMin(rest_min + (size_t)(blockIdx.x & (STAT_SLOTS - 1)) * STAT_STRIDE, (unsigned long long)rmin);
+    if (threadIdx.x == 0 && r) stat_add(rest_cnt, (unsigned long long)r);
   }
   uint32_t c = __popc(keep[0]) + __popc(keep[1]) + __popc(keep[2]) + __popc(keep[3]);
   c = block_sum(c);
@@ -251,14 +254,18 @@ int frontier_compact_bfs(const GpuPart &g, Workspace &ws, uint32_t *visited, uin
 int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
                           int32_t *settled, int32_t thresh, bool near, const BinBounds &bb, hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
+  unsigned long long *rest_cnt = nullptr, *rest_min = nullptr;
   if (near) {
-    // rest[0] = active vertices left behind, rest[1] (low word) = their least distance
-    const unsigned long long init[2] = {0ull, (unsigned long long)(uint32_t)TG_INF};
-    TG_HIP(hipMemcpyAsync(ws.rest, init, sizeof(init), hipMemcpyHostToDevice, s));
+    // counter 5: active vertices left beyond the threshold; counter 6: their
+    // least distance (all-ones slots: none)
+    rest_cnt = stat_counter(ws.work, 5);
+    rest_min = stat_counter(ws.work, 6);
+    TG_TRY(stat_zero(ws, 5, s));
+    TG_HIP(hipMemsetAsync(rest_min, 0xFF, STAT_SPAN * sizeof(unsigned long long), s));
   }
   // the taken bits go to bits_b (free during SSSP and connected components)
   hipLaunchKernelGGL(k_sssp_filter, dim3(blocks), dim3(BLOCK), 0, s, bits, ws.bits_b, ws.bcount, dist, settled,
-                     near ? thresh : TG_INF, near ? ws.rest : nullptr);
+                     near ? thresh : TG_INF, rest_cnt, rest_min);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, ws.bits_b, nullptr, 4, ws.bcount, queue,
                      nullptr, 0, bb, g.n, ws.plan, nullptr, nullptr, nullptr);
   TG_HIP(hipGetLastError());

@@ -104,7 +104,8 @@ __global__ __launch_bounds__(BLOCK) void k_ms_clear(const Plan *__restrict__ Pp,
     frontier[queue[i]] = 0;
 }
 
-// OR over the block, then one atomic per block.
+// OR over the block, then one atomic per block into slot (block mod
+// STAT_SLOTS) of `dst` (slots STAT_STRIDE words apart; the host ORs them).
 __device__ __forceinline__ void block_or_into(u64 x, u64 *dst) {
   for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
   __shared__ u64 red[BLOCK / 64];
@@ -114,7 +115,7 @@ __device__ __forceinline__ void block_or_into(u64 x, u64 *dst) {
   if (threadIdx.x == 0) {
     u64 s = 0;
     for (int k = 0; k < BLOCK / 64; ++k) s |= red[k];
-    if (s) atomicOr(dst, s);
+    if (s) atomicOr(dst + (size_t)(blockIdx.x & (STAT_SLOTS - 1)) * STAT_STRIDE, s);
   }
 }
 
@@ -216,7 +217,7 @@ int SlotEngine::init(tg_partition *part, int kind_, hipStream_t stream) {
   const int64_t n = std::max<int64_t>(g.n, 1);
   TG_TRY(dalloc(arena, &frontier, (size_t)n));
   TG_TRY(dalloc(arena, &next, (size_t)n));
-  TG_TRY(dalloc(arena, &alive, 2));
+  TG_TRY(dalloc(arena, &alive, STAT_SPAN));
   TG_HIP(hipMemset(frontier, 0, (size_t)n * sizeof(u64)));
   TG_HIP(hipMemset(next, 0, (size_t)n * sizeof(u64)));
   if (kind == kSlotBfs) {
@@ -227,7 +228,7 @@ int SlotEngine::init(tg_partition *part, int kind_, hipStream_t stream) {
     hipLaunchKernelGGL(k_fill_i32_all, dim3(2048), dim3(BLOCK), 0, s, dist, n * kSlots, TG_INF);
     TG_HIP(hipGetLastError());
   }
-  if (!h_alive) TG_HIP(hipHostMalloc((void **)&h_alive, 2 * sizeof(u64), hipHostMallocDefault));
+  if (!h_alive) TG_HIP(hipHostMalloc((void **)&h_alive, STAT_SPAN * sizeof(u64), hipHostMallocDefault));
   TG_HIP(hipMemset(ws.bits_a, 0, ws.nwords * sizeof(uint32_t)));
   TG_HIP(hipMemset(ws.counters, 0, 64 * sizeof(uint32_t)));
   memset(&tab, 0, sizeof(tab));
@@ -288,7 +289,7 @@ int SlotEngine::launch_step() {
   // next frontier: every vertex that received a slot bit (mode 1 takes and clears)
   TG_TRY(frontier_compact(g, ws, 1, ws.bits_a, nullptr, ws.queue, nullptr, 0, s));
   TG_TRY(frontier_plan(g, ws, ws.queue, t, s, false));
-  TG_HIP(hipMemsetAsync(alive, 0, sizeof(u64), s));
+  TG_HIP(hipMemsetAsync(alive, 0, STAT_SPAN * sizeof(u64), s));
   const unsigned fgrid = nblk(std::min<int64_t>(g.n, 1 << 20));
   if (kind == kSlotBfs)
     hipLaunchKernelGGL(k_ms_bfs_finalize, dim3(fgrid), dim3(BLOCK), 0, s, ws.plan, ws.queue, visited, frontier, next,
@@ -297,7 +298,7 @@ int SlotEngine::launch_step() {
     hipLaunchKernelGGL(k_ms_sssp_finalize, dim3(fgrid), dim3(BLOCK), 0, s, ws.plan, ws.queue, frontier, next, alive);
   TG_HIP(hipGetLastError());
   TG_HIP(hipMemcpyAsync(ws.h_plan, ws.plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
-  TG_HIP(hipMemcpyAsync(h_alive, alive, sizeof(u64), hipMemcpyDeviceToHost, s));
+  TG_HIP(hipMemcpyAsync(h_alive, alive, STAT_SPAN * sizeof(u64), hipMemcpyDeviceToHost, s));
   return TG_OK;
 }
 
@@ -307,7 +308,9 @@ int SlotEngine::finish_step(u64 *finished) {
   have_queue = true;
   ++supersteps;
   // a busy slot with no bit on the new frontier has finished
-  *finished = busy & ~h_alive[0];
+  u64 any = 0;
+  for (int i = 0; i < STAT_SLOTS; ++i) any |= h_alive[(size_t)i * STAT_STRIDE];
+  *finished = busy & ~any;
   return TG_OK;
 }
 

@@ -325,12 +325,16 @@ int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) 
     } else {
       TG_TRY(frontier_compact_sssp(g, ws, active, ws.queue, dist, ws.settled,
                                    (int32_t)std::min<int64_t>(thresh, TG_INF), true, bb, s));
-      TG_HIP(hipMemcpyAsync(ws.h_work + 4, ws.rest, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+      TG_TRY(stat_fetch(ws, 5, s));
+      TG_TRY(stat_fetch(ws, 6, s));
       TG_TRY(frontier_plan_bins(g, ws, ws.queue, bb, len, p->tune, s, true));
       if (ws.h_plan->count == 0) {
-        if (ws.h_work[4] == 0) break;  // nothing left beyond the threshold either
+        if (stat_sum(ws, 5) == 0) break;  // nothing left beyond the threshold either
         // jump to the least distance still waiting
-        thresh = (int64_t)(int32_t)(ws.h_work[5] & 0xFFFFFFFFull) + delta;
+        unsigned long long m = ~0ull;
+        const unsigned long long *mins = stat_counter(ws.h_stat, 6);
+        for (int i = 0; i < STAT_SLOTS; ++i) m = std::min(m, mins[(size_t)i * STAT_STRIDE]);
+        thresh = (int64_t)m + delta;
         continue;
       }
     }

@@ -256,9 +256,9 @@ struct Workspace {
   // per-call counters, STAT_COUNTERS of them, each spread over STAT_SLOTS
   // slots (stat_counter / stat_add): 0 edges scanned or relaxations, 1
   // vertices expanded or activations, 2 bottom-up edges checked, 3
-  // bottom-up steps, 4 the BFS frontier's out-degree sum
+  // bottom-up steps, 4 the BFS frontier's out-degree sum, 5 and 6 the
+  // near/far SSSP vertices left beyond the threshold and their least distance
   unsigned long long *work = nullptr;
-  unsigned long long *rest = nullptr;  // near/far compaction: [0] left active, [1] their least distance
   unsigned long long *h_work = nullptr;  // small pinned scratch
   unsigned long long *h_stat = nullptr;  // pinned mirror of `work`
   uint32_t *bcount = nullptr;    // per-block counts for compaction
@@ -326,7 +326,8 @@ int frontier_compact_bfs(const GpuPart &g, Workspace &ws, uint32_t *visited, uin
 // SSSP compaction of the active bitmap: a vertex is taken if dist < settled
 // (it really got lower since it last relaxed; settled := dist when taken) and,
 // with `near`, dist < thresh; stale bits are dropped; with `near` the others
-// stay active and ws.rest gets their count and least distance.
+// stay active and spread counters 5 and 6 get their count and least
+// distance.
 int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
                           int32_t *settled, int32_t thresh, bool near, const BinBounds &bb, hipStream_t s);
 // Plan over the queue with bins `bb` (queue positions set by a compaction
