@@ -110,6 +110,8 @@ __device__ __forceinline__ unsigned long long joined_degree(const int64_t *ooff,
 // looks at its in-neighbours four at a time and joins the next frontier at
 // the first one found in `fbits` (the level-L set).  The out-degrees of the
 // vertices that join are summed into `degsum` (the direction switch's m_f).
+// Waves cover whole bitmap words (lanes 0-31 one word, 32-63 the next), so
+// the joins of a word are set with one atomic instead of one per lane.
 __global__ __launch_bounds__(BLOCK) void k_bfs_bottom_up_thread(const int64_t *__restrict__ ioff,
                                                                 const int32_t *__restrict__ icol,
                                                                 const uint32_t *__restrict__ fbits, uint32_t *visited,
@@ -117,24 +119,31 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_bottom_up_thread(const int64_t *_
                                                                 const int64_t *__restrict__ ooff,
                                                                 unsigned long long *degsum) {
   unsigned long long checked = 0, joined = 0;
-  for (int64_t v = v0 + (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < v1; v += (int64_t)gridDim.x * BLOCK) {
-    const uint32_t bit = 1u << (v & 31);
-    if (visited[v >> 5] & bit) continue;
-    const int64_t e0 = ioff[v], e1 = ioff[v + 1];
-    for (int64_t e = e0; e < e1; e += 4) {
-      int32_t u[4];
+  const int lane = threadIdx.x & 63;
+  const int64_t start = v0 & ~(int64_t)31;
+  for (int64_t vb = start + (int64_t)blockIdx.x * BLOCK; vb < v1; vb += (int64_t)gridDim.x * BLOCK) {
+    const int64_t v = vb + threadIdx.x;
+    bool joins = false;
+    if (v >= v0 && v < v1 && !(visited[v >> 5] & (1u << (v & 31)))) {
+      const int64_t e0 = ioff[v], e1 = ioff[v + 1];
+      for (int64_t e = e0; e < e1; e += 4) {
+        int32_t u[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) u[k] = icol[e + k < e1 ? e + k : e1 - 1];
-      bool hit = false;
+        for (int k = 0; k < 4; ++k) u[k] = icol[e + k < e1 ? e + k : e1 - 1];
+        bool hit = false;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) hit |= (e + k < e1) && ((fbits[u[k] >> 5] >> (u[k] & 31)) & 1u);
-      checked += (unsigned long long)(e1 - e < 4 ? e1 - e : 4);
-      if (hit) {
-        atomicOr(visited + (v >> 5), bit);
-        joined += joined_degree(ooff, v, e0, e1);
-        break;
+        for (int k = 0; k < 4; ++k) hit |= (e + k < e1) && ((fbits[u[k] >> 5] >> (u[k] & 31)) & 1u);
+        checked += (unsigned long long)(e1 - e < 4 ? e1 - e : 4);
+        if (hit) {
+          joins = true;
+          joined += joined_degree(ooff, v, e0, e1);
+          break;
+        }
       }
     }
+    const uint64_t m = __ballot(joins);
+    if (lane == 0 && (uint32_t)m) atomicOr(visited + (v >> 5), (uint32_t)m);
+    if (lane == 32 && (uint32_t)(m >> 32)) atomicOr(visited + (v >> 5), (uint32_t)(m >> 32));
   }
   checked = block_sum(checked);
   joined = block_sum(joined);
