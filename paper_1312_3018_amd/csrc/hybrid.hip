@@ -36,6 +36,7 @@ struct CpuPart {
   std::vector<int64_t> ioff;
   std::vector<int32_t> icol;      // local in-edges
   std::vector<int32_t> g_of_l;    // host-local -> global id
+  std::vector<int32_t> l_of_g;    // global id -> host-local id (-1 on the GPU side)
   std::vector<int32_t> bdeg;      // boundary out-degree per host vertex
   int64_t n_dangling = 0;
 };
@@ -259,6 +260,7 @@ int build_hybrid(tg_partition *p, uint64_t seed) {
   // channels: GPU -> host uses the GPU's boundary edges, host -> GPU the host's
   build_channel(gb.src_off, gb.dst, gb.w, c_l_of_g, C.n, hy->g2c);
   build_channel(cb_off, cb_dst, cb_w, p->h_l_of_g, p->gpu.n, hy->c2g);
+  C.l_of_g = std::move(c_l_of_g);
   hy->raw_boundary_edges = (int64_t)gb.dst.size() + (int64_t)cb_dst.size();
 
   // device side
@@ -522,7 +524,6 @@ int hybrid_bfs(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *level
   std::vector<int32_t> clev((size_t)C.n);
   std::vector<int32_t> cfront, cnext;
   std::vector<std::vector<int32_t>> tl((size_t)omp_get_max_threads());
-  std::vector<int32_t> c_l_of_g;  // built lazily for root lookup
   Phase ph;
   hipEvent_t e0, e1, e2, e3;
   TG_HIP(hipEventCreate(&e0));
@@ -543,9 +544,8 @@ int hybrid_bfs(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *level
     if (gl >= 0) {
       TG_TRY(set_bit(visited, gl, s));
     } else {
-      int32_t cl = -1;
-      for (int64_t i = 0; i < C.n; ++i)
-        if (C.g_of_l[i] == root) { cl = (int32_t)i; break; }
+      const int32_t cl = C.l_of_g[root];
+      if (cl < 0) return set_error(TG_EDEVICE, "hybrid bfs: root %d is on neither side", root);
       cvis[cl] = 1;
       clev[cl] = 0;
       cfront.push_back(cl);
@@ -670,9 +670,8 @@ int hybrid_sssp(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *dist
       hipLaunchKernelGGL(k_set_i32h, dim3(1), dim3(64), 0, s, dist, (int64_t)gl, 0);
       TG_TRY(set_bit(active, gl, s));
     } else {
-      int32_t cl = -1;
-      for (int64_t i = 0; i < C.n; ++i)
-        if (C.g_of_l[i] == root) { cl = (int32_t)i; break; }
+      const int32_t cl = C.l_of_g[root];
+      if (cl < 0) return set_error(TG_EDEVICE, "hybrid sssp: root %d is on neither side", root);
       cdist[cl] = 0;
       cfront.push_back(cl);
     }
