@@ -402,31 +402,55 @@ struct PrOutbox : SumF64 {
   __device__ void finish(int32_t slot, double r) const { msg[slot] = r; }
 };
 
-__global__ void k_inbox_bfs(const int32_t *__restrict__ dst, const int64_t *__restrict__ msg, int64_t n,
-                            uint32_t *visited) {
-  const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (k >= n || msg[k] == I64_INF) return;
-  const int32_t v = dst[k];
-  atomicOr(visited + (v >> 5), 1u << (v & 31));
+// Sets bit v of the bitmap for every lane with `on`.  Lanes with ascending
+// ids hit the same 32-bit word in runs; each run ORs its bits together with
+// shuffles and only its first lane issues the atomic, so one word gets one
+// atomic instead of up to 32 (atomics on one address serialize).  Every lane
+// of the wave must call it.
+__device__ __forceinline__ void wave_or_bits(uint32_t *bits, int32_t v, bool on) {
+  if (!__ballot(on)) return;  // the same for the whole wave
+  const int lane = threadIdx.x & 63;
+  const int32_t w = on ? (v >> 5) : -1;
+  uint32_t b = on ? (1u << (v & 31)) : 0u;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t ow = __shfl_down(w, o, 64);
+    const uint32_t ob = __shfl_down(b, o, 64);
+    if (lane + o < 64 && ow == w) b |= ob;
+  }
+  const int32_t pw = __shfl_up(w, 1, 64);
+  if (on && (lane == 0 || pw != w)) atomicOr(bits + w, b);
 }
 
-__global__ void k_inbox_sssp(const int32_t *__restrict__ dst, const int64_t *__restrict__ msg, int64_t n,
-                             int32_t *dist, uint32_t *active, uint32_t *ovf, uint32_t *flags) {
+// Inbox vertices are ascending by slot, so a wave's visited bits come in
+// runs on a few words (wave_or_bits).
+__global__ __launch_bounds__(BLOCK) void k_inbox_bfs(const int32_t *__restrict__ dst,
+                                                     const int64_t *__restrict__ msg, int64_t n, uint32_t *visited) {
   const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (k >= n || msg[k] == I64_INF) return;
-  const int32_t v = dst[k];
-  const int64_t m = msg[k];
-  if (m >= (int64_t)TG_INF) {
-    if (dist[v] == TG_INF) {
-      atomicOr(ovf + (v >> 5), 1u << (v & 31));
-      flags[0] = 1u;
+  const bool on = k < n && msg[k] != I64_INF;
+  wave_or_bits(visited, on ? dst[k] : 0, on);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_inbox_sssp(const int32_t *__restrict__ dst,
+                                                      const int64_t *__restrict__ msg, int64_t n, int32_t *dist,
+                                                      uint32_t *active, uint32_t *ovf, uint32_t *flags) {
+  const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  int32_t v = 0;
+  bool act = false;
+  if (k < n && msg[k] != I64_INF) {
+    v = dst[k];
+    const int64_t m = msg[k];
+    if (m >= (int64_t)TG_INF) {
+      if (dist[v] == TG_INF) {
+        atomicOr(ovf + (v >> 5), 1u << (v & 31));
+        flags[0] = 1u;
+      }
+    } else if (m < (int64_t)dist[v]) {  // inbox ids are distinct: no other writer
+      dist[v] = (int32_t)m;
+      act = true;
     }
-    return;
   }
-  if (m < (int64_t)dist[v]) {  // inbox ids are distinct: no other writer
-    dist[v] = (int32_t)m;
-    atomicOr(active + (v >> 5), 1u << (v & 31));
-  }
+  wave_or_bits(active, v, act);
 }
 
 __global__ void k_inbox_pr(const int32_t *__restrict__ dst, const double *__restrict__ msg, int64_t n,
