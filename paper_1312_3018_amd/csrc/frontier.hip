@@ -13,21 +13,62 @@ using namespace tgk;
 
 namespace {
 
-constexpr int WPT = 4;                     // bitmap words per thread
-constexpr int WPB = WPT * BLOCK;           // words per block (1024)
+// Compaction kernels run 1024-thread blocks, one bitmap word per thread:
+// at 2 MiB of bitmap per RMAT-24 frontier that is 512 blocks, enough waves
+// to keep every SIMD busy, and a thread walks at most 32 bits serially.
+constexpr int CT = 1024;  // threads per compaction block
+constexpr int WPB = CT;   // bitmap words per block
 
-// SSSP filter over the set bits of a thread's four words.  A bit whose
+// Sum over the compaction block; every thread gets the result.
+template <typename T>
+__device__ __forceinline__ T cblock_sum(T x) {
+  __shared__ T red[CT / 64];
+  x = wave_sum(x);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = x;
+  __syncthreads();
+  T s = red[0];
+#pragma unroll
+  for (int k = 1; k < CT / 64; ++k) s += red[k];
+  return s;
+}
+
+// Exclusive prefix sum over the compaction block; `total` gets the sum.
+__device__ __forceinline__ uint32_t cblock_exclusive_scan(uint32_t x, uint32_t &total) {
+  __shared__ uint32_t wsum[CT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = x;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  __syncthreads();
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t before = 0;
+  total = 0;
+#pragma unroll
+  for (int k = 0; k < CT / 64; ++k) {
+    if (k < w) before += wsum[k];
+    total += wsum[k];
+  }
+  return before + inc - x;
+}
+
+// SSSP filter over the set bits of a thread's N words.  A bit whose
 // vertex has dist >= settled (the distance it had when it last relaxed its
 // edges) is dropped: an attempt to lower it set the bit but found it already
 // as low.  Of the rest, bits with dist < thresh are kept (the near set; their
 // settled distance is updated here) and the others are counted, with their
 // least distance, and stay active.  Eight set bits are handled at a time so
 // that their distance loads are in flight together.
-__device__ __forceinline__ void sssp_filter4(uint32_t (&w)[4], int64_t word0, const int32_t *__restrict__ dist,
-                                             int32_t *__restrict__ settled, int32_t thresh, uint32_t (&keep)[4],
-                                             uint32_t (&dropped)[4], uint32_t &rest, int32_t &rest_min) {
+template <int N>
+__device__ __forceinline__ void sssp_filter_words(uint32_t (&w)[N], int64_t word0, const int32_t *__restrict__ dist,
+                                                  int32_t *__restrict__ settled, int32_t thresh, uint32_t (&keep)[N],
+                                                  uint32_t (&dropped)[N], uint32_t &rest, int32_t &rest_min) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < N; ++k) {
     keep[k] = 0;
     dropped[k] = 0;
     uint32_t x = w[k];
@@ -63,26 +104,25 @@ __device__ __forceinline__ void sssp_filter4(uint32_t (&w)[4], int64_t word0, co
   }
 }
 
-// SSSP compaction, first pass: filter the active bitmap (sssp_filter4),
+// SSSP compaction, first pass: filter the active bitmap (sssp_filter_words),
 // leave the untaken active bits in `bits`, the taken ones in `keep_out`, and
 // each block's count in bcount.  With rest_cnt, the vertices left active
 // beyond the threshold are counted into it and their least distance goes
 // into rest_min (both spread counters; rest_min's slots start all ones).
-__global__ __launch_bounds__(BLOCK) void k_sssp_filter(uint32_t *__restrict__ bits, uint32_t *__restrict__ keep_out,
-                                                       uint32_t *__restrict__ bcount, const int32_t *__restrict__ dist,
-                                                       int32_t *__restrict__ settled, int32_t thresh,
-                                                       unsigned long long *rest_cnt, unsigned long long *rest_min) {
-  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // uint4 index
-  const uint4 v = reinterpret_cast<const uint4 *>(bits)[q];
-  uint32_t w[4] = {v.x, v.y, v.z, v.w}, keep[4], dr[4];
+__global__ __launch_bounds__(CT) void k_sssp_filter(uint32_t *__restrict__ bits, uint32_t *__restrict__ keep_out,
+                                                    uint32_t *__restrict__ bcount, const int32_t *__restrict__ dist,
+                                                    int32_t *__restrict__ settled, int32_t thresh,
+                                                    unsigned long long *rest_cnt, unsigned long long *rest_min) {
+  const int64_t q = (int64_t)blockIdx.x * CT + threadIdx.x;  // word index
+  const uint32_t v = bits[q];
+  uint32_t w[1] = {v}, keep[1], dr[1];
   uint32_t r = 0;
   int32_t rmin = TG_INF;
-  sssp_filter4(w, q * 4, dist, settled, thresh, keep, dr, r, rmin);
-  reinterpret_cast<uint4 *>(bits)[q] =
-      make_uint4(v.x & ~(keep[0] | dr[0]), v.y & ~(keep[1] | dr[1]), v.z & ~(keep[2] | dr[2]), v.w & ~(keep[3] | dr[3]));
-  reinterpret_cast<uint4 *>(keep_out)[q] = make_uint4(keep[0], keep[1], keep[2], keep[3]);
+  sssp_filter_words<1>(w, q, dist, settled, thresh, keep, dr, r, rmin);
+  bits[q] = v & ~(keep[0] | dr[0]);
+  keep_out[q] = keep[0];
   if (rest_cnt) {
-    r = block_sum(r);
+    r = cblock_sum(r);
     for (int o = 32; o > 0; o >>= 1) {
       const int32_t y = __shfl_xor(rmin, o, 64);
       rmin = y < rmin ? y : rmin;
@@ -91,86 +131,66 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_filter(uint32_t *__restrict__ bi
       atomicMin(rest_min + (size_t)(blockIdx.x & (STAT_SLOTS - 1)) * STAT_STRIDE, (unsigned long long)rmin);
     if (threadIdx.x == 0 && r) stat_add(rest_cnt, (unsigned long long)r);
   }
-  uint32_t c = __popc(keep[0]) + __popc(keep[1]) + __popc(keep[2]) + __popc(keep[3]);
-  c = block_sum(c);
+  const uint32_t c = cblock_sum((uint32_t)__popc(keep[0]));
   if (threadIdx.x == 0) bcount[blockIdx.x] = c;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_compact_count(const uint32_t *__restrict__ bits,
-                                                         const uint32_t *__restrict__ prev,
-                                                         uint32_t *__restrict__ bcount) {
-  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // uint4 index
-  uint4 v = reinterpret_cast<const uint4 *>(bits)[q];
-  if (prev) {
-    uint4 p = reinterpret_cast<const uint4 *>(prev)[q];
-    v.x &= ~p.x; v.y &= ~p.y; v.z &= ~p.z; v.w &= ~p.w;
-  }
-  uint32_t c = __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
-  c = block_sum(c);
+__global__ __launch_bounds__(CT) void k_compact_count(const uint32_t *__restrict__ bits,
+                                                      const uint32_t *__restrict__ prev,
+                                                      uint32_t *__restrict__ bcount) {
+  const int64_t q = (int64_t)blockIdx.x * CT + threadIdx.x;  // word index
+  uint32_t v = bits[q];
+  if (prev) v &= ~prev[q];
+  const uint32_t c = cblock_sum((uint32_t)__popc(v));
   if (threadIdx.x == 0) bcount[blockIdx.x] = c;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_compact_write(uint32_t *__restrict__ bits, uint32_t *__restrict__ prev,
-                                                         int mode, const uint32_t *__restrict__ bcount,
-                                                         int32_t *__restrict__ queue, int32_t *__restrict__ level,
-                                                         int32_t level_value, BinBounds bb, int64_t n,
-                                                         Plan *__restrict__ plan, uint32_t *__restrict__ fbits,
-                                                         const int64_t *__restrict__ off, unsigned long long *degsum) {
+__global__ __launch_bounds__(CT) void k_compact_write(uint32_t *__restrict__ bits, uint32_t *__restrict__ prev,
+                                                      int mode, const uint32_t *__restrict__ bcount,
+                                                      int32_t *__restrict__ queue, int32_t *__restrict__ level,
+                                                      int32_t level_value, BinBounds bb, int64_t n,
+                                                      Plan *__restrict__ plan, uint32_t *__restrict__ fbits,
+                                                      const int64_t *__restrict__ off, unsigned long long *degsum) {
+  const int64_t q = (int64_t)blockIdx.x * CT + threadIdx.x;  // word index
+  const uint32_t v = bits[q];
   // this block's offset: sum of the counts of all earlier blocks
   uint32_t part = 0;
-  for (uint32_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) part += bcount[i];
-  const uint32_t base = block_sum(part);
+  for (uint32_t i = threadIdx.x; i < blockIdx.x; i += CT) part += bcount[i];
+  const uint32_t base = cblock_sum(part);
 
-  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const int64_t w0 = q * WPT;
-  uint4 v = reinterpret_cast<uint4 *>(bits)[q];
-  uint32_t nw[4] = {v.x, v.y, v.z, v.w};
+  uint32_t nw = v;
   if (mode == 0) {
-    uint4 p = reinterpret_cast<uint4 *>(prev)[q];
-    nw[0] &= ~p.x; nw[1] &= ~p.y; nw[2] &= ~p.z; nw[3] &= ~p.w;
-    reinterpret_cast<uint4 *>(prev)[q] = v;  // prev := visited
-    if (fbits) reinterpret_cast<uint4 *>(fbits)[q] = make_uint4(nw[0], nw[1], nw[2], nw[3]);  // the new frontier
+    nw &= ~prev[q];
+    prev[q] = v;             // prev := visited
+    if (fbits) fbits[q] = nw;  // the new frontier
   } else if (mode == 4) {
     // a bitmap already filtered (k_sssp_filter): take it as it is
   } else {
-    if (mode == 2) reinterpret_cast<uint4 *>(prev)[q] = v;  // prev := the set taken
-    reinterpret_cast<uint4 *>(bits)[q] = make_uint4(0, 0, 0, 0);
+    if (mode == 2) prev[q] = v;  // prev := the set taken
+    bits[q] = 0;
   }
-  const uint32_t cnt = __popc(nw[0]) + __popc(nw[1]) + __popc(nw[2]) + __popc(nw[3]);
   uint32_t total;
-  const uint32_t excl = base + block_exclusive_scan(cnt, total);
+  const uint32_t excl = base + cblock_exclusive_scan((uint32_t)__popc(nw), total);
 
-  // queue positions of the bin boundaries that fall inside this thread's words
+  // queue positions of the bin boundaries that fall inside this thread's word
 #pragma unroll
   for (int b = 0; b < NBIN; ++b) {
     const int64_t t = bb.bstart[b];
-    if (t < n && (t >> 5) >= w0 && (t >> 5) < w0 + WPT) {
-      const int k = (int)((t >> 5) - w0);
-      uint32_t before = 0;
-      for (int j = 0; j < k; ++j) before += __popc(nw[j]);
-      before += __popc(nw[k] & ((1u << (t & 31)) - 1u));
-      plan->pos[b] = (int32_t)(excl + before);
-    }
+    if (t < n && (t >> 5) == q) plan->pos[b] = (int32_t)(excl + __popc(nw & ((1u << (t & 31)) - 1u)));
   }
   uint32_t o = excl;
   unsigned long long deg = 0;
-#pragma unroll
-  for (int k = 0; k < WPT; ++k) {
-    uint32_t w = nw[k];
-    while (w) {
-      const int bit = __ffs(w) - 1;
-      const int32_t vtx = (int32_t)((w0 + k) * 32 + bit);
-      queue[o++] = vtx;
-      if (level) level[vtx] = level_value;
-      if (degsum) deg += (unsigned long long)(off[vtx + 1] - off[vtx]);
-      w &= w - 1;
-    }
+  for (uint32_t w = nw; w; w &= w - 1) {
+    const int32_t vtx = (int32_t)(q * 32 + (__ffs(w) - 1));
+    queue[o++] = vtx;
+    if (level) level[vtx] = level_value;
+    if (degsum) deg += (unsigned long long)(off[vtx + 1] - off[vtx]);
   }
   if (degsum) {
-    deg = block_sum(deg);
+    deg = cblock_sum(deg);
     if (threadIdx.x == 0 && deg) stat_add(degsum, deg);
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == BLOCK - 1) plan->count = (int32_t)o;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == CT - 1) plan->count = (int32_t)o;
 }
 
 // One block: fix up empty-tail positions, hub chunk prefix, virtual blocks.
@@ -232,8 +252,8 @@ int launch_grid(int64_t vblocks) {
 int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, uint32_t *prev,
                      int32_t *queue, int32_t *level, int32_t level_value, hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
-  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, bits, mode == 0 ? prev : nullptr, ws.bcount);
-  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, bits, prev, mode, ws.bcount, queue, level,
+  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(CT), 0, s, bits, mode == 0 ? prev : nullptr, ws.bcount);
+  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, bits, prev, mode, ws.bcount, queue, level,
                      level_value, g.out_bins, g.n, ws.plan, nullptr, nullptr, nullptr);
   TG_HIP(hipGetLastError());
   return TG_OK;
@@ -244,8 +264,8 @@ int frontier_compact_bfs(const GpuPart &g, Workspace &ws, uint32_t *visited, uin
                          bool count_degrees, hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
   if (count_degrees) TG_HIP(hipMemsetAsync(degsum, 0, STAT_SPAN * sizeof(unsigned long long), s));
-  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(BLOCK), 0, s, visited, prev, ws.bcount);
-  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, visited, prev, 0, ws.bcount, queue, level,
+  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(CT), 0, s, visited, prev, ws.bcount);
+  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, visited, prev, 0, ws.bcount, queue, level,
                      level_value, g.out_bins, g.n, ws.plan, fbits, g.out.off, count_degrees ? degsum : nullptr);
   TG_HIP(hipGetLastError());
   return TG_OK;
@@ -264,9 +284,9 @@ int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32
     TG_HIP(hipMemsetAsync(rest_min, 0xFF, STAT_SPAN * sizeof(unsigned long long), s));
   }
   // the taken bits go to bits_b (free during SSSP and connected components)
-  hipLaunchKernelGGL(k_sssp_filter, dim3(blocks), dim3(BLOCK), 0, s, bits, ws.bits_b, ws.bcount, dist, settled,
+  hipLaunchKernelGGL(k_sssp_filter, dim3(blocks), dim3(CT), 0, s, bits, ws.bits_b, ws.bcount, dist, settled,
                      near ? thresh : TG_INF, rest_cnt, rest_min);
-  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(BLOCK), 0, s, ws.bits_b, nullptr, 4, ws.bcount, queue,
+  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, ws.bits_b, nullptr, 4, ws.bcount, queue,
                      nullptr, 0, bb, g.n, ws.plan, nullptr, nullptr, nullptr);
   TG_HIP(hipGetLastError());
   return TG_OK;
