@@ -160,7 +160,6 @@ __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
-// Sum over the 256-thread block; every thread gets the result.
 // Per-call counters that every block of a large grid adds to.  Atomics from
 // thousands of blocks on one address serialize (device-scope atomics are
 // resolved beyond the L2): a counter is STAT_SLOTS slots on separate
@@ -179,6 +178,7 @@ __device__ __forceinline__ void stat_add(unsigned long long *counter, unsigned l
   atomicAdd(counter + (size_t)(blockIdx.x & (STAT_SLOTS - 1)) * STAT_STRIDE, x);
 }
 
+// Sum over the 256-thread block; every thread gets the result.
 template <typename T>
 __device__ __forceinline__ T block_sum(T x) {
   __shared__ T red[BLOCK / 64];
