@@ -21,6 +21,8 @@ one BFS call and one SSSP call, PageRank with uniform dangling mass).
 * Batched Brandes BC on RMAT-20 (section 7.2; the BC workload's graph): 64
   sources in one chain against the oracle within 1e-4 relative, and 1024
   sources in one call equal to the sum of its sixteen 64-source chunks.
+* Serving: the eight resident graphs of the serving workload (R-MAT scales
+  18-23, uniform 2^20 and 2^22) under continuous batching.
 """
 import concurrent.futures as cf
 
@@ -143,3 +145,58 @@ def test_rmat20_bc_batched(gpu):
     chunks = sum(gpu.bc_batched(P, srcs[k:k + 64]).cpu().numpy().astype(np.float64)
                  for k in range(0, 1024, 64))
     assert np.all(np.abs(whole - chunks) <= 1e-4 * np.abs(chunks) + 1e-6 * max(chunks.max(), 1.0))
+
+
+SERVED = ["rmat18", "rmat19", "rmat20", "rmat21", "rmat22", "rmat23", "uniform20", "uniform22"]
+
+
+def test_serving_eight_resident_graphs(gpu):
+    """The serving workload's eight graphs at their real sizes, with weights
+    and roots drawn as the serving bench draws them: 128 BFS/SSSP queries
+    arrive in four waves while earlier ones still run (64 slots).  Every
+    result equals the same query run alone; one query per (graph, kind) is
+    also checked whole against the oracle."""
+    import torch
+    graphs = []
+    for name in SERVED:
+        g = graphgen.workload(name)
+        w = graphgen.weights(g, seed=2)
+        G = gpu.graph_load_csr(g.n, g.offsets, g.cols, w, symmetric=g.symmetric, validate=False)
+        graphs.append((g, w, gpu.partition_by_degree(G)))
+    rng = np.random.default_rng(4)
+    cand = [np.nonzero(np.diff(g.offsets) > 0)[0] for (g, _, _) in graphs]
+    S = gpu.Server(max_slots=64)
+    gids = [S.add_graph(P) for (_, _, P) in graphs]
+    jobs, pending = [], []
+    for wave in range(4):
+        for k in range(32):
+            gi = (wave * 32 + k) % len(graphs)
+            kind = int(rng.integers(2))
+            root = int(cand[gi][rng.integers(len(cand[gi]))])
+            out = torch.empty(graphs[gi][0].n, dtype=torch.int32, device="cuda")
+            t = S.submit(gids[gi], kind, root, out)
+            jobs.append((gi, kind, root, out))
+            pending.append(t)
+        for t in pending[: len(pending) // 2]:
+            S.wait(t)
+        pending = pending[len(pending) // 2:]
+    for t in pending:
+        S.wait(t)
+    st = S.stats()
+    S.close()
+    assert st["completed"] == 128 and st["max_concurrent"] > 1
+    firsts = {}
+    for gi, kind, root, out in jobs:
+        _, _, P = graphs[gi]
+        solo = (gpu.bfs(P, [root]) if kind == 0 else gpu.sssp(P, [root]))[0]
+        assert torch.equal(out, solo), (SERVED[gi], kind, root)
+        firsts.setdefault((gi, kind), (root, out))
+
+    def check(key):
+        (gi, kind), (root, out) = key
+        g, w, _ = graphs[gi]
+        ref = oracle.bfs(g.offsets, g.cols, root) if kind == 0 else oracle.sssp(g.offsets, g.cols, w, root)
+        return np.array_equal(out.cpu().numpy(), ref)
+
+    items = sorted(firsts.items())
+    assert all(_threads(check, items)), [SERVED[gi] for (gi, _), _ in items]
