@@ -12,8 +12,8 @@
  *
  * R-MAT follows Chakrabarti, Zhan and Faloutsos (SDM 2004): each edge picks
  * one of four quadrants per bit level with probabilities (a, b, c, d).  The
- * paper's workloads use (a, b, c) = (0.57, 0.19, 0.19) and an average of 16
- * generated edges per vertex (section 5, Table 2).
+ * paper's workloads take (a, b, c) = (0.57, 0.19, 0.19), with 16 generated
+ * edges per vertex on average (section 5, Table 2).
  */
 #include <stdint.h>
 #include <stdlib.h>

@@ -130,8 +130,8 @@ int partition_retune(tg_partition *p, const char *tuning_json);
  * bottom-up instead: every unvisited vertex looks for an in-neighbour on the
  * frontier.  Levels are the same either way.
  *   roots     host array of num_roots original vertex ids.
- *   levels    device int32 [num_roots * V]; row r holds the level of every
- *             vertex from roots[r] (TG_INF when unreachable).
+ *   levels    device int32 [num_roots * V]; row r holds each vertex's hop
+ *             count from roots[r] (TG_INF when unreachable).
  *   parents   NULL, or device int32 [num_roots * V]: parent[root] = root,
  *             -1 when unreachable, otherwise an in-neighbour one level up
  *             (the lowest such id in the partition's internal order).

@@ -8,9 +8,8 @@
  *
  * Every function computes the plain definition of its result:
  *   - BFS levels: fewest edges on a directed path from the root (section 6.3.2,
- *     Figure 11; Appendix 1 defines the output as "the distance (named level)
- *     of every vertex from the source").  FIFO queue, first discoverer is the
- *     parent.
+ *     Figure 11; in Appendix 1 the output is this hop count, called the
+ *     level, for each vertex).  FIFO queue, first discoverer is the parent.
  *   - SSSP distances: least total weight over directed paths (section 7.3,
  *     Figure 20).  Dijkstra with a binary heap and 64-bit sums; plain
  *     Bellman-Ford (|V|-1 sweeps over every edge) as a second oracle.
