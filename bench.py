@@ -567,8 +567,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in DESIGN.md but not built)"}))
+        print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1 (sharding across "
+                                   "GPUs is not built)"}))
         sys.exit(2)
 
     import numpy as np
