@@ -102,21 +102,26 @@ def measure(part, cfg, roots, sssp_roots, pr_iters, family: str, bufs, repeats: 
 
 def tune(part, roots: Sequence[int], sssp_roots: Optional[Sequence[int]] = None, pr_iters: int = 5,
          start: Optional[Dict[str, int]] = None, rounds: int = 1,
-         log: Callable[[str], None] = lambda s: None) -> Dict[str, object]:
-    import torch
-    V = part.n
-    lev = torch.empty((len(roots), V), dtype=torch.int32, device="cuda")
-    n_ss = 0 if sssp_roots is None else len(sssp_roots)
-    dist = torch.empty((max(n_ss, 1), V), dtype=torch.int32, device="cuda")
-    rank = torch.empty((V,), dtype=torch.float32, device="cuda")
-    bufs = (lev, dist, rank)
+         log: Callable[[str], None] = lambda s: None,
+         measure_fn: Optional[Callable[[Dict[str, int], str], float]] = None) -> Dict[str, object]:
+    """Coordinate descent from `start` (or DEFAULTS).  `measure_fn(cfg,
+    family)` replaces the timed runs (no device buffers are allocated then)."""
+    if measure_fn is None:
+        import torch
+        V = part.n
+        lev = torch.empty((len(roots), V), dtype=torch.int32, device="cuda")
+        n_ss = 0 if sssp_roots is None else len(sssp_roots)
+        dist = torch.empty((max(n_ss, 1), V), dtype=torch.int32, device="cuda")
+        rank = torch.empty((V,), dtype=torch.float32, device="cuda")
+        bufs = (lev, dist, rank)
+        measure_fn = lambda c, f: measure(part, c, roots, sssp_roots, pr_iters, f, bufs)
     cfg = dict(DEFAULTS)
     if start:
         cfg.update(start)
     trials: List[dict] = []
     t0 = time.perf_counter()
     fams = ("all", "bfs", "pr", "sssp")
-    base = {f: measure(part, cfg, roots, sssp_roots, pr_iters, f, bufs) for f in fams}
+    base = {f: measure_fn(cfg, f) for f in fams}
     initial = dict(base)
     for r in range(rounds):
         for key, values in SPACE.items():
@@ -127,7 +132,7 @@ def tune(part, roots: Sequence[int], sssp_roots: Optional[Sequence[int]] = None,
                 cand = dict(cfg, **{key: v})
                 if not valid(cand):
                     continue
-                ms = measure(part, cand, roots, sssp_roots, pr_iters, fam, bufs)
+                ms = measure_fn(cand, fam)
                 trials.append({"key": key, "value": v, "family": fam, "ms": ms})
                 if ms < base[fam] * 0.98:
                     log(f"[autotune] {key}={v}: {base[fam]:.3f} -> {ms:.3f} ms ({fam})")
@@ -136,8 +141,9 @@ def tune(part, roots: Sequence[int], sssp_roots: Optional[Sequence[int]] = None,
                     # a shared key changes the per-family baselines too
                     if fam == "all":
                         for f in fams[1:]:
-                            base[f] = measure(part, cfg, roots, sssp_roots, pr_iters, f, bufs)
-    partition_retune(part, cfg)
+                            base[f] = measure_fn(cfg, f)
+    if part is not None:
+        partition_retune(part, cfg)
     return {"config": cfg, "initial_ms": initial, "final_ms": base, "trials": len(trials),
             "seconds": round(time.perf_counter() - t0, 1), "log": trials}
 
