@@ -66,6 +66,55 @@ def load_traffic(kernel: str, workload: str):
     return None
 
 
+# Rows of profiles/traffic.json: the kernels whose HBM bytes make up one
+# launch of each bench kernel, and the pass directories (<algo>_fetch,
+# <algo>_write, <algo>_hit) their counters come from.
+TRAFFIC_ROWS = {
+    "sssp_relax": ("sssp", ["k_sssp_relax"]),
+    "pr_gather": ("pr", ["k_pr_rows<true, int, 8>", "k_pr_long<true>", "k_pr_combine", "k_pr_dsum"]),
+    "bfs_expand": ("bfs", ["k_bfs_expand"]),
+    "bfs_bottom_up": ("bfs", ["k_bfs_bottom_up_thread", "k_bfs_bottom_up_wave"]),
+}
+# A 1 GiB device-to-device copy (--copy-calibration) reads FETCH_SIZE =
+# 524317 KiB and WRITE_SIZE = 1048576 KiB on MI355X.
+FETCH_SCALE = round(1073741824 / (524317 * 1024), 4)
+WRITE_SCALE = 1.0
+
+
+def traffic_from(pmc_dir: str, workload: str = "rmat24") -> dict:
+    """profiles/traffic.json from rocprofv3 --pmc counter CSVs: per bench
+    kernel, the mean bytes per launch of each of its kernels (FETCH_SIZE and
+    WRITE_SIZE in KiB, scaled by the copy calibration), summed, with the L2
+    hit rate and the digest of the sources and launch shapes measured."""
+    import csv
+    import re
+
+    def kname(s):
+        m = re.search(r"(k_[a-z_0-9]+)(<[^>(]*>)?", s)
+        return m.group(1) + (m.group(2) or "") if m else s.split("(")[0]
+
+    def mean_by_kernel(tag):
+        agg = {}
+        with open(os.path.join(pmc_dir, tag, "run_counter_collection.csv")) as fh:
+            for r in csv.DictReader(fh):
+                agg.setdefault((kname(r["Kernel_Name"]), r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+        return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
+
+    out = {}
+    for kernel, (algo, names) in TRAFFIC_ROWS.items():
+        fe, wr, hit = (mean_by_kernel(f"{algo}_{kind}") for kind in ("fetch", "write", "hit"))
+        f = sum(fe.get((n, "FETCH_SIZE"), (0.0, 0))[0] for n in names) * FETCH_SCALE * 1024
+        w = sum(wr.get((n, "WRITE_SIZE"), (0.0, 0))[0] for n in names) * WRITE_SCALE * 1024
+        h = sum(hit.get((n, "TCC_HIT_sum"), (0.0, 0))[0] for n in names)
+        m = sum(hit.get((n, "TCC_MISS_sum"), (0.0, 0))[0] for n in names)
+        out[kernel] = {"bytes_per_launch": round(f + w), "fetch_bytes": round(f), "write_bytes": round(w),
+                       "l2_hit_rate": round(h / max(h + m, 1.0), 4),
+                       "sources": kernel_sources_digest(KERNEL_FILES[kernel]),
+                       "launches_sampled": fe.get((names[0], "FETCH_SIZE"), (0.0, 0))[1]}
+    return {workload: out, "calibration": {"fetch_scale": round(FETCH_SCALE, 4), "write_scale": WRITE_SCALE,
+                                           "copy_bytes": 1073741824}}
+
+
 def gather_reference(n, cols, count=1 << 27, reps=3):
     """A reference for the SSSP relaxation's access pattern, measured
     with torch.index_select (not this library's kernels) on an n-element int32
@@ -555,7 +604,16 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (to scale HBM byte counters)")
+    ap.add_argument("--traffic-from", default=None, metavar="DIR",
+                    help="only write profiles/traffic.json from the rocprofv3 --pmc passes under DIR")
     args = ap.parse_args()
+    if args.traffic_from:
+        d = traffic_from(args.traffic_from)
+        d["command"] = "python bench.py --traffic-from <pmc dir>; passes as in profiles/rmat24_hbm_traffic.md"
+        with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+            json.dump(d, fh, indent=1)
+        print(json.dumps(d))
+        return
     if args.copy_calibration:
         import torch
         a = torch.empty(args.copy_calibration // 4, dtype=torch.int32, device="cuda").fill_(1)

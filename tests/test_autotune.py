@@ -109,3 +109,33 @@ def test_traffic_is_tied_to_sources_and_tuning(tmp_path, monkeypatch):
     with open(tmp_path / "paper_1312_3018_amd" / "tuning_cache.json", "a") as fh:
         fh.write("\n")  # new launch shapes: the stored figure no longer applies
     assert bench.load_traffic("sssp_relax", "w") is None
+
+
+def test_traffic_from_counter_csvs(tmp_path):
+    """traffic.json rows from rocprofv3 counter CSVs: per-kernel means over
+    launches, summed over a bench kernel's kernels, scaled by the copy
+    calibration; the L2 hit rate from the hit/miss pass."""
+    rows = {"fetch": "FETCH_SIZE", "write": "WRITE_SIZE"}
+    names = {"sssp": ["k_sssp_relax(int const*)"],
+             "pr": ["k_pr_rows<true, int, 8>(Args)", "k_pr_long<true>(Args)", "k_pr_combine(x)", "k_pr_dsum(y)"],
+             "bfs": ["k_bfs_expand(a)", "k_bfs_bottom_up_thread(b)", "k_bfs_bottom_up_wave(c)"]}
+    for algo, kernels in names.items():
+        for kind in ("fetch", "write", "hit"):
+            d = tmp_path / f"{algo}_{kind}"
+            d.mkdir()
+            lines = ["Kernel_Name,Counter_Name,Counter_Value"]
+            for i, k in enumerate(kernels):
+                if kind == "hit":
+                    lines += [f'"{k}",TCC_HIT_sum,30', f'"{k}",TCC_MISS_sum,10']
+                else:  # two launches per kernel: 100 and 300 KiB, mean 200
+                    lines += [f'"{k}",{rows[kind]},100', f'"{k}",{rows[kind]},300']
+            (d / "run_counter_collection.csv").write_text("\n".join(lines) + "\n")
+    t = bench.traffic_from(str(tmp_path))["rmat24"]
+    kib = 200 * 1024
+    assert t["sssp_relax"]["fetch_bytes"] == round(kib * bench.FETCH_SCALE)
+    assert t["sssp_relax"]["write_bytes"] == round(kib * bench.WRITE_SCALE)
+    assert t["sssp_relax"]["launches_sampled"] == 2
+    assert t["pr_gather"]["fetch_bytes"] == round(4 * kib * bench.FETCH_SCALE)
+    assert t["bfs_bottom_up"]["write_bytes"] == 2 * kib and t["bfs_expand"]["write_bytes"] == kib
+    assert all(r["l2_hit_rate"] == 0.75 for r in t.values())
+    assert t["sssp_relax"]["sources"] == bench.kernel_sources_digest(bench.KERNEL_FILES["sssp_relax"])
