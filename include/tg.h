@@ -95,11 +95,20 @@ int graph_load_csr(int64_t num_vertices, int64_t num_edges,
  *                   host partition takes whole vertices, in strategy order,
  *                   until it holds at least alpha * E edges (section 6.3.1).
  *   seed            drives TG_PART_RAND only.
- *   tuning_json     NULL for the built-in degree thresholds, or a JSON object
- *                   with any of "hub_min_deg", "block_min_deg",
+ *   tuning_json     a JSON object with any of "hub_min_deg", "block_min_deg",
  *                   "wave_min_deg", "g16_min_deg", "g4_min_deg", "hub_chunk"
- *                   and the launch-shape keys of partition_retune (as written
- *                   by the autotuner).
+ *                   and the launch-shape keys of partition_retune; keys it
+ *                   leaves out take their built-in values ("{}" = all
+ *                   built-in).  NULL: the autotuner's cached entry for this
+ *                   device and graph, if there is one, else the built-in
+ *                   values.  The cache is the file named by the environment
+ *                   variable TG_TUNING_CACHE, else tuning_cache.json in the
+ *                   directory of this library: a JSON object keyed
+ *                   "<arch>:V2^<round(log2 V)>:deg<round(E/V)>:<sym|dir>"
+ *                   (round to nearest, ties to even; sym when loaded with
+ *                   TG_SYMMETRIC) whose values hold the tuning object under
+ *                   "config".  partition_info reports the choice as
+ *                   "tuning_source".
  * The graph must outlive the partition (the partition reads its host CSR).
  * Errors: TG_EINVAL, TG_ENOMEM, TG_EDEVICE. */
 int partition_by_degree(const tg_graph *g, int strategy, double cpu_edge_share,
@@ -157,10 +166,10 @@ int sssp(const tg_partition *p, const int32_t *roots, int32_t num_roots,
          int32_t *dist, void *stream);
 
 /* Batched SSSP: the same result as sssp(), up to 64 roots per chain of
- * supersteps with one distance per root per vertex ([V][64] int32 scratch).
- * If a candidate distance reaches INT32_MAX the affected roots are redone
- * with sssp()'s exact overflow check.  GPU-only partitions.  Same buffers and
- * errors as sssp(). */
+ * supersteps with one distance per root per vertex ([V][64] int32 scratch),
+ * including sssp()'s exact overflow verdict per root (TG_ERANGE names the
+ * first root whose distances do not fit).  GPU-only partitions.  Same
+ * buffers and errors as sssp(). */
 int sssp_batched(const tg_partition *p, const int32_t *roots, int32_t num_roots,
                  int32_t *dist, void *stream);
 
@@ -230,8 +239,10 @@ int server_submit(tg_server *s, int32_t graph_id, int32_t kind, int32_t root,
 /* Wait for a ticket (timeout_us < 0: no limit).  latency_us gets the time
  * from submission to the result being in `out`.  A ticket can be waited for
  * once.  Errors: TG_ETIMEOUT (not done yet; the ticket stays valid),
- * TG_EINVAL (unknown ticket), TG_ERANGE (an SSSP candidate distance reached
- * INT32_MAX: use sssp() for an exact verdict), or the query's own error. */
+ * TG_EINVAL (unknown ticket), TG_ERANGE (an SSSP distance from this query's
+ * root does not fit below INT32_MAX: the same verdict sssp() gives for that
+ * root, independent of the other queries in flight), or the query's own
+ * error. */
 int server_wait(tg_server *s, uint64_t ticket, int64_t timeout_us, double *latency_us);
 
 /* JSON counters (completed, supersteps, max_concurrent, waiting,
@@ -250,6 +261,22 @@ void server_destroy(tg_server *s);
  * errors as bc(), plus TG_EUNSUPPORTED on a hybrid partition. */
 int bc_batched(const tg_partition *p, const int32_t *sources, int32_t num_sources,
                float *scores, void *stream);
+
+/* Betweenness of many independent graphs in one call (section 5 runs each
+ * algorithm over graphs of very different size; small graphs alone leave most
+ * of the device idle).  Graph i's scores are those of bc_batched(parts[i],
+ * sources[i], num_sources[i], scores[i]); graphs run concurrently, each on a
+ * library stream of its own (at most 8 at a time, largest first), ordered
+ * after earlier work on `stream`, and the call returns when every score is in
+ * place.
+ *   parts        num_graphs distinct GPU-only partitions (a partition may
+ *                appear once: its scratch is used by the run).
+ *   sources      per graph, a host array of num_sources[i] original ids.
+ *   scores       per graph, device float [V_i].
+ * Errors: as bc_batched, for the first graph that fails (its index is in the
+ * message); TG_EINVAL for a repeated partition. */
+int bc_multi(const tg_partition *const *parts, int32_t num_graphs, const int32_t *const *sources,
+             const int32_t *num_sources, float *const *scores, void *stream);
 
 void graph_free(tg_graph *g);
 void partition_free(tg_partition *p);

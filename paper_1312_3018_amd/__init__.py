@@ -59,6 +59,9 @@ def _load():
     lib.sssp_batched.argtypes = [vp, _c_i32p, ctypes.c_int32, vp, vp]
     lib.pagerank.argtypes = [vp, ctypes.c_float, ctypes.c_int32, ctypes.c_int32, vp, vp]
     lib.bc.argtypes = [vp, _c_i32p, ctypes.c_int32, vp, vp]
+    lib.bc_multi.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(_c_i32p), _c_i32p,
+                             ctypes.POINTER(vp), vp]
+    lib.bc_multi.restype = ctypes.c_int
     lib.cc.argtypes = [vp, vp, vp]
     lib.server_create.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
     lib.server_add_graph.argtypes = [vp, vp, _c_i32p]
@@ -301,6 +304,22 @@ def bc_batched(part: Partition, sources: Sequence[int], scores=None, stream=None
     scores = _out(scores, (part.n,), "float32")
     _check(_load().bc_batched(part.handle, s.ctypes.data_as(_c_i32p), s.size, scores.data_ptr(),
                               _stream_handle(stream)))
+    return scores
+
+
+def bc_multi(parts: Sequence[Partition], sources: Sequence[Sequence[int]], scores=None, stream=None):
+    """bc_batched() over several graphs in one call; returns one score tensor
+    per graph."""
+    lib = _load()
+    k = len(parts)
+    assert len(sources) == k
+    srcs = [_roots(s) for s in sources]
+    scores = [_out(None if scores is None else scores[i], (parts[i].n,), "float32") for i in range(k)]
+    ph = (ctypes.c_void_p * k)(*[p.handle for p in parts])
+    sp = (_c_i32p * k)(*[s.ctypes.data_as(_c_i32p) for s in srcs])
+    ns = (ctypes.c_int32 * k)(*[s.size for s in srcs])
+    op = (ctypes.c_void_p * k)(*[t.data_ptr() for t in scores])
+    _check(lib.bc_multi(ph, k, sp, ns, op, _stream_handle(stream)))
     return scores
 
 

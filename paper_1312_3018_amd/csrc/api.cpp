@@ -1,6 +1,8 @@
 // C ABI entry points, graph loading and validation, partition by degree
 // centrality (section 6.2), device memory and error reporting.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <omp.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -8,7 +10,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hybrid.h"
@@ -585,6 +589,82 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
 
 }  // namespace tg
 
+namespace {
+
+// The autotuner's cache: a JSON object whose keys are
+// "<arch>:V2^<round(log2 V)>:deg<round(E / V)>:<sym|dir>" and whose values
+// hold a "config" object of tuning keys.  Rounding is to nearest, ties to
+// even.  The file is TG_TUNING_CACHE if set, else tuning_cache.json beside
+// this library.
+std::string tuning_cache_path() {
+  const char *env = getenv("TG_TUNING_CACHE");
+  if (env && *env) return env;
+  Dl_info info;
+  if (dladdr((void *)&tuning_cache_path, &info) && info.dli_fname) {
+    std::string lib = info.dli_fname;
+    const size_t slash = lib.rfind('/');
+    return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/tuning_cache.json";
+  }
+  return "tuning_cache.json";
+}
+
+std::string graph_signature(const tg_graph &g, int device) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+  }
+  const double v = (double)std::max<int64_t>(g.n, 1);
+  char buf[160];
+  snprintf(buf, sizeof(buf), "%s:V2^%.0f:deg%.0f:%s", arch.c_str(), nearbyint(log2(v)),
+           nearbyint((double)g.m / v), g.symmetric ? "sym" : "dir");
+  return buf;
+}
+
+// The "config" object of `key` in the cache text, or "" if absent.
+std::string cached_config(const std::string &text, const std::string &key) {
+  const size_t k = text.find("\"" + key + "\"");
+  if (k == std::string::npos) return "";
+  const size_t c = text.find("\"config\"", k);
+  if (c == std::string::npos) return "";
+  const size_t open = text.find('{', c);
+  if (open == std::string::npos) return "";
+  int depth = 0;
+  for (size_t i = open; i < text.size(); ++i) {
+    if (text[i] == '{') ++depth;
+    else if (text[i] == '}' && --depth == 0) return text.substr(open, i - open + 1);
+  }
+  return "";
+}
+
+// tuning_json == NULL: the cached entry for this device and graph signature,
+// else the built-in values.  `source` names what was used.
+int resolve_tuning(const tg_graph &g, int device, const char *tuning_json, Tuning *t, std::string *source) {
+  if (tuning_json) {
+    *source = "caller";
+    return parse_tuning(tuning_json, t);
+  }
+  const std::string key = graph_signature(g, device);
+  std::string text;
+  if (FILE *f = fopen(tuning_cache_path().c_str(), "rb")) {
+    char buf[65536];
+    size_t k;
+    while ((k = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, k);
+    fclose(f);
+  }
+  const std::string cfg = cached_config(text, key);
+  if (!cfg.empty() && parse_tuning(cfg.c_str(), t) == TG_OK) {
+    *source = "cache " + key;
+    return TG_OK;
+  }
+  *source = "built-in";
+  return parse_tuning(nullptr, t);
+}
+
+}  // namespace
+
 extern "C" int partition_by_degree(const tg_graph *g, int strategy, double alpha, uint64_t seed,
                                    const char *tuning_json, tg_partition **out) {
   clear_error();
@@ -599,8 +679,8 @@ extern "C" int partition_by_degree(const tg_graph *g, int strategy, double alpha
   p->g = g;
   p->strategy = strategy;
   p->alpha = alpha;
-  int rc = parse_tuning(tuning_json, &p->tune);
-  if (rc == TG_OK) rc = (hipGetDevice(&p->device) == hipSuccess) ? TG_OK : set_error(TG_EDEVICE, "no HIP device");
+  int rc = (hipGetDevice(&p->device) == hipSuccess) ? TG_OK : set_error(TG_EDEVICE, "no HIP device");
+  if (rc == TG_OK) rc = resolve_tuning(*g, p->device, tuning_json, &p->tune, &p->tuning_source);
   if (rc == TG_OK) {
     try {
       if (alpha == 0.0) {
@@ -629,6 +709,7 @@ extern "C" int partition_retune(tg_partition *p, const char *tuning_json) {
   TG_TRY(parse_tuning(tuning_json, &t));
   if (hipSetDevice(p->device) != hipSuccess) return set_error(TG_EDEVICE, "partition_retune: hipSetDevice failed");
   TG_HIP(hipDeviceSynchronize());
+  p->tuning_source = tuning_json ? "caller" : "built-in";
   return apply_tuning(p, t);
 }
 
@@ -697,6 +778,7 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            (long long)p->tune.pr_rows, (long long)p->tune.bfs_do, (long long)p->tune.bfs_alpha,
            (long long)p->tune.bfs_beta, (long long)p->tune.sssp_xcd);
   s += buf;
+  s += ",\"tuning_source\":\"" + p->tuning_source + "\"";
   s += hybrid_info_json(p);
   s += "}";
   return emit(s, json, cap);
@@ -909,5 +991,105 @@ extern "C" int bc_batched(const tg_partition *pc, const int32_t *sources, int32_
   TG_HIP(hipStreamSynchronize(s));
   stats_add("sources", num_sources);
   ktimer_emit();
+  return TG_OK;
+}
+
+// Many graphs (section 5's workloads of uneven size): each graph's batched BC
+// runs on a stream of its own, at most kMultiStreams graphs at a time, the
+// largest first, so that small graphs fill the device together.  Each worker
+// host thread drives one stream; the caller's stream is ordered before the
+// first and after the last of them.
+extern "C" int bc_multi(const tg_partition *const *parts, int32_t num_graphs, const int32_t *const *sources,
+                        const int32_t *num_sources, float *const *scores, void *stream) {
+  clear_error();
+  constexpr int kMultiStreams = 8;
+  if (num_graphs < 0) return set_error(TG_EINVAL, "bc_multi: negative graph count");
+  if (num_graphs == 0) return TG_OK;
+  if (!parts || !sources || !num_sources || !scores) return set_error(TG_EINVAL, "bc_multi: NULL array");
+  for (int32_t i = 0; i < num_graphs; ++i) {
+    TG_TRY(check_call(parts[i], scores[i], "bc_multi"));
+    TG_TRY(check_roots(parts[i], sources[i], num_sources[i], "bc_multi"));
+    if (parts[i]->alpha > 0.0) return set_error(TG_EUNSUPPORTED, "bc_multi: graph %d is a hybrid partition", i);
+    if (parts[i]->device != parts[0]->device) return set_error(TG_EINVAL, "bc_multi: graphs on different devices");
+    for (int32_t j = 0; j < i; ++j)
+      if (parts[j] == parts[i]) return set_error(TG_EINVAL, "bc_multi: graph %d repeats graph %d", i, j);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  stats_reset("bc_multi");
+  const int nstreams = std::min<int>(kMultiStreams, num_graphs);
+  std::vector<hipStream_t> ws((size_t)nstreams, nullptr);
+  hipEvent_t start = nullptr;
+  TG_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  TG_HIP(hipEventRecord(start, s));
+  int rc = TG_OK;
+  for (int k = 0; k < nstreams && rc == TG_OK; ++k) {
+    if (hipStreamCreateWithFlags(&ws[k], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamWaitEvent(ws[k], start, 0) != hipSuccess)
+      rc = set_error(TG_EDEVICE, "bc_multi: stream set-up failed");
+  }
+  if (rc == TG_OK) {
+    std::vector<int32_t> order((size_t)num_graphs);
+    for (int32_t i = 0; i < num_graphs; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return parts[a]->gpu.m + parts[a]->gpu.n > parts[b]->gpu.m + parts[b]->gpu.n;
+    });
+    std::atomic<int32_t> next{0};
+    std::vector<int> wrc((size_t)nstreams, TG_OK);
+    std::vector<std::string> werr((size_t)nstreams);
+    auto work = [&](int k) {
+      if (hipSetDevice(parts[0]->device) != hipSuccess) {
+        wrc[k] = set_error(TG_EDEVICE, "bc_multi: hipSetDevice failed");
+        werr[k] = tg_last_error();
+        return;
+      }
+      for (;;) {
+        const int32_t q = next.fetch_add(1);
+        if (q >= num_graphs) break;
+        const int32_t i = order[q];
+        tg_partition *p = const_cast<tg_partition *>(parts[i]);
+        auto one = [&]() -> int {
+          TG_TRY(p->ws.ensure(p->gpu, 0));
+          TG_TRY(fill_f64(p->ws.bc_acc, p->gpu.n, 0.0, ws[k]));
+          TG_TRY(gpu_bc_batched(p, sources[i], num_sources[i], ws[k]));
+          TG_TRY(collect_f64_to_f32(p->gpu, p->ws.bc_acc, scores[i], ws[k]));
+          TG_HIP(hipStreamSynchronize(ws[k]));
+          return TG_OK;
+        };
+        const int r = one();
+        if (r != TG_OK) {
+          wrc[k] = r;
+          werr[k] = std::string("graph ") + std::to_string(i) + ": " + tg_last_error();
+          next.store(num_graphs);  // stop handing out graphs
+          return;
+        }
+      }
+    };
+    std::vector<std::thread> th;
+    for (int k = 1; k < nstreams; ++k) th.emplace_back(work, k);
+    work(0);
+    for (auto &t : th) t.join();
+    for (int k = 0; k < nstreams && rc == TG_OK; ++k)
+      if (wrc[k] != TG_OK) rc = set_error(wrc[k], "bc_multi: %s", werr[k].c_str());
+  }
+  // the caller's stream waits for every worker stream
+  for (int k = 0; k < nstreams; ++k) {
+    if (!ws[k]) continue;
+    hipEvent_t done = nullptr;
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess) {
+      TG_QUIET(hipEventRecord(done, ws[k]));
+      TG_QUIET(hipStreamWaitEvent(s, done, 0));
+      TG_QUIET(hipEventDestroy(done));
+    }
+  }
+  TG_QUIET(hipStreamSynchronize(s));
+  for (int k = 0; k < nstreams; ++k)
+    if (ws[k]) TG_QUIET(hipStreamDestroy(ws[k]));
+  TG_QUIET(hipEventDestroy(start));
+  if (rc != TG_OK) return rc;
+  int64_t total = 0;
+  for (int32_t i = 0; i < num_graphs; ++i) total += num_sources[i];
+  stats_add("graphs", num_graphs);
+  stats_add("sources", (double)total);
+  stats_add("streams", nstreams);
   return TG_OK;
 }

@@ -63,6 +63,7 @@ struct HybridState {
   int32_t *d_rsrc = nullptr, *d_rw = nullptr, *d_slot_order = nullptr;
   Plan h_splan{};
   Plan *d_splan = nullptr;
+  int64_t splan_hub_chunk = 0;  // edges per hub chunk of the static slot plan (fixed at build)
   int64_t *d_shubpref = nullptr;
   double *d_shub_partials_f = nullptr;
   int64_t *d_shub_partials_i = nullptr;
@@ -302,6 +303,7 @@ int build_hybrid(tg_partition *p, uint64_t seed) {
       if (b != BIN_ZERO) vb += (P.pos[b + 1] - P.pos[b] + verts_per_vblock(b) - 1) / verts_per_vblock(b);
       P.vb[b + 1] = vb;
     }
+    hy->splan_hub_chunk = p->tune.hub_chunk;
     TG_TRY(up(A, &hy->d_shubpref, hubpref.data(), hubpref.size()));
     TG_TRY(up(A, &hy->d_splan, &P, 1));
     TG_TRY(dalloc(A, &hy->d_shub_partials_f, (size_t)hubpref[nh] + 1));
@@ -477,11 +479,14 @@ __global__ void k_set_i32h(int32_t *p, int64_t i, int32_t v) {
 
 inline unsigned nblk(int64_t n) { return (unsigned)std::max<int64_t>((n + BLOCK - 1) / BLOCK, 1); }
 
+// The slot plan, its hub chunk prefix and the partials buffer were sized at
+// partition time with splan_hub_chunk; a later retune must not change the
+// chunking they were built for.
 template <class Op>
-int launch_outbox(HybridState &h, const Tuning &t, hipStream_t s, Op op, typename Op::T *partials) {
+int launch_outbox(HybridState &h, hipStream_t s, Op op, typename Op::T *partials) {
   if (h.g2c.nslots == 0) return TG_OK;
   hipLaunchKernelGGL(k_gather<Op>, dim3(launch_grid(h.h_splan.vb[NBIN])), dim3(BLOCK), 0, s, h.d_splan,
-                     h.d_slot_order, h.d_shubpref, h.d_roff, t.hub_chunk, partials, op);
+                     h.d_slot_order, h.d_shubpref, h.d_roff, h.splan_hub_chunk, partials, op);
   if (h.h_splan.pos[1] > h.h_splan.pos[0])
     hipLaunchKernelGGL(k_gather_hubs<Op>, dim3(64), dim3(BLOCK), 0, s, h.d_splan, h.d_slot_order, h.d_shubpref,
                        partials, op);
@@ -583,7 +588,7 @@ int hybrid_bfs(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *level
       // GPU: expand the local frontier, reduce the outbox, start its copy
       TG_HIP(hipEventRecord(e0, s));
       TG_TRY(bfs_expand_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], t, s));
-      TG_TRY(launch_outbox(h, t, s, BfsOutbox{h.d_rsrc, ws.state, L, h.d_out_i}, h.d_shub_partials_i));
+      TG_TRY(launch_outbox(h, s, BfsOutbox{h.d_rsrc, ws.state, L, h.d_out_i}, h.d_shub_partials_i));
       TG_HIP(hipEventRecord(e1, s));
       if (h.g2c.nslots)
         TG_HIP(hipMemcpyAsync(h.h_out_i, h.d_out_i, h.g2c.nslots * sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -707,7 +712,7 @@ int hybrid_sssp(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *dist
       ++ph.supersteps;
       const auto tg0 = clk::now();
       TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], t, s));
-      TG_TRY(launch_outbox(h, t, s, SsspOutbox{h.d_rsrc, h.d_rw, dist, cur, h.d_out_i}, h.d_shub_partials_i));
+      TG_TRY(launch_outbox(h, s, SsspOutbox{h.d_rsrc, h.d_rw, dist, cur, h.d_out_i}, h.d_shub_partials_i));
       if (h.g2c.nslots)
         TG_HIP(hipMemcpyAsync(h.h_out_i, h.d_out_i, h.g2c.nslots * sizeof(int64_t), hipMemcpyDeviceToHost, s));
       // host: relax its frontier, reduce its outbox
@@ -799,7 +804,6 @@ int hybrid_pagerank(tg_partition *p, double damping, int32_t iters, int mode, fl
   GpuPart &g = p->gpu;
   Workspace &ws = p->ws;
   CpuPart &C = h.cpu;
-  const Tuning &t = p->tune;
   const double N = (double)p->g->n;
   const double base = (1.0 - damping) / N;
   const bool drop = mode == TG_PR_DANGLING_DROP;
@@ -822,7 +826,7 @@ int hybrid_pagerank(tg_partition *p, double damping, int32_t iters, int mode, fl
     const bool last = k == iters - 1;
     const auto tg0 = clk::now();
     // outboxes: per remote vertex, the sum of the contributions bound for it
-    TG_TRY(launch_outbox(h, t, s, PrOutbox{{}, h.d_rsrc, ws.cbuf[k & 1], h.d_out_f}, h.d_shub_partials_f));
+    TG_TRY(launch_outbox(h, s, PrOutbox{{}, h.d_rsrc, ws.cbuf[k & 1], h.d_out_f}, h.d_shub_partials_f));
     if (h.g2c.nslots)
       TG_HIP(hipMemcpyAsync(h.h_out_f, h.d_out_f, h.g2c.nslots * sizeof(double), hipMemcpyDeviceToHost, s));
     const auto tc = clk::now();

@@ -166,11 +166,16 @@ void tg_server::run() {
       continue;
     }
     // 2. complete whichever lanes' supersteps are done; lanes advance
-    //    independently, so a slow graph does not hold back the others
+    //    independently, so a slow graph does not hold back the others.
+    //    server_add_graph may grow `lanes` meanwhile: walk a copy of the
+    //    lane pointers taken under the lock (each Lane stays where it is).
+    std::vector<Lane *> snap;
+    snap.reserve(lanes.size());
+    for (auto &lp : lanes) snap.push_back(lp.get());
     lk.unlock();
     std::vector<std::pair<Lane *, unsigned long long>> fin;
     bool progressed = false;
-    for (auto &lp : lanes) {
+    for (Lane *lp : snap) {
       Lane &L = *lp;
       if (!L.launched || hipStreamQuery(L.stream) != hipSuccess) continue;
       (void)hipGetLastError();  // hipStreamQuery reports "not ready" through the error state
@@ -181,12 +186,14 @@ void tg_server::run() {
         if (L.kind == kSlotSssp)
           for (int k = 0; k < kSlots; ++k)
             if ((f >> k) & 1ull) L.eng->tab.out[k] = L.slot_q[k]->out;
-        bool ovf = false;
+        unsigned long long ovf = 0;
         const int rc = L.eng->retire(f, &ovf);
         fin.emplace_back(&L, f);
-        if (rc != TG_OK || ovf)
-          for (int k = 0; k < kSlots; ++k)
-            if ((f >> k) & 1ull) L.slot_q[k]->status = rc != TG_OK ? rc : TG_ERANGE;
+        for (int k = 0; k < kSlots; ++k)
+          if ((f >> k) & 1ull) {
+            if (rc != TG_OK) L.slot_q[k]->status = rc;
+            else if ((ovf >> k) & 1ull) L.slot_q[k]->status = TG_ERANGE;
+          }
       }
     }
     (void)hipGetLastError();
@@ -200,7 +207,8 @@ void tg_server::run() {
           Query *q = L.slot_q[k];
           L.slot_q[k] = nullptr;
           const int st = q->status;
-          finish(this, q, st, st == TG_ERANGE ? "sssp: a candidate distance reached INT32_MAX" : "");
+          finish(this, q, st,
+                 st == TG_ERANGE ? "sssp: a shortest-path distance does not fit below INT32_MAX" : "");
         }
     }
     if (!fin.empty()) cv_done.notify_all();

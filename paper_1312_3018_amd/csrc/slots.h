@@ -25,7 +25,10 @@ struct SlotEngine {
   DevArena arena;
   unsigned long long *visited = nullptr, *frontier = nullptr, *next = nullptr, *alive = nullptr;
   int32_t *dist = nullptr;  // SSSP: [n][kSlots]
-  unsigned long long *h_alive = nullptr;
+  // SSSP overflow: per vertex, the slots whose candidate for it did not fit
+  // in int32; ovf_slots[0] = the slots with any such mark, [1] = scratch
+  unsigned long long *ovf = nullptr, *ovf_slots = nullptr;
+  unsigned long long *h_alive = nullptr, *h_ovf = nullptr;
   SlotTable tab{};
   unsigned long long busy = 0;  // slots in use
   int64_t step = 0;             // superstep counter (levels are step - join)
@@ -43,8 +46,10 @@ struct SlotEngine {
   int superstep(unsigned long long *finished);
   int launch_step();
   int finish_step(unsigned long long *finished);
-  // Release finished slots (SSSP: write their distances to tab.out first).
-  int retire(unsigned long long mask, bool *overflow);
+  // Release finished slots (SSSP: write their distances to tab.out first,
+  // and set in *overflow the slots among them whose true distances do not
+  // all fit below INT32_MAX, the exact verdict of sssp()).
+  int retire(unsigned long long mask, unsigned long long *overflow);
 };
 
 int slots_run_batch(tg_partition *p, int kind, const int32_t *roots, int32_t nr, int32_t *out, hipStream_t s,

@@ -61,8 +61,8 @@ __global__ __launch_bounds__(BLOCK) void k_ms_sssp_expand(const Plan *__restrict
                                                           const int64_t *__restrict__ off,
                                                           const int32_t *__restrict__ col,
                                                           const int32_t *__restrict__ wgt, const u64 *frontier,
-                                                          int32_t *dist, u64 *next, uint32_t *touched,
-                                                          uint32_t *flags, int64_t hub_chunk) {
+                                                          int32_t *dist, u64 *next, uint32_t *touched, u64 *ovf,
+                                                          u64 *ovf_slots, int64_t hub_chunk) {
   const Plan &P = load_plan(Pp);
   const int64_t total = P.vb[NBIN];
   for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
@@ -81,7 +81,12 @@ __global__ __launch_bounds__(BLOCK) void k_ms_sssp_expand(const Plan *__restrict
         bits &= bits - 1;
         const int64_t nd = (int64_t)dv[s] + (int64_t)w;
         if (nd >= (int64_t)TG_INF) {
-          flags[0] = 1u;  // candidate does not fit; checked when the slot retires
+          // the candidate does not fit: mark (vertex, slot); the slot's
+          // verdict is taken when it retires (k_ms_ovf_check)
+          if (dn[s] == TG_INF) {
+            atomicOr(ovf + nb, 1ull << s);
+            atomicOr(ovf_slots, 1ull << s);
+          }
           continue;
         }
         if (nd < (int64_t)dn[s]) {
@@ -169,10 +174,33 @@ __global__ void k_ms_join(u64 *next, uint32_t *touched, int32_t *dist, int32_t r
   if (dist) dist[(int64_t)root * kSlots + slot] = 0;
 }
 
-// Retiring slots: drop their bits / reset their distances everywhere.
-__global__ __launch_bounds__(BLOCK) void k_ms_release(u64 *visited, int32_t *dist, int64_t n, u64 mask) {
+// Overflow verdict of retiring slots: bit s of *bad is set if some vertex
+// received an overflowing candidate from slot s and stayed unreached (its
+// true distance is finite but does not fit below INT32_MAX).  A vertex whose
+// candidate overflowed but that was reached otherwise has its exact
+// distance: path prefixes only grow, so an overflowing prefix never leads to
+// a shorter path.
+__global__ __launch_bounds__(BLOCK) void k_ms_ovf_check(const u64 *__restrict__ ovf, const int32_t *__restrict__ dist,
+                                                        int64_t n, u64 mask, u64 *bad) {
+  u64 found = 0;
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK) {
+    u64 bits = ovf[v] & mask;
+    while (bits) {
+      const int s = __ffsll((long long)bits) - 1;
+      bits &= bits - 1;
+      if (dist[v * kSlots + s] == TG_INF) found |= 1ull << s;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) found |= __shfl_xor(found, o, 64);
+  if ((threadIdx.x & 63) == 0 && found) atomicOr(bad, found);
+}
+
+// Retiring slots: drop their bits / reset their distances and overflow
+// marks everywhere.
+__global__ __launch_bounds__(BLOCK) void k_ms_release(u64 *visited, int32_t *dist, u64 *ovf, int64_t n, u64 mask) {
   for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK) {
     if (visited) visited[v] &= ~mask;
+    if (ovf) ovf[v] &= ~mask;
     if (dist) {
       u64 bits = mask;
       while (bits) {
@@ -184,12 +212,15 @@ __global__ __launch_bounds__(BLOCK) void k_ms_release(u64 *visited, int32_t *dis
   }
 }
 
-// SSSP result of one slot into its output (original ids); flags[1] = 1 if
-// the slot saw an overflowing candidate and some vertex stayed unreached.
+// SSSP result of one slot into its output (original ids).
 __global__ __launch_bounds__(BLOCK) void k_ms_sssp_collect(const int32_t *__restrict__ dist, int64_t n, int slot,
                                                            const int32_t *__restrict__ g_of_l, int32_t *out) {
   for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK)
     out[g_of_l[v]] = dist[v * kSlots + slot];
+}
+
+__global__ void k_clear_bits64(u64 *word, u64 mask) {
+  if (threadIdx.x == 0) atomicAnd(word, ~mask);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_fill_i32_out(int32_t *p, int64_t n, int32_t v) {
@@ -204,6 +235,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill_i32_all(int32_t *p, int64_t n, i
 
 SlotEngine::~SlotEngine() {
   if (h_alive) TG_QUIET(hipHostFree(h_alive));
+  if (h_ovf) TG_QUIET(hipHostFree(h_ovf));
 }
 
 int SlotEngine::init(tg_partition *part, int kind_, hipStream_t stream) {
@@ -224,11 +256,16 @@ int SlotEngine::init(tg_partition *part, int kind_, hipStream_t stream) {
     TG_TRY(dalloc(arena, &visited, (size_t)n));
     TG_HIP(hipMemset(visited, 0, (size_t)n * sizeof(u64)));
   } else {
+    TG_TRY(dalloc(arena, &ovf, (size_t)n));
+    TG_TRY(dalloc(arena, &ovf_slots, 2));
+    TG_HIP(hipMemset(ovf, 0, (size_t)n * sizeof(u64)));
+    TG_HIP(hipMemset(ovf_slots, 0, 2 * sizeof(u64)));
     TG_TRY(dalloc(arena, &dist, (size_t)n * kSlots));
     hipLaunchKernelGGL(k_fill_i32_all, dim3(2048), dim3(BLOCK), 0, s, dist, n * kSlots, TG_INF);
     TG_HIP(hipGetLastError());
   }
   if (!h_alive) TG_HIP(hipHostMalloc((void **)&h_alive, STAT_SPAN * sizeof(u64), hipHostMallocDefault));
+  if (!h_ovf) TG_HIP(hipHostMalloc((void **)&h_ovf, 2 * sizeof(u64), hipHostMallocDefault));
   TG_HIP(hipMemset(ws.bits_a, 0, ws.nwords * sizeof(uint32_t)));
   TG_HIP(hipMemset(ws.counters, 0, 64 * sizeof(uint32_t)));
   memset(&tab, 0, sizeof(tab));
@@ -277,7 +314,8 @@ int SlotEngine::launch_step() {
                          g.out.col, frontier, visited, next, ws.bits_a, t.hub_chunk);
     else
       hipLaunchKernelGGL(k_ms_sssp_expand, dim3(grid), dim3(BLOCK), 0, s, ws.plan, ws.queue, ws.hubpref,
-                         g.out.off, g.out.col, g.out.w, frontier, dist, next, ws.bits_a, ws.counters, t.hub_chunk);
+                         g.out.off, g.out.col, g.out.w, frontier, dist, next, ws.bits_a, ovf, ovf_slots,
+                         t.hub_chunk);
     ktimer_stop(tk, s, kind == kSlotBfs ? "msbfs_expand" : "mssssp_expand");
     hipLaunchKernelGGL(k_ms_clear, dim3(nblk(std::min<int64_t>(ws.h_plan->count, 1 << 20))), dim3(BLOCK), 0, s,
                        ws.plan, ws.queue, frontier);
@@ -314,25 +352,37 @@ int SlotEngine::finish_step(u64 *finished) {
   return TG_OK;
 }
 
-int SlotEngine::retire(u64 mask, bool *overflow) {
+int SlotEngine::retire(u64 mask, u64 *overflow) {
   const GpuPart &g = p->gpu;
-  if (overflow) *overflow = false;
+  if (overflow) *overflow = 0;
   if (!mask) return TG_OK;
+  const unsigned grid = nblk(std::min<int64_t>(g.n, 1 << 20));
   if (kind == kSlotSssp) {
     for (int k = 0; k < kSlots; ++k)
       if ((mask >> k) & 1ull) {
         if (tab.out[k])
-          hipLaunchKernelGGL(k_ms_sssp_collect, dim3(nblk(std::min<int64_t>(g.n, 1 << 20))), dim3(BLOCK), 0, s,
-                             dist, g.n, k, g.g_of_l, tab.out[k]);
+          hipLaunchKernelGGL(k_ms_sssp_collect, dim3(grid), dim3(BLOCK), 0, s, dist, g.n, k, g.g_of_l, tab.out[k]);
       }
-    // overflow candidates are rare: any flagged run is re-checked exactly
-    TG_HIP(hipMemcpyAsync(ws.h_flags, ws.counters, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    // slots that saw an overflowing candidate get the exact verdict
+    TG_HIP(hipMemcpyAsync(h_ovf, ovf_slots, sizeof(u64), hipMemcpyDeviceToHost, s));
+    TG_HIP(hipStreamSynchronize(s));
+    const u64 flagged = h_ovf[0] & mask;
+    if (flagged) {
+      TG_HIP(hipMemsetAsync(ovf_slots + 1, 0, sizeof(u64), s));
+      hipLaunchKernelGGL(k_ms_ovf_check, dim3(grid), dim3(BLOCK), 0, s, ovf, dist, g.n, flagged, ovf_slots + 1);
+      hipLaunchKernelGGL(k_clear_bits64, dim3(1), dim3(64), 0, s, ovf_slots, flagged);
+      TG_HIP(hipMemcpyAsync(h_ovf + 1, ovf_slots + 1, sizeof(u64), hipMemcpyDeviceToHost, s));
+    }
+    hipLaunchKernelGGL(k_ms_release, dim3(grid), dim3(BLOCK), 0, s, nullptr, dist, flagged ? ovf : nullptr, g.n,
+                       mask);
+    TG_HIP(hipGetLastError());
+    TG_HIP(hipStreamSynchronize(s));
+    if (flagged && overflow) *overflow = h_ovf[1] & flagged;
+  } else {
+    hipLaunchKernelGGL(k_ms_release, dim3(grid), dim3(BLOCK), 0, s, visited, nullptr, nullptr, g.n, mask);
+    TG_HIP(hipGetLastError());
+    TG_HIP(hipStreamSynchronize(s));
   }
-  hipLaunchKernelGGL(k_ms_release, dim3(nblk(std::min<int64_t>(g.n, 1 << 20))), dim3(BLOCK), 0, s,
-                     kind == kSlotBfs ? visited : nullptr, kind == kSlotSssp ? dist : nullptr, g.n, mask);
-  TG_HIP(hipGetLastError());
-  TG_HIP(hipStreamSynchronize(s));
-  if (kind == kSlotSssp && ws.h_flags[0] && overflow) *overflow = true;
   busy &= ~mask;
   for (int k = 0; k < kSlots; ++k)
     if ((mask >> k) & 1ull) tab.out[k] = nullptr;
@@ -353,7 +403,6 @@ int slots_run_batch(tg_partition *p, int kind, const int32_t *roots, int32_t nr,
   int64_t total = 0;
   for (int32_t c0 = 0; c0 < nr; c0 += kSlots) {
     const int32_t cn = std::min<int32_t>(kSlots, nr - c0);
-    TG_HIP(hipMemsetAsync(E.ws.counters, 0, 4 * sizeof(uint32_t), s));
     for (int32_t k = 0; k < cn; ++k)
       TG_TRY(E.join(k, p->h_l_of_g[roots[c0 + k]], kind == kSlotBfs ? out + (int64_t)(c0 + k) * V : nullptr));
     u64 pending = E.busy;
@@ -365,17 +414,12 @@ int slots_run_batch(tg_partition *p, int kind, const int32_t *roots, int32_t nr,
         if (kind == kSlotSssp)
           for (int k = 0; k < kSlots; ++k)
             if ((fin >> k) & 1ull) E.tab.out[k] = out + (int64_t)(c0 + k) * V;
-        bool ovf = false;
+        u64 ovf = 0;
         TG_TRY(E.retire(fin, &ovf));
         if (ovf) {
-          // a candidate distance did not fit in int32: redo these roots with
-          // the single-source path, which decides overflow exactly
-          for (int k = 0; k < kSlots; ++k)
-            if ((fin >> k) & 1ull) {
-              TG_TRY(gpu_sssp(p, p->h_l_of_g[roots[c0 + k]], s, nullptr));
-              TG_TRY(collect_i32(p->gpu, p->ws.state, out + (int64_t)(c0 + k) * V, s));
-            }
-          TG_HIP(hipMemsetAsync(E.ws.counters, 0, 4 * sizeof(uint32_t), s));
+          const int k = __builtin_ctzll(ovf);
+          return set_error(TG_ERANGE, "sssp_batched: the distances from root %d do not fit below INT32_MAX",
+                           roots[c0 + k]);
         }
         pending &= ~fin;
       }

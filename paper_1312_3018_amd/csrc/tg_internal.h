@@ -292,6 +292,7 @@ struct tg_partition {
   double alpha = 0.0;
   int device = 0;
   tg::Tuning tune{};
+  std::string tuning_source = "built-in";  // "caller", "built-in" or "cache <key>"
   tg::DevArena arena;
   tg::GpuPart gpu;
   tg::Workspace ws;

@@ -88,3 +88,62 @@ def test_bc_batched_many_graphs_in_one_chain(gpu):
         sub = got[vbase:vbase + g.n]
         assert np.all(np.abs(sub - ref) <= 1e-4 * np.abs(ref) + 1e-6 * max(ref.max(), 1.0))
         vbase += g.n
+
+
+def test_bc_multi_equals_each_graph(gpu):
+    """bc_multi over graphs of uneven size (more graphs than worker streams,
+    one directed, one with no sources): each graph's scores equal the oracle
+    and its own bc_batched run."""
+    specs = [(7, True), (10, True), (8, False), (12, True), (7, True), (9, True), (11, False), (8, True),
+             (9, True), (6, True)]
+    graphs, parts, srcs = [], [], []
+    for i, (scale, sym) in enumerate(specs):
+        g = graphgen.rmat(scale, seed=200 + i, symmetrize=sym)
+        G = gpu.graph_load_csr(g.n, g.offsets, g.cols, symmetric=sym)
+        graphs.append(g)
+        parts.append(gpu.partition_by_degree(G, tuning=SMALL_BINS if i % 2 else None))
+        srcs.append([] if i == 4 else graphgen.sample_roots(g, 40 + 13 * i, seed=i).tolist())
+    got = gpu.bc_multi(parts, srcs)
+    assert gpu.tg_last_stats()["graphs"] == len(specs)
+    for i, g in enumerate(graphs):
+        v = got[i].cpu().numpy().astype(np.float64)
+        ref = oracle.bc(g.offsets, g.cols, srcs[i])
+        assert np.all(np.abs(v - ref) <= 1e-4 * np.abs(ref) + 1e-6 * max(np.abs(ref).max(), 1.0)), i
+        if srcs[i]:
+            assert np.array_equal(v, gpu.bc_batched(parts[i], srcs[i]).cpu().numpy()), i
+    with pytest.raises(gpu.TGError) as ei:
+        gpu.bc_multi([parts[0], parts[0]], [srcs[0], srcs[0]])
+    assert ei.value.code == gpu.TG_EINVAL
+    with pytest.raises(gpu.TGError) as ei:
+        gpu.bc_multi([parts[1], parts[0]], [srcs[1], [graphs[0].n]])
+    assert ei.value.code == gpu.TG_EINVAL
+    assert gpu.bc_multi([], []) == []
+
+
+def test_tuning_cache_resolved_by_the_library(gpu, tmp_path, monkeypatch):
+    """partition_by_degree(tuning_json=NULL) takes the cached entry keyed by
+    device architecture and graph signature; "{}" and an unmatched graph
+    take the built-in values."""
+    import json
+    import math
+    g = graphgen.rmat(12)
+    G = gpu.graph_load_csr(g.n, g.offsets, g.cols, symmetric=True)
+    avg = g.nnz / g.n
+    key = f"gfx950:V2^{round(math.log2(g.n))}:deg{round(avg)}:sym"
+    cfg = dict(SMALL_BINS, hub_chunk=512, bfs_alpha=7)
+    path = tmp_path / "cache.json"
+    path.write_text(json.dumps({"gfx950:V2^30:deg1:dir": {"config": {"hub_chunk": 8192}},
+                                key: {"config": cfg, "final_ms": {"all": 1.0}}}))
+    monkeypatch.setenv("TG_TUNING_CACHE", str(path))
+    P = gpu.partition_by_degree(G)
+    info = P.info()
+    assert info["tuning_source"] == "cache " + key
+    for k, v in cfg.items():
+        assert info["tuning"][k] == v, k
+    root = graphgen.max_degree_vertex(g)
+    assert np.array_equal(gpu.bfs(P, [root]).cpu().numpy()[0], oracle.bfs(g.offsets, g.cols, root))
+    assert gpu.partition_by_degree(G, tuning="{}").info()["tuning_source"] == "caller"
+    assert gpu.partition_by_degree(G, tuning="{}").info()["tuning"]["hub_chunk"] == 4096
+    d = graphgen.rmat(12, symmetrize=False)
+    D = gpu.graph_load_csr(d.n, d.offsets, d.cols, symmetric=False)
+    assert gpu.partition_by_degree(D).info()["tuning_source"] == "built-in"

@@ -114,3 +114,74 @@ def test_timeout_and_errors(gpu):
     with pytest.raises(gpu.TGError):
         S.submit(gid, gpu.TG_QUERY_BFS, n, out)
     S.close()
+
+
+def test_overflowing_query_does_not_poison_its_lane(gpu):
+    """An SSSP query whose distances do not fit in int32 fails with
+    TG_ERANGE; queries before, beside and after it on the same (graph, SSSP)
+    lane keep their exact results (the overflow verdict is per query)."""
+    import torch
+    big = 2**31 - 10
+    # 0 -> 1 -> 2 with huge weights (root 0 overflows at vertex 2); a path
+    # 3 -> 4 -> ... -> 202 with small weights keeps other queries in flight
+    src = [0, 1] + list(range(3, 202))
+    dst = [1, 2] + list(range(4, 203))
+    g = graphgen.from_edges(203, np.array(src), np.array(dst), symmetrize=False)
+    wmap = {(0, 1): big, (1, 2): big}
+    w = np.array([wmap.get((u, int(v)), 3 + (u % 5)) for u in range(g.n)
+                  for v in g.cols[g.offsets[u]:g.offsets[u + 1]]], dtype=np.int32)
+    G = gpu.graph_load_csr(g.n, g.offsets, g.cols, w)
+    P = gpu.partition_by_degree(G)
+    S = gpu.Server()
+    gid = S.add_graph(P)
+    roots_before = [3, 1, 10]
+    roots_after = [0, 3, 1, 50, 4, 0, 200, 1]
+    outs, tickets = [], []
+    for r in roots_before + [0] + roots_after:
+        o = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        outs.append((r, o))
+        tickets.append(S.submit(gid, gpu.TG_QUERY_SSSP, r, o))
+    for (r, o), t in zip(outs, tickets):
+        if r == 0:
+            with pytest.raises(gpu.TGError) as ei:
+                S.wait(t)
+            assert ei.value.code == gpu.TG_ERANGE
+        else:
+            S.wait(t)
+            assert np.array_equal(o.cpu().numpy(), oracle.sssp(g.offsets, g.cols, w, r)), r
+    # the lane stays healthy for later queries
+    o = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    S.wait(S.submit(gid, gpu.TG_QUERY_SSSP, 3, o))
+    assert np.array_equal(o.cpu().numpy(), oracle.sssp(g.offsets, g.cols, w, 3))
+    S.close()
+    with pytest.raises(gpu.TGError) as ei:
+        gpu.sssp(P, [0])
+    assert ei.value.code == gpu.TG_ERANGE
+
+
+def test_add_graph_while_queries_run(gpu, graphs):
+    """Graphs registered while earlier queries are in flight (the worker walks
+    its lanes meanwhile): every result, old and new, equals the oracle."""
+    import torch
+    n = 3000
+    path = graphgen.from_edges(n, np.arange(n - 1), np.arange(1, n), symmetrize=True)
+    PG = gpu.graph_load_csr(path.n, path.offsets, path.cols, symmetric=True)
+    PP = gpu.partition_by_degree(PG)
+    S = gpu.Server()
+    pid = S.add_graph(PP)
+    long_out = torch.empty(n, dtype=torch.int32, device="cuda")
+    long_t = S.submit(pid, gpu.TG_QUERY_BFS, 0, long_out)  # thousands of supersteps
+    jobs = []
+    for rep in range(4):  # grow the lane table several times over
+        for (g, w, _, P) in graphs:
+            gid = S.add_graph(P)
+            for kind in (0, 1):
+                root = int(graphgen.sample_roots(g, 3, seed=rep)[kind])
+                out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+                jobs.append((g, w, kind, root, out, S.submit(gid, kind, root, out)))
+    for (g, w, kind, root, out, t) in jobs:
+        S.wait(t)
+        assert np.array_equal(out.cpu().numpy(), expected(g, w, kind, root)), (kind, root)
+    S.wait(long_t)
+    assert np.array_equal(long_out.cpu().numpy(), np.arange(n))
+    S.close()
