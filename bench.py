@@ -44,8 +44,7 @@ def kernel_sources_digest(files):
 # launch shapes (a traffic figure is only reused while these are unchanged).
 KERNEL_FILES = {
     "pr_gather": ["pagerank.hip", "pr_sliced.hip", "pr_rows.hip", "kcommon.h", "../tuning_cache.json"],
-    "bfs_expand": ["bfs.hip", "kcommon.h", "../tuning_cache.json"],
-    "bfs_bottom_up": ["bfs.hip", "kcommon.h", "../tuning_cache.json"],
+    "bfs_step": ["bfs.hip", "frontier.hip", "kcommon.h", "../tuning_cache.json"],
     "sssp_relax": ["sssp.hip", "kcommon.h", "../tuning_cache.json"],
 }
 
@@ -72,8 +71,7 @@ def load_traffic(kernel: str, workload: str):
 TRAFFIC_ROWS = {
     "sssp_relax": ("sssp", ["k_sssp_relax"]),
     "pr_gather": ("pr", ["k_pr_rows<true, int, 8>", "k_pr_long<true>", "k_pr_combine", "k_pr_dsum"]),
-    "bfs_expand": ("bfs", ["k_bfs_expand"]),
-    "bfs_bottom_up": ("bfs", ["k_bfs_bottom_up_thread", "k_bfs_bottom_up_wave"]),
+    "bfs_step": ("bfs", ["k_bfs_step<int>"]),
 }
 # A 1 GiB device-to-device copy (--copy-calibration) reads FETCH_SIZE =
 # 524317 KiB and WRITE_SIZE = 1048576 KiB on MI355X.
@@ -147,8 +145,33 @@ def gather_reference(n, cols, count=1 << 27, reps=3):
                    "and the CSR column array (int32) as indices"}
 
 
-def cpu_baseline(g, w, roots, iters, step_units):
-    """The oracle on the host cores over a bounded sample of the same work."""
+def host_facts() -> dict:
+    """The host the oracle runs on: logical CPUs, the ones this process may
+    use, CPU model, sockets and memory (from /proc)."""
+    facts = {"nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+    try:
+        txt = open("/proc/cpuinfo").read()
+        models = [ln.split(":", 1)[1].strip() for ln in txt.splitlines() if ln.startswith("model name")]
+        facts["cpu_model"] = models[0] if models else None
+        facts["sockets"] = len({ln.split(":", 1)[1].strip() for ln in txt.splitlines()
+                                if ln.startswith("physical id")}) or None
+    except OSError:
+        pass
+    try:
+        for ln in open("/proc/meminfo"):
+            if ln.startswith("MemTotal"):
+                facts["mem_gib"] = round(int(ln.split()[1]) / 2**20, 1)
+    except OSError:
+        pass
+    return facts
+
+
+def cpu_baseline(g, w, roots, iters, step_units, max_threads=16):
+    """The oracle on the host cores over a bounded sample of the same work,
+    in two modes: one thread (the jobs one after another) and all usable
+    cores (as many independent jobs of each kind as cores, run at once:
+    BFS and SSSP per root, one PageRank iteration per job).  Each kind's
+    rate (edges per second) is scaled to one step's edge mix."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -156,45 +179,64 @@ def cpu_baseline(g, w, roots, iters, step_units):
     import oracle
 
     deg = np.diff(g.offsets)
-    jobs = [("bfs", int(r)) for r in roots[:4]] + [("sssp", int(r)) for r in roots[:2]] + [("pr", 1)]
 
     def run(job):
         kind, arg = job
-        t = time.perf_counter()
         if kind == "bfs":
             lev = oracle.bfs(g.offsets, g.cols, arg)
-            edges = int(deg[lev != INF].sum())
-        elif kind == "sssp":
+            return int(deg[lev != INF].sum())
+        if kind == "sssp":
             d = oracle.sssp(g.offsets, g.cols, w, arg)
-            edges = int(deg[d != INF].sum())
-        else:
-            oracle.pagerank(g.offsets, g.cols, 0.85, arg)
-            edges = g.nnz * arg
-        return kind, edges, time.perf_counter() - t
+            return int(deg[d != INF].sum())
+        oracle.pagerank(g.offsets, g.cols, 0.85, 1)
+        return g.nnz
 
-    threads = min(len(jobs), os.cpu_count() or 1, 16)
-    t0 = time.perf_counter()
-    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
-        res = list(ex.map(run, jobs))
-    wall = time.perf_counter() - t0
-    per = {}
-    for kind, edges, secs in res:
-        e, s = per.get(kind, (0, 0.0))
-        per[kind] = (e + edges, s + secs)
-    # thread-seconds per edge of each kind, scaled to one step's edge mix, then
-    # divided by the threads that ran concurrently
-    cpu_seconds = sum(step_units[k] * (per[k][1] / per[k][0]) for k in per if per[k][0] > 0)
-    step_edges = sum(step_units.values())
-    gteps = step_edges / (cpu_seconds / threads) / 1e9
+    def rates(jobs_by_kind, threads):
+        out, wall = {}, {}
+        for kind, jobs in jobs_by_kind.items():
+            t = time.perf_counter()
+            if threads == 1:
+                edges = sum(run(j) for j in jobs)
+            else:
+                with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+                    edges = sum(ex.map(run, jobs))
+            wall[kind] = time.perf_counter() - t
+            out[kind] = edges / wall[kind]
+        step_s = sum(step_units[k] / out[k] for k in out if step_units.get(k))
+        return sum(step_units.values()) / step_s / 1e9, wall
+
+    facts = host_facts()
+    cores = max(1, min(facts["usable_cpus"], max_threads))
+    one, wall1 = rates({"bfs": [("bfs", int(r)) for r in roots[:4]], "sssp": [("sssp", int(r)) for r in roots[:2]],
+                        "pr": [("pr", 1)]}, 1)
+    allc, wallc = rates({"bfs": [("bfs", int(r)) for r in roots[:cores]],
+                         "sssp": [("sssp", int(r)) for r in roots[:cores]],
+                         "pr": [("pr", 1)] * cores}, cores)
     return {
-        "value": round(gteps, 4),
+        "value": round(allc, 4),
         "unit": "GTEPS",
-        "cores": threads,
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"{len(roots[:4])} BFS roots, {len(roots[:2])} SSSP roots (Dijkstra) and 1 PageRank "
-                   f"iteration of the same graph, run concurrently on {threads} threads in {wall:.1f} s; "
-                   "per-kind seconds per edge scaled to one step's edge mix"),
+        "sample": (f"all-cores mode: {cores} BFS roots, {cores} SSSP roots (Dijkstra) and {cores} independent "
+                   f"PageRank iterations of the same graph, each kind's jobs run at once on {cores} threads "
+                   f"({sum(wallc.values()):.1f} s); rates per kind scaled to one step's edge mix"),
+        "one_thread": {"value": round(one, 4), "cores": 1,
+                       "sample": f"4 BFS roots, 2 SSSP roots, 1 PageRank iteration, one after another "
+                                 f"({sum(wall1.values()):.1f} s)"},
+        "host": facts,
     }
+
+
+def dist_stats(xs) -> dict:
+    """Median, p99, mean and its 95% confidence half-width (Student t)."""
+    import numpy as np
+    from scipy import stats as st
+
+    a = np.asarray(xs, dtype=np.float64)
+    n = a.size
+    half = float(st.t.ppf(0.975, n - 1) * a.std(ddof=1) / np.sqrt(n)) if n > 1 else None
+    return {"n": int(n), "median": round(float(np.median(a)), 4), "p99": round(float(np.percentile(a, 99)), 4),
+            "mean": round(float(a.mean()), 4), "ci95": None if half is None else round(half, 4)}
 
 
 SERVE_GRAPHS = ["rmat18", "rmat19", "rmat20", "rmat21", "rmat22", "rmat23", "uniform20", "uniform22"]
@@ -592,6 +634,8 @@ def main():
     ap.add_argument("--roots", type=int, default=64)
     ap.add_argument("--pr-iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=3,
+                    help="steps of the second pass that times every kernel launch with HIP events")
     ap.add_argument("--tuning", default="auto",
                     help="JSON tuning object, 'auto' (autotuner cache if present, else built-in) or 'none'")
     ap.add_argument("--autotune", action="store_true", help="run the autotuner (untimed) and update its cache")
@@ -701,6 +745,10 @@ def main():
         ev[3].record(stream)
         stats.append((ev, s_bfs, s_sssp, s_pr))
 
+    # timed region: per-kernel timing events off (they add a few
+    # microseconds per launch); a second pass with them on gives the
+    # kernels' durations for the roofline
+    tg.tg_set_timing(False)
     for i in range(args.warmup):
         step([])
         print(f"[bench] warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
@@ -719,6 +767,22 @@ def main():
     total_ms = t0.elapsed_time(t1)
     ms_step = total_ms / args.steps
 
+    # kernel durations: HIP events recorded by libtg around each launch on
+    # the launching stream, over a separate timed pass of the same steps
+    tg.tg_set_timing(True)
+    prof = []
+    n_prof = max(1, min(args.steps, args.profile_steps))
+    p0 = torch.cuda.Event(enable_timing=True)
+    p1 = torch.cuda.Event(enable_timing=True)
+    p0.record(stream)
+    for i in range(n_prof):
+        step(prof)
+    p1.record(stream)
+    torch.cuda.synchronize()
+    prof_ms_step = p0.elapsed_time(p1) / n_prof
+    tg.tg_set_timing(False)
+    print(f"[bench] {n_prof} profiled step(s) done", file=sys.stderr, flush=True)
+
     # traversed edges (section 5): out-degrees of reached vertices
     deg = torch.from_numpy(np.diff(g.offsets)).to("cuda")
     run_bfs = args.only in (None, "bfs")
@@ -730,16 +794,21 @@ def main():
     pr_edges = args.pr_iters * E if run_pr else 0
     step_edges = bfs_edges + sssp_edges + pr_edges
 
-    def phase(k):
-        return sum(s[0][k].elapsed_time(s[0][k + 1]) for s in stats) / len(stats)
+    def phase_list(st, k):
+        return [x[0][k].elapsed_time(x[0][k + 1]) for x in st]
 
-    t_bfs, t_sssp, t_pr = (max(phase(k), 1e-9) for k in range(3))
-    last = stats[-1]
-    sb, ss, sp = last[1], last[2], last[3]
+    t_bfs, t_sssp, t_pr = (max(sum(phase_list(stats, k)) / len(stats), 1e-9) for k in range(3))
+    sb, ss, sp = prof[-1][1], prof[-1][2], prof[-1][3]
     # algorithmic bytes (int32 ids, int64 offsets)
-    bfs_bytes = 4.125 * bfs_edges + 20.0 * bfs_verts            # whole BFS, all roots
+    bfs_bytes = 4.125 * bfs_edges + 20.0 * bfs_verts            # whole top-down BFS, all roots
     pr_bytes_iter = 8.0 * E + 16.0 * V                          # one pull iteration
     sssp_bytes = 12.0 * ss.get("relaxations", 0) + 16.0 * ss.get("activations", 0)
+    # what the direction-optimizing BFS kernels read: top-down, per edge
+    # scanned its id and visited bit, per vertex expanded its offsets and
+    # queue entry; bottom-up, per vertex examined two int32 offsets, per
+    # in-edge checked its id and frontier bit
+    bfs_step_bytes = (4.125 * sb.get("edges_scanned", 0) + 12.0 * sb.get("vertices_expanded", 0) +
+                      8.0 * sb.get("bottom_up_vertices_examined", 0) + 4.125 * sb.get("bottom_up_edges_checked", 0))
 
     kernels = {}
     if "pr_gather_ms" in sp:
@@ -750,13 +819,8 @@ def main():
         # the XCD-split gather: one iteration = class gathers + their combine
         kernels["pr_gather"] = dict(ms=sp["pr_slice_gather_ms"] + sp["pr_combine_ms"], n=sp["pr_slice_gather_n"],
                                     bytes=pr_bytes_iter * sp["pr_slice_gather_n"])
-    if "bfs_expand_ms" in sb:
-        exp_bytes = 4.125 * sb["edges_scanned"] + 12.0 * sb["vertices_expanded"]
-        kernels["bfs_expand"] = dict(ms=sb["bfs_expand_ms"], n=sb["bfs_expand_n"], bytes=exp_bytes)
-    if "bfs_bottom_up_ms" in sb:
-        # bottom-up steps: an in-neighbour id (4 B) and a frontier bit per edge checked
-        kernels["bfs_bottom_up"] = dict(ms=sb["bfs_bottom_up_ms"], n=sb["bfs_bottom_up_n"],
-                                        bytes=4.125 * sb.get("bottom_up_edges_checked", 0))
+    if "bfs_step_ms" in sb:
+        kernels["bfs_step"] = dict(ms=sb["bfs_step_ms"], n=sb["bfs_step_n"], bytes=bfs_step_bytes)
     if "sssp_relax_ms" in ss:
         kernels["sssp_relax"] = dict(ms=ss["sssp_relax_ms"], n=ss["sssp_relax_n"], bytes=sssp_bytes)
     roofs = {}
@@ -769,8 +833,34 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": tr, "algorithmic_bytes_per_launch": round(bytes_per_launch),
                     "avg_launch_ms": round(avg_ms, 5), "launches": int(v["n"]), "share_of_step":
-                        round(v["ms"] / ms_step, 4)}
+                        round(v["ms"] / prof_ms_step, 4)}
     dominant = max(kernels, key=lambda k: kernels[k]["ms"]) if kernels else None
+
+    # per-root latency: each root alone (one search in flight)
+    lat = {}
+    if run_bfs:
+        one = torch.empty((1, V), dtype=torch.int32, device="cuda")
+        xs = []
+        for r in roots:
+            a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a_.record(stream)
+            tg.bfs(P, [int(r)], one)
+            b_.record(stream)
+            b_.synchronize()
+            xs.append(a_.elapsed_time(b_))
+        lat["bfs_ms"] = dist_stats(xs)
+    if run_sssp:
+        one = torch.empty((1, V), dtype=torch.int32, device="cuda")
+        xs = []
+        for r in roots:
+            a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a_.record(stream)
+            tg.sssp(P, [int(r)], one)
+            b_.record(stream)
+            b_.synchronize()
+            xs.append(a_.elapsed_time(b_))
+        lat["sssp_ms"] = dist_stats(xs)
+    print("[bench] single-root latency pass done", file=sys.stderr, flush=True)
 
     out = {
         "metric": "GTEPS (BFS + SSSP + PageRank step) on RMAT-24",
@@ -783,26 +873,35 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32 (bfs/sssp), f32 ranks with f64 sums (pagerank)",
+        "dtype": "int32 (bfs/sssp); pagerank: f32 ranks and contributions, per-class partial sums rounded to f32, "
+                 "combined in f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: V={V}, E={E} directed (symmetrized), {nr} BFS roots + {nr} "
                                f"SSSP roots (weights 1..255) + {args.pr_iters} PageRank iterations",
                    "global_batch": nr, "parallelism": "none (1 GPU)"},
         "bfs": {"gteps": round(bfs_edges / (t_bfs / 1e3) / 1e9, 2), "ms_per_root": round(t_bfs / nr, 4),
-                "hbm_gbs_algorithmic": round(bfs_bytes / (t_bfs / 1e3) / 1e9, 1),
+                "hbm_gbs_top_down_equivalent": round(bfs_bytes / (t_bfs / 1e3) / 1e9, 1),
+                "hbm_gbs_kernel_bytes": round(bfs_step_bytes / (t_bfs / 1e3) / 1e9, 1),
                 "graph500_undirected_gteps": round(bfs_edges / 2 / (t_bfs / 1e3) / 1e9, 2),
                 "top_down_edges_per_root": round(sb.get("edges_scanned", 0) / nr),
                 "bottom_up_edges_checked_per_root": round(sb.get("bottom_up_edges_checked", 0) / nr),
-                "bottom_up_steps_per_root": round(sb.get("bottom_up_steps", 0) / nr, 2)},
+                "bottom_up_vertices_examined_per_root": round(sb.get("bottom_up_vertices_examined", 0) / nr),
+                "bottom_up_steps_per_root": round(sb.get("bottom_up_steps", 0) / nr, 2),
+                "supersteps_per_root": round(sb.get("supersteps", 0) / nr, 2),
+                "ms_per_root_over_steps": dist_stats([x / nr for x in phase_list(stats, 0)])},
         "sssp": {"gteps": round(sssp_edges / (t_sssp / 1e3) / 1e9, 2), "ms_per_root": round(t_sssp / nr, 4),
                  "supersteps_per_root": round(ss.get("supersteps", 0) / nr, 1),
-                 "work_efficiency": round(ss.get("relaxations", 0) / max(sssp_edges, 1), 3)},
+                 "work_efficiency": round(ss.get("relaxations", 0) / max(sssp_edges, 1), 3),
+                 "ms_per_root_over_steps": dist_stats([x / nr for x in phase_list(stats, 1)])},
         "gather_reference": None,
         "pagerank": {"gteps": round(pr_edges / (t_pr / 1e3) / 1e9, 2),
                      "ms_per_iter": round(t_pr / args.pr_iters, 4),
-                     "hbm_gbs_algorithmic": round(pr_bytes_iter * args.pr_iters / (t_pr / 1e3) / 1e9, 1)},
+                     "hbm_gbs_algorithmic": round(pr_bytes_iter * args.pr_iters / (t_pr / 1e3) / 1e9, 1),
+                     "ms_per_iter_over_steps": dist_stats([x / args.pr_iters for x in phase_list(stats, 2)])},
+        "single_root_latency": lat,
         "roofline": dict(roofs[dominant], kernel=dominant) if dominant else None,
         "kernels": roofs,
+        "profiled_ms_per_step": round(prof_ms_step, 3),
         "tuning": {"source": tuning_used, "values": tg.partition_info(P)["tuning"]},
         "host_wall_s": round(wall, 3),
     }

@@ -298,6 +298,14 @@ int partition_info(const tg_partition *p, char *json, size_t cap);
  * partition_info. */
 int tg_last_stats(char *json, size_t cap);
 
+/* Per-kernel timing: with on != 0, every timed kernel launch is bracketed
+ * by HIP events on its stream and tg_last_stats() reports "<kernel>_ms"
+ * (summed duration) and "<kernel>_n" (launches); the events themselves add
+ * a few microseconds per launch.  The initial setting comes from the
+ * TG_TIMING environment variable (unset or "0": off).  Process-wide; takes
+ * effect for calls that start after it returns. */
+void tg_set_timing(int on);
+
 #ifdef __cplusplus
 }
 #endif

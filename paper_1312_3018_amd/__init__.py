@@ -78,6 +78,8 @@ def _load():
     lib.tg_last_error.restype = ctypes.c_char_p
     lib.partition_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     lib.tg_last_stats.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    lib.tg_set_timing.argtypes = [ctypes.c_int]
+    lib.tg_set_timing.restype = None
     for f in (lib.graph_load_csr, lib.partition_by_degree, lib.partition_retune, lib.bfs, lib.sssp, lib.pagerank, lib.bc,
               lib.bfs_batched, lib.sssp_batched,
               lib.partition_info, lib.tg_last_stats):
@@ -232,6 +234,11 @@ def tg_last_stats() -> dict:
     buf = ctypes.create_string_buffer(need + 1)
     lib.tg_last_stats(buf, need + 1)
     return json.loads(buf.value.decode())
+
+
+def tg_set_timing(on: bool) -> None:
+    """Per-kernel HIP-event timing on (reported by tg_last_stats) or off."""
+    _load().tg_set_timing(1 if on else 0)
 
 
 def _roots(roots) -> np.ndarray:

@@ -24,6 +24,7 @@ DEFAULTS = {
     "hub_chunk": 4096, "pr_lds_verts": 40960, "pr_grid": 256, "bfs_lds_words": 4096, "bfs_grid": 2048,
     "bfs_lds_min_vblocks": 4096, "sssp_delta": 0, "sssp_lds_verts": 0, "sssp_grid": 2048, "pr_xcd": 1,
     "pr_rows": 512, "bfs_do": 1, "bfs_alpha": 14, "bfs_beta": 24, "sssp_xcd": 0,
+    "bfs_lanes": 2, "bfs_td_grid": 1024, "bfs_bu_grid": 4096,
 }
 
 SPACE = {
@@ -37,9 +38,9 @@ SPACE = {
     "pr_rows": [256, 512],
     "pr_lds_verts": [0, 8192, 16384, 24576, 32768, 40960],
     "pr_grid": [256, 512, 1024],
-    "bfs_lds_words": [0, 1024, 4096, 8192],
-    "bfs_grid": [1024, 2048, 4096, 16384],
-    "bfs_lds_min_vblocks": [1024, 4096, 16384, 1 << 40],
+    "bfs_td_grid": [512, 1024, 2048],
+    "bfs_bu_grid": [2048, 4096, 8192],
+    "bfs_lanes": [1, 2],
     "bfs_alpha": [4, 14, 32, 64],
     "bfs_beta": [8, 24, 64],
     "sssp_delta": [0, 64, 128, 256, 512, 1024, 4096],
@@ -50,9 +51,9 @@ SPACE = {
 
 FAMILY = {k: "all" for k in ("hub_min_deg", "block_min_deg", "wave_min_deg", "g16_min_deg", "g4_min_deg",
                              "hub_chunk")}
-FAMILY.update({"pr_xcd": "pr", "pr_rows": "pr", "pr_lds_verts": "pr", "pr_grid": "pr", "bfs_lds_words": "bfs", "bfs_grid": "bfs",
-               "bfs_alpha": "bfs", "bfs_beta": "bfs",
-               "bfs_lds_min_vblocks": "bfs", "sssp_delta": "sssp", "sssp_lds_verts": "sssp",
+FAMILY.update({"pr_xcd": "pr", "pr_rows": "pr", "pr_lds_verts": "pr", "pr_grid": "pr", "bfs_td_grid": "bfs",
+               "bfs_bu_grid": "bfs", "bfs_lanes": "bfs", "bfs_alpha": "bfs", "bfs_beta": "bfs",
+               "sssp_delta": "sssp", "sssp_lds_verts": "sssp",
                "sssp_grid": "sssp", "sssp_xcd": "sssp"})
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")

@@ -103,6 +103,7 @@ Workspace::~Workspace() {
   if (h_flags) TG_QUIET(hipHostFree(h_flags));
   if (h_work) TG_QUIET(hipHostFree(h_work));
   if (h_stat) TG_QUIET(hipHostFree(h_stat));
+  if (h_ctl) TG_QUIET(hipHostFree(h_ctl));
 }
 
 int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
@@ -138,6 +139,7 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   TG_TRY(dalloc(arena, &work, (size_t)tgk::STAT_COUNTERS * tgk::STAT_SPAN));
   TG_TRY(dalloc(arena, &bcount, nwords / 1024 + 1));
   TG_TRY(dalloc(arena, &plan, 1));
+  TG_TRY(dalloc(arena, &ctl, 1));
   TG_HIP(hipMemset(bits_a, 0, nwords * sizeof(uint32_t)));
   TG_HIP(hipMemset(bits_b, 0, nwords * sizeof(uint32_t)));
   TG_HIP(hipMemset(bits_c, 0, nwords * sizeof(uint32_t)));
@@ -145,6 +147,7 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   TG_HIP(hipMemset(work, 0, (size_t)tgk::STAT_COUNTERS * tgk::STAT_SPAN * sizeof(unsigned long long)));
   if (!h_plan) TG_HIP(hipHostMalloc((void **)&h_plan, sizeof(Plan), hipHostMallocDefault));
   if (!h_flags) TG_HIP(hipHostMalloc((void **)&h_flags, 64 * sizeof(uint32_t), hipHostMallocDefault));
+  if (!h_ctl) TG_HIP(hipHostMalloc((void **)&h_ctl, sizeof(tgk::BfsCtl), hipHostMallocDefault));
   if (!h_work) TG_HIP(hipHostMalloc((void **)&h_work, 8 * sizeof(unsigned long long), hipHostMallocDefault));
   if (!h_stat)
     TG_HIP(hipHostMalloc((void **)&h_stat, (size_t)tgk::STAT_COUNTERS * tgk::STAT_SPAN * sizeof(unsigned long long),
@@ -199,6 +202,9 @@ Tuning default_tuning() {
   t.bfs_alpha = 14;
   t.bfs_beta = 24;
   t.sssp_xcd = 0;  // measured slower than the plain relax (8 x the per-vertex work)
+  t.bfs_lanes = 2;
+  t.bfs_td_grid = 1024;
+  t.bfs_bu_grid = 4096;
   return t;
 }
 
@@ -239,6 +245,12 @@ int parse_tuning(const char *json, Tuning *t) {
   if (json_int(json, "bfs_alpha", &v)) t->bfs_alpha = v;
   if (json_int(json, "bfs_beta", &v)) t->bfs_beta = v;
   if (json_int(json, "sssp_xcd", &v)) t->sssp_xcd = v;
+  if (json_int(json, "bfs_lanes", &v)) t->bfs_lanes = v;
+  if (json_int(json, "bfs_td_grid", &v)) t->bfs_td_grid = v;
+  if (json_int(json, "bfs_bu_grid", &v)) t->bfs_bu_grid = v;
+  if (t->bfs_lanes != 1 && t->bfs_lanes != 2) return set_error(TG_EINVAL, "tuning: bfs_lanes must be 1 or 2");
+  if (t->bfs_td_grid < 1 || t->bfs_td_grid > 16384 || t->bfs_bu_grid < 2 || t->bfs_bu_grid > 16384)
+    return set_error(TG_EINVAL, "tuning: bfs_td_grid must be in [1, 16384] and bfs_bu_grid in [2, 16384]");
   if (t->sssp_xcd != 0 && t->sssp_xcd != 1) return set_error(TG_EINVAL, "tuning: sssp_xcd must be 0 or 1");
   if (t->bfs_do != 0 && t->bfs_do != 1) return set_error(TG_EINVAL, "tuning: bfs_do must be 0 or 1");
   if (t->bfs_alpha < 1 || t->bfs_alpha > 1000000 || t->bfs_beta < 1 || t->bfs_beta > 1000000)
@@ -469,6 +481,16 @@ int apply_tuning(tg_partition *p, const Tuning &t) {
   return TG_OK;
 }
 
+// A 32-bit copy of CSR offsets when every offset fits (m < 2^31): half the
+// offset bytes of a bottom-up BFS step, which reads them for every
+// unvisited vertex.  Left null otherwise.
+int upload_off32(DevArena &A, int32_t **d, const std::vector<int64_t> &off, int64_t m) {
+  if (m >= (int64_t)INT32_MAX) return TG_OK;
+  std::vector<int32_t> o32(off.size());
+  for (size_t i = 0; i < off.size(); ++i) o32[i] = (int32_t)off[i];
+  return upload(A, d, o32.data(), o32.size());
+}
+
 // Build and upload the GPU partition over the vertex subset `verts` (global
 // ids).  Edges to vertices outside the subset are boundary edges: they are
 // returned through `boundary` (per local source, the global destinations and
@@ -557,12 +579,14 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
     in_deg_in_order = deg_in_order;
     for (int64_t i = 0; i < n; ++i) gp.n_dangling += (deg_in_order[i] == 0);
     gp.n_isolated = gp.n_dangling;
+    TG_TRY(upload_off32(A, &gp.in_off32, off, m));
   } else {
     std::vector<int64_t> ioff;
     std::vector<int32_t> icol;
     transpose_csr(n, off, col, ioff, icol);
     TG_TRY(upload(A, &gp.in.off, ioff.data(), (size_t)n + 1));
     TG_TRY(upload(A, &gp.in.col, icol.data(), (size_t)m));
+    TG_TRY(upload_off32(A, &gp.in_off32, ioff, m));
     gp.in.n = n;
     gp.in.m = m;
     gp.in_alias = false;
@@ -723,10 +747,13 @@ extern "C" void partition_free(tg_partition *p) {
   pr_slices_free(p->gpu);
   pr_rows_free(p->gpu);
   sssp_slices_free(p->gpu);
+  if (p->aux_stream) TG_QUIET(hipStreamDestroy(p->aux_stream));
   delete p;
 }
 
 extern "C" const char *tg_last_error(void) { return g_err.c_str(); }
+
+extern "C" void tg_set_timing(int on) { set_timing(on != 0); }
 
 static int emit(const std::string &s, char *buf, size_t cap) {
   if (buf && cap) {
@@ -769,14 +796,16 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            "\"g16_min_deg\":%lld,\"g4_min_deg\":%lld,\"hub_chunk\":%lld,\"pr_lds_verts\":%lld,"
            "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld,"
            "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld,\"pr_xcd\":%lld,\"pr_rows\":%lld,"
-           "\"bfs_do\":%lld,\"bfs_alpha\":%lld,\"bfs_beta\":%lld,\"sssp_xcd\":%lld}",
+           "\"bfs_do\":%lld,\"bfs_alpha\":%lld,\"bfs_beta\":%lld,\"sssp_xcd\":%lld,\"bfs_lanes\":%lld,"
+           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld}",
            (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
            (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk,
            (long long)p->tune.pr_lds_verts, (long long)p->tune.pr_grid, (long long)p->tune.bfs_lds_words,
            (long long)p->tune.bfs_grid, (long long)p->tune.bfs_lds_min_vblocks, (long long)p->tune.sssp_delta,
            (long long)p->tune.sssp_lds_verts, (long long)p->tune.sssp_grid, (long long)p->tune.pr_xcd,
            (long long)p->tune.pr_rows, (long long)p->tune.bfs_do, (long long)p->tune.bfs_alpha,
-           (long long)p->tune.bfs_beta, (long long)p->tune.sssp_xcd);
+           (long long)p->tune.bfs_beta, (long long)p->tune.sssp_xcd, (long long)p->tune.bfs_lanes,
+           (long long)p->tune.bfs_td_grid, (long long)p->tune.bfs_bu_grid);
   s += buf;
   s += ",\"tuning_source\":\"" + p->tuning_source + "\"";
   s += hybrid_info_json(p);
@@ -815,26 +844,27 @@ extern "C" int bfs(const tg_partition *pc, const int32_t *roots, int32_t num_roo
   stats_reset("bfs");
   ktimer_reset();
   if (p->alpha > 0.0) return hybrid_bfs(p, roots, num_roots, levels, parents, s);
-  const int64_t V = p->g->n;
+  std::vector<int32_t> local((size_t)num_roots);
+  for (int32_t r = 0; r < num_roots; ++r) local[r] = p->h_l_of_g[roots[r]];
   int64_t supersteps = 0;
-  TG_TRY(p->ws.ensure(p->gpu, 0));
-  TG_TRY(stat_zero_all(p->ws, s));
-  for (int32_t r = 0; r < num_roots; ++r) {
-    const int32_t l = p->h_l_of_g[roots[r]];
-    int64_t depth = 0;
-    TG_TRY(gpu_bfs(p, l, s, &depth));
-    supersteps += depth + 1;
-    TG_TRY(collect_levels(p->gpu, p->ws.bits_a, p->ws.state, levels + (int64_t)r * V, s));
-    if (parents) TG_TRY(bfs_parents(p->gpu, p->ws.bits_a, p->ws.state, l, parents + (int64_t)r * V, s));
-  }
-  for (int k = 0; k < 4; ++k) TG_TRY(stat_fetch(p->ws, k, s));
+  TG_TRY(gpu_bfs_roots(p, local.data(), num_roots, levels, parents, s, &supersteps));
+  // counters of both lanes (the second lane's work is ordered before s)
+  Workspace *lanes[2] = {&p->ws, &p->ws2};
+  const int nl = (p->tune.bfs_lanes > 1 && num_roots > 1) ? 2 : 1;
+  for (int l = 0; l < nl; ++l)
+    for (int k = 0; k < 6; ++k) TG_TRY(stat_fetch(*lanes[l], k, s));
   TG_HIP(hipStreamSynchronize(s));
+  double sums[6] = {0, 0, 0, 0, 0, 0};
+  for (int l = 0; l < nl; ++l)
+    for (int k = 0; k < 6; ++k) sums[k] += (double)stat_sum(*lanes[l], k);
   stats_add("roots", num_roots);
   stats_add("supersteps", (double)supersteps);
-  stats_add("edges_scanned", (double)stat_sum(p->ws, 0));
-  stats_add("vertices_expanded", (double)stat_sum(p->ws, 1));
-  stats_add("bottom_up_edges_checked", (double)stat_sum(p->ws, 2));
-  stats_add("bottom_up_steps", (double)stat_sum(p->ws, 3));
+  stats_add("edges_scanned", sums[0]);
+  stats_add("vertices_expanded", sums[1]);
+  stats_add("bottom_up_edges_checked", sums[2]);
+  stats_add("bottom_up_steps", sums[3]);
+  stats_add("bottom_up_vertices_examined", sums[5]);
+  stats_add("lanes", nl);
   ktimer_emit();
   return TG_OK;
 }

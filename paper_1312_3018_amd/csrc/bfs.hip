@@ -23,10 +23,6 @@ __global__ void k_set_bit(uint32_t *bits, int32_t v) {
   if (threadIdx.x == 0) atomicOr(bits + (v >> 5), 1u << (v & 31));
 }
 
-__global__ void k_count_step(unsigned long long *c) {
-  if (threadIdx.x == 0) *c += 1ull;
-}
-
 // Test-then-set on the visited bitmap.  A plain load filters out neighbours
 // already visited before this superstep (stale reads only cost a redundant
 // atomic); the atomic OR is the arbiter.  No return value is needed: the
@@ -52,19 +48,16 @@ __device__ __forceinline__ void mark(uint32_t *visited, uint32_t *lds_bits, int3
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_bfs_expand(const Plan *__restrict__ Pp,
-                                                      const int32_t *__restrict__ queue,
-                                                      const int64_t *__restrict__ hubpref,
-                                                      const int64_t *__restrict__ off,
-                                                      const int32_t *__restrict__ col,
-                                                      uint32_t *visited, int64_t hub_chunk,
-                                                      unsigned long long *work, int32_t hot_words) {
-  extern __shared__ uint32_t lds_bits[];
-  for (int32_t i = threadIdx.x; i < hot_words; i += BLOCK) lds_bits[i] = visited[i];
-  const Plan &P = load_plan(Pp);  // (its barrier also publishes lds_bits)
+// Top-down expansion of the frontier in `queue` (plan P, already in LDS):
+// every frontier vertex marks its out-neighbours in `visited`.  Virtual
+// blocks blk, blk + nblk, ...
+__device__ __forceinline__ void expand_body(const Plan &P, const int32_t *__restrict__ queue,
+                                            const int64_t *__restrict__ hubpref, const int64_t *__restrict__ off,
+                                            const int32_t *__restrict__ col, uint32_t *visited, uint32_t *lds_bits,
+                                            int32_t hot_words, int64_t hub_chunk, int64_t blk, int64_t nblk,
+                                            unsigned long long &n_edges, unsigned long long &n_verts) {
   const int64_t total = P.vb[NBIN];
-  unsigned long long n_edges = 0, n_verts = 0;
-  for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
+  for (int64_t vb = blk; vb < total; vb += nblk) {
     const Assign a = assign_work(vb, P, queue, nullptr, hubpref, off, hub_chunk);
     if (!a.ok) continue;
     if (a.lane == 0) {
@@ -91,6 +84,21 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_expand(const Plan *__restrict__ P
       mark(visited, lds_bits, hot_words, n0, *word_ptr(visited, lds_bits, hot_words, n0));
     }
   }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_bfs_expand(const Plan *__restrict__ Pp,
+                                                      const int32_t *__restrict__ queue,
+                                                      const int64_t *__restrict__ hubpref,
+                                                      const int64_t *__restrict__ off,
+                                                      const int32_t *__restrict__ col,
+                                                      uint32_t *visited, int64_t hub_chunk,
+                                                      unsigned long long *work, int32_t hot_words) {
+  extern __shared__ uint32_t lds_bits[];
+  for (int32_t i = threadIdx.x; i < hot_words; i += BLOCK) lds_bits[i] = visited[i];
+  const Plan &P = load_plan(Pp);  // (its barrier also publishes lds_bits)
+  unsigned long long n_edges = 0, n_verts = 0;
+  expand_body(P, queue, hubpref, off, col, visited, lds_bits, hot_words, hub_chunk, blockIdx.x, gridDim.x, n_edges,
+              n_verts);
   n_edges = block_sum(n_edges);
   n_verts = block_sum(n_verts);
   if (threadIdx.x == 0 && n_edges + n_verts > 0) {
@@ -106,26 +114,35 @@ __device__ __forceinline__ unsigned long long joined_degree(const int64_t *ooff,
   return (unsigned long long)(ooff ? ooff[v + 1] - ooff[v] : e1 - e0);
 }
 
+// A vertex that joins in a bottom-up step writes its level (by local id:
+// the lanes of a wave hold consecutive vertices, so the stores coalesce).
+struct LevelOut {
+  int32_t *level;
+  int32_t value;
+  __device__ __forceinline__ void put(int32_t v) const { level[v] = value; }
+};
+
 // Bottom-up step, one thread per vertex in [v0, v1): an unvisited vertex
 // looks at its in-neighbours four at a time and joins the next frontier at
 // the first one found in `fbits` (the level-L set).  The out-degrees of the
-// vertices that join are summed into `degsum` (the direction switch's m_f).
+// vertices that join are summed into `joined` (the direction switch's m_f).
 // Waves cover whole bitmap words (lanes 0-31 one word, 32-63 the next), so
 // the joins of a word are set with one atomic instead of one per lane.
-__global__ __launch_bounds__(BLOCK) void k_bfs_bottom_up_thread(const int64_t *__restrict__ ioff,
-                                                                const int32_t *__restrict__ icol,
-                                                                const uint32_t *__restrict__ fbits, uint32_t *visited,
-                                                                int64_t v0, int64_t v1, unsigned long long *work,
-                                                                const int64_t *__restrict__ ooff,
-                                                                unsigned long long *degsum) {
-  unsigned long long checked = 0, joined = 0;
+// Blocks [blk0, blk0 + nblk) of the grid share the range.
+template <typename OffT>
+__device__ __forceinline__ void bottom_up_threads(const OffT *__restrict__ ioff, const int32_t *__restrict__ icol,
+                                                  const uint32_t *__restrict__ fbits, uint32_t *visited, int64_t v0,
+                                                  int64_t v1, const int64_t *__restrict__ ooff, int64_t blk,
+                                                  int64_t nblk, const LevelOut &lo, unsigned long long &checked,
+                                                  unsigned long long &joined, unsigned long long &examined) {
   const int lane = threadIdx.x & 63;
   const int64_t start = v0 & ~(int64_t)31;
-  for (int64_t vb = start + (int64_t)blockIdx.x * BLOCK; vb < v1; vb += (int64_t)gridDim.x * BLOCK) {
+  for (int64_t vb = start + blk * BLOCK; vb < v1; vb += nblk * BLOCK) {
     const int64_t v = vb + threadIdx.x;
     bool joins = false;
     if (v >= v0 && v < v1 && !(visited[v >> 5] & (1u << (v & 31)))) {
-      const int64_t e0 = ioff[v], e1 = ioff[v + 1];
+      ++examined;
+      const int64_t e0 = (int64_t)ioff[v], e1 = (int64_t)ioff[v + 1];
       for (int64_t e = e0; e < e1; e += 4) {
         int32_t u[4];
 #pragma unroll
@@ -137,6 +154,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_bottom_up_thread(const int64_t *_
         if (hit) {
           joins = true;
           joined += joined_degree(ooff, v, e0, e1);
+          lo.put((int32_t)v);
           break;
         }
       }
@@ -145,27 +163,23 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_bottom_up_thread(const int64_t *_
     if (lane == 0 && (uint32_t)m) atomicOr(visited + (v >> 5), (uint32_t)m);
     if (lane == 32 && (uint32_t)(m >> 32)) atomicOr(visited + (v >> 5), (uint32_t)(m >> 32));
   }
-  checked = block_sum(checked);
-  joined = block_sum(joined);
-  if (threadIdx.x == 0 && checked) stat_add(work, checked);
-  if (threadIdx.x == 0 && joined) stat_add(degsum, joined);
 }
 
 // The same with one wave per vertex in [v0, v1) (high in-degree): the wave
 // checks 64 in-neighbours per round and stops at the first round with a hit.
-__global__ __launch_bounds__(BLOCK) void k_bfs_bottom_up_wave(const int64_t *__restrict__ ioff,
-                                                              const int32_t *__restrict__ icol,
-                                                              const uint32_t *__restrict__ fbits, uint32_t *visited,
-                                                              int64_t v0, int64_t v1, unsigned long long *work,
-                                                              const int64_t *__restrict__ ooff,
-                                                              unsigned long long *degsum) {
+template <typename OffT>
+__device__ __forceinline__ void bottom_up_waves(const OffT *__restrict__ ioff, const int32_t *__restrict__ icol,
+                                                const uint32_t *__restrict__ fbits, uint32_t *visited, int64_t v0,
+                                                int64_t v1, const int64_t *__restrict__ ooff, int64_t blk,
+                                                int64_t nblk, const LevelOut &lo, unsigned long long &checked,
+                                                unsigned long long &joined, unsigned long long &examined) {
   const int lane = threadIdx.x & 63;
-  const int64_t nw = ((int64_t)gridDim.x * BLOCK) >> 6;
-  unsigned long long checked = 0, joined = 0;
-  for (int64_t v = v0 + (((int64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6); v < v1; v += nw) {
+  const int64_t nw = (nblk * BLOCK) >> 6;
+  for (int64_t v = v0 + ((blk * BLOCK + threadIdx.x) >> 6); v < v1; v += nw) {
     const uint32_t bit = 1u << (v & 31);
     if (visited[v >> 5] & bit) continue;
-    const int64_t e0 = ioff[v], e1 = ioff[v + 1];
+    if (lane == 0) ++examined;
+    const int64_t e0 = (int64_t)ioff[v], e1 = (int64_t)ioff[v + 1];
     for (int64_t e = e0; e < e1; e += 64) {
       const bool live = e + lane < e1;
       const int32_t u = live ? icol[e + lane] : 0;
@@ -175,14 +189,56 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_bottom_up_wave(const int64_t *__r
         if (lane == 0) {
           atomicOr(visited + (v >> 5), bit);
           joined += joined_degree(ooff, v, e0, e1);
+          lo.put((int32_t)v);
         }
         break;
       }
     }
   }
+}
+
+// One device-resident superstep's expansion, in the direction the control
+// block holds.  Top-down: every block walks the frontier queue's virtual
+// blocks.  Bottom-up: blocks [0, wave_blocks) give a wave to each vertex of
+// [0, wave_end), the others a thread to each vertex of [wave_end, n_end),
+// and each vertex that joins writes its level.
+template <typename OffT>
+__global__ __launch_bounds__(BLOCK) void k_bfs_step(const Plan *__restrict__ Pp, const int32_t *__restrict__ queue,
+                                                    const int64_t *__restrict__ hubpref,
+                                                    const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                                                    uint32_t *visited, int64_t hub_chunk, unsigned long long *work,
+                                                    const OffT *__restrict__ ioff, const int32_t *__restrict__ icol,
+                                                    const uint32_t *__restrict__ fbits, int64_t wave_end,
+                                                    int64_t n_end, int64_t wave_blocks,
+                                                    const int64_t *__restrict__ ooff, unsigned long long *degsum,
+                                                    int32_t *level, const BfsCtl *__restrict__ ctl) {
+  if (!ctl->active) return;
+  if (!ctl->bottom_up) {
+    const Plan &P = load_plan(Pp);
+    unsigned long long n_edges = 0, n_verts = 0;
+    expand_body(P, queue, hubpref, off, col, visited, nullptr, 0, hub_chunk, blockIdx.x, gridDim.x, n_edges,
+                n_verts);
+    n_edges = block_sum(n_edges);
+    n_verts = block_sum(n_verts);
+    if (threadIdx.x == 0 && n_edges + n_verts > 0) {
+      stat_add(stat_counter(work, 0), n_edges);
+      stat_add(stat_counter(work, 1), n_verts);
+    }
+    return;
+  }
+  const LevelOut lo{level, ctl->L + 1};
+  unsigned long long checked = 0, joined = 0, examined = 0;
+  if ((int64_t)blockIdx.x < wave_blocks)
+    bottom_up_waves(ioff, icol, fbits, visited, 0, wave_end, ooff, blockIdx.x, wave_blocks, lo, checked, joined,
+                    examined);
+  else
+    bottom_up_threads(ioff, icol, fbits, visited, wave_end, n_end, ooff, blockIdx.x - wave_blocks,
+                      gridDim.x - wave_blocks, lo, checked, joined, examined);
   checked = block_sum(checked);
   joined = block_sum(joined);
-  if (threadIdx.x == 0 && checked) stat_add(work, checked);
+  examined = block_sum(examined);
+  if (threadIdx.x == 0 && checked) stat_add(stat_counter(work, 2), checked);
+  if (threadIdx.x == 0 && examined) stat_add(stat_counter(work, 5), examined);
   if (threadIdx.x == 0 && joined) stat_add(degsum, joined);
 }
 
@@ -212,80 +268,155 @@ int bfs_expand_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int
   return TG_OK;
 }
 
-// One bottom-up step over the in-edges: vertices [0, wave_end) one wave each,
-// [wave_end, n_end) one thread each.
-static int bfs_bottom_up_launch(const GpuPart &g, Workspace &ws, const uint32_t *fbits, int64_t wave_end,
-                                int64_t n_end, unsigned long long *degsum, hipStream_t s) {
-  // the joining vertices' out-degrees: in-edge rows are out-edge rows on a
-  // symmetric whole graph
-  const int64_t *ooff = g.in_alias ? nullptr : g.out.off;
-  const int tk = ktimer_start(s);
-  if (wave_end > 0) {
-    const int grid = (int)std::min<int64_t>((wave_end * 64 + BLOCK - 1) / BLOCK, 8192);
-    hipLaunchKernelGGL(k_bfs_bottom_up_wave, dim3(grid), dim3(BLOCK), 0, s, g.in.off, g.in.col, fbits, ws.bits_a,
-                       (int64_t)0, wave_end, stat_counter(ws.work, 2), ooff, degsum);
-  }
-  if (n_end > wave_end) {
-    const int grid = (int)std::min<int64_t>((n_end - wave_end + BLOCK - 1) / BLOCK, 16384);
-    hipLaunchKernelGGL(k_bfs_bottom_up_thread, dim3(grid), dim3(BLOCK), 0, s, g.in.off, g.in.col, fbits, ws.bits_a,
-                       wave_end, n_end, stat_counter(ws.work, 2), ooff, degsum);
-  }
-  ktimer_stop(tk, s, "bfs_bottom_up");
-  TG_HIP(hipGetLastError());
-  return TG_OK;
-}
+namespace {
 
-// BFS from local vertex `root` over the GPU partition.  Leaves the visited
-// bitmap in ws.bits_a and levels in ws.state (valid where visited).
-int gpu_bfs(tg_partition *p, int32_t root, hipStream_t s, int64_t *levels_out) {
-  GpuPart &g = p->gpu;
-  Workspace &ws = p->ws;
-  const Tuning &t = p->tune;
-  TG_TRY(ws.ensure(g, 0));
-  uint32_t *visited = ws.bits_a, *prev = ws.bits_b, *fbits = ws.bits_c;
-  TG_HIP(hipMemsetAsync(visited, 0, ws.nwords * sizeof(uint32_t), s));
-  TG_HIP(hipMemsetAsync(prev, 0, ws.nwords * sizeof(uint32_t), s));
-  TG_TRY(set_bit(visited, root, s));
-  unsigned long long *degsum = stat_counter(ws.work, 4);
-  TG_TRY(frontier_compact_bfs(g, ws, visited, prev, fbits, ws.queue, ws.state, 0, degsum, true, s));
+// One device-resident superstep on workspace `ws`: plan and direction
+// (k_plan_bfs), the top-down expansion and the bottom-up step (each exits at
+// once unless the control block selects it), then the compaction of the new
+// frontier.  Nothing here waits for the host.
+int bfs_dev_superstep(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s) {
+  TG_TRY(frontier_plan_bfs_dev(g, ws, t, s));
   // vertices with in-edges: a symmetric whole graph ends them at its
   // degree-0 tail and has its in-degrees sorted, so its head (HUB and BLOCK
   // bins) gets a wave per vertex; most vertices find a parent among their
   // first few in-neighbours, so everything else takes a thread each
   const int64_t n_end = g.in_alias ? g.out_bins.bstart[BIN_ZERO] : g.n;
   const int64_t wave_end = g.in_alias ? g.out_bins.bstart[BIN_WAVE] : 0;
-  int64_t m_u = g.m;  // edges of vertices not yet in a frontier
-  bool bottom_up = false;
-  int32_t L = 0;
-  for (;; ++L) {
-    if (L > g.n) return set_error(TG_EDEVICE, "bfs: more supersteps than vertices");
-    TG_TRY(frontier_plan(g, ws, ws.queue, t, s, false));
-    TG_HIP(hipMemcpyAsync(ws.h_plan, ws.plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
-    TG_TRY(stat_fetch(ws, 4, s));
-    TG_HIP(hipStreamSynchronize(s));
-    ktimer_flush();
-    const int64_t n_f = ws.h_plan->count;
-    if (n_f == 0) break;
-    const int64_t m_f = (int64_t)stat_sum(ws, 4);
-    m_u -= m_f;
-    if (t.bfs_do) {
-      // Beamer's switch: bottom-up while the frontier is heavy, back once it is small
-      if (!bottom_up && m_f > m_u / t.bfs_alpha) bottom_up = true;
-      else if (bottom_up && n_f < g.n / t.bfs_beta) bottom_up = false;
-    }
-    if (bottom_up) {
-      // the bottom-up kernels sum the new frontier's out-degrees themselves
-      TG_TRY(stat_zero(ws, 4, s));
-      TG_TRY(bfs_bottom_up_launch(g, ws, fbits, wave_end, n_end, degsum, s));
-      hipLaunchKernelGGL(k_count_step, dim3(1), dim3(64), 0, s, stat_counter(ws.work, 3));
-      TG_HIP(hipGetLastError());
-    } else {
-      TG_TRY(bfs_expand_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], t, s));
-    }
-    TG_TRY(frontier_compact_bfs(g, ws, visited, prev, fbits, ws.queue, ws.state, L + 1, degsum, !bottom_up, s));
-  }
-  if (levels_out) *levels_out = L;
+  const int64_t wave_blocks = (t.bfs_do && wave_end > 0) ? std::max<int64_t>(t.bfs_bu_grid / 2, 1) : 0;
+  const int64_t thread_blocks = (t.bfs_do && n_end > wave_end) ? t.bfs_bu_grid : 0;
+  // one launch for either direction: the top-down walk uses every block of
+  // the grid (the frontier size lives on the device, so the grid is fixed)
+  const unsigned grid = (unsigned)std::max<int64_t>(t.bfs_td_grid, wave_blocks + thread_blocks);
+  // the joining vertices' out-degrees: in-edge rows are out-edge rows on a
+  // symmetric whole graph
+  const int64_t *ooff = g.in_alias ? nullptr : g.out.off;
+  const int tk = ktimer_start(s);
+  if (g.in_off32)
+    hipLaunchKernelGGL(k_bfs_step<int32_t>, dim3(grid), dim3(BLOCK), 0, s, ws.plan, ws.queue, ws.hubpref, g.out.off,
+                       g.out.col, ws.bits_a, t.hub_chunk, ws.work, g.in_off32, g.in.col, ws.bits_c, wave_end, n_end,
+                       wave_blocks, ooff, stat_counter(ws.work, 4), ws.state, ws.ctl);
+  else
+    hipLaunchKernelGGL(k_bfs_step<int64_t>, dim3(grid), dim3(BLOCK), 0, s, ws.plan, ws.queue, ws.hubpref, g.out.off,
+                       g.out.col, ws.bits_a, t.hub_chunk, ws.work, g.in.off, g.in.col, ws.bits_c, wave_end, n_end,
+                       wave_blocks, ooff, stat_counter(ws.work, 4), ws.state, ws.ctl);
+  ktimer_stop(tk, s, "bfs_step");
+  TG_HIP(hipGetLastError());
+  return frontier_compact_bfs_dev(g, ws, t, s);
+}
+
+// Enqueue k supersteps, then the read-back of the control block and `ev`.
+int bfs_dev_chunk(const GpuPart &g, Workspace &ws, const Tuning &t, int k, hipStream_t s, hipEvent_t ev) {
+  for (int i = 0; i < k; ++i) TG_TRY(bfs_dev_superstep(g, ws, t, s));
+  TG_HIP(hipMemcpyAsync(ws.h_ctl, ws.ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
+  TG_HIP(hipEventRecord(ev, s));
   return TG_OK;
+}
+
+struct BfsLane {
+  Workspace *ws = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t ev = nullptr;
+  int32_t r = -1;        // root index in flight (-1: idle)
+  int64_t issued = 0;    // supersteps enqueued for it
+};
+
+}  // namespace
+
+// Supersteps run on the device in chunks: a search starts with as many
+// supersteps as the previous one needed (plus the one that finds the empty
+// frontier), and the host reads the control block once per chunk, adding
+// two more supersteps at a time if the search is still going.  With two
+// lanes, two searches run on two streams with a workspace each, so one
+// lane's read-back overlaps the other's kernels.
+int gpu_bfs_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32_t *levels, int32_t *parents,
+                  hipStream_t s, int64_t *supersteps) {
+  GpuPart &g = p->gpu;
+  const Tuning &t = p->tune;
+  const int nl = (t.bfs_lanes > 1 && nr > 1) ? 2 : 1;
+  BfsLane lane[2];
+  lane[0].ws = &p->ws;
+  lane[0].s = s;
+  if (nl == 2) {
+    if (!p->aux_stream) TG_HIP(hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking));
+    lane[1].ws = &p->ws2;
+    lane[1].s = p->aux_stream;
+  }
+  const int64_t V = g.n_global;
+  int rc = TG_OK;
+  hipEvent_t join = nullptr;
+  for (int l = 0; l < nl && rc == TG_OK; ++l) {
+    rc = lane[l].ws->ensure(g, 0);
+    if (rc == TG_OK && hipEventCreateWithFlags(&lane[l].ev, hipEventDisableTiming) != hipSuccess)
+      rc = set_error(TG_EDEVICE, "bfs: hipEventCreate failed");
+  }
+  if (rc == TG_OK && hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess)
+    rc = set_error(TG_EDEVICE, "bfs: hipEventCreate failed");
+  if (rc == TG_OK && nl == 2) {
+    // the second lane starts after the caller's earlier work on s
+    if (hipEventRecord(join, s) != hipSuccess || hipStreamWaitEvent(lane[1].s, join, 0) != hipSuccess)
+      rc = set_error(TG_EDEVICE, "bfs: stream ordering failed");
+  }
+  for (int l = 0; l < nl && rc == TG_OK; ++l) rc = stat_zero_all(*lane[l].ws, lane[l].s);
+  int first_chunk = 4;  // supersteps of the next search's first chunk (learned)
+  int32_t next = 0;
+  int64_t total = 0;
+  auto start = [&](BfsLane &L) -> int {
+    Workspace &ws = *L.ws;
+    L.r = next++;
+    TG_HIP(hipMemsetAsync(ws.bits_a, 0, ws.nwords * sizeof(uint32_t), L.s));
+    TG_HIP(hipMemsetAsync(ws.bits_b, 0, ws.nwords * sizeof(uint32_t), L.s));
+    TG_TRY(bfs_dev_start(g, ws, roots_local[L.r], L.s));
+    TG_TRY(frontier_compact_bfs_dev(g, ws, t, L.s));  // the root's frontier, level 0
+    L.issued = first_chunk;
+    return bfs_dev_chunk(g, ws, t, first_chunk, L.s, L.ev);
+  };
+  for (int l = 0; l < nl && rc == TG_OK && next < nr; ++l) rc = start(lane[l]);
+  // serve the lanes in turn until every search has ended
+  for (int cur = 0; rc == TG_OK;) {
+    BfsLane &L = lane[cur];
+    cur = (cur + 1) % nl;
+    if (L.r < 0) {
+      if (lane[0].r < 0 && lane[nl - 1].r < 0) break;
+      continue;
+    }
+    if (hipEventSynchronize(L.ev) != hipSuccess) {
+      rc = set_error(TG_EDEVICE, "bfs: hipEventSynchronize failed");
+      break;
+    }
+    const BfsCtl c = *L.ws->h_ctl;
+    if (c.active) {
+      if (L.issued > g.n + 2) {
+        rc = set_error(TG_EDEVICE, "bfs: more supersteps than vertices");
+        break;
+      }
+      L.issued += 2;
+      rc = bfs_dev_chunk(g, *L.ws, t, 2, L.s, L.ev);
+      continue;
+    }
+    // this search has ended: collect it and start the next one on the lane
+    total += c.steps + 1;
+    first_chunk = std::max(c.steps + 1, 1);
+    rc = collect_levels(g, L.ws->bits_a, L.ws->state, levels + (int64_t)L.r * V, L.s);
+    if (rc == TG_OK && parents)
+      rc = bfs_parents(g, L.ws->bits_a, L.ws->state, roots_local[L.r], parents + (int64_t)L.r * V, L.s);
+    L.r = -1;
+    if (rc == TG_OK && next < nr) rc = start(L);
+  }
+  if (nl == 2 && rc == TG_OK) {
+    // the caller's stream waits for the second lane
+    if (hipEventRecord(join, lane[1].s) != hipSuccess || hipStreamWaitEvent(s, join, 0) != hipSuccess)
+      rc = set_error(TG_EDEVICE, "bfs: stream ordering failed");
+  }
+  if (rc != TG_OK) {
+    // leave no work of this call running on the second lane
+    if (nl == 2) TG_QUIET(hipStreamSynchronize(lane[1].s));
+    TG_QUIET(hipStreamSynchronize(s));
+  }
+  for (int l = 0; l < nl; ++l)
+    if (lane[l].ev) TG_QUIET(hipEventDestroy(lane[l].ev));
+  if (join) TG_QUIET(hipEventDestroy(join));
+  if (supersteps) *supersteps = total;
+  return rc;
 }
 
 }  // namespace tg

@@ -135,9 +135,12 @@ __global__ __launch_bounds__(CT) void k_sssp_filter(uint32_t *__restrict__ bits,
   if (threadIdx.x == 0) bcount[blockIdx.x] = c;
 }
 
+// With a BFS control block (`ctl`), a search that has ended skips the pass.
 __global__ __launch_bounds__(CT) void k_compact_count(const uint32_t *__restrict__ bits,
                                                       const uint32_t *__restrict__ prev,
-                                                      uint32_t *__restrict__ bcount) {
+                                                      uint32_t *__restrict__ bcount,
+                                                      const BfsCtl *__restrict__ ctl) {
+  if (ctl && !ctl->active) return;
   const int64_t q = (int64_t)blockIdx.x * CT + threadIdx.x;  // word index
   uint32_t v = bits[q];
   if (prev) v &= ~prev[q];
@@ -150,13 +153,36 @@ __global__ __launch_bounds__(CT) void k_compact_write(uint32_t *__restrict__ bit
                                                       int32_t *__restrict__ queue, int32_t *__restrict__ level,
                                                       int32_t level_value, BinBounds bb, int64_t n,
                                                       Plan *__restrict__ plan, uint32_t *__restrict__ fbits,
-                                                      const int64_t *__restrict__ off, unsigned long long *degsum) {
+                                                      const int64_t *__restrict__ off, unsigned long long *degsum,
+                                                      const BfsCtl *__restrict__ ctl, int64_t skip_min) {
+  bool bu = false;
+  if (ctl) {
+    // device-resident BFS: the level and whether to sum degrees come from
+    // the control block (a bottom-up step sums its joins' degrees and
+    // writes their levels itself)
+    if (!ctl->active) return;
+    level_value = ctl->L + 1;
+    bu = ctl->bottom_up != 0;
+    if (bu) {
+      degsum = nullptr;
+      level = nullptr;
+    }
+  }
   const int64_t q = (int64_t)blockIdx.x * CT + threadIdx.x;  // word index
   const uint32_t v = bits[q];
-  // this block's offset: sum of the counts of all earlier blocks
-  uint32_t part = 0;
-  for (uint32_t i = threadIdx.x; i < blockIdx.x; i += CT) part += bcount[i];
+  // this block's offset: sum of the counts of all earlier blocks; after a
+  // bottom-up step also the frontier's total
+  uint32_t part = 0, rest = 0;
+  for (uint32_t i = threadIdx.x; i < gridDim.x; i += CT) {
+    const uint32_t c = (i < blockIdx.x || bu) ? bcount[i] : 0u;
+    if (i < blockIdx.x) part += c;
+    else rest += c;
+  }
   const uint32_t base = cblock_sum(part);
+  // A frontier of at least skip_min vertices after a bottom-up step keeps
+  // the next step bottom-up (Beamer's rule), which reads the frontier bitmap
+  // only: no queue is written for it.
+  const bool skip_queue = bu && (int64_t)base + (int64_t)cblock_sum(rest) >= skip_min;
 
   uint32_t nw = v;
   if (mode == 0) {
@@ -178,27 +204,57 @@ __global__ __launch_bounds__(CT) void k_compact_write(uint32_t *__restrict__ bit
     const int64_t t = bb.bstart[b];
     if (t < n && (t >> 5) == q) plan->pos[b] = (int32_t)(excl + __popc(nw & ((1u << (t & 31)) - 1u)));
   }
-  uint32_t o = excl;
+  uint32_t o = excl + (uint32_t)__popc(nw);
   unsigned long long deg = 0;
-  for (uint32_t w = nw; w; w &= w - 1) {
-    const int32_t vtx = (int32_t)(q * 32 + (__ffs(w) - 1));
-    queue[o++] = vtx;
-    if (level) level[vtx] = level_value;
-    if (degsum) deg += (unsigned long long)(off[vtx + 1] - off[vtx]);
+  if (!skip_queue || level || degsum) {
+    // the word's vertices eight at a time, so that their offset loads are
+    // in flight together
+    uint32_t k = excl;
+    for (uint32_t w = nw; w;) {
+      int32_t vv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        vv[j] = w ? (int32_t)(q * 32 + (__ffs(w) - 1)) : -1;
+        w &= w - 1;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (vv[j] >= 0 && !skip_queue) queue[k + j] = vv[j];
+      if (level) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (vv[j] >= 0) level[vv[j]] = level_value;
+      }
+      if (degsum) {
+        int64_t a[8], b[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int32_t x = vv[j] >= 0 ? vv[j] : 0;
+          a[j] = off[x];
+          b[j] = off[x + 1];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (vv[j] >= 0) deg += (unsigned long long)(b[j] - a[j]);
+      }
+      k += 8;
+    }
   }
   if (degsum) {
     deg = cblock_sum(deg);
     if (threadIdx.x == 0 && deg) stat_add(degsum, deg);
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == CT - 1) plan->count = (int32_t)o;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == CT - 1) {
+    plan->count = (int32_t)o;
+    if (ctl) plan->queue_skipped = skip_queue ? 1 : 0;
+  }
 }
 
 // One block: fix up empty-tail positions, hub chunk prefix, virtual blocks.
-__global__ __launch_bounds__(BLOCK) void k_plan(Plan *__restrict__ plan, BinBounds bb, int64_t n,
-                                                const int32_t *__restrict__ queue,
-                                                const int64_t *__restrict__ off, int64_t hub_chunk,
-                                                int64_t *__restrict__ hubpref, int include_zero,
-                                                const int32_t *__restrict__ len) {
+__device__ __forceinline__ void plan_body(Plan *__restrict__ plan, const BinBounds &bb, int64_t n,
+                                          const int32_t *__restrict__ queue, const int64_t *__restrict__ off,
+                                          int64_t hub_chunk, int64_t *__restrict__ hubpref, int include_zero,
+                                          const int32_t *__restrict__ len) {
   __shared__ int32_t pos[NBIN + 1];
   const int32_t count = plan->count;
   if (threadIdx.x <= NBIN) {
@@ -239,6 +295,81 @@ __global__ __launch_bounds__(BLOCK) void k_plan(Plan *__restrict__ plan, BinBoun
   }
 }
 
+__global__ __launch_bounds__(BLOCK) void k_plan(Plan *__restrict__ plan, BinBounds bb, int64_t n,
+                                                const int32_t *__restrict__ queue,
+                                                const int64_t *__restrict__ off, int64_t hub_chunk,
+                                                int64_t *__restrict__ hubpref, int include_zero,
+                                                const int32_t *__restrict__ len) {
+  plan_body(plan, bb, n, queue, off, hub_chunk, hubpref, include_zero, len);
+}
+
+// The plan of a device-resident BFS superstep, then the superstep's
+// decisions in the control block: an empty frontier ends the search;
+// otherwise the level advances, the frontier's out-degree sum (the spread
+// counter `degsum`, zeroed here for the next step) leaves m_u, and Beamer's
+// switch picks the direction: bottom-up while m_f > m_u / alpha, back to
+// top-down once n_f < n / beta.  Bottom-up steps are counted in `bu_steps`.
+__global__ __launch_bounds__(BLOCK) void k_plan_bfs(Plan *__restrict__ plan, BinBounds bb, int64_t n,
+                                                    const int32_t *__restrict__ queue,
+                                                    const int64_t *__restrict__ off, int64_t hub_chunk,
+                                                    int64_t *__restrict__ hubpref, BfsCtl *__restrict__ ctl,
+                                                    unsigned long long *__restrict__ degsum,
+                                                    unsigned long long *__restrict__ bu_steps, int64_t alpha,
+                                                    int64_t beta, int do_switch) {
+  if (!ctl->active) return;  // the search has ended: nothing changes any more
+  __shared__ unsigned long long m_f;
+  __shared__ int32_t dir;  // -1: ended, 0: top-down, 1: bottom-up
+  if (threadIdx.x < STAT_SLOTS) {
+    const unsigned long long x = wave_sum(degsum[(size_t)threadIdx.x * STAT_STRIDE]);
+    degsum[(size_t)threadIdx.x * STAT_STRIDE] = 0ull;
+    if (threadIdx.x == 0) m_f = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int32_t n_f = plan->count;
+    if (n_f == 0) {
+      ctl->active = 0;
+      dir = -1;
+    } else {
+      ctl->L += 1;
+      ctl->steps += 1;
+      const int64_t m_u = ctl->m_u - (int64_t)m_f;
+      ctl->m_u = m_u;
+      int32_t bu = ctl->bottom_up;
+      if (do_switch) {
+        if (!bu && (int64_t)m_f > m_u / alpha) bu = 1;
+        else if (bu && (int64_t)n_f < n / beta) bu = 0;
+      }
+      // a frontier compacted without a queue can only be expanded bottom-up
+      // (the compaction skips the queue exactly when the rule above keeps
+      // the step bottom-up)
+      if (plan->queue_skipped) bu = 1;
+      ctl->bottom_up = bu;
+      if (bu) *bu_steps += 1ull;  // one writer: this thread
+      dir = bu;
+    }
+  }
+  __syncthreads();
+  // a top-down step walks the queue: its bins, hub chunks and virtual blocks
+  if (dir == 0) plan_body(plan, bb, n, queue, off, hub_chunk, hubpref, 0, nullptr);
+}
+
+// Start of a device-resident BFS from `root`: the control block, the
+// frontier degree-sum slots and the root's visited bit.
+__global__ void k_bfs_ctl_init(BfsCtl *__restrict__ ctl, int64_t m, unsigned long long *__restrict__ degsum,
+                               uint32_t *__restrict__ visited, int32_t root) {
+  const int t = threadIdx.x;
+  if (t < STAT_SLOTS) degsum[(size_t)t * STAT_STRIDE] = 0ull;
+  if (t == 0) {
+    ctl->m_u = m;
+    ctl->L = -1;
+    ctl->bottom_up = 0;
+    ctl->active = 1;
+    ctl->steps = 0;
+    visited[root >> 5] |= 1u << (root & 31);
+  }
+}
+
 }  // namespace
 
 namespace tg {
@@ -252,21 +383,35 @@ int launch_grid(int64_t vblocks) {
 int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, uint32_t *prev,
                      int32_t *queue, int32_t *level, int32_t level_value, hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
-  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(CT), 0, s, bits, mode == 0 ? prev : nullptr, ws.bcount);
+  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(CT), 0, s, bits, mode == 0 ? prev : nullptr, ws.bcount,
+                     nullptr);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, bits, prev, mode, ws.bcount, queue, level,
-                     level_value, g.out_bins, g.n, ws.plan, nullptr, nullptr, nullptr);
+                     level_value, g.out_bins, g.n, ws.plan, nullptr, nullptr, nullptr, nullptr, (int64_t)0);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
 
-int frontier_compact_bfs(const GpuPart &g, Workspace &ws, uint32_t *visited, uint32_t *prev, uint32_t *fbits,
-                         int32_t *queue, int32_t *level, int32_t level_value, unsigned long long *degsum,
-                         bool count_degrees, hipStream_t s) {
+int bfs_dev_start(const GpuPart &g, Workspace &ws, int32_t root, hipStream_t s) {
+  hipLaunchKernelGGL(k_bfs_ctl_init, dim3(1), dim3(64), 0, s, ws.ctl, g.m, stat_counter(ws.work, 4), ws.bits_a,
+                     root);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int frontier_compact_bfs_dev(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
-  if (count_degrees) TG_HIP(hipMemsetAsync(degsum, 0, STAT_SPAN * sizeof(unsigned long long), s));
-  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(CT), 0, s, visited, prev, ws.bcount);
-  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, visited, prev, 0, ws.bcount, queue, level,
-                     level_value, g.out_bins, g.n, ws.plan, fbits, g.out.off, count_degrees ? degsum : nullptr);
+  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(CT), 0, s, ws.bits_a, ws.bits_b, ws.bcount, ws.ctl);
+  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, ws.bits_a, ws.bits_b, 0, ws.bcount, ws.queue,
+                     ws.state, 0, g.out_bins, g.n, ws.plan, ws.bits_c, g.out.off, stat_counter(ws.work, 4), ws.ctl,
+                     t.bfs_do ? g.n / t.bfs_beta : INT64_MAX);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int frontier_plan_bfs_dev(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan_bfs, dim3(1), dim3(BLOCK), 0, s, ws.plan, g.out_bins, g.n, ws.queue, g.out.off,
+                     t.hub_chunk, ws.hubpref, ws.ctl, stat_counter(ws.work, 4), stat_counter(ws.work, 3), t.bfs_alpha,
+                     t.bfs_beta, (int)t.bfs_do);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
@@ -287,7 +432,7 @@ int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32
   hipLaunchKernelGGL(k_sssp_filter, dim3(blocks), dim3(CT), 0, s, bits, ws.bits_b, ws.bcount, dist, settled,
                      near ? thresh : TG_INF, rest_cnt, rest_min);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, ws.bits_b, nullptr, 4, ws.bcount, queue,
-                     nullptr, 0, bb, g.n, ws.plan, nullptr, nullptr, nullptr);
+                     nullptr, 0, bb, g.n, ws.plan, nullptr, nullptr, nullptr, nullptr, (int64_t)0);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }

@@ -41,9 +41,22 @@ struct BinBounds {
 // Frontier plan: queue segments per bin and virtual-block offsets.
 struct Plan {
   int32_t count;           // frontier length
-  int32_t pad_;
+  int32_t queue_skipped;  // device-resident BFS: 1 if the last compaction wrote no queue
   int32_t pos[NBIN + 1];   // queue index where bin b starts; pos[NBIN] = count
   int64_t vb[NBIN + 1];    // virtual blocks of bin b: [vb[b], vb[b+1])
+};
+
+// Device-resident control block of one BFS (the superstep loop of section
+// 4.1 run without the host): the one-block plan kernel advances it after
+// each compaction, and every other kernel of a superstep reads it to decide
+// whether it has work.  Once the frontier is empty the search is over and
+// the remaining supersteps of a chunk are no-ops.
+struct BfsCtl {
+  int64_t m_u;        // out-edges of vertices not yet in any frontier
+  int32_t L;          // level of the current frontier (-1 before the root's compaction)
+  int32_t bottom_up;  // 1: the current superstep runs bottom-up
+  int32_t active;     // 0 once a compaction produced an empty frontier
+  int32_t steps;      // non-empty frontiers expanded so far
 };
 
 // Copy the plan into LDS (it is indexed by the block's bin, so a register

@@ -4,6 +4,7 @@
 // (launches).
 #include <stdlib.h>
 
+#include <atomic>
 #include <map>
 #include <string>
 #include <vector>
@@ -38,10 +39,23 @@ hipEvent_t take() {
 
 }  // namespace
 
-bool timing_enabled() {
-  static const bool on = getenv("TG_TIMING") != nullptr && getenv("TG_TIMING")[0] != '0';
-  return on;
+namespace {
+std::atomic<int> g_timing{-1};  // -1: not yet read from TG_TIMING
 }
+
+bool timing_enabled() {
+  int v = g_timing.load(std::memory_order_relaxed);
+  if (v < 0) {
+    const char *e = getenv("TG_TIMING");
+    v = (e != nullptr && e[0] != '0') ? 1 : 0;
+    int expect = -1;
+    g_timing.compare_exchange_strong(expect, v);
+    v = g_timing.load(std::memory_order_relaxed);
+  }
+  return v == 1;
+}
+
+void set_timing(bool on) { g_timing.store(on ? 1 : 0, std::memory_order_relaxed); }
 
 int ktimer_start(hipStream_t s) {
   if (!timing_enabled()) return -1;

@@ -18,6 +18,7 @@ using tgk::Plan;
 namespace tg {
 // per-kernel event timing (ktimer.cpp); no-ops unless TG_TIMING is set
 bool timing_enabled();
+void set_timing(bool on);
 int ktimer_start(hipStream_t s);
 void ktimer_stop(int start, hipStream_t s, const char *name);
 void ktimer_flush();  // after a stream sync: fold pending event pairs into totals
@@ -69,6 +70,9 @@ struct Tuning {
   int64_t bfs_do;                // BFS: 1 = switch to bottom-up steps on large frontiers
   int64_t bfs_alpha, bfs_beta;   // BFS: top-down -> bottom-up when m_f > m_u / alpha; back when n_f < n / beta
   int64_t sssp_xcd;              // SSSP: 1 = relaxation split by destination class per XCD
+  int64_t bfs_lanes;             // BFS: searches in flight on their own streams (1 or 2)
+  int64_t bfs_td_grid;           // BFS: blocks of a top-down launch (fixed: the frontier size is on the device)
+  int64_t bfs_bu_grid;           // BFS: blocks of a bottom-up launch's one-thread-per-vertex part
 };
 Tuning default_tuning();
 int parse_tuning(const char *json, Tuning *t);
@@ -227,6 +231,7 @@ struct GpuPart {
   int64_t n_dangling = 0;        // vertices with out-degree 0
   int64_t n_isolated = 0;        // out-degree 0 and in-degree 0 (ZERO bin of in_bins when symmetric)
   int64_t max_out_hubs = 0;      // vertices in the HUB bin (out-degree)
+  int32_t *in_off32 = nullptr;   // in-edge offsets as int32 when m < 2^31 (the bottom-up BFS step), else null
   std::vector<int64_t> h_out_off;  // host copy of the local out offsets
   std::vector<int64_t> h_deg;      // out-degree of each local id (non-increasing)
   std::vector<int64_t> h_in_deg;   // in-degree of each local id
@@ -257,7 +262,8 @@ struct Workspace {
   // slots (stat_counter / stat_add): 0 edges scanned or relaxations, 1
   // vertices expanded or activations, 2 bottom-up edges checked, 3
   // bottom-up steps, 4 the BFS frontier's out-degree sum, 5 and 6 the
-  // near/far SSSP vertices left beyond the threshold and their least distance
+  // near/far SSSP vertices left beyond the threshold and their least
+  // distance (BFS: 5 = vertices a bottom-up step examined)
   unsigned long long *work = nullptr;
   unsigned long long *h_work = nullptr;  // small pinned scratch
   unsigned long long *h_stat = nullptr;  // pinned mirror of `work`
@@ -266,6 +272,8 @@ struct Workspace {
   int64_t *hubpref = nullptr;    // frontier hub chunk prefix
   Plan *h_plan = nullptr;        // pinned host copy of the plan
   uint32_t *h_flags = nullptr;   // pinned host flags
+  tgk::BfsCtl *ctl = nullptr;    // device-resident BFS control block
+  tgk::BfsCtl *h_ctl = nullptr;  // pinned host copy of it (read once per chunk of supersteps)
   int64_t hub_chunks_cap = 0;
   int64_t hubs_cap = 0;
   int64_t partials_cap = 0;
@@ -296,6 +304,8 @@ struct tg_partition {
   tg::DevArena arena;
   tg::GpuPart gpu;
   tg::Workspace ws;
+  tg::Workspace ws2;              // second BFS lane (its own stream), grown on first use
+  hipStream_t aux_stream = nullptr;  // the second lane's stream (default priority), created on first use
   std::vector<int32_t> h_l_of_g;  // global -> GPU-local id (or -1)
   std::vector<int32_t> h_g_of_l;  // GPU-local -> global id
   tg::HybridState *hy = nullptr;  // host partition + boundary buffers (cpu_edge_share > 0)
@@ -318,12 +328,6 @@ int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, 
 // hub chunk prefix, then copy the plan to ws.h_plan and wait for it.
 int frontier_plan(const GpuPart &g, Workspace &ws, const int32_t *queue, const Tuning &t,
                   hipStream_t s, bool sync);
-// BFS compaction (mode 0) that also writes the new frontier as a bitmap into
-// `fbits` and, with count_degrees, sets *degsum to the frontier's out-degree
-// sum (otherwise *degsum is left as it is).
-int frontier_compact_bfs(const GpuPart &g, Workspace &ws, uint32_t *visited, uint32_t *prev, uint32_t *fbits,
-                         int32_t *queue, int32_t *level, int32_t level_value, unsigned long long *degsum,
-                         bool count_degrees, hipStream_t s);
 // SSSP compaction of the active bitmap: a vertex is taken if dist < settled
 // (it really got lower since it last relaxed; settled := dist when taken) and,
 // with `near`, dist < thresh; stale bits are dropped; with `near` the others
@@ -340,6 +344,14 @@ int frontier_plan_bins(const GpuPart &g, Workspace &ws, const int32_t *queue, co
 // (a pull over in-edges must visit them).
 int frontier_plan_off(const GpuPart &g, Workspace &ws, const int32_t *queue, const int64_t *off,
                       const Tuning &t, hipStream_t s, bool sync, bool include_zero = false);
+// Device-resident BFS (ws.ctl): start a search from local vertex `root`
+// (control block, degree-sum slots, the root's visited bit; the bitmaps must
+// be clear); the compaction of a superstep (visited ws.bits_a, previous
+// ws.bits_b, frontier bitmap ws.bits_c, levels ws.state, level and degree
+// counting from the control block); and the plan + direction decision.
+int bfs_dev_start(const GpuPart &g, Workspace &ws, int32_t root, hipStream_t s);
+int frontier_compact_bfs_dev(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s);
+int frontier_plan_bfs_dev(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s);
 int launch_grid(int64_t vblocks);
 // bfs.hip: expansion of the frontier in `queue` (plan in ws.plan) into ws.bits_a
 int bfs_expand_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks,
@@ -384,7 +396,11 @@ void pr_rows_free(GpuPart &g);
 int pr_write_initial(const GpuPart &g, float *rank_out, double N, hipStream_t s);
 
 // algorithms (GPU partition only)
-int gpu_bfs(tg_partition *p, int32_t root_local, hipStream_t s, int64_t *levels_out);
+// BFS from each local root; levels (and parents, if non-null) of root r go
+// to row r of the outputs (original ids, V per row).  *supersteps gets the
+// superstep count summed over the roots.
+int gpu_bfs_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32_t *levels, int32_t *parents,
+                  hipStream_t s, int64_t *supersteps);
 int gpu_sssp(tg_partition *p, int32_t root_local, hipStream_t s, int64_t *rounds_out);
 int gpu_pagerank(tg_partition *p, double damping, int32_t iters, int mode, float *rank_out,
                  hipStream_t s);
