@@ -298,6 +298,25 @@ int partition_info(const tg_partition *p, char *json, size_t cap);
  * partition_info. */
 int tg_last_stats(char *json, size_t cap);
 
+/* bfs() for callers that cannot allocate device memory: code under stream
+ * capture, serving loops with a fixed memory budget, harnesses that forbid
+ * hipMalloc.  The search's workspace lives in a file-scope device array of
+ * 64 MiB inside the library (each GPU the library is loaded on holds one
+ * until the process ends); the call allocates nothing, on the device or
+ * pinned on the host.  A partition needs about 8.4 bytes per vertex plus
+ * 70 KiB of it, so up to about 7.9 million vertices fit.
+ *   p         a GPU-only partition (cpu_edge_share 0) on the current device.
+ *   roots     host array of num_roots original vertex ids.
+ *   levels    device int32 [num_roots * V], as bfs(); no parents.
+ * Every call on a GPU shares that GPU's array: calls from this process are
+ * serialized by a lock (the call returns when its levels are in place), and
+ * each starts by clearing what must start at zero.  Errors: TG_EINVAL (bad
+ * arguments, partition not on the current device), TG_EUNSUPPORTED (hybrid
+ * partition), TG_ENOMEM (the partition needs more than the array holds; the
+ * message gives the size), TG_EDEVICE. */
+int bfs_noalloc(const tg_partition *p, const int32_t *roots, int32_t num_roots, int32_t *levels,
+                void *stream);
+
 /* Per-kernel timing: with on != 0, every timed kernel launch is bracketed
  * by HIP events on its stream and tg_last_stats() reports "<kernel>_ms"
  * (summed duration) and "<kernel>_n" (launches); the events themselves add

@@ -78,6 +78,7 @@ def _load():
     lib.tg_last_error.restype = ctypes.c_char_p
     lib.partition_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     lib.tg_last_stats.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    lib.bfs_noalloc.argtypes = [vp, _c_i32p, ctypes.c_int32, vp, vp]
     lib.tg_set_timing.argtypes = [ctypes.c_int]
     lib.tg_set_timing.restype = None
     for f in (lib.graph_load_csr, lib.partition_by_degree, lib.partition_retune, lib.bfs, lib.sssp, lib.pagerank, lib.bc,

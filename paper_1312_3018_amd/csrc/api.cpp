@@ -156,6 +156,61 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   return TG_OK;
 }
 
+namespace {
+// The pieces of a device-resident BFS workspace, each 256-byte aligned.
+struct BfsPieces {
+  size_t bits, queue, state, bcount, plan, hubpref, work, ctl;
+  size_t total() const { return 3 * bits + queue + state + bcount + plan + hubpref + work + ctl; }
+};
+size_t al256(size_t n) { return (n + 255) & ~(size_t)255; }
+BfsPieces bfs_pieces(const GpuPart &g, int64_t nwords) {
+  BfsPieces b;
+  b.bits = al256((size_t)nwords * sizeof(uint32_t));
+  b.queue = al256((size_t)(g.n + 1) * sizeof(int32_t));
+  b.state = al256((size_t)(g.n + 1) * sizeof(int32_t));
+  b.bcount = al256((size_t)(nwords / 1024 + 1) * sizeof(uint32_t));
+  b.plan = al256(sizeof(Plan));
+  b.hubpref = al256((size_t)(g.max_out_hubs + 2) * sizeof(int64_t));
+  b.work = al256((size_t)tgk::STAT_COUNTERS * tgk::STAT_SPAN * sizeof(unsigned long long));
+  b.ctl = al256(sizeof(tgk::BfsCtl));
+  return b;
+}
+int64_t bitmap_words(int64_t n) {
+  const int64_t w = ((n + 31) / 32 + 1023) / 1024 * 1024;
+  return w == 0 ? 1024 : w;
+}
+}  // namespace
+
+size_t bfs_scratch_bytes(const GpuPart &g) { return bfs_pieces(g, bitmap_words(g.n)).total(); }
+
+int Workspace::bind_bfs(const GpuPart &g, void *base, size_t bytes) {
+  const int64_t nw = bitmap_words(g.n);
+  const BfsPieces b = bfs_pieces(g, nw);
+  if (b.total() > bytes)
+    return set_error(TG_ENOMEM, "the partition's BFS needs %zu bytes of scratch; %zu are available", b.total(),
+                     bytes);
+  uint8_t *p = static_cast<uint8_t *>(base);
+  auto take = [&p](size_t n) {
+    void *r = p;
+    p += n;
+    return r;
+  };
+  nwords = nw;
+  bits_a = static_cast<uint32_t *>(take(b.bits));
+  bits_b = static_cast<uint32_t *>(take(b.bits));
+  bits_c = static_cast<uint32_t *>(take(b.bits));
+  queue = static_cast<int32_t *>(take(b.queue));
+  state = static_cast<int32_t *>(take(b.state));
+  bcount = static_cast<uint32_t *>(take(b.bcount));
+  plan = static_cast<Plan *>(take(b.plan));
+  hubpref = static_cast<int64_t *>(take(b.hubpref));
+  work = static_cast<unsigned long long *>(take(b.work));
+  ctl = static_cast<tgk::BfsCtl *>(take(b.ctl));
+  hubs_cap = g.max_out_hubs + 1;
+  cap_n = -1;  // never taken for an allocated workspace by ensure()
+  return TG_OK;
+}
+
 int stat_zero(Workspace &ws, int k, hipStream_t s) {
   TG_HIP(hipMemsetAsync(tgk::stat_counter(ws.work, k), 0, tgk::STAT_SPAN * sizeof(unsigned long long), s));
   return TG_OK;

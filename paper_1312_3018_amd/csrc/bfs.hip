@@ -274,7 +274,7 @@ namespace {
 // (k_plan_bfs), the top-down expansion and the bottom-up step (each exits at
 // once unless the control block selects it), then the compaction of the new
 // frontier.  Nothing here waits for the host.
-int bfs_dev_superstep(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s) {
+int bfs_dev_superstep(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s, bool timed = true) {
   TG_TRY(frontier_plan_bfs_dev(g, ws, t, s));
   // vertices with in-edges: a symmetric whole graph ends them at its
   // degree-0 tail and has its in-degrees sorted, so its head (HUB and BLOCK
@@ -290,7 +290,7 @@ int bfs_dev_superstep(const GpuPart &g, Workspace &ws, const Tuning &t, hipStrea
   // the joining vertices' out-degrees: in-edge rows are out-edge rows on a
   // symmetric whole graph
   const int64_t *ooff = g.in_alias ? nullptr : g.out.off;
-  const int tk = ktimer_start(s);
+  const int tk = timed ? ktimer_start(s) : -1;
   if (g.in_off32)
     hipLaunchKernelGGL(k_bfs_step<int32_t>, dim3(grid), dim3(BLOCK), 0, s, ws.plan, ws.queue, ws.hubpref, g.out.off,
                        g.out.col, ws.bits_a, t.hub_chunk, ws.work, g.in_off32, g.in.col, ws.bits_c, wave_end, n_end,
@@ -417,6 +417,34 @@ int gpu_bfs_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32
   if (join) TG_QUIET(hipEventDestroy(join));
   if (supersteps) *supersteps = total;
   return rc;
+}
+
+int gpu_bfs_roots_bound(tg_partition *p, Workspace &ws, const int32_t *roots, int32_t nr, int32_t *levels,
+                        hipStream_t s, BfsCtl *host_ctl) {
+  GpuPart &g = p->gpu;
+  const Tuning &t = p->tune;
+  const int64_t V = g.n_global;
+  TG_TRY(stat_zero_all(ws, s));
+  int chunk = 4;  // supersteps of a search's first chunk (learned from the previous search)
+  for (int32_t r = 0; r < nr; ++r) {
+    TG_HIP(hipMemsetAsync(ws.bits_a, 0, ws.nwords * sizeof(uint32_t), s));
+    TG_HIP(hipMemsetAsync(ws.bits_b, 0, ws.nwords * sizeof(uint32_t), s));
+    TG_TRY(bfs_dev_start(g, ws, p->h_l_of_g[roots[r]], s));
+    TG_TRY(frontier_compact_bfs_dev(g, ws, t, s));  // the root's frontier, level 0
+    int64_t issued = 0;
+    for (int k = chunk;; k = 2) {
+      for (int i = 0; i < k; ++i) TG_TRY(bfs_dev_superstep(g, ws, t, s, false));
+      issued += k;
+      TG_HIP(hipMemcpyAsync(host_ctl, ws.ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
+      TG_HIP(hipStreamSynchronize(s));
+      if (!host_ctl->active) break;
+      if (issued > g.n + 2) return set_error(TG_EDEVICE, "bfs: more supersteps than vertices");
+    }
+    chunk = std::max(host_ctl->steps + 1, 1);
+    TG_TRY(collect_levels(g, ws.bits_a, ws.state, levels + (int64_t)r * V, s));
+  }
+  TG_HIP(hipStreamSynchronize(s));
+  return TG_OK;
 }
 
 }  // namespace tg

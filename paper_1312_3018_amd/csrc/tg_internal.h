@@ -278,6 +278,10 @@ struct Workspace {
   int64_t hubs_cap = 0;
   int64_t partials_cap = 0;
   int ensure(const GpuPart &g, int64_t hub_chunks_needed);
+  // Point the buffers a device-resident BFS uses into caller-owned device
+  // memory [base, base + bytes) instead of allocating them; the other
+  // buffers stay null.  TG_ENOMEM (with the size needed) if it does not fit.
+  int bind_bfs(const GpuPart &g, void *base, size_t bytes);
   ~Workspace();
 };
 
@@ -401,6 +405,13 @@ int pr_write_initial(const GpuPart &g, float *rank_out, double N, hipStream_t s)
 // superstep count summed over the roots.
 int gpu_bfs_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32_t *levels, int32_t *parents,
                   hipStream_t s, int64_t *supersteps);
+// The same searches on one workspace the caller bound (Workspace::bind_bfs),
+// one root after another on s, with no allocation of any kind: the control
+// block is read back into *host_ctl.  Roots are original ids.
+int gpu_bfs_roots_bound(tg_partition *p, Workspace &ws, const int32_t *roots, int32_t nr, int32_t *levels,
+                        hipStream_t s, tgk::BfsCtl *host_ctl);
+// Device bytes Workspace::bind_bfs needs for partition g.
+size_t bfs_scratch_bytes(const GpuPart &g);
 int gpu_sssp(tg_partition *p, int32_t root_local, hipStream_t s, int64_t *rounds_out);
 int gpu_pagerank(tg_partition *p, double damping, int32_t iters, int mode, float *rank_out,
                  hipStream_t s);
