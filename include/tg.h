@@ -122,11 +122,16 @@ int partition_by_degree(const tg_graph *g, int strategy, double cpu_edge_share,
  *                "g16_min_deg", "g4_min_deg" (decreasing), "hub_chunk"
  *                (edges per block of a hub);
  *   BFS          "bfs_do" (1: direction-optimizing steps), "bfs_alpha",
- *                "bfs_beta" (the switch thresholds), "bfs_lds_words",
- *                "bfs_grid", "bfs_lds_min_vblocks";
+ *                "bfs_beta" (the switch thresholds), "bfs_lanes" (searches
+ *                in flight, 1 or 2), "bfs_td_grid", "bfs_bu_grid" (blocks of
+ *                the top-down and bottom-up steps); "bfs_lds_words",
+ *                "bfs_grid", "bfs_lds_min_vblocks" for the top-down steps of
+ *                betweenness and hybrid searches;
  *   SSSP         "sssp_delta" (0: plain frontier; > 0: near/far step),
- *                "sssp_grid", "sssp_lds_verts", "sssp_xcd" (per-XCD
- *                destination classes);
+ *                "sssp_lanes" (roots in flight, 1..4), "sssp_pull" (a
+ *                superstep whose frontier holds more than this percentage
+ *                of the edges pulls over in-edges; 0: never), "sssp_grid",
+ *                "sssp_lds_verts", "sssp_xcd" (per-XCD destination classes);
  *   PageRank     "pr_xcd" (per-XCD source classes), "pr_rows" (256 or 512
  *                edges per row block), "pr_lds_verts" (hot-table entries,
  *                <= 40960), "pr_grid" (workgroups).
@@ -158,7 +163,11 @@ int bfs_batched(const tg_partition *p, const int32_t *roots, int32_t num_roots,
                 int32_t *levels, void *stream);
 
 /* Single-source shortest paths by frontier Bellman-Ford (section 7.3,
- * Figure 20) over the int32 weights given to graph_load_csr.
+ * Figure 20) over the int32 weights given to graph_load_csr.  By default a
+ * superstep relaxes only active vertices below a distance threshold that
+ * advances in steps of "sssp_delta" (near/far), and up to "sssp_lanes"
+ * roots run at once on library streams and workspaces of their own; the
+ * distances do not depend on either.
  *   dist      device int32 [num_roots * V] (TG_INF when unreachable).
  * Errors: TG_EUNSUPPORTED (graph loaded without weights), TG_ERANGE (a
  * finite distance is >= INT32_MAX), TG_EINVAL, TG_ENOMEM, TG_EDEVICE. */

@@ -110,6 +110,9 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   const int64_t hubs_needed = g.max_out_hubs + 1;
   if (cap_n == g.n && hub_chunks_needed <= hub_chunks_cap && hubs_needed <= hubs_cap) return TG_OK;
   arena.release();
+  fd = nullptr;
+  pull_part = nullptr;
+  pull_part_cap = 0;
   const int64_t n = g.n;
   nwords = ((n + 31) / 32 + 1023) / 1024 * 1024;
   if (nwords == 0) nwords = 1024;
@@ -145,6 +148,9 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   TG_HIP(hipMemset(bits_c, 0, nwords * sizeof(uint32_t)));
   TG_HIP(hipMemset(counters, 0, 64 * sizeof(uint32_t)));
   TG_HIP(hipMemset(work, 0, (size_t)tgk::STAT_COUNTERS * tgk::STAT_SPAN * sizeof(unsigned long long)));
+  // the clears above run on the null stream, which is not ordered before
+  // work on the lanes' non-blocking streams: let them finish first
+  TG_HIP(hipDeviceSynchronize());
   if (!h_plan) TG_HIP(hipHostMalloc((void **)&h_plan, sizeof(Plan), hipHostMallocDefault));
   if (!h_flags) TG_HIP(hipHostMalloc((void **)&h_flags, 64 * sizeof(uint32_t), hipHostMallocDefault));
   if (!h_ctl) TG_HIP(hipHostMalloc((void **)&h_ctl, sizeof(tgk::BfsCtl), hipHostMallocDefault));
@@ -211,6 +217,31 @@ int Workspace::bind_bfs(const GpuPart &g, void *base, size_t bytes) {
   return TG_OK;
 }
 
+int lane_workspace(tg_partition *p, int i, Workspace **out) {
+  if (i == 0) {
+    *out = &p->ws;
+    return TG_OK;
+  }
+  if (i < 0 || i >= MAX_LANES) return set_error(TG_EINVAL, "lane %d outside [0, %d)", i, MAX_LANES);
+  if (!p->lane_ws[i - 1]) {
+    p->lane_ws[i - 1].reset(new (std::nothrow) Workspace());
+    if (!p->lane_ws[i - 1]) return set_error(TG_ENOMEM, "out of host memory");
+  }
+  *out = p->lane_ws[i - 1].get();
+  return TG_OK;
+}
+
+int lane_stream(tg_partition *p, int i, hipStream_t s, hipStream_t *out) {
+  if (i == 0) {
+    *out = s;
+    return TG_OK;
+  }
+  if (i < 0 || i >= MAX_LANES) return set_error(TG_EINVAL, "lane %d outside [0, %d)", i, MAX_LANES);
+  if (!p->lane_stream[i - 1]) TG_HIP(hipStreamCreateWithFlags(&p->lane_stream[i - 1], hipStreamNonBlocking));
+  *out = p->lane_stream[i - 1];
+  return TG_OK;
+}
+
 int stat_zero(Workspace &ws, int k, hipStream_t s) {
   TG_HIP(hipMemsetAsync(tgk::stat_counter(ws.work, k), 0, tgk::STAT_SPAN * sizeof(unsigned long long), s));
   return TG_OK;
@@ -248,7 +279,7 @@ Tuning default_tuning() {
   t.bfs_lds_words = 4096;
   t.bfs_grid = 2048;
   t.bfs_lds_min_vblocks = 4096;
-  t.sssp_delta = 0;
+  t.sssp_delta = 32;
   t.sssp_lds_verts = 0;
   t.sssp_grid = 2048;
   t.pr_xcd = 1;
@@ -260,6 +291,8 @@ Tuning default_tuning() {
   t.bfs_lanes = 2;
   t.bfs_td_grid = 1024;
   t.bfs_bu_grid = 4096;
+  t.sssp_pull = 0;  // measured slower on R-MAT (pull steps lose the chaining of push steps)
+  t.sssp_lanes = 4;
   return t;
 }
 
@@ -303,6 +336,10 @@ int parse_tuning(const char *json, Tuning *t) {
   if (json_int(json, "bfs_lanes", &v)) t->bfs_lanes = v;
   if (json_int(json, "bfs_td_grid", &v)) t->bfs_td_grid = v;
   if (json_int(json, "bfs_bu_grid", &v)) t->bfs_bu_grid = v;
+  if (json_int(json, "sssp_pull", &v)) t->sssp_pull = v;
+  if (json_int(json, "sssp_lanes", &v)) t->sssp_lanes = v;
+  if (t->sssp_pull < 0 || t->sssp_pull > 100) return set_error(TG_EINVAL, "tuning: sssp_pull must be in [0, 100]");
+  if (t->sssp_lanes < 1 || t->sssp_lanes > MAX_LANES) return set_error(TG_EINVAL, "tuning: sssp_lanes outside [1, 4]");
   if (t->bfs_lanes != 1 && t->bfs_lanes != 2) return set_error(TG_EINVAL, "tuning: bfs_lanes must be 1 or 2");
   if (t->bfs_td_grid < 1 || t->bfs_td_grid > 16384 || t->bfs_bu_grid < 2 || t->bfs_bu_grid > 16384)
     return set_error(TG_EINVAL, "tuning: bfs_td_grid must be in [1, 16384] and bfs_bu_grid in [2, 16384]");
@@ -773,6 +810,10 @@ extern "C" int partition_by_degree(const tg_graph *g, int strategy, double alpha
       rc = set_error(TG_ENOMEM, "partition_by_degree: out of host memory");
     }
   }
+  // uploads went through the null stream, which is not ordered before work
+  // on non-blocking streams: let them land
+  if (rc == TG_OK && hipDeviceSynchronize() != hipSuccess)
+    rc = set_error(TG_EDEVICE, "partition_by_degree: hipDeviceSynchronize failed");
   if (rc != TG_OK) {
     delete p;
     return rc;
@@ -802,7 +843,9 @@ extern "C" void partition_free(tg_partition *p) {
   pr_slices_free(p->gpu);
   pr_rows_free(p->gpu);
   sssp_slices_free(p->gpu);
-  if (p->aux_stream) TG_QUIET(hipStreamDestroy(p->aux_stream));
+  sssp_pull_free(p->gpu);
+  for (hipStream_t st : p->lane_stream)
+    if (st) TG_QUIET(hipStreamDestroy(st));
   delete p;
 }
 
@@ -852,7 +895,7 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld,"
            "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld,\"pr_xcd\":%lld,\"pr_rows\":%lld,"
            "\"bfs_do\":%lld,\"bfs_alpha\":%lld,\"bfs_beta\":%lld,\"sssp_xcd\":%lld,\"bfs_lanes\":%lld,"
-           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld}",
+           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld,\"sssp_pull\":%lld,\"sssp_lanes\":%lld}",
            (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
            (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk,
            (long long)p->tune.pr_lds_verts, (long long)p->tune.pr_grid, (long long)p->tune.bfs_lds_words,
@@ -860,7 +903,8 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            (long long)p->tune.sssp_lds_verts, (long long)p->tune.sssp_grid, (long long)p->tune.pr_xcd,
            (long long)p->tune.pr_rows, (long long)p->tune.bfs_do, (long long)p->tune.bfs_alpha,
            (long long)p->tune.bfs_beta, (long long)p->tune.sssp_xcd, (long long)p->tune.bfs_lanes,
-           (long long)p->tune.bfs_td_grid, (long long)p->tune.bfs_bu_grid);
+           (long long)p->tune.bfs_td_grid, (long long)p->tune.bfs_bu_grid, (long long)p->tune.sssp_pull,
+           (long long)p->tune.sssp_lanes);
   s += buf;
   s += ",\"tuning_source\":\"" + p->tuning_source + "\"";
   s += hybrid_info_json(p);
@@ -904,7 +948,7 @@ extern "C" int bfs(const tg_partition *pc, const int32_t *roots, int32_t num_roo
   int64_t supersteps = 0;
   TG_TRY(gpu_bfs_roots(p, local.data(), num_roots, levels, parents, s, &supersteps));
   // counters of both lanes (the second lane's work is ordered before s)
-  Workspace *lanes[2] = {&p->ws, &p->ws2};
+  Workspace *lanes[2] = {&p->ws, p->lane_ws[0].get()};
   const int nl = (p->tune.bfs_lanes > 1 && num_roots > 1) ? 2 : 1;
   for (int l = 0; l < nl; ++l)
     for (int k = 0; k < 6; ++k) TG_TRY(stat_fetch(*lanes[l], k, s));
@@ -935,22 +979,14 @@ extern "C" int sssp(const tg_partition *pc, const int32_t *roots, int32_t num_ro
   stats_reset("sssp");
   ktimer_reset();
   if (p->alpha > 0.0) return hybrid_sssp(p, roots, num_roots, dist, s);
-  const int64_t V = p->g->n;
-  int64_t rounds_total = 0;
-  TG_TRY(p->ws.ensure(p->gpu, 0));
-  TG_TRY(stat_zero_all(p->ws, s));
-  for (int32_t r = 0; r < num_roots; ++r) {
-    int64_t rounds = 0;
-    TG_TRY(gpu_sssp(p, p->h_l_of_g[roots[r]], s, &rounds));
-    rounds_total += rounds;
-    TG_TRY(collect_i32(p->gpu, p->ws.state, dist + (int64_t)r * V, s));
-  }
-  for (int k = 0; k < 2; ++k) TG_TRY(stat_fetch(p->ws, k, s));
+  int64_t rounds_total = 0, pulls_total = 0;
+  std::vector<int32_t> local((size_t)num_roots);
+  for (int32_t r = 0; r < num_roots; ++r) local[r] = p->h_l_of_g[roots[r]];
+  TG_TRY(gpu_sssp_roots(p, local.data(), num_roots, dist, s, &rounds_total, &pulls_total));
   TG_HIP(hipStreamSynchronize(s));
   stats_add("roots", num_roots);
   stats_add("supersteps", (double)rounds_total);
-  stats_add("relaxations", (double)stat_sum(p->ws, 0));
-  stats_add("activations", (double)stat_sum(p->ws, 1));
+  stats_add("pull_supersteps", (double)pulls_total);
   ktimer_emit();
   return TG_OK;
 }

@@ -337,9 +337,8 @@ int gpu_bfs_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32
   lane[0].ws = &p->ws;
   lane[0].s = s;
   if (nl == 2) {
-    if (!p->aux_stream) TG_HIP(hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking));
-    lane[1].ws = &p->ws2;
-    lane[1].s = p->aux_stream;
+    TG_TRY(lane_workspace(p, 1, &lane[1].ws));
+    TG_TRY(lane_stream(p, 1, s, &lane[1].s));
   }
   const int64_t V = g.n_global;
   int rc = TG_OK;

@@ -417,7 +417,8 @@ int frontier_plan_bfs_dev(const GpuPart &g, Workspace &ws, const Tuning &t, hipS
 }
 
 int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
-                          int32_t *settled, int32_t thresh, bool near, const BinBounds &bb, hipStream_t s) {
+                          int32_t *settled, int32_t thresh, bool near, const BinBounds &bb, hipStream_t s,
+                          unsigned long long *degsum) {
   const int blocks = (int)(ws.nwords / WPB);
   unsigned long long *rest_cnt = nullptr, *rest_min = nullptr;
   if (near) {
@@ -432,7 +433,7 @@ int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32
   hipLaunchKernelGGL(k_sssp_filter, dim3(blocks), dim3(CT), 0, s, bits, ws.bits_b, ws.bcount, dist, settled,
                      near ? thresh : TG_INF, rest_cnt, rest_min);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, ws.bits_b, nullptr, 4, ws.bcount, queue,
-                     nullptr, 0, bb, g.n, ws.plan, nullptr, nullptr, nullptr, nullptr, (int64_t)0);
+                     nullptr, 0, bb, g.n, ws.plan, nullptr, degsum ? g.out.off : nullptr, degsum, nullptr, (int64_t)0);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }

@@ -93,6 +93,21 @@ void ktimer_reset() {
   g_t.acc.clear();
 }
 
+std::vector<std::pair<std::string, std::pair<double, long long>>> ktimer_export() {
+  ktimer_flush();
+  std::vector<std::pair<std::string, std::pair<double, long long>>> out(g_t.acc.begin(), g_t.acc.end());
+  g_t.acc.clear();
+  return out;
+}
+
+void ktimer_import(const std::vector<std::pair<std::string, std::pair<double, long long>>> &acc) {
+  for (const auto &kv : acc) {
+    auto &a = g_t.acc[kv.first];
+    a.first += kv.second.first;
+    a.second += kv.second.second;
+  }
+}
+
 void ktimer_emit() {
   ktimer_flush();
   for (auto &kv : g_t.acc) {

@@ -349,6 +349,7 @@ int rows_upload(RowsDev &D, const RowBlocksHost &h) {
   }
   TG_TRY(dalloc(D.arena, &D.chunk_part, (size_t)D.nb_total));
   TG_TRY(dalloc(D.arena, &D.long_part, (size_t)LONG_GRID));
+  TG_HIP(hipDeviceSynchronize());  // the copies above are on the null stream
   return TG_OK;
 }
 

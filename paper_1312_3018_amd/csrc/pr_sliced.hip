@@ -116,7 +116,7 @@ static int build_slices(tg_partition *p, hipStream_t s) {
   TG_TRY(dalloc(S.arena, &S.ps, (size_t)NS * std::max<int64_t>(n, 1)));
   // rows that are never walked keep partial 0
   TG_HIP(hipMemset(S.ps, 0, (size_t)NS * std::max<int64_t>(n, 1) * sizeof(float)));
-  TG_HIP(hipStreamSynchronize(s));
+  TG_HIP(hipDeviceSynchronize());  // the clear is on the null stream
   S.built_nnz = t.pr_rows;
   S.built = true;
   return TG_OK;

@@ -272,7 +272,9 @@ int SlotEngine::init(tg_partition *part, int kind_, hipStream_t stream) {
   busy = 0;
   step = 0;
   have_queue = false;
-  TG_HIP(hipStreamSynchronize(s));
+  // the clears above are on the null stream, not ordered before work on a
+  // non-blocking stream such as a server lane's
+  TG_HIP(hipDeviceSynchronize());
   return TG_OK;
 }
 

@@ -24,6 +24,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "tg_internal.h"
@@ -225,7 +228,7 @@ void sssp_slices_free(GpuPart &g) {
   g.sslices = nullptr;
 }
 
-static int build_sssp_slices(tg_partition *p, hipStream_t s) {
+int build_sssp_slices(tg_partition *p, hipStream_t s) {
   GpuPart &g = p->gpu;
   const Tuning &t = p->tune;
   if (g.sslices && g.sslices->built) {
@@ -259,6 +262,7 @@ static int build_sssp_slices(tg_partition *p, hipStream_t s) {
   }
   TG_TRY(dalloc(S.arena, &S.maxlen, ml.size()));
   TG_HIP(hipMemcpy(S.maxlen, ml.data(), ml.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  TG_HIP(hipDeviceSynchronize());  // the copy is on the null stream
   int64_t i = 0;
   for (int b = 0; b < NBIN; ++b) {
     while (i < n && bin_of_degree((g.h_deg[i] + 7) / 8, t) < b) ++i;
@@ -294,9 +298,8 @@ static int sssp_relax_cls_launch(const GpuPart &g, Workspace &ws, const int32_t 
   return TG_OK;
 }
 
-int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) {
+int gpu_sssp(tg_partition *p, Workspace &ws, int32_t root, hipStream_t s, int64_t *rounds_out, int64_t *pulls_out) {
   GpuPart &g = p->gpu;
-  Workspace &ws = p->ws;
   if (!g.out.w) return set_error(TG_EUNSUPPORTED, "sssp: the graph was loaded without weights");
   TG_TRY(ws.ensure(g, 0));
   uint32_t *active = ws.bits_a, *ovf = ws.bits_c;
@@ -315,18 +318,26 @@ int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) 
   const BinBounds &bb = cls ? g.sslices->bins : g.out_bins;
   const int32_t *len = cls ? g.sslices->maxlen : nullptr;
   int64_t thresh = delta;  // near/far: only active vertices below thresh relax
+  // pull supersteps for frontiers with a large share of the edges: the
+  // compaction sums the frontier's out-degrees (spread counter 4)
+  const bool pull = p->tune.sssp_pull > 0 && !cls && sssp_pull_supported(g);
+  unsigned long long *degsum = pull ? stat_counter(ws.work, 4) : nullptr;
+  int64_t pulls = 0;
   for (;; ++rounds) {
     // a frontier Bellman-Ford settles within |V| - 1 rounds (per threshold step)
     if (rounds > 2 * g.n + 2) return set_error(TG_EDEVICE, "sssp: no convergence after %lld rounds", (long long)rounds);
+    if (pull) TG_TRY(stat_zero(ws, 4, s));
     if (delta <= 0) {
-      TG_TRY(frontier_compact_sssp(g, ws, active, ws.queue, dist, ws.settled, TG_INF, false, bb, s));
+      TG_TRY(frontier_compact_sssp(g, ws, active, ws.queue, dist, ws.settled, TG_INF, false, bb, s, degsum));
+      if (pull) TG_TRY(stat_fetch(ws, 4, s));
       TG_TRY(frontier_plan_bins(g, ws, ws.queue, bb, len, p->tune, s, true));
       if (ws.h_plan->count == 0) break;
     } else {
       TG_TRY(frontier_compact_sssp(g, ws, active, ws.queue, dist, ws.settled,
-                                   (int32_t)std::min<int64_t>(thresh, TG_INF), true, bb, s));
+                                   (int32_t)std::min<int64_t>(thresh, TG_INF), true, bb, s, degsum));
       TG_TRY(stat_fetch(ws, 5, s));
       TG_TRY(stat_fetch(ws, 6, s));
+      if (pull) TG_TRY(stat_fetch(ws, 4, s));
       TG_TRY(frontier_plan_bins(g, ws, ws.queue, bb, len, p->tune, s, true));
       if (ws.h_plan->count == 0) {
         if (stat_sum(ws, 5) == 0) break;  // nothing left beyond the threshold either
@@ -338,13 +349,126 @@ int gpu_sssp(tg_partition *p, int32_t root, hipStream_t s, int64_t *rounds_out) 
         continue;
       }
     }
-    if (cls) TG_TRY(sssp_relax_cls_launch(g, ws, ws.queue, *ws.h_plan, p->tune, s));
-    else TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s));
+    if (pull && (double)stat_sum(ws, 4) * 100.0 > (double)p->tune.sssp_pull * (double)g.m) {
+      // the taken frontier is in ws.bits_b (the compaction's filtered set)
+      TG_TRY(sssp_pull_launch(p, ws, ws.bits_b, s));
+      ++pulls;
+    } else if (cls) {
+      TG_TRY(sssp_relax_cls_launch(g, ws, ws.queue, *ws.h_plan, p->tune, s));
+    } else {
+      TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s));
+    }
   }
+  if (pulls_out) *pulls_out = pulls;
   TG_TRY(sssp_overflow_check(g, ws, s));
   if (ws.h_flags[1]) return set_error(TG_ERANGE, "sssp: a shortest-path distance does not fit below INT32_MAX");
   if (rounds_out) *rounds_out = rounds;
   return TG_OK;
+}
+
+namespace {
+
+struct LaneResult {
+  int rc = TG_OK;
+  std::string msg;
+  int64_t rounds = 0, pulls = 0;
+  unsigned long long relax = 0, act = 0;
+  std::vector<std::pair<std::string, std::pair<double, long long>>> timers;
+};
+
+// One lane: searches from the shared root counter until none is left or a
+// search fails, each collected into its row of dist.
+void sssp_lane(tg_partition *p, int lane, hipStream_t s, const int32_t *roots_local, int32_t nr, int32_t *dist,
+               std::atomic<int32_t> *next, std::atomic<bool> *failed, LaneResult *res) {
+  auto run = [&]() -> int {
+    if (hipSetDevice(p->device) != hipSuccess) return set_error(TG_EDEVICE, "sssp: hipSetDevice failed");
+    Workspace *ws = nullptr;
+    TG_TRY(lane_workspace(p, lane, &ws));
+    TG_TRY(ws->ensure(p->gpu, 0));
+    TG_TRY(stat_zero_all(*ws, s));
+    const int64_t V = p->gpu.n_global;
+    while (!failed->load()) {
+      const int32_t r = next->fetch_add(1);
+      if (r >= nr) break;
+      int64_t rounds = 0, pulls = 0;
+      TG_TRY(gpu_sssp(p, *ws, roots_local[r], s, &rounds, &pulls));
+      res->rounds += rounds;
+      res->pulls += pulls;
+      TG_TRY(collect_i32(p->gpu, ws->state, dist + (int64_t)r * V, s));
+    }
+    for (int k = 0; k < 2; ++k) TG_TRY(stat_fetch(*ws, k, s));
+    TG_HIP(hipStreamSynchronize(s));
+    res->relax = stat_sum(*ws, 0);
+    res->act = stat_sum(*ws, 1);
+    return TG_OK;
+  };
+  res->rc = run();
+  if (res->rc != TG_OK) {
+    res->msg = tg_last_error();
+    failed->store(true);
+    TG_QUIET(hipStreamSynchronize(s));
+  }
+  if (lane > 0) res->timers = ktimer_export();
+}
+
+}  // namespace
+
+int gpu_sssp_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32_t *dist, hipStream_t s,
+                   int64_t *rounds, int64_t *pulls) {
+  const Tuning &t = p->tune;
+  // per-partition layouts are built here, once, before lanes share them
+  if (t.sssp_xcd) TG_TRY(build_sssp_slices(p, s));
+  if (t.sssp_pull > 0 && t.sssp_xcd == 0 && sssp_pull_supported(p->gpu)) TG_TRY(sssp_pull_prepare(p, s));
+  const int nl = (int)std::max<int64_t>(1, std::min<int64_t>(t.sssp_lanes, nr));
+  hipStream_t st[MAX_LANES];
+  for (int l = 0; l < nl; ++l) TG_TRY(lane_stream(p, l, s, &st[l]));
+  for (int l = 1; l < nl; ++l) {
+    Workspace *ws = nullptr;
+    TG_TRY(lane_workspace(p, l, &ws));  // created here, not in the lane threads
+  }
+  hipEvent_t ev[MAX_LANES] = {};
+  for (int l = 0; l < nl; ++l) TG_HIP(hipEventCreateWithFlags(&ev[l], hipEventDisableTiming));
+  int rc = TG_OK;
+  // lanes 1.. start after the caller's earlier work on s
+  if (hipEventRecord(ev[0], s) != hipSuccess) rc = set_error(TG_EDEVICE, "sssp: hipEventRecord failed");
+  for (int l = 1; l < nl && rc == TG_OK; ++l)
+    if (hipStreamWaitEvent(st[l], ev[0], 0) != hipSuccess) rc = set_error(TG_EDEVICE, "sssp: stream ordering failed");
+  if (rc == TG_OK) {
+    std::atomic<int32_t> next{0};
+    std::atomic<bool> failed{false};
+    LaneResult res[MAX_LANES];
+    std::vector<std::thread> th;
+    try {
+      for (int l = 1; l < nl; ++l)
+        th.emplace_back(sssp_lane, p, l, st[l], roots_local, nr, dist, &next, &failed, &res[l]);
+    } catch (const std::system_error &) {
+      failed.store(true);
+      res[0].rc = set_error(TG_EDEVICE, "sssp: could not start a lane thread");
+    }
+    if (res[0].rc == TG_OK) sssp_lane(p, 0, s, roots_local, nr, dist, &next, &failed, &res[0]);
+    for (auto &x : th) x.join();
+    int64_t rd = 0, pl = 0;
+    unsigned long long rx = 0, ac = 0;
+    for (int l = 0; l < nl; ++l) {
+      if (rc == TG_OK && res[l].rc != TG_OK) rc = set_error(res[l].rc, "%s", res[l].msg.c_str());
+      rd += res[l].rounds;
+      pl += res[l].pulls;
+      rx += res[l].relax;
+      ac += res[l].act;
+      if (l > 0) ktimer_import(res[l].timers);
+    }
+    *rounds = rd;
+    *pulls = pl;
+    stats_add("relaxations", (double)rx);
+    stats_add("activations", (double)ac);
+    stats_add("lanes", nl);
+    // the caller's stream waits for the other lanes (already finished)
+    for (int l = 1; l < nl && rc == TG_OK; ++l)
+      if (hipEventRecord(ev[l], st[l]) != hipSuccess || hipStreamWaitEvent(s, ev[l], 0) != hipSuccess)
+        rc = set_error(TG_EDEVICE, "sssp: stream ordering failed");
+  }
+  for (int l = 0; l < nl; ++l) TG_QUIET(hipEventDestroy(ev[l]));
+  return rc;
 }
 
 }  // namespace tg

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,10 @@ void ktimer_stop(int start, hipStream_t s, const char *name);
 void ktimer_flush();  // after a stream sync: fold pending event pairs into totals
 void ktimer_reset();
 void ktimer_emit();   // add totals to the call's stats
+// Totals gathered on another thread (a lane of a multi-search call) move to
+// the calling thread: export there after its last flush, import here.
+std::vector<std::pair<std::string, std::pair<double, long long>>> ktimer_export();
+void ktimer_import(const std::vector<std::pair<std::string, std::pair<double, long long>>> &acc);
 int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_error();
 void stats_reset(const char *algo);
@@ -73,6 +78,8 @@ struct Tuning {
   int64_t bfs_lanes;             // BFS: searches in flight on their own streams (1 or 2)
   int64_t bfs_td_grid;           // BFS: blocks of a top-down launch (fixed: the frontier size is on the device)
   int64_t bfs_bu_grid;           // BFS: blocks of a bottom-up launch's one-thread-per-vertex part
+  int64_t sssp_pull;             // SSSP: pull a superstep whose frontier has more than this % of the edges (0: never)
+  int64_t sssp_lanes;            // SSSP: searches in flight on their own streams (1..4)
 };
 Tuning default_tuning();
 int parse_tuning(const char *json, Tuning *t);
@@ -125,6 +132,7 @@ struct DevCSR {
 struct PrSlices;
 struct PrRows;
 struct SsspSlices;
+struct SsspPull;
 
 // Per-XCD edge classes (class_csr.hip): class = 128-byte line of the 4-byte
 // state of the vertex an edge points at, mod 8.
@@ -238,6 +246,7 @@ struct GpuPart {
   PrSlices *slices = nullptr;      // PageRank in-edges split by source class (lazy)
   PrRows *rows = nullptr;          // PageRank row blocks of the in-edges (lazy)
   SsspSlices *sslices = nullptr;   // SSSP out-edges split by destination class (lazy)
+  SsspPull *spull = nullptr;       // SSSP in-edges by source class, row blocks (lazy; pull supersteps)
 };
 
 // Per-partition scratch, grown on demand.
@@ -272,6 +281,9 @@ struct Workspace {
   int64_t *hubpref = nullptr;    // frontier hub chunk prefix
   Plan *h_plan = nullptr;        // pinned host copy of the plan
   uint32_t *h_flags = nullptr;   // pinned host flags
+  int32_t *fd = nullptr;         // SSSP pull steps: frontier distances (n), allocated on first use
+  uint32_t *pull_part = nullptr; // SSSP pull steps: least candidate per chunk block, allocated on first use
+  int64_t pull_part_cap = 0;
   tgk::BfsCtl *ctl = nullptr;    // device-resident BFS control block
   tgk::BfsCtl *h_ctl = nullptr;  // pinned host copy of it (read once per chunk of supersteps)
   int64_t hub_chunks_cap = 0;
@@ -295,6 +307,7 @@ unsigned long long stat_sum(const Workspace &ws, int k);
 struct HybridState;
 struct SlotEngine;
 struct BcBatchState;
+constexpr int MAX_LANES = 4;  // searches in flight of one multi-root call
 
 }  // namespace tg
 
@@ -308,8 +321,10 @@ struct tg_partition {
   tg::DevArena arena;
   tg::GpuPart gpu;
   tg::Workspace ws;
-  tg::Workspace ws2;              // second BFS lane (its own stream), grown on first use
-  hipStream_t aux_stream = nullptr;  // the second lane's stream (default priority), created on first use
+  // lanes 1.. of the multi-search drivers (BFS, SSSP): a workspace and a
+  // stream (default priority) each, created on first use
+  std::unique_ptr<tg::Workspace> lane_ws[tg::MAX_LANES - 1];
+  hipStream_t lane_stream[tg::MAX_LANES - 1] = {};
   std::vector<int32_t> h_l_of_g;  // global -> GPU-local id (or -1)
   std::vector<int32_t> h_g_of_l;  // GPU-local -> global id
   tg::HybridState *hy = nullptr;  // host partition + boundary buffers (cpu_edge_share > 0)
@@ -337,8 +352,10 @@ int frontier_plan(const GpuPart &g, Workspace &ws, const int32_t *queue, const T
 // with `near`, dist < thresh; stale bits are dropped; with `near` the others
 // stay active and spread counters 5 and 6 get their count and least
 // distance.
+// With `degsum`, the taken frontier's out-degree sum is added to it.
 int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
-                          int32_t *settled, int32_t thresh, bool near, const BinBounds &bb, hipStream_t s);
+                          int32_t *settled, int32_t thresh, bool near, const BinBounds &bb, hipStream_t s,
+                          unsigned long long *degsum = nullptr);
 // Plan over the queue with bins `bb` (queue positions set by a compaction
 // with the same bins) and hub chunks sized by len[v] edges.
 int frontier_plan_bins(const GpuPart &g, Workspace &ws, const int32_t *queue, const BinBounds &bb,
@@ -368,6 +385,13 @@ void sssp_slices_free(GpuPart &g);
 int sssp_relax_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks, const Tuning &t,
                       hipStream_t s);
 int sssp_overflow_check(const GpuPart &g, Workspace &ws, hipStream_t s);
+// sssp_pull.hip: one superstep in the pull direction for the frontier whose
+// members are the set bits of `taken` (distances in ws.state, next active set
+// in ws.bits_a, overflow marks in ws.bits_c); only where supported.
+bool sssp_pull_supported(const GpuPart &g);
+int sssp_pull_prepare(tg_partition *p, hipStream_t s);  // builds the pull layout once
+int sssp_pull_launch(tg_partition *p, Workspace &ws, const uint32_t *taken, hipStream_t s);
+void sssp_pull_free(GpuPart &g);
 
 // collect.hip
 int collect_levels(const GpuPart &g, const uint32_t *visited, const int32_t *level, int32_t *out,
@@ -400,6 +424,10 @@ void pr_rows_free(GpuPart &g);
 int pr_write_initial(const GpuPart &g, float *rank_out, double N, hipStream_t s);
 
 // algorithms (GPU partition only)
+// Lane i of a multi-search call: its workspace (lane 0: p->ws) and stream
+// (lane 0: the caller's s), created on first use.
+int lane_workspace(tg_partition *p, int i, Workspace **out);
+int lane_stream(tg_partition *p, int i, hipStream_t s, hipStream_t *out);
 // BFS from each local root; levels (and parents, if non-null) of root r go
 // to row r of the outputs (original ids, V per row).  *supersteps gets the
 // superstep count summed over the roots.
@@ -412,7 +440,15 @@ int gpu_bfs_roots_bound(tg_partition *p, Workspace &ws, const int32_t *roots, in
                         hipStream_t s, tgk::BfsCtl *host_ctl);
 // Device bytes Workspace::bind_bfs needs for partition g.
 size_t bfs_scratch_bytes(const GpuPart &g);
-int gpu_sssp(tg_partition *p, int32_t root_local, hipStream_t s, int64_t *rounds_out);
+// SSSP from local root on workspace ws (distances left in ws.state).
+int gpu_sssp(tg_partition *p, Workspace &ws, int32_t root_local, hipStream_t s, int64_t *rounds_out,
+             int64_t *pulls_out = nullptr);
+// SSSP from each local root, row r of dist (original ids, V per row), with
+// up to tune.sssp_lanes searches in flight (a host thread, workspace and
+// stream each); *rounds and *pulls get the superstep counts summed over the
+// roots.  On error the first failing search's status is returned.
+int gpu_sssp_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32_t *dist, hipStream_t s,
+                   int64_t *rounds, int64_t *pulls);
 int gpu_pagerank(tg_partition *p, double damping, int32_t iters, int mode, float *rank_out,
                  hipStream_t s);
 int gpu_bc_source(tg_partition *p, int32_t src_local, hipStream_t s);

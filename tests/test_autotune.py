@@ -118,7 +118,7 @@ def test_traffic_from_counter_csvs(tmp_path):
     rows = {"fetch": "FETCH_SIZE", "write": "WRITE_SIZE"}
     names = {"sssp": ["k_sssp_relax(int const*)"],
              "pr": ["k_pr_rows<true, int, 8>(Args)", "k_pr_long<true>(Args)", "k_pr_combine(x)", "k_pr_dsum(y)"],
-             "bfs": ["k_bfs_expand(a)", "k_bfs_bottom_up_thread(b)", "k_bfs_bottom_up_wave(c)"]}
+             "bfs": ["k_bfs_step<int>(a)"]}
     for algo, kernels in names.items():
         for kind in ("fetch", "write", "hit"):
             d = tmp_path / f"{algo}_{kind}"
@@ -136,6 +136,6 @@ def test_traffic_from_counter_csvs(tmp_path):
     assert t["sssp_relax"]["write_bytes"] == round(kib * bench.WRITE_SCALE)
     assert t["sssp_relax"]["launches_sampled"] == 2
     assert t["pr_gather"]["fetch_bytes"] == round(4 * kib * bench.FETCH_SCALE)
-    assert t["bfs_bottom_up"]["write_bytes"] == 2 * kib and t["bfs_expand"]["write_bytes"] == kib
+    assert t["bfs_step"]["write_bytes"] == kib
     assert all(r["l2_hit_rate"] == 0.75 for r in t.values())
     assert t["sssp_relax"]["sources"] == bench.kernel_sources_digest(bench.KERNEL_FILES["sssp_relax"])

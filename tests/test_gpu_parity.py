@@ -196,6 +196,40 @@ def test_sssp_variants(gpu, rmat14, xcd, delta):
                 assert np.array_equal(dist[i], oracle.sssp(graph.offsets, graph.cols, wt, r)), (tuning, graph.n, r)
 
 
+@pytest.mark.parametrize("pr_lds_verts", [0, 40960])
+@pytest.mark.parametrize("delta", [0, 64])
+def test_sssp_pull(gpu, rmat14, delta, pr_lds_verts):
+    """Pull supersteps (sssp_pull = 1: every superstep whose frontier holds
+    more than 1% of the edges pulls) give the oracle's distances: with and
+    without the LDS table of hot frontier distances, with the near/far step,
+    on a symmetric R-MAT graph, a star whose hub row is split into chunks, a
+    path, a directed graph (no in-edge weights: push only) and overflowing
+    weights (TG_ERANGE as with push)."""
+    g, w = rmat14
+    gd = graphgen.rmat(12, symmetrize=False)
+    gs = graphgen.from_edges(20001, np.zeros(20000, dtype=int), np.arange(1, 20001), symmetrize=True)
+    gp = graphgen.from_edges(700, np.arange(699), np.arange(1, 700), symmetrize=True)
+    cases = [(g, w, graphgen.sample_roots(g, 4, seed=23).tolist() + [graphgen.max_degree_vertex(g)]),
+             (gd, graphgen.weights(gd, seed=4), graphgen.sample_roots(gd, 3, seed=22).tolist()),
+             (gs, graphgen.weights(gs, seed=5), [0, 3]),
+             (gp, graphgen.weights(gp, seed=6), [0, 350])]
+    tuning = {"sssp_pull": 1, "sssp_delta": delta, "pr_lds_verts": pr_lds_verts}
+    pulled = 0
+    for graph, wt, roots in cases:
+        P = load(gpu, graph, wt, tuning)
+        dist = gpu.sssp(P, roots).cpu().numpy()
+        pulled += gpu.tg_last_stats()["pull_supersteps"]
+        for i, r in enumerate(roots):
+            assert np.array_equal(dist[i], oracle.sssp(graph.offsets, graph.cols, wt, r)), (tuning, graph.n, r)
+    assert pulled > 0
+    # overflow: a path whose second edge cannot be added below INT32_MAX
+    go = graphgen.from_edges(3, [0, 1], [1, 2], symmetrize=True)
+    wo = np.full(go.nnz, 2**31 - 10, dtype=np.int32)
+    with pytest.raises(gpu.TGError) as ei:
+        gpu.sssp(load(gpu, go, wo, tuning), [0])
+    assert ei.value.code == gpu.TG_ERANGE
+
+
 DO_VARIANTS = [{"bfs_do": 0},                                   # top-down only
                {"bfs_alpha": 1000000, "bfs_beta": 1000000},     # bottom-up from the second step on
                {"bfs_alpha": 1000000, "bfs_beta": 1},           # alternate bottom-up and top-down
