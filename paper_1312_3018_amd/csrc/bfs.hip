@@ -350,6 +350,9 @@ int gpu_bfs_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32
   }
   if (rc == TG_OK && hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess)
     rc = set_error(TG_EDEVICE, "bfs: hipEventCreate failed");
+  // kernel timings (if on) are measured from a reference recorded on s
+  // before either lane starts
+  ktimer_ensure_ref(s);
   if (rc == TG_OK && nl == 2) {
     // the second lane starts after the caller's earlier work on s
     if (hipEventRecord(join, s) != hipSuccess || hipStreamWaitEvent(lane[1].s, join, 0) != hipSuccess)

@@ -373,13 +373,17 @@ struct LaneResult {
   std::string msg;
   int64_t rounds = 0, pulls = 0;
   unsigned long long relax = 0, act = 0;
-  std::vector<std::pair<std::string, std::pair<double, long long>>> timers;
+  KTimes timers;
 };
 
 // One lane: searches from the shared root counter until none is left or a
 // search fails, each collected into its row of dist.
 void sssp_lane(tg_partition *p, int lane, hipStream_t s, const int32_t *roots_local, int32_t nr, int32_t *dist,
-               std::atomic<int32_t> *next, std::atomic<bool> *failed, LaneResult *res) {
+               std::atomic<int32_t> *next, std::atomic<bool> *failed, LaneResult *res, hipEvent_t ref) {
+  if (lane > 0) {
+    ktimer_reset();
+    ktimer_set_ref(ref);
+  }
   auto run = [&]() -> int {
     if (hipSetDevice(p->device) != hipSuccess) return set_error(TG_EDEVICE, "sssp: hipSetDevice failed");
     Workspace *ws = nullptr;
@@ -429,10 +433,15 @@ int gpu_sssp_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int3
   hipEvent_t ev[MAX_LANES] = {};
   for (int l = 0; l < nl; ++l) TG_HIP(hipEventCreateWithFlags(&ev[l], hipEventDisableTiming));
   int rc = TG_OK;
+  // the reference event of this call's kernel timings (with timing on),
+  // recorded on s before any lane starts
+  const hipEvent_t ref = ktimer_ensure_ref(s);
   // lanes 1.. start after the caller's earlier work on s
   if (hipEventRecord(ev[0], s) != hipSuccess) rc = set_error(TG_EDEVICE, "sssp: hipEventRecord failed");
   for (int l = 1; l < nl && rc == TG_OK; ++l)
     if (hipStreamWaitEvent(st[l], ev[0], 0) != hipSuccess) rc = set_error(TG_EDEVICE, "sssp: stream ordering failed");
+  // the reference event of this call's kernel timings, recorded on s before
+  // any lane starts
   if (rc == TG_OK) {
     std::atomic<int32_t> next{0};
     std::atomic<bool> failed{false};
@@ -440,12 +449,12 @@ int gpu_sssp_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int3
     std::vector<std::thread> th;
     try {
       for (int l = 1; l < nl; ++l)
-        th.emplace_back(sssp_lane, p, l, st[l], roots_local, nr, dist, &next, &failed, &res[l]);
+        th.emplace_back(sssp_lane, p, l, st[l], roots_local, nr, dist, &next, &failed, &res[l], ref);
     } catch (const std::system_error &) {
       failed.store(true);
       res[0].rc = set_error(TG_EDEVICE, "sssp: could not start a lane thread");
     }
-    if (res[0].rc == TG_OK) sssp_lane(p, 0, s, roots_local, nr, dist, &next, &failed, &res[0]);
+    if (res[0].rc == TG_OK) sssp_lane(p, 0, s, roots_local, nr, dist, &next, &failed, &res[0], ref);
     for (auto &x : th) x.join();
     int64_t rd = 0, pl = 0;
     unsigned long long rx = 0, ac = 0;

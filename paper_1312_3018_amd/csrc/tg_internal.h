@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -25,10 +26,21 @@ void ktimer_stop(int start, hipStream_t s, const char *name);
 void ktimer_flush();  // after a stream sync: fold pending event pairs into totals
 void ktimer_reset();
 void ktimer_emit();   // add totals to the call's stats
+// Per kernel name: summed duration and launches, and each launch's interval
+// from the call's reference event.
+struct KTimes {
+  std::map<std::string, std::pair<double, long long>> acc;
+  std::map<std::string, std::vector<std::pair<float, float>>> iv;
+};
 // Totals gathered on another thread (a lane of a multi-search call) move to
-// the calling thread: export there after its last flush, import here.
-std::vector<std::pair<std::string, std::pair<double, long long>>> ktimer_export();
-void ktimer_import(const std::vector<std::pair<std::string, std::pair<double, long long>>> &acc);
+// the calling thread: the lane measures from the caller's reference event
+// (ktimer_ensure_ref there: records it on s if the call has none yet; null
+// with timing off; ktimer_set_ref in the lane), exports after its last
+// launch, and the caller imports.
+KTimes ktimer_export();
+void ktimer_import(const KTimes &k);
+hipEvent_t ktimer_ensure_ref(hipStream_t s);
+void ktimer_set_ref(hipEvent_t ref);
 int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_error();
 void stats_reset(const char *algo);
