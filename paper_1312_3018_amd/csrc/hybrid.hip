@@ -161,6 +161,98 @@ int up(DevArena &a, T **d, const T *h, size_t n) {
 
 }  // namespace
 
+// ------------------------------------------------------------ static checks
+// Every index the outbox, inbox and staging kernels take from the partition
+// (not from a frontier) comes from the structures built here, so they are
+// checked once, on the host: the channels' slot lists and reverse CSRs, the
+// slot order and the static plan over slots, including a replay of the
+// mapping from each virtual block of the plan to its slots and edge ranges
+// (the arithmetic of assign_work_rows).
+namespace {
+
+int check_channel(const Channel &ch, int64_t sender_n, int64_t receiver_n, bool weighted, const char *name) {
+  if ((int64_t)ch.dst.size() != ch.nslots || (int64_t)ch.roff.size() != ch.nslots + 1 || ch.roff[0] != 0)
+    return set_error(TG_EDEVICE, "hybrid %s: slot arrays of inconsistent length", name);
+  if (ch.roff.back() != (int64_t)ch.rsrc.size() || (weighted && ch.rw.size() != ch.rsrc.size()))
+    return set_error(TG_EDEVICE, "hybrid %s: reverse CSR length", name);
+  for (int64_t k = 0; k < ch.nslots; ++k) {
+    if (ch.roff[k + 1] <= ch.roff[k]) return set_error(TG_EDEVICE, "hybrid %s: slot %lld has no source", name, (long long)k);
+    if (ch.dst[k] < 0 || ch.dst[k] >= receiver_n || (k > 0 && ch.dst[k] <= ch.dst[k - 1]))
+      return set_error(TG_EDEVICE, "hybrid %s: slot %lld receiver id out of range or not ascending", name,
+                       (long long)k);
+  }
+  for (size_t e = 0; e < ch.rsrc.size(); ++e)
+    if (ch.rsrc[e] < 0 || ch.rsrc[e] >= sender_n)
+      return set_error(TG_EDEVICE, "hybrid %s: source %d of entry %zu out of range", name, ch.rsrc[e], e);
+  return TG_OK;
+}
+
+int check_hybrid(const tg_partition &p, const std::vector<int32_t> &sorder, const std::vector<int64_t> &sdeg) {
+  const HybridState &h = *p.hy;
+  const CpuPart &C = h.cpu;
+  const int64_t gn = p.gpu.n;
+  TG_TRY(check_channel(h.g2c, gn, C.n, p.g->has_w, "GPU-to-host channel"));
+  TG_TRY(check_channel(h.c2g, C.n, gn, p.g->has_w, "host-to-GPU channel"));
+  const Channel &o = h.g2c;
+  // slot order: a permutation, by non-increasing source count
+  std::vector<char> seen((size_t)o.nslots, 0);
+  for (int64_t i = 0; i < o.nslots; ++i) {
+    const int32_t sl = sorder[i];
+    if (sl < 0 || sl >= o.nslots || seen[sl]) return set_error(TG_EDEVICE, "hybrid: slot order is not a permutation");
+    seen[sl] = 1;
+    if (sdeg[i] != o.roff[sl + 1] - o.roff[sl] || (i > 0 && sdeg[i] > sdeg[i - 1]))
+      return set_error(TG_EDEVICE, "hybrid: slot order is not by source count");
+  }
+  // the static plan and a replay of its virtual blocks
+  const Plan &P = h.h_splan;
+  if (P.count != o.nslots || P.pos[0] != 0 || P.pos[NBIN] != o.nslots)
+    return set_error(TG_EDEVICE, "hybrid: slot plan does not cover the slots");
+  for (int b = 0; b < NBIN; ++b)
+    if (P.pos[b + 1] < P.pos[b] || P.vb[b + 1] < P.vb[b]) return set_error(TG_EDEVICE, "hybrid: slot plan not monotone");
+  const int64_t nh = P.pos[1] - P.pos[0], hc = h.splan_hub_chunk;
+  std::vector<int64_t> hubpref((size_t)nh + 1, 0);
+  for (int64_t k = 0; k < nh; ++k) hubpref[k + 1] = hubpref[k] + (sdeg[k] + hc - 1) / hc;
+  if (P.vb[1] != hubpref[nh]) return set_error(TG_EDEVICE, "hybrid: hub chunks of the slot plan");
+  std::vector<int64_t> covered((size_t)o.nslots, 0);
+  for (int64_t vb = 0; vb < P.vb[NBIN]; ++vb) {
+    int b = 0;
+    for (int k = 1; k < NBIN; ++k) b += vb >= P.vb[k] ? 1 : 0;
+    const int64_t local = vb - P.vb[b];
+    if (b == BIN_HUB) {
+      const int64_t i = std::upper_bound(hubpref.begin(), hubpref.end(), local) - hubpref.begin() - 1;
+      if (i < 0 || i >= nh || local >= hubpref[nh]) return set_error(TG_EDEVICE, "hybrid: hub virtual block %lld", (long long)vb);
+      const int32_t sl = sorder[P.pos[0] + i];
+      const int64_t e0 = o.roff[sl] + (local - hubpref[i]) * hc;
+      const int64_t e1 = std::min<int64_t>(e0 + hc, o.roff[sl + 1]);
+      if (e0 < o.roff[sl] || e0 >= e1) return set_error(TG_EDEVICE, "hybrid: hub chunk %lld of slot %d", (long long)vb, sl);
+      covered[sl] += e1 - e0;
+      continue;
+    }
+    if (b == BIN_ZERO) return set_error(TG_EDEVICE, "hybrid: a slot in the empty bin");
+    for (int t = 0; t < BLOCK; t += lanes_per_vertex(b)) {
+      const int64_t qi = P.pos[b] + local * verts_per_vblock(b) + t / lanes_per_vertex(b);
+      if (qi >= P.pos[b + 1]) break;
+      const int32_t sl = sorder[qi];
+      covered[sl] += o.roff[sl + 1] - o.roff[sl];
+    }
+  }
+  for (int64_t sl = 0; sl < o.nslots; ++sl)
+    if (covered[sl] != o.roff[sl + 1] - o.roff[sl])
+      return set_error(TG_EDEVICE, "hybrid: slot plan covers %lld of the %lld sources of slot %lld", (long long)covered[sl],
+                       (long long)(o.roff[sl + 1] - o.roff[sl]), (long long)sl);
+  // the host partition's own CSRs and id maps
+  if ((int64_t)C.off.size() != C.n + 1 || C.off.back() != C.m || (int64_t)C.g_of_l.size() != C.n)
+    return set_error(TG_EDEVICE, "hybrid: host partition CSR");
+  for (int32_t x : C.col)
+    if (x < 0 || x >= C.n) return set_error(TG_EDEVICE, "hybrid: host edge target out of range");
+  for (int64_t i = 0; i < C.n; ++i)
+    if (C.g_of_l[i] < 0 || C.g_of_l[i] >= p.g->n || p.h_l_of_g[C.g_of_l[i]] >= 0)
+      return set_error(TG_EDEVICE, "hybrid: host vertex %lld is not a host-only vertex", (long long)i);
+  return TG_OK;
+}
+
+}  // namespace
+
 // ------------------------------------------------------------------ building
 int build_hybrid(tg_partition *p, uint64_t seed) {
   const tg_graph &G = *p->g;
@@ -326,7 +418,7 @@ int build_hybrid(tg_partition *p, uint64_t seed) {
   TG_HIP(hipHostMalloc((void **)&hy->h_out_f, no * sizeof(double), hipHostMallocDefault));
   TG_HIP(hipHostMalloc((void **)&hy->h_in_f, ni * sizeof(double), hipHostMallocDefault));
   TG_HIP(hipHostMalloc((void **)&hy->h_stage, (size_t)C.n * sizeof(int32_t), hipHostMallocDefault));
-  return TG_OK;
+  return check_hybrid(*p, sorder, sdeg);
 }
 
 void hybrid_free(tg_partition *p) {
