@@ -124,7 +124,9 @@ int partition_by_degree(const tg_graph *g, int strategy, double cpu_edge_share,
  *   BFS          "bfs_do" (1: direction-optimizing steps), "bfs_alpha",
  *                "bfs_beta" (the switch thresholds), "bfs_lanes" (searches
  *                in flight, 1 or 2), "bfs_td_grid", "bfs_bu_grid" (blocks of
- *                the top-down and bottom-up steps); "bfs_lds_words",
+ *                the top-down and bottom-up steps), "bfs_graph" (1: chunks of
+ *                supersteps captured once as HIP graphs and replayed; kernel
+ *                timing off only); "bfs_lds_words",
  *                "bfs_grid", "bfs_lds_min_vblocks" for the top-down steps of
  *                betweenness and hybrid searches;
  *   SSSP         "sssp_delta" (0: plain frontier; > 0: near/far step),

@@ -25,6 +25,7 @@ DEFAULTS = {
     "bfs_lds_min_vblocks": 4096, "sssp_delta": 32, "sssp_lds_verts": 0, "sssp_grid": 2048, "pr_xcd": 1,
     "pr_rows": 512, "bfs_do": 1, "bfs_alpha": 14, "bfs_beta": 24, "sssp_xcd": 0,
     "bfs_lanes": 2, "bfs_td_grid": 1024, "bfs_bu_grid": 4096, "sssp_lanes": 4, "sssp_pull": 0,
+    "bfs_graph": 0,
 }
 
 SPACE = {
@@ -41,6 +42,7 @@ SPACE = {
     "bfs_td_grid": [512, 1024, 2048],
     "bfs_bu_grid": [2048, 4096, 8192],
     "bfs_lanes": [1, 2],
+    "bfs_graph": [0, 1],
     "bfs_alpha": [4, 14, 32, 64],
     "bfs_beta": [8, 24, 64],
     "sssp_delta": [0, 16, 24, 32, 48, 64, 128],
@@ -54,7 +56,7 @@ SPACE = {
 FAMILY = {k: "all" for k in ("hub_min_deg", "block_min_deg", "wave_min_deg", "g16_min_deg", "g4_min_deg",
                              "hub_chunk")}
 FAMILY.update({"pr_xcd": "pr", "pr_rows": "pr", "pr_lds_verts": "pr", "pr_grid": "pr", "bfs_td_grid": "bfs",
-               "bfs_bu_grid": "bfs", "bfs_lanes": "bfs", "bfs_alpha": "bfs", "bfs_beta": "bfs",
+               "bfs_bu_grid": "bfs", "bfs_lanes": "bfs", "bfs_graph": "bfs", "bfs_alpha": "bfs", "bfs_beta": "bfs",
                "sssp_delta": "sssp", "sssp_lds_verts": "sssp", "sssp_lanes": "sssp", "sssp_pull": "sssp",
                "sssp_grid": "sssp", "sssp_xcd": "sssp"})
 

@@ -98,7 +98,13 @@ void DevArena::release() {
   bytes = 0;
 }
 
+void Workspace::drop_graphs() {
+  for (GraphChunk &c : graphs) TG_QUIET(hipGraphExecDestroy(c.exec));
+  graphs.clear();
+}
+
 Workspace::~Workspace() {
+  drop_graphs();
   if (h_plan) TG_QUIET(hipHostFree(h_plan));
   if (h_flags) TG_QUIET(hipHostFree(h_flags));
   if (h_work) TG_QUIET(hipHostFree(h_work));
@@ -109,6 +115,8 @@ Workspace::~Workspace() {
 int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   const int64_t hubs_needed = g.max_out_hubs + 1;
   if (cap_n == g.n && hub_chunks_needed <= hub_chunks_cap && hubs_needed <= hubs_cap) return TG_OK;
+  drop_graphs();
+  ++gen;
   arena.release();
   fd = nullptr;
   pull_part = nullptr;
@@ -231,6 +239,13 @@ int lane_workspace(tg_partition *p, int i, Workspace **out) {
   return TG_OK;
 }
 
+int graph_stream(tg_partition *p, int i, hipStream_t *out) {
+  if (i < 0 || i >= MAX_LANES) return set_error(TG_EINVAL, "lane %d outside [0, %d)", i, MAX_LANES);
+  if (!p->graph_stream[i]) TG_HIP(hipStreamCreateWithFlags(&p->graph_stream[i], hipStreamNonBlocking));
+  *out = p->graph_stream[i];
+  return TG_OK;
+}
+
 int lane_stream(tg_partition *p, int i, hipStream_t s, hipStream_t *out) {
   if (i == 0) {
     *out = s;
@@ -293,6 +308,7 @@ Tuning default_tuning() {
   t.bfs_bu_grid = 4096;
   t.sssp_pull = 0;  // measured slower on R-MAT (pull steps lose the chaining of push steps)
   t.sssp_lanes = 4;
+  t.bfs_graph = 0;  // replaying captured chunks measured 1-2% slower than direct launches
   return t;
 }
 
@@ -338,6 +354,8 @@ int parse_tuning(const char *json, Tuning *t) {
   if (json_int(json, "bfs_bu_grid", &v)) t->bfs_bu_grid = v;
   if (json_int(json, "sssp_pull", &v)) t->sssp_pull = v;
   if (json_int(json, "sssp_lanes", &v)) t->sssp_lanes = v;
+  if (json_int(json, "bfs_graph", &v)) t->bfs_graph = v;
+  if (t->bfs_graph != 0 && t->bfs_graph != 1) return set_error(TG_EINVAL, "tuning: bfs_graph must be 0 or 1");
   if (t->sssp_pull < 0 || t->sssp_pull > 100) return set_error(TG_EINVAL, "tuning: sssp_pull must be in [0, 100]");
   if (t->sssp_lanes < 1 || t->sssp_lanes > MAX_LANES) return set_error(TG_EINVAL, "tuning: sssp_lanes outside [1, 4]");
   if (t->bfs_lanes != 1 && t->bfs_lanes != 2) return set_error(TG_EINVAL, "tuning: bfs_lanes must be 1 or 2");
@@ -567,6 +585,7 @@ namespace tg {
 int apply_tuning(tg_partition *p, const Tuning &t) {
   GpuPart &gp = p->gpu;
   p->tune = t;
+  ++p->tune_gen;
   gp.out_bins = bins_of(gp.h_deg, t);
   gp.in_bins = gp.in_alias ? gp.out_bins : bins_of_unsorted(gp.h_in_deg, t);
   gp.max_out_hubs = gp.out_bins.bstart[1] - gp.out_bins.bstart[0];
@@ -846,6 +865,8 @@ extern "C" void partition_free(tg_partition *p) {
   sssp_pull_free(p->gpu);
   for (hipStream_t st : p->lane_stream)
     if (st) TG_QUIET(hipStreamDestroy(st));
+  for (hipStream_t st : p->graph_stream)
+    if (st) TG_QUIET(hipStreamDestroy(st));
   delete p;
 }
 
@@ -895,7 +916,7 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld,"
            "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld,\"pr_xcd\":%lld,\"pr_rows\":%lld,"
            "\"bfs_do\":%lld,\"bfs_alpha\":%lld,\"bfs_beta\":%lld,\"sssp_xcd\":%lld,\"bfs_lanes\":%lld,"
-           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld,\"sssp_pull\":%lld,\"sssp_lanes\":%lld}",
+           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld,\"sssp_pull\":%lld,\"sssp_lanes\":%lld,\"bfs_graph\":%lld}",
            (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
            (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk,
            (long long)p->tune.pr_lds_verts, (long long)p->tune.pr_grid, (long long)p->tune.bfs_lds_words,
@@ -904,7 +925,7 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            (long long)p->tune.pr_rows, (long long)p->tune.bfs_do, (long long)p->tune.bfs_alpha,
            (long long)p->tune.bfs_beta, (long long)p->tune.sssp_xcd, (long long)p->tune.bfs_lanes,
            (long long)p->tune.bfs_td_grid, (long long)p->tune.bfs_bu_grid, (long long)p->tune.sssp_pull,
-           (long long)p->tune.sssp_lanes);
+           (long long)p->tune.sssp_lanes, (long long)p->tune.bfs_graph);
   s += buf;
   s += ",\"tuning_source\":\"" + p->tuning_source + "\"";
   s += hybrid_info_json(p);

@@ -305,8 +305,43 @@ int bfs_dev_superstep(const GpuPart &g, Workspace &ws, const Tuning &t, hipStrea
 }
 
 // Enqueue k supersteps, then the read-back of the control block and `ev`.
-int bfs_dev_chunk(const GpuPart &g, Workspace &ws, const Tuning &t, int k, hipStream_t s, hipEvent_t ev) {
-  for (int i = 0; i < k; ++i) TG_TRY(bfs_dev_superstep(g, ws, t, s));
+// The k supersteps as one captured graph (captured on first use, replayed
+// after): their launches take fixed pointers and read everything else from
+// the device, so one capture serves every search on this workspace until
+// the buffers or the tuning change.  No memory set or copy is captured.
+int bfs_graph_chunk(const tg_partition *p, Workspace &ws, int k, hipStream_t s) {
+  for (const Workspace::GraphChunk &c : ws.graphs)
+    if (c.k == k && c.tune_gen == p->tune_gen && c.gen == ws.gen) {
+      TG_HIP(hipGraphLaunch(c.exec, s));
+      return TG_OK;
+    }
+  TG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int rc = TG_OK;
+  for (int i = 0; i < k && rc == TG_OK; ++i) rc = bfs_dev_superstep(p->gpu, ws, p->tune, s, false);
+  hipGraph_t gr = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &gr);
+  if (rc == TG_OK && e != hipSuccess) rc = set_error(TG_EDEVICE, "bfs: capture failed: %s", hipGetErrorString(e));
+  hipGraphExec_t ex = nullptr;
+  if (rc == TG_OK && hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) != hipSuccess)
+    rc = set_error(TG_EDEVICE, "bfs: hipGraphInstantiate failed");
+  if (gr) TG_QUIET(hipGraphDestroy(gr));
+  if (rc != TG_OK) return rc;
+  // a few chunk lengths recur (the learned first chunk, the follow-up chunk)
+  if (ws.graphs.size() >= 6) {
+    TG_QUIET(hipGraphExecDestroy(ws.graphs.front().exec));
+    ws.graphs.erase(ws.graphs.begin());
+  }
+  ws.graphs.push_back({k, p->tune_gen, ws.gen, ex});
+  TG_HIP(hipGraphLaunch(ex, s));
+  return TG_OK;
+}
+
+// Enqueue k supersteps (eagerly, or replaying a captured chunk), then the
+// read-back of the control block and `ev`.
+int bfs_dev_chunk(const tg_partition *p, Workspace &ws, int k, hipStream_t s, hipEvent_t ev, bool graph) {
+  if (graph) TG_TRY(bfs_graph_chunk(p, ws, k, s));
+  else
+    for (int i = 0; i < k; ++i) TG_TRY(bfs_dev_superstep(p->gpu, ws, p->tune, s));
   TG_HIP(hipMemcpyAsync(ws.h_ctl, ws.ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
   TG_HIP(hipEventRecord(ev, s));
   return TG_OK;
@@ -333,12 +368,17 @@ int gpu_bfs_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32
   GpuPart &g = p->gpu;
   const Tuning &t = p->tune;
   const int nl = (t.bfs_lanes > 1 && nr > 1) ? 2 : 1;
+  // captured chunks replay without per-kernel timing events; capture needs
+  // streams of the library's own (the caller's may be the null stream)
+  const bool graph = t.bfs_graph != 0 && !timing_enabled();
   BfsLane lane[2];
   lane[0].ws = &p->ws;
   lane[0].s = s;
+  if (graph) TG_TRY(graph_stream(p, 0, &lane[0].s));
   if (nl == 2) {
     TG_TRY(lane_workspace(p, 1, &lane[1].ws));
-    TG_TRY(lane_stream(p, 1, s, &lane[1].s));
+    if (graph) TG_TRY(graph_stream(p, 1, &lane[1].s));
+    else TG_TRY(lane_stream(p, 1, s, &lane[1].s));
   }
   const int64_t V = g.n_global;
   int rc = TG_OK;
@@ -353,10 +393,12 @@ int gpu_bfs_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32
   // kernel timings (if on) are measured from a reference recorded on s
   // before either lane starts
   ktimer_ensure_ref(s);
-  if (rc == TG_OK && nl == 2) {
-    // the second lane starts after the caller's earlier work on s
-    if (hipEventRecord(join, s) != hipSuccess || hipStreamWaitEvent(lane[1].s, join, 0) != hipSuccess)
-      rc = set_error(TG_EDEVICE, "bfs: stream ordering failed");
+  if (rc == TG_OK) {
+    // lanes on streams other than s start after the caller's earlier work on s
+    bool ok = hipEventRecord(join, s) == hipSuccess;
+    for (int l = 0; l < nl && ok; ++l)
+      if (lane[l].s != s) ok = hipStreamWaitEvent(lane[l].s, join, 0) == hipSuccess;
+    if (!ok) rc = set_error(TG_EDEVICE, "bfs: stream ordering failed");
   }
   for (int l = 0; l < nl && rc == TG_OK; ++l) rc = stat_zero_all(*lane[l].ws, lane[l].s);
   int first_chunk = 4;  // supersteps of the next search's first chunk (learned)
@@ -370,7 +412,7 @@ int gpu_bfs_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32
     TG_TRY(bfs_dev_start(g, ws, roots_local[L.r], L.s));
     TG_TRY(frontier_compact_bfs_dev(g, ws, t, L.s));  // the root's frontier, level 0
     L.issued = first_chunk;
-    return bfs_dev_chunk(g, ws, t, first_chunk, L.s, L.ev);
+    return bfs_dev_chunk(p, ws, first_chunk, L.s, L.ev, graph);
   };
   for (int l = 0; l < nl && rc == TG_OK && next < nr; ++l) rc = start(lane[l]);
   // serve the lanes in turn until every search has ended
@@ -392,7 +434,7 @@ int gpu_bfs_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32
         break;
       }
       L.issued += 2;
-      rc = bfs_dev_chunk(g, *L.ws, t, 2, L.s, L.ev);
+      rc = bfs_dev_chunk(p, *L.ws, 2, L.s, L.ev, graph);
       continue;
     }
     // this search has ended: collect it and start the next one on the lane
@@ -404,14 +446,15 @@ int gpu_bfs_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32
     L.r = -1;
     if (rc == TG_OK && next < nr) rc = start(L);
   }
-  if (nl == 2 && rc == TG_OK) {
-    // the caller's stream waits for the second lane
-    if (hipEventRecord(join, lane[1].s) != hipSuccess || hipStreamWaitEvent(s, join, 0) != hipSuccess)
+  for (int l = 0; l < nl && rc == TG_OK; ++l) {
+    // the caller's stream waits for the lanes on other streams
+    if (lane[l].s == s) continue;
+    if (hipEventRecord(lane[l].ev, lane[l].s) != hipSuccess || hipStreamWaitEvent(s, lane[l].ev, 0) != hipSuccess)
       rc = set_error(TG_EDEVICE, "bfs: stream ordering failed");
   }
   if (rc != TG_OK) {
-    // leave no work of this call running on the second lane
-    if (nl == 2) TG_QUIET(hipStreamSynchronize(lane[1].s));
+    // leave no work of this call running on the lanes' streams
+    for (int l = 0; l < nl; ++l) TG_QUIET(hipStreamSynchronize(lane[l].s));
     TG_QUIET(hipStreamSynchronize(s));
   }
   for (int l = 0; l < nl; ++l)

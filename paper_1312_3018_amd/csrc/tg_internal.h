@@ -92,6 +92,7 @@ struct Tuning {
   int64_t bfs_bu_grid;           // BFS: blocks of a bottom-up launch's one-thread-per-vertex part
   int64_t sssp_pull;             // SSSP: pull a superstep whose frontier has more than this % of the edges (0: never)
   int64_t sssp_lanes;            // SSSP: searches in flight on their own streams (1..4)
+  int64_t bfs_graph;             // BFS: 1 = chunks of supersteps replayed as captured HIP graphs
 };
 Tuning default_tuning();
 int parse_tuning(const char *json, Tuning *t);
@@ -301,6 +302,16 @@ struct Workspace {
   int64_t hub_chunks_cap = 0;
   int64_t hubs_cap = 0;
   int64_t partials_cap = 0;
+  // captured chunks of device-resident BFS supersteps (k supersteps each),
+  // valid for this workspace's buffers (gen) and one tuning of the partition
+  struct GraphChunk {
+    int k;
+    uint64_t tune_gen, gen;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphChunk> graphs;
+  uint64_t gen = 0;  // bumped whenever the buffers are reallocated
+  void drop_graphs();
   int ensure(const GpuPart &g, int64_t hub_chunks_needed);
   // Point the buffers a device-resident BFS uses into caller-owned device
   // memory [base, base + bytes) instead of allocating them; the other
@@ -329,6 +340,7 @@ struct tg_partition {
   double alpha = 0.0;
   int device = 0;
   tg::Tuning tune{};
+  uint64_t tune_gen = 0;  // bumped by every (re)tuning: captured launches depend on it
   std::string tuning_source = "built-in";  // "caller", "built-in" or "cache <key>"
   tg::DevArena arena;
   tg::GpuPart gpu;
@@ -337,6 +349,7 @@ struct tg_partition {
   // stream (default priority) each, created on first use
   std::unique_ptr<tg::Workspace> lane_ws[tg::MAX_LANES - 1];
   hipStream_t lane_stream[tg::MAX_LANES - 1] = {};
+  hipStream_t graph_stream[tg::MAX_LANES] = {};  // lanes of a BFS replaying captured chunks (capture needs an own stream)
   std::vector<int32_t> h_l_of_g;  // global -> GPU-local id (or -1)
   std::vector<int32_t> h_g_of_l;  // GPU-local -> global id
   tg::HybridState *hy = nullptr;  // host partition + boundary buffers (cpu_edge_share > 0)
@@ -440,6 +453,7 @@ int pr_write_initial(const GpuPart &g, float *rank_out, double N, hipStream_t s)
 // (lane 0: the caller's s), created on first use.
 int lane_workspace(tg_partition *p, int i, Workspace **out);
 int lane_stream(tg_partition *p, int i, hipStream_t s, hipStream_t *out);
+int graph_stream(tg_partition *p, int i, hipStream_t *out);
 // BFS from each local root; levels (and parents, if non-null) of root r go
 // to row r of the outputs (original ids, V per row).  *supersteps gets the
 // superstep count summed over the roots.

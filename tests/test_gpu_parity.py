@@ -230,6 +230,25 @@ def test_sssp_pull(gpu, rmat14, delta, pr_lds_verts):
     assert ei.value.code == gpu.TG_ERANGE
 
 
+def test_bfs_captured_chunks(gpu, rmat14):
+    """Superstep chunks captured as HIP graphs and replayed: every replay
+    (three calls of twelve roots on two lanes, with other work on the stream
+    between them, then after a retune that forces a new capture) gives the
+    oracle's levels."""
+    g, w = rmat14
+    roots = [graphgen.max_degree_vertex(g)] + graphgen.sample_roots(g, 11, seed=31).tolist()
+    refs = [oracle.bfs(g.offsets, g.cols, r) for r in roots]
+    P = load(gpu, g, w, {"bfs_graph": 1})
+    for tuning in ({"bfs_graph": 1}, {"bfs_graph": 1, "bfs_alpha": 1000000, "bfs_beta": 1}):
+        gpu.partition_retune(P, tuning)
+        for rep in range(3):
+            lev = gpu.bfs(P, roots).cpu().numpy()
+            for i, r in enumerate(roots):
+                assert np.array_equal(lev[i], refs[i]), (tuning, rep, r)
+            gpu.sssp(P, roots[:2])
+            gpu.pagerank(P, 0.85, 2)
+
+
 DO_VARIANTS = [{"bfs_do": 0},                                   # top-down only
                {"bfs_alpha": 1000000, "bfs_beta": 1000000},     # bottom-up from the second step on
                {"bfs_alpha": 1000000, "bfs_beta": 1},           # alternate bottom-up and top-down
