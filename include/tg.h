@@ -134,6 +134,11 @@ int partition_by_degree(const tg_graph *g, int strategy, double cpu_edge_share,
  *                superstep whose frontier holds more than this percentage
  *                of the edges pulls over in-edges; 0: never), "sssp_grid",
  *                "sssp_lds_verts", "sssp_xcd" (per-XCD destination classes);
+ *   layout       "mapped_edges" (1: the edge arrays -- neighbour ids, weights,
+ *                in-edge ids -- stay in pinned host memory mapped into the
+ *                GPU and kernels read them over the host link, for graphs
+ *                beyond device memory; honoured by partition_by_degree only,
+ *                and it keeps the per-XCD class layouts off);
  *   PageRank     "pr_xcd" (per-XCD source classes), "pr_rows" (256 or 512
  *                edges per row block), "pr_lds_verts" (hot-table entries,
  *                <= 40960), "pr_grid" (workgroups).

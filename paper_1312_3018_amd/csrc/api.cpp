@@ -83,6 +83,24 @@ int DevArena::alloc(void **p, size_t n) {
   return TG_OK;
 }
 
+int HostMappedArena::upload(void **dev, const void *src, size_t n) {
+  void *h = nullptr;
+  const size_t sz = n ? n : 256;
+  if (hipHostMalloc(&h, sz, hipHostMallocMapped) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(TG_ENOMEM, "hipHostMalloc(%zu bytes, mapped) failed", sz);
+  }
+  ptrs.push_back(h);
+  bytes += sz;
+  if (n) memcpy(h, src, n);
+  TG_HIP(hipHostGetDevicePointer(dev, h, 0));
+  return TG_OK;
+}
+
+HostMappedArena::~HostMappedArena() {
+  for (void *h : ptrs) TG_QUIET(hipHostFree(h));
+}
+
 void DevArena::release_one(void *p) {
   for (size_t i = 0; i < ptrs.size(); ++i)
     if (ptrs[i] == p) {
@@ -309,6 +327,7 @@ Tuning default_tuning() {
   t.sssp_pull = 0;  // measured slower on R-MAT (pull steps lose the chaining of push steps)
   t.sssp_lanes = 4;
   t.bfs_graph = 0;  // replaying captured chunks measured 1-2% slower than direct launches
+  t.mapped_edges = 0;
   return t;
 }
 
@@ -355,6 +374,8 @@ int parse_tuning(const char *json, Tuning *t) {
   if (json_int(json, "sssp_pull", &v)) t->sssp_pull = v;
   if (json_int(json, "sssp_lanes", &v)) t->sssp_lanes = v;
   if (json_int(json, "bfs_graph", &v)) t->bfs_graph = v;
+  if (json_int(json, "mapped_edges", &v)) t->mapped_edges = v;
+  if (t->mapped_edges != 0 && t->mapped_edges != 1) return set_error(TG_EINVAL, "tuning: mapped_edges must be 0 or 1");
   if (t->bfs_graph != 0 && t->bfs_graph != 1) return set_error(TG_EINVAL, "tuning: bfs_graph must be 0 or 1");
   if (t->sssp_pull < 0 || t->sssp_pull > 100) return set_error(TG_EINVAL, "tuning: sssp_pull must be in [0, 100]");
   if (t->sssp_lanes < 1 || t->sssp_lanes > MAX_LANES) return set_error(TG_EINVAL, "tuning: sssp_lanes outside [1, 4]");
@@ -586,6 +607,14 @@ int apply_tuning(tg_partition *p, const Tuning &t) {
   GpuPart &gp = p->gpu;
   p->tune = t;
   ++p->tune_gen;
+  if (gp.mapped_edges) {
+    // the per-XCD class layouts copy the edges into device memory: with the
+    // edges kept on the host the kernels read the CSR itself
+    p->tune.pr_xcd = 0;
+    p->tune.sssp_xcd = 0;
+    p->tune.sssp_pull = 0;
+  }
+  p->tune.mapped_edges = gp.mapped_edges ? 1 : 0;  // fixed at build
   gp.out_bins = bins_of(gp.h_deg, t);
   gp.in_bins = gp.in_alias ? gp.out_bins : bins_of_unsorted(gp.h_in_deg, t);
   gp.max_out_hubs = gp.out_bins.bstart[1] - gp.out_bins.bstart[0];
@@ -675,8 +704,14 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
   gp.n_dangling = 0;
   DevArena &A = p->arena;
   TG_TRY(upload(A, &gp.out.off, off.data(), (size_t)n + 1));
-  TG_TRY(upload(A, &gp.out.col, col.data(), (size_t)m));
-  if (G.has_w) TG_TRY(upload(A, &gp.out.w, w.data(), (size_t)m));
+  // edge arrays: device memory, or mapped host memory read over the host link
+  gp.mapped_edges = p->tune.mapped_edges != 0;
+  auto edges = [&](int32_t **d, const std::vector<int32_t> &h) -> int {
+    if (!gp.mapped_edges) return upload(A, d, h.data(), (size_t)m);
+    return p->mapped.upload(reinterpret_cast<void **>(d), h.data(), (size_t)m * sizeof(int32_t));
+  };
+  TG_TRY(edges(&gp.out.col, col));
+  if (G.has_w) TG_TRY(edges(&gp.out.w, w));
   gp.out.n = n;
   gp.out.m = m;
   gp.h_out_off = off;
@@ -696,7 +731,7 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
     std::vector<int32_t> icol;
     transpose_csr(n, off, col, ioff, icol);
     TG_TRY(upload(A, &gp.in.off, ioff.data(), (size_t)n + 1));
-    TG_TRY(upload(A, &gp.in.col, icol.data(), (size_t)m));
+    TG_TRY(edges(&gp.in.col, icol));
     TG_TRY(upload_off32(A, &gp.in_off32, ioff, m));
     gp.in.n = n;
     gp.in.m = m;
@@ -916,7 +951,7 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld,"
            "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld,\"pr_xcd\":%lld,\"pr_rows\":%lld,"
            "\"bfs_do\":%lld,\"bfs_alpha\":%lld,\"bfs_beta\":%lld,\"sssp_xcd\":%lld,\"bfs_lanes\":%lld,"
-           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld,\"sssp_pull\":%lld,\"sssp_lanes\":%lld,\"bfs_graph\":%lld}",
+           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld,\"sssp_pull\":%lld,\"sssp_lanes\":%lld,\"bfs_graph\":%lld,\"mapped_edges\":%lld}",
            (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
            (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk,
            (long long)p->tune.pr_lds_verts, (long long)p->tune.pr_grid, (long long)p->tune.bfs_lds_words,
@@ -925,7 +960,7 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            (long long)p->tune.pr_rows, (long long)p->tune.bfs_do, (long long)p->tune.bfs_alpha,
            (long long)p->tune.bfs_beta, (long long)p->tune.sssp_xcd, (long long)p->tune.bfs_lanes,
            (long long)p->tune.bfs_td_grid, (long long)p->tune.bfs_bu_grid, (long long)p->tune.sssp_pull,
-           (long long)p->tune.sssp_lanes, (long long)p->tune.bfs_graph);
+           (long long)p->tune.sssp_lanes, (long long)p->tune.bfs_graph, (long long)p->tune.mapped_edges);
   s += buf;
   s += ",\"tuning_source\":\"" + p->tuning_source + "\"";
   s += hybrid_info_json(p);

@@ -93,6 +93,7 @@ struct Tuning {
   int64_t sssp_pull;             // SSSP: pull a superstep whose frontier has more than this % of the edges (0: never)
   int64_t sssp_lanes;            // SSSP: searches in flight on their own streams (1..4)
   int64_t bfs_graph;             // BFS: 1 = chunks of supersteps replayed as captured HIP graphs
+  int64_t mapped_edges;          // partition build: 1 = edge arrays in mapped host memory
 };
 Tuning default_tuning();
 int parse_tuning(const char *json, Tuning *t);
@@ -119,6 +120,16 @@ template <typename T>
 int dalloc(DevArena &a, T **p, size_t count) {
   return a.alloc(reinterpret_cast<void **>(p), count * sizeof(T));
 }
+
+// Pinned host memory mapped into the device's address space (kernels read it
+// over the host link), freed with the owner.
+struct HostMappedArena {
+  std::vector<void *> ptrs;
+  size_t bytes = 0;
+  // *dev: the device address of a new copy of src[0, count)
+  int upload(void **dev, const void *src, size_t bytes);
+  ~HostMappedArena();
+};
 
 // ------------------------------------------------------------ graph object
 }  // namespace tg
@@ -253,6 +264,7 @@ struct GpuPart {
   int64_t n_isolated = 0;        // out-degree 0 and in-degree 0 (ZERO bin of in_bins when symmetric)
   int64_t max_out_hubs = 0;      // vertices in the HUB bin (out-degree)
   int32_t *in_off32 = nullptr;   // in-edge offsets as int32 when m < 2^31 (the bottom-up BFS step), else null
+  bool mapped_edges = false;     // edge arrays (col, w; in-edge col) in mapped host memory (fixed at build)
   std::vector<int64_t> h_out_off;  // host copy of the local out offsets
   std::vector<int64_t> h_deg;      // out-degree of each local id (non-increasing)
   std::vector<int64_t> h_in_deg;   // in-degree of each local id
@@ -343,6 +355,7 @@ struct tg_partition {
   uint64_t tune_gen = 0;  // bumped by every (re)tuning: captured launches depend on it
   std::string tuning_source = "built-in";  // "caller", "built-in" or "cache <key>"
   tg::DevArena arena;
+  tg::HostMappedArena mapped;     // edge arrays kept in host memory (mapped_edges)
   tg::GpuPart gpu;
   tg::Workspace ws;
   // lanes 1.. of the multi-search drivers (BFS, SSSP): a workspace and a

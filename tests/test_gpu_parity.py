@@ -249,6 +249,34 @@ def test_bfs_captured_chunks(gpu, rmat14):
             gpu.pagerank(P, 0.85, 2)
 
 
+def test_mapped_edges(gpu, rmat14):
+    """Edge arrays kept in mapped host memory (read by the kernels over the
+    host link): every algorithm gives the oracle's results on a symmetric and
+    a directed graph, and the per-XCD class layouts (which would copy the
+    edges to the device) stay off even when a retune asks for them."""
+    g, w = rmat14
+    gd = graphgen.rmat(12, symmetrize=False)
+    wd = graphgen.weights(gd, seed=4)
+    for graph, wt in ((g, w), (gd, wd)):
+        P = load(gpu, graph, wt, {"mapped_edges": 1})
+        assert gpu.partition_info(P)["tuning"]["mapped_edges"] == 1
+        roots = [graphgen.max_degree_vertex(graph)] + graphgen.sample_roots(graph, 3, seed=41).tolist()
+        for tuning in (None, {"mapped_edges": 1, "pr_xcd": 1, "sssp_xcd": 1, "sssp_pull": 1}):
+            if tuning:
+                gpu.partition_retune(P, tuning)
+                t = gpu.partition_info(P)["tuning"]
+                assert t["pr_xcd"] == 0 and t["sssp_xcd"] == 0 and t["sssp_pull"] == 0
+            lev = gpu.bfs(P, roots).cpu().numpy()
+            dist = gpu.sssp(P, roots).cpu().numpy()
+            for i, r in enumerate(roots):
+                assert np.array_equal(lev[i], oracle.bfs(graph.offsets, graph.cols, r)), (graph.n, r)
+                assert np.array_equal(dist[i], oracle.sssp(graph.offsets, graph.cols, wt, r)), (graph.n, r)
+            rank = gpu.pagerank(P, 0.85, 10).cpu().numpy()
+            assert pr_rel_l1(rank, oracle.pagerank(graph.offsets, graph.cols, 0.85, 10)) <= 1e-5
+            assert bc_close(gpu.bc(P, roots[:2]).cpu().numpy(), oracle.bc(graph.offsets, graph.cols, roots[:2]))
+            assert np.array_equal(gpu.cc(P).cpu().numpy(), oracle.cc(graph.offsets, graph.cols))
+
+
 DO_VARIANTS = [{"bfs_do": 0},                                   # top-down only
                {"bfs_alpha": 1000000, "bfs_beta": 1000000},     # bottom-up from the second step on
                {"bfs_alpha": 1000000, "bfs_beta": 1},           # alternate bottom-up and top-down
