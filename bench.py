@@ -601,9 +601,12 @@ def bench_hybrid(args):
                      "bfs_exchange_bytes": int(sum(s.get("exchange_bytes", 0) for s in st_b)),
                      "bfs_h2d_bytes": int(sum(s.get("exchange_h2d_bytes", 0) for s in st_b)),
                      "bfs_cpu_edges": int(sum(s.get("cpu_edges", 0) for s in st_b)),
+                     "bfs_supersteps": int(sum(s.get("supersteps", 0) for s in st_b)),
+                     "bfs_host_pulls": int(sum(s.get("host_outbox_pulls", 0) for s in st_b)),
                      "pr_ms_per_iter": round(pr_ms / args.pr_iters, 2),
                      "pr_gteps": round(g.nnz * args.pr_iters / (pr_ms / 1e3) / 1e9, 3),
                      "pr_gpu_ms": round(sp.get("gpu_ms", 0), 2), "pr_cpu_ms": round(sp.get("cpu_ms", 0), 2),
+                     "pr_exchange_ms": round(sp.get("exchange_ms", 0), 2),
                      "pr_exchange_bytes": int(sp.get("exchange_bytes", 0)),
                      "pr_cpu_edges": int(sp.get("cpu_edges", 0))})
         log(f"[hybrid] {rows[-1]}")

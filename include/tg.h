@@ -207,6 +207,12 @@ int pagerank(const tg_partition *p, float damping, int32_t iterations,
  *   sources   host array of num_sources original ids (repeats allowed).
  *   scores    device float [V]: sum over the given sources s of delta_s(v)
  *             for v != s — ordered pairs, not halved, not normalised.
+ * On a hybrid partition both sides run each sweep: the forward sweep sends,
+ * per boundary slot, the sum of sigma over the sender's vertices one level
+ * up (the first time a slot has any); the level and sigma of the vertices
+ * each side's boundary edges reach then cross once; the backward sweep
+ * sends, per level, the deltas of those vertices.  Host deltas are summed
+ * in fp64.
  * Errors: TG_EINVAL, TG_ENOMEM, TG_EDEVICE, TG_ERANGE (a path count reached
  * 2^53, beyond which fp64 counts are no longer exact). */
 int bc(const tg_partition *p, const int32_t *sources, int32_t num_sources,
@@ -308,9 +314,12 @@ int partition_info(const tg_partition *p, char *json, size_t cap);
 
 /* JSON statistics of the last algorithm call on this thread: supersteps,
  * edges scanned or relaxations, and on hybrid partitions per-phase
- * milliseconds (gpu_ms, cpu_ms, exchange_ms), bytes exchanged
- * (exchange_bytes, of which exchange_h2d_bytes host-to-GPU) and the host
- * vertices' out-edges processed (cpu_edges).  Same return convention as
+ * milliseconds (gpu_ms: the GPU's kernels; cpu_ms: the host threads;
+ * exchange_ms: the copies of both directions on their copy streams), bytes
+ * exchanged (exchange_bytes, of which exchange_h2d_bytes host-to-GPU), the
+ * host vertices' out-edges processed (cpu_edges) and the supersteps whose
+ * host outbox was pulled over the slots' source lists rather than pushed
+ * from the frontier (host_outbox_pulls).  Same return convention as
  * partition_info. */
 int tg_last_stats(char *json, size_t cap);
 

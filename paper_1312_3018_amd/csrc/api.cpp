@@ -1098,7 +1098,7 @@ extern "C" int bc(const tg_partition *pc, const int32_t *sources, int32_t num_so
   hipStream_t s = (hipStream_t)stream;
   stats_reset("bc");
   ktimer_reset();
-  if (p->alpha > 0.0) return set_error(TG_EUNSUPPORTED, "bc: hybrid (cpu_edge_share > 0) partitions run bfs, sssp and pagerank only");
+  if (p->alpha > 0.0) return hybrid_bc(p, sources, num_sources, scores, s);
   TG_TRY(p->ws.ensure(p->gpu, 0));
   TG_TRY(fill_f64(p->ws.bc_acc, p->gpu.n, 0.0, s));
   TG_HIP(hipMemsetAsync(p->ws.counters, 0, 64 * sizeof(uint32_t), s));

@@ -1,7 +1,9 @@
 // Generic degree-binned gather-reduce over a queue of rows: for each row v,
 // r(v) = reduce over edges e of v of op.term(vs, e), then op.finish(v, r(v))
-// once, where vs = op.vstate(v) is loaded once per row.  The reduction is
-// op.combine (associative, commutative) with identity op.identity().
+// once, where vs = op.vstate(v) is loaded once per row; a row whose state
+// fails op.live(vs) skips its edges and reduces to the identity.  The
+// reduction is op.combine (associative, commutative) with identity
+// op.identity().
 //
 // Hub rows are split into chunks of `hub_chunk` edges, one block each; a chunk
 // block stores its partial and a second launch (k_gather_hubs, one wave per
@@ -40,6 +42,8 @@ struct SumF64 {
   using T = double;
   __device__ static double identity() { return 0.0; }
   __device__ static double combine(double a, double b) { return a + b; }
+  template <typename V>
+  __device__ static bool live(V) { return true; }
 };
 
 template <class Op>
@@ -55,7 +59,8 @@ __global__ __launch_bounds__(BLOCK) void k_gather(const Plan *__restrict__ Pp, c
     T s = op.identity();
     if (a.ok) {
       const auto vs = op.vstate(a.v);
-      for (int64_t e = a.e_begin + a.lane; e < a.e_end; e += a.stride) s = op.combine(s, op.term(vs, e));
+      if (op.live(vs))
+        for (int64_t e = a.e_begin + a.lane; e < a.e_end; e += a.stride) s = op.combine(s, op.term(vs, e));
     }
     if (a.bin == BIN_HUB) {
       s = block_reduce(s, op);

@@ -19,8 +19,8 @@ one BFS call and one SSSP call, PageRank with uniform dangling mass).
 * The hybrid split at the hybrid workload's shape (directed R-MAT, here at
   scale 22): HIGH at cpu_edge_share 0.1 and 0.5 against the GPU-only
   partition of the same graph, BFS levels and SSSP distances equal element
-  by element and PageRank within 1e-5 relative L1 (one BFS and one SSSP row
-  also whole against the oracle).
+  by element, PageRank within 1e-5 relative L1 and BC of two sources within
+  1e-4 relative (one BFS and one SSSP row also whole against the oracle).
 * Connected components: the whole label vector, bit-exact.
 * Batched Brandes BC on RMAT-20 (section 7.2; the BC workload's graph): 64
   sources in one chain against the oracle within 1e-4 relative, and 1024
@@ -140,6 +140,7 @@ def test_hybrid_rmat22_directed_equals_gpu_only(gpu):
     lev0 = gpu.bfs(P0, roots)
     dist0 = gpu.sssp(P0, roots)
     rank0 = gpu.pagerank(P0, 0.85, 20, "uniform").cpu().numpy().astype(np.float64)
+    bc0 = gpu.bc(P0, roots[:2]).cpu().numpy().astype(np.float64)
     refs = _threads(lambda k: oracle.bfs(g.offsets, g.cols, roots[0]) if k == 0 else
                     oracle.sssp(g.offsets, g.cols, w, roots[0]), [0, 1])
     assert np.array_equal(lev0[0].cpu().numpy(), refs[0])
@@ -150,6 +151,8 @@ def test_hybrid_rmat22_directed_equals_gpu_only(gpu):
         assert torch.equal(gpu.sssp(H, roots), dist0), alpha
         rank = gpu.pagerank(H, 0.85, 20, "uniform").cpu().numpy().astype(np.float64)
         assert np.abs(rank - rank0).sum() / np.abs(rank0).sum() <= 1e-5, alpha
+        bc = gpu.bc(H, roots[:2]).cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(bc - bc0) <= 1e-4 * np.abs(bc0) + 1e-6 * bc0.max()), alpha
         del H
         torch.cuda.synchronize()
 

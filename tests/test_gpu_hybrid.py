@@ -1,7 +1,7 @@
 """Hybrid split (one GPU partition + one host-thread partition exchanging
 reduced boundary messages each superstep) against the oracle: results must
 equal the single-partition definitions exactly (BFS, SSSP) or within the
-PageRank tolerance, for every strategy and CPU edge share."""
+PageRank and BC tolerances, for every strategy and CPU edge share."""
 import numpy as np
 import pytest
 
@@ -16,6 +16,12 @@ SMALL_BINS = {"hub_min_deg": 300, "block_min_deg": 100, "wave_min_deg": 24, "g16
 
 def pr_rel_l1(got, ref):
     return float(np.abs(got.astype(np.float64) - ref).sum() / np.abs(ref).sum())
+
+
+def bc_close(got, ref):
+    got = got.astype(np.float64)
+    tol = 1e-4 * np.abs(ref) + 1e-6 * max(np.abs(ref).max(), 1.0)
+    return np.all(np.abs(got - ref) <= tol)
 
 
 @pytest.fixture(scope="module", params=["sym", "dir"])
@@ -37,6 +43,11 @@ def test_hybrid_matches_oracle(gpu, graph, strategy, alpha):
     roots = [graphgen.max_degree_vertex(g), int(np.argmin(np.where(deg > 0, deg, 1 << 30)))]
     roots += graphgen.sample_roots(g, 2, seed=4).tolist()
     lev = gpu.bfs(P, roots).cpu().numpy()
+    st = gpu.tg_last_stats()
+    # bitmap messages, each slot at most once per search: never more than
+    # one bit per slot and direction per superstep
+    words = (info["outbox_gpu_to_cpu"] + 31) // 32 + (info["outbox_cpu_to_gpu"] + 31) // 32
+    assert st["exchange_bytes"] <= 4 * words * st["supersteps"]
     dist = gpu.sssp(P, roots).cpu().numpy()
     for i, r in enumerate(roots):
         assert np.array_equal(lev[i], oracle.bfs(g.offsets, g.cols, r)), (strategy, alpha, r)
@@ -45,7 +56,12 @@ def test_hybrid_matches_oracle(gpu, graph, strategy, alpha):
         rank = gpu.pagerank(P, 0.85, 10, mode).cpu().numpy()
         assert pr_rel_l1(rank, oracle.pagerank(g.offsets, g.cols, 0.85, 10, mode)) <= 1e-5
     st = gpu.tg_last_stats()
-    assert st["supersteps"] == 10 and st["exchange_bytes"] > 0
+    assert st["supersteps"] == 10
+    # 4-byte messages: every slot both ways, every iteration
+    assert st["exchange_bytes"] == 4 * 10 * (info["outbox_gpu_to_cpu"] + info["outbox_cpu_to_gpu"])
+    # Brandes BC with sigma and delta messages (sources on both sides)
+    got = gpu.bc(P, roots).cpu().numpy()
+    assert bc_close(got, oracle.bc(g.offsets, g.cols, roots)), (strategy, alpha)
 
 
 def test_partition_statistics(gpu):
@@ -68,15 +84,16 @@ def test_hybrid_rejects_unsupported(gpu):
     g = graphgen.rmat(10)
     G = gpu.graph_load_csr(g.n, g.offsets, g.cols, symmetric=True)
     P = gpu.partition_by_degree(G, "high", 0.3)
-    with pytest.raises(gpu.TGError) as ei:
-        gpu.bc(P, [0])
-    assert ei.value.code == gpu.TG_EUNSUPPORTED
+    for call in (lambda: gpu.bc_batched(P, [0]), lambda: gpu.cc(P)):
+        with pytest.raises(gpu.TGError) as ei:
+            call()
+        assert ei.value.code == gpu.TG_EUNSUPPORTED
     with pytest.raises(gpu.TGError):
         gpu.partition_by_degree(G, "high", 0.999999)
 
 
-@pytest.mark.skip(reason="a GPU run that included this test ended in a device fault whose cause was not found; "
-                         "kept off the GPU until one is shown")
+@pytest.mark.skip(reason="a GPU run that included this test (with an outbox variant since removed) ended in a "
+                         "device fault whose cause was not found; kept off the GPU until one is shown")
 @pytest.mark.parametrize("strategy", ["rand", "low"])
 def test_hybrid_deep_search(gpu, strategy):
     """A 48x48 grid plus a directed tail: about a hundred supersteps with
@@ -104,3 +121,26 @@ def test_hybrid_deep_search(gpu, strategy):
         assert np.array_equal(dist[i], oracle.sssp(g.offsets, g.cols, w, r)), (strategy, r)
     inf = np.iinfo(np.int32).max
     assert (lev[0] == inf).sum() == 20 and lev[0][lev[0] < inf].max() >= 90
+
+
+@pytest.mark.parametrize("strategy", ["rand", "high"])
+def test_hybrid_long_path(gpu, strategy):
+    """A path of 1500 vertices with a few chords, split so that the frontier
+    crosses the boundary at most supersteps: hundreds of supersteps with
+    one-vertex frontiers, each side's outbox sending a slot at most once
+    (BFS, BC) or again after every improvement (SSSP)."""
+    n = 1500
+    src = np.concatenate([np.arange(n - 1), [0, 100, 700]])
+    dst = np.concatenate([np.arange(1, n), [50, 400, 1499]])
+    g = graphgen.from_edges(n, src, dst, symmetrize=True)
+    w = graphgen.weights(g, seed=9)
+    G = gpu.graph_load_csr(g.n, g.offsets, g.cols, w, symmetric=True)
+    P = gpu.partition_by_degree(G, strategy, 0.5, seed=3)
+    roots = [0, 777, n - 1]
+    lev = gpu.bfs(P, roots).cpu().numpy()
+    assert gpu.tg_last_stats()["supersteps"] > 300
+    dist = gpu.sssp(P, roots).cpu().numpy()
+    for i, r in enumerate(roots):
+        assert np.array_equal(lev[i], oracle.bfs(g.offsets, g.cols, r)), (strategy, r)
+        assert np.array_equal(dist[i], oracle.sssp(g.offsets, g.cols, w, r)), (strategy, r)
+    assert bc_close(gpu.bc(P, roots[:2]).cpu().numpy(), oracle.bc(g.offsets, g.cols, roots[:2]))
