@@ -270,12 +270,11 @@ int bfs_expand_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int
 
 namespace {
 
-// One device-resident superstep on workspace `ws`: plan and direction
-// (k_plan_bfs), the top-down expansion and the bottom-up step (each exits at
-// once unless the control block selects it), then the compaction of the new
-// frontier.  Nothing here waits for the host.
-int bfs_dev_superstep(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s, bool timed = true) {
-  TG_TRY(frontier_plan_bfs_dev(g, ws, t, s));
+}  // namespace
+
+// The expansion of one device-resident superstep (k_bfs_step in the
+// direction the control block holds), without the plan and the compaction.
+int bfs_dev_step(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s, bool timed) {
   // vertices with in-edges: a symmetric whole graph ends them at its
   // degree-0 tail and has its in-degrees sorted, so its head (HUB and BLOCK
   // bins) gets a wave per vertex; most vertices find a parent among their
@@ -301,8 +300,21 @@ int bfs_dev_superstep(const GpuPart &g, Workspace &ws, const Tuning &t, hipStrea
                        wave_blocks, ooff, stat_counter(ws.work, 4), ws.state, ws.ctl);
   ktimer_stop(tk, s, "bfs_step");
   TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+namespace {
+
+// One device-resident superstep on workspace `ws`: plan and direction
+// (k_plan_bfs), the top-down expansion and the bottom-up step (each exits at
+// once unless the control block selects it), then the compaction of the new
+// frontier.  Nothing here waits for the host.
+int bfs_dev_superstep(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s, bool timed = true) {
+  TG_TRY(frontier_plan_bfs_dev(g, ws, t, s));
+  TG_TRY(bfs_dev_step(g, ws, t, s, timed));
   return frontier_compact_bfs_dev(g, ws, t, s);
 }
+
 
 // Enqueue k supersteps, then the read-back of the control block and `ev`.
 // The k supersteps as one captured graph (captured on first use, replayed

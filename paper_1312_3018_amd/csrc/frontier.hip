@@ -366,7 +366,21 @@ __global__ void k_bfs_ctl_init(BfsCtl *__restrict__ ctl, int64_t m, unsigned lon
     ctl->bottom_up = 0;
     ctl->active = 1;
     ctl->steps = 0;
-    visited[root >> 5] |= 1u << (root & 31);
+    if (root >= 0) visited[root >> 5] |= 1u << (root & 31);
+  }
+}
+
+// Superstep L of a search whose frontier may also grow from outside the
+// partition (the hybrid split): the compaction that follows takes new
+// vertices at level L + 1 even if this partition's own frontier at L was
+// empty (which ended the search in the control block).
+__global__ void k_bfs_ctl_resume(BfsCtl *__restrict__ ctl, int32_t L) {
+  if (threadIdx.x == 0) {
+    if (!ctl->active) {
+      ctl->active = 1;
+      ctl->bottom_up = 0;
+    }
+    ctl->L = L;
   }
 }
 
@@ -394,6 +408,12 @@ int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, 
 int bfs_dev_start(const GpuPart &g, Workspace &ws, int32_t root, hipStream_t s) {
   hipLaunchKernelGGL(k_bfs_ctl_init, dim3(1), dim3(64), 0, s, ws.ctl, g.m, stat_counter(ws.work, 4), ws.bits_a,
                      root);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int bfs_dev_resume(Workspace &ws, int32_t L, hipStream_t s) {
+  hipLaunchKernelGGL(k_bfs_ctl_resume, dim3(1), dim3(64), 0, s, ws.ctl, L);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }

@@ -45,6 +45,24 @@ struct Channel {
   int64_t edges() const { return roff.empty() ? 0 : roff.back(); }
 };
 
+// A channel's reverse CSR on the device with a static degree-binned plan
+// over its slots (slots ordered by decreasing source count), reduced by the
+// generic gather: the GPU reduces the GPU-to-host channel from its own
+// vertex state (push to the host) and the host-to-GPU channel from the host
+// vertex state the host sends (pull, section 4.3.2).
+struct DevChannel {
+  int64_t nslots = 0;
+  int64_t *roff = nullptr;
+  int32_t *rsrc = nullptr, *rw = nullptr, *order = nullptr;
+  int32_t *dst = nullptr;  // slot -> receiver-local id
+  Plan h_plan{};
+  Plan *d_plan = nullptr;
+  int64_t hub_chunk = 0;  // edges per hub chunk of the plan (fixed at build)
+  int64_t *hubpref = nullptr;
+  double *partials_f = nullptr;
+  int64_t *partials_i = nullptr;
+};
+
 // Message buffers of one direction, double-buffered by superstep parity: the
 // sender fills buffer (step & 1) while the receiver may still read the other.
 struct Box {
@@ -57,20 +75,12 @@ struct HybridState {
   CpuPart cpu;
   Channel g2c, c2g;
   int64_t raw_boundary_edges = 0;  // boundary edges before reduction (both directions)
-  // host boundary edges per host source (push from the host frontier):
-  // the host-to-GPU slot of each edge and its weight
+  // host boundary edges per host source: the host-to-GPU slot of each edge
+  // and its weight (the host's part of the BC backward sweep)
   std::vector<int64_t> hb_off;
   std::vector<int32_t> hb_slot, hb_w;
   DevArena arena;
-  // GPU-sent channel: reverse CSR and a static degree-binned plan over slots
-  int64_t *d_roff = nullptr;
-  int32_t *d_rsrc = nullptr, *d_rw = nullptr, *d_slot_order = nullptr;
-  Plan h_splan{};
-  Plan *d_splan = nullptr;
-  int64_t splan_hub_chunk = 0;  // edges per hub chunk of the static slot plan (fixed at build)
-  int64_t *d_shubpref = nullptr;
-  double *d_shub_partials_f = nullptr;
-  int64_t *d_shub_partials_i = nullptr;
+  DevChannel dout, din;  // GPU-to-host and host-to-GPU channels on the device
   // GPU boundary edges per GPU source: the GPU-to-host slot of each edge
   int64_t *d_fb_off = nullptr;
   int32_t *d_fb_slot = nullptr;
@@ -79,7 +89,11 @@ struct HybridState {
   int32_t *d_osent = nullptr;
   int64_t *d_oval = nullptr;
   uint32_t *d_ochg = nullptr;
-  int32_t *d_in_dst = nullptr;  // GPU inbox: GPU-local id per host-to-GPU slot
+  // host vertex state the host sends for the host-to-GPU reduction: a
+  // membership bitmap (frontier, active set), distances, path counts
+  uint32_t *d_hbits = nullptr;
+  int32_t *d_hdist = nullptr;
+  double *d_hsig = nullptr;
   int32_t *d_bdeg = nullptr;    // GPU vertices' boundary out-degree
   double *d_ghost = nullptr;    // PageRank: inbox sums per GPU vertex
   double *d_bdel = nullptr;     // BC: boundary part of delta per GPU vertex

@@ -4,13 +4,12 @@
 // cpu_edge_share of the edges, LOW the lowest-degree ones, RAND a seeded
 // random subset.
 //
-// Message reductions are atomic-free where the sender pulls: every channel
-// keeps, per outbox slot (one distinct remote vertex), the list of local
-// sources (a reverse CSR), and the sender reduces each slot's list with the
-// degree-binned gather.  Where the sender pushes from its frontier (the host
-// in BFS, SSSP and the BC forward sweep; the GPU's delta terms in the BC
-// backward sweep), per-source lists of boundary edges name the slot of each
-// edge.  The supersteps and the exchange are in hybrid_algos.hip.
+// Message reductions are atomic-free: every channel keeps, per slot (one
+// distinct remote vertex), the list of its sources (a reverse CSR), and the
+// degree-binned gather reduces each slot's list on the GPU, for both
+// directions.  Per-source lists of boundary edges name the slot of each
+// edge for the sweeps that push from a frontier (the BC backward sweep).
+// The supersteps and the exchange are in hybrid_algos.hip.
 #include <omp.h>
 #include <stdint.h>
 #include <string.h>
@@ -121,32 +120,28 @@ int check_channel(const Channel &ch, int64_t sender_n, int64_t receiver_n, bool 
   return TG_OK;
 }
 
-int check_hybrid(const tg_partition &p, const std::vector<int32_t> &sorder, const std::vector<int64_t> &sdeg) {
-  const HybridState &h = *p.hy;
-  const CpuPart &C = h.cpu;
-  const int64_t gn = p.gpu.n;
-  TG_TRY(check_channel(h.g2c, gn, C.n, p.g->has_w, "GPU-to-host channel"));
-  TG_TRY(check_channel(h.c2g, C.n, gn, p.g->has_w, "host-to-GPU channel"));
-  const Channel &o = h.g2c;
-  // slot order: a permutation, by non-increasing source count
+// The static plan of a device channel: its slot order is a permutation by
+// non-increasing source count, and a replay of its virtual blocks (the
+// arithmetic of assign_work_rows) covers every source of every slot once.
+int check_plan(const Channel &o, const DevChannel &dc, const std::vector<int32_t> &sorder,
+               const std::vector<int64_t> &sdeg, const char *name) {
   std::vector<char> seen((size_t)o.nslots, 0);
   for (int64_t i = 0; i < o.nslots; ++i) {
     const int32_t sl = sorder[i];
-    if (sl < 0 || sl >= o.nslots || seen[sl]) return set_error(TG_EDEVICE, "hybrid: slot order is not a permutation");
+    if (sl < 0 || sl >= o.nslots || seen[sl]) return set_error(TG_EDEVICE, "hybrid %s: slot order is not a permutation", name);
     seen[sl] = 1;
     if (sdeg[i] != o.roff[sl + 1] - o.roff[sl] || (i > 0 && sdeg[i] > sdeg[i - 1]))
-      return set_error(TG_EDEVICE, "hybrid: slot order is not by source count");
+      return set_error(TG_EDEVICE, "hybrid %s: slot order is not by source count", name);
   }
-  // the static plan and a replay of its virtual blocks
-  const Plan &P = h.h_splan;
+  const Plan &P = dc.h_plan;
   if (P.count != o.nslots || P.pos[0] != 0 || P.pos[NBIN] != o.nslots)
-    return set_error(TG_EDEVICE, "hybrid: slot plan does not cover the slots");
+    return set_error(TG_EDEVICE, "hybrid %s: slot plan does not cover the slots", name);
   for (int b = 0; b < NBIN; ++b)
-    if (P.pos[b + 1] < P.pos[b] || P.vb[b + 1] < P.vb[b]) return set_error(TG_EDEVICE, "hybrid: slot plan not monotone");
-  const int64_t nh = P.pos[1] - P.pos[0], hc = h.splan_hub_chunk;
+    if (P.pos[b + 1] < P.pos[b] || P.vb[b + 1] < P.vb[b]) return set_error(TG_EDEVICE, "hybrid %s: slot plan not monotone", name);
+  const int64_t nh = P.pos[1] - P.pos[0], hc = dc.hub_chunk;
   std::vector<int64_t> hubpref((size_t)nh + 1, 0);
   for (int64_t k = 0; k < nh; ++k) hubpref[k + 1] = hubpref[k] + (sdeg[k] + hc - 1) / hc;
-  if (P.vb[1] != hubpref[nh]) return set_error(TG_EDEVICE, "hybrid: hub chunks of the slot plan");
+  if (P.vb[1] != hubpref[nh]) return set_error(TG_EDEVICE, "hybrid %s: hub chunks of the slot plan", name);
   std::vector<int64_t> covered((size_t)o.nslots, 0);
   for (int64_t vb = 0; vb < P.vb[NBIN]; ++vb) {
     int b = 0;
@@ -154,15 +149,17 @@ int check_hybrid(const tg_partition &p, const std::vector<int32_t> &sorder, cons
     const int64_t local = vb - P.vb[b];
     if (b == BIN_HUB) {
       const int64_t i = std::upper_bound(hubpref.begin(), hubpref.end(), local) - hubpref.begin() - 1;
-      if (i < 0 || i >= nh || local >= hubpref[nh]) return set_error(TG_EDEVICE, "hybrid: hub virtual block %lld", (long long)vb);
+      if (i < 0 || i >= nh || local >= hubpref[nh])
+        return set_error(TG_EDEVICE, "hybrid %s: hub virtual block %lld", name, (long long)vb);
       const int32_t sl = sorder[P.pos[0] + i];
       const int64_t e0 = o.roff[sl] + (local - hubpref[i]) * hc;
       const int64_t e1 = std::min<int64_t>(e0 + hc, o.roff[sl + 1]);
-      if (e0 < o.roff[sl] || e0 >= e1) return set_error(TG_EDEVICE, "hybrid: hub chunk %lld of slot %d", (long long)vb, sl);
+      if (e0 < o.roff[sl] || e0 >= e1)
+        return set_error(TG_EDEVICE, "hybrid %s: hub chunk %lld of slot %d", name, (long long)vb, sl);
       covered[sl] += e1 - e0;
       continue;
     }
-    if (b == BIN_ZERO) return set_error(TG_EDEVICE, "hybrid: a slot in the empty bin");
+    if (b == BIN_ZERO) return set_error(TG_EDEVICE, "hybrid %s: a slot in the empty bin", name);
     for (int t = 0; t < BLOCK; t += lanes_per_vertex(b)) {
       const int64_t qi = P.pos[b] + local * verts_per_vblock(b) + t / lanes_per_vertex(b);
       if (qi >= P.pos[b + 1]) break;
@@ -172,8 +169,17 @@ int check_hybrid(const tg_partition &p, const std::vector<int32_t> &sorder, cons
   }
   for (int64_t sl = 0; sl < o.nslots; ++sl)
     if (covered[sl] != o.roff[sl + 1] - o.roff[sl])
-      return set_error(TG_EDEVICE, "hybrid: slot plan covers %lld of the %lld sources of slot %lld", (long long)covered[sl],
-                       (long long)(o.roff[sl + 1] - o.roff[sl]), (long long)sl);
+      return set_error(TG_EDEVICE, "hybrid %s: slot plan covers %lld of the %lld sources of slot %lld", name,
+                       (long long)covered[sl], (long long)(o.roff[sl + 1] - o.roff[sl]), (long long)sl);
+  return TG_OK;
+}
+
+int check_hybrid(const tg_partition &p) {
+  const HybridState &h = *p.hy;
+  const CpuPart &C = h.cpu;
+  const int64_t gn = p.gpu.n;
+  TG_TRY(check_channel(h.g2c, gn, C.n, p.g->has_w, "GPU-to-host channel"));
+  TG_TRY(check_channel(h.c2g, C.n, gn, p.g->has_w, "host-to-GPU channel"));
   // the host partition's own CSRs and id maps
   if ((int64_t)C.off.size() != C.n + 1 || C.off.back() != C.m || (int64_t)C.g_of_l.size() != C.n)
     return set_error(TG_EDEVICE, "hybrid: host partition CSR");
@@ -206,6 +212,52 @@ int check_boundary_lists(const HybridState &h, const std::vector<int32_t> &fb_sl
                          const std::vector<int64_t> &fb_off, int64_t gn) {
   TG_TRY(check_slot_list(h.hb_off, h.hb_slot, h.cpu.n, h.c2g, "host boundary lists"));
   return check_slot_list(fb_off, fb_slot, gn, h.g2c, "GPU boundary lists");
+}
+
+// A channel on the device: reverse CSR, receiver ids, slots ordered by
+// decreasing source count (the gather's degree bins) and the static plan
+// over them with its hub chunk prefix and partials; checked on the host.
+int upload_channel(DevArena &A, const Channel &o, bool weighted, const Tuning &t, DevChannel &dc, const char *name) {
+  dc.nslots = o.nslots;
+  TG_TRY(up(A, &dc.roff, o.roff.data(), o.roff.size()));
+  TG_TRY(up(A, &dc.rsrc, o.rsrc.data(), std::max<size_t>(o.rsrc.size(), 1)));
+  if (weighted) TG_TRY(up(A, &dc.rw, o.rw.data(), std::max<size_t>(o.rw.size(), 1)));
+  TG_TRY(up(A, &dc.dst, o.dst.data(), std::max<size_t>(o.dst.size(), 1)));
+  std::vector<int32_t> sorder((size_t)o.nslots);
+  for (int64_t i = 0; i < o.nslots; ++i) sorder[i] = (int32_t)i;
+  std::stable_sort(sorder.begin(), sorder.end(), [&](int32_t a, int32_t b) {
+    return o.roff[a + 1] - o.roff[a] > o.roff[b + 1] - o.roff[b];
+  });
+  std::vector<int64_t> sdeg((size_t)o.nslots);
+  for (int64_t i = 0; i < o.nslots; ++i) sdeg[i] = o.roff[sorder[i] + 1] - o.roff[sorder[i]];
+  TG_TRY(up(A, &dc.order, sorder.data(), std::max<size_t>(sorder.size(), 1)));
+  BinBounds bb{};
+  int64_t i = 0;
+  for (int b = 0; b < NBIN; ++b) {
+    while (i < o.nslots && bin_of_degree(sdeg[i], t) < b) ++i;
+    bb.bstart[b] = i;
+  }
+  bb.bstart[NBIN] = o.nslots;
+  Plan &P = dc.h_plan;
+  memset(&P, 0, sizeof(P));
+  P.count = (int32_t)o.nslots;
+  for (int b = 0; b <= NBIN; ++b) P.pos[b] = (int32_t)bb.bstart[b];
+  const int64_t nh = bb.bstart[1];
+  std::vector<int64_t> hubpref((size_t)nh + 1, 0);
+  for (int64_t k = 0; k < nh; ++k) hubpref[k + 1] = hubpref[k] + (sdeg[k] + t.hub_chunk - 1) / t.hub_chunk;
+  int64_t vb = hubpref[nh];
+  P.vb[0] = 0;
+  P.vb[1] = vb;
+  for (int b = 1; b < NBIN; ++b) {
+    if (b != BIN_ZERO) vb += (P.pos[b + 1] - P.pos[b] + verts_per_vblock(b) - 1) / verts_per_vblock(b);
+    P.vb[b + 1] = vb;
+  }
+  dc.hub_chunk = t.hub_chunk;
+  TG_TRY(up(A, &dc.hubpref, hubpref.data(), hubpref.size()));
+  TG_TRY(up(A, &dc.d_plan, &P, 1));
+  TG_TRY(dalloc(A, &dc.partials_f, (size_t)hubpref[nh] + 1));
+  TG_TRY(dalloc(A, &dc.partials_i, (size_t)hubpref[nh] + 1));
+  return check_plan(o, dc, sorder, sdeg, name);
 }
 
 }  // namespace
@@ -331,58 +383,21 @@ int build_hybrid(tg_partition *p, uint64_t seed) {
   }
   C.l_of_g = std::move(c_l_of_g);
 
+  TG_TRY(check_hybrid(*p));
   // device side
   GpuPart &g = p->gpu;
   DevArena &A = hy->arena;
-  Channel &o = hy->g2c;
-  TG_TRY(up(A, &hy->d_roff, o.roff.data(), o.roff.size()));
-  TG_TRY(up(A, &hy->d_rsrc, o.rsrc.data(), std::max<size_t>(o.rsrc.size(), 1)));
-  if (G.has_w) TG_TRY(up(A, &hy->d_rw, o.rw.data(), std::max<size_t>(o.rw.size(), 1)));
-  // slots ordered by decreasing source count: the gather's degree bins
-  std::vector<int32_t> sorder((size_t)o.nslots);
-  for (int64_t i = 0; i < o.nslots; ++i) sorder[i] = (int32_t)i;
-  std::stable_sort(sorder.begin(), sorder.end(), [&](int32_t a, int32_t b) {
-    return o.roff[a + 1] - o.roff[a] > o.roff[b + 1] - o.roff[b];
-  });
-  std::vector<int64_t> sdeg((size_t)o.nslots);
-  for (int64_t i = 0; i < o.nslots; ++i) sdeg[i] = o.roff[sorder[i] + 1] - o.roff[sorder[i]];
-  TG_TRY(up(A, &hy->d_slot_order, sorder.data(), std::max<size_t>(sorder.size(), 1)));
-  {
-    // static plan over the slots (same bins as the vertex kernels)
-    BinBounds bb{};
-    int64_t i = 0;
-    for (int b = 0; b < NBIN; ++b) {
-      while (i < o.nslots && bin_of_degree(sdeg[i], p->tune) < b) ++i;
-      bb.bstart[b] = i;
-    }
-    bb.bstart[NBIN] = o.nslots;
-    Plan &P = hy->h_splan;
-    memset(&P, 0, sizeof(P));
-    P.count = (int32_t)o.nslots;
-    for (int b = 0; b <= NBIN; ++b) P.pos[b] = (int32_t)bb.bstart[b];
-    const int64_t nh = bb.bstart[1];
-    std::vector<int64_t> hubpref((size_t)nh + 1, 0);
-    for (int64_t k = 0; k < nh; ++k) hubpref[k + 1] = hubpref[k] + (sdeg[k] + p->tune.hub_chunk - 1) / p->tune.hub_chunk;
-    int64_t vb = hubpref[nh];
-    P.vb[0] = 0;
-    P.vb[1] = vb;
-    for (int b = 1; b < NBIN; ++b) {
-      if (b != BIN_ZERO) vb += (P.pos[b + 1] - P.pos[b] + verts_per_vblock(b) - 1) / verts_per_vblock(b);
-      P.vb[b + 1] = vb;
-    }
-    hy->splan_hub_chunk = p->tune.hub_chunk;
-    TG_TRY(up(A, &hy->d_shubpref, hubpref.data(), hubpref.size()));
-    TG_TRY(up(A, &hy->d_splan, &P, 1));
-    TG_TRY(dalloc(A, &hy->d_shub_partials_f, (size_t)hubpref[nh] + 1));
-    TG_TRY(dalloc(A, &hy->d_shub_partials_i, (size_t)hubpref[nh] + 1));
-  }
-  const size_t no = (size_t)std::max<int64_t>(o.nslots, 1);
+  TG_TRY(upload_channel(A, hy->g2c, G.has_w, p->tune, hy->dout, "GPU-to-host channel"));
+  TG_TRY(upload_channel(A, hy->c2g, G.has_w, p->tune, hy->din, "host-to-GPU channel"));
+  const size_t no = (size_t)std::max<int64_t>(hy->g2c.nslots, 1), nc = (size_t)std::max<int64_t>(C.n, 1);
   TG_TRY(up(A, &hy->d_fb_off, gb.src_off.data(), gb.src_off.size()));
   TG_TRY(up(A, &hy->d_fb_slot, fb_slot.data(), std::max<size_t>(fb_slot.size(), 1)));
   TG_TRY(dalloc(A, &hy->d_osent, no));
   TG_TRY(dalloc(A, &hy->d_oval, no));
   TG_TRY(dalloc(A, &hy->d_ochg, (no + 31) / 32));
-  TG_TRY(up(A, &hy->d_in_dst, hy->c2g.dst.data(), std::max<size_t>(hy->c2g.dst.size(), 1)));
+  TG_TRY(dalloc(A, &hy->d_hbits, (nc + 31) / 32));
+  TG_TRY(dalloc(A, &hy->d_hdist, nc));
+  TG_TRY(dalloc(A, &hy->d_hsig, nc));
   std::vector<int32_t> gb_deg((size_t)g.n);
   for (int64_t i = 0; i < g.n; ++i) gb_deg[i] = (int32_t)(gb.src_off[i + 1] - gb.src_off[i]);
   TG_TRY(up(A, &hy->d_bdeg, gb_deg.data(), std::max<size_t>(gb_deg.size(), 1)));
@@ -407,7 +422,6 @@ int build_hybrid(tg_partition *p, uint64_t seed) {
   TG_HIP(hipEventCreateWithFlags(&hy->ev_step, hipEventDisableTiming));
   // the uploads above ran on the null stream; the copy streams do not wait for it
   TG_HIP(hipDeviceSynchronize());
-  TG_TRY(check_hybrid(*p, sorder, sdeg));
   return check_boundary_lists(*hy, fb_slot, gb.src_off, g.n);
 }
 

@@ -3,24 +3,27 @@
 // into one value at the source (section 3.4), the messages cross PCIe and
 // each receiver folds its inbox into its vertex state.
 //
-// Exchange.  Messages are 4 bytes per slot (a PageRank sum, an SSSP
-// distance, a BC delta) or one bit (BFS); the BC forward sweep's path counts
-// are 8.  Only the message arrays travel (the slot order is fixed at
-// partition time, section 4.3.2), on two copy streams of their own, one per
-// direction, into buffers double-buffered by superstep parity and ordered by
-// events (section 4.3.4 (iv)).  Where a superstep sends to few slots (the
-// traversals), only the slots whose value changed are sent (the compression
-// that section 4.4 points to): BFS sends a bitmap of the slots reached for
-// the first time; SSSP and BC send (slot, value) lists of the slots whose
-// value improved.  PageRank sends every slot every iteration, and the host's
-// gather runs while the GPU's step runs, so an iteration takes the longer of
-// the two plus the exchange.
+// Reductions.  The GPU reduces both channels, over their reverse CSRs on
+// the device (atomic-free and deterministic, the degree-binned gather): the
+// GPU-to-host channel from its own vertex state (the sender reduces,
+// section 3.4), the host-to-GPU channel from the state of the host's
+// boundary sources, which the host sends (the receiver pulls its remote
+// in-neighbours' state, section 4.3.2).  The host threads only expand their
+// own frontier over local edges and apply the GPU's messages; the boundary
+// edges, nearly all of them hub edges under HIGH, are scanned on the GPU.
 //
-// Reductions.  The GPU reduces its outbox by pulling over the channel's
-// reverse CSR (atomic-free, deterministic).  The host pushes from its
-// frontier over its per-source boundary lists when the frontier is small,
-// and pulls over the reverse CSR otherwise (BFS; the pull stops at the first
-// source found on the frontier).
+// Exchange.  The GPU sends one bit per slot (BFS: reached for the first
+// time), or (slot, value) lists of the slots whose value improved (SSSP: a
+// 4-byte distance; BC: an 8-byte path count, a 4-byte delta), or 4 bytes
+// per slot (PageRank).  The host sends its frontier as a bitmap (BFS), its
+// active set or frontier with values (SSSP, BC), or one 4-byte contribution
+// per vertex (PageRank).  Copies run on two copy streams of their own, one
+// per direction, into buffers double-buffered by superstep parity and
+// ordered by events (section 4.3.4 (iv)); sending only what changed is the
+// compression that section 4.4 points to.  The host's part of a superstep
+// is sent before it computes, so the GPU's reduction never waits for the
+// host's expansion, and PageRank's host gather runs beside the GPU step.
+
 #include <omp.h>
 #include <stdint.h>
 #include <string.h>
@@ -45,10 +48,11 @@ constexpr int32_t OVF_MSG = -1;          // SSSP message: a candidate distance >
 constexpr size_t LIST_HDR = 16;          // list header: the entry count (uint32)
 constexpr int64_t LIST_PREFIX = 16384;   // entries copied with the header
 
-// One entry of a (slot, value) list.
+// One entry of an (id, value) list: a slot of the GPU-to-host channel, or a
+// host vertex whose state the host sends.
 template <typename T>
 struct Msg {
-  int32_t slot;
+  int32_t id;
   T val;
 };
 
@@ -291,76 +295,127 @@ __global__ __launch_bounds__(BLOCK) void k_select(Sel sel, int64_t n, char *box)
   }
 }
 
-// Sets bit v of the bitmap for every lane with `on`.  Lanes with ascending
-// ids hit the same 32-bit word in runs; each run ORs its bits together with
-// shuffles and only its first lane issues the atomic.  Every lane of the
-// wave must call it.
-__device__ __forceinline__ void wave_or_bits(uint32_t *bits, int32_t v, bool on) {
-  if (!__ballot(on)) return;  // the same for the whole wave
-  const int lane = threadIdx.x & 63;
-  const int32_t w = on ? (v >> 5) : -1;
-  uint32_t b = on ? (1u << (v & 31)) : 0u;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int32_t ow = __shfl_down(w, o, 64);
-    const uint32_t ob = __shfl_down(b, o, 64);
-    if (lane + o < 64 && ow == w) b |= ob;
+// Host-to-GPU reductions over the device copy of that channel, from the
+// host vertex state the host sent (its frontier, active set, distances,
+// contributions, path counts): the GPU pulls its remote in-neighbours'
+// state (section 4.3.2) and folds the result straight into its own.
+
+// BFS: an unvisited GPU vertex is reached, at level `lv`, if a host
+// in-neighbour is on the host frontier (skipped once visited: the bottom-up
+// test over remote in-edges).
+struct BfsIn {
+  using T = int32_t;
+  const int32_t *rsrc;
+  const uint32_t *hfront;
+  const int32_t *dst;
+  uint32_t *visited;
+  int32_t *level;
+  int32_t lv;
+  __device__ static int32_t identity() { return 0; }
+  __device__ static int32_t combine(int32_t a, int32_t b) { return a | b; }
+  __device__ int32_t vstate(int32_t slot) const {
+    const int32_t v = dst[slot];
+    return (int32_t)((visited[v >> 5] >> (v & 31)) & 1u);
   }
-  const int32_t pw = __shfl_up(w, 1, 64);
-  if (on && (lane == 0 || pw != w)) atomicOr(bits + w, b);
-}
+  __device__ static bool live(int32_t was_visited) { return was_visited == 0; }
+  __device__ int32_t term(int32_t, int64_t e) const {
+    const int32_t u = rsrc[e];
+    return (int32_t)((hfront[u >> 5] >> (u & 31)) & 1u);
+  }
+  __device__ void finish(int32_t slot, int32_t r) const {
+    if (!r) return;
+    const int32_t v = dst[slot];
+    atomicOr(visited + (v >> 5), 1u << (v & 31));
+    level[v] = lv;
+  }
+};
 
-// Inboxes.  BFS: every set bit k marks GPU vertex dst[k] visited (inbox ids
-// ascend with k, so a wave's bits come in runs on a few words).
-__global__ __launch_bounds__(BLOCK) void k_inbox_bits(const int32_t *__restrict__ dst,
-                                                      const uint32_t *__restrict__ bits, int64_t n,
-                                                      uint32_t *visited) {
-  const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const bool on = k < n && ((bits[k >> 5] >> (k & 31)) & 1u);
-  wave_or_bits(visited, on ? dst[k] : 0, on);
-}
-
-// SSSP: slots are distinct within a list, so no two entries write one vertex.
-__global__ __launch_bounds__(BLOCK) void k_inbox_sssp(const int32_t *__restrict__ dst,
-                                                      const Msg<int32_t> *__restrict__ ent, int64_t n, int32_t *dist,
-                                                      uint32_t *active, uint32_t *ovf, uint32_t *flags) {
-  const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (k >= n) return;
-  const Msg<int32_t> m = ent[k];
-  const int32_t v = dst[m.slot];
-  if (m.val == OVF_MSG) {
-    if (dist[v] == TG_INF) {
-      atomicOr(ovf + (v >> 5), 1u << (v & 31));
-      flags[0] = 1u;
+// SSSP: least hdist(u) + w over the host in-neighbours active this
+// superstep; a GPU vertex that improves joins the active set.  Slots are
+// distinct vertices, so no two finishers write one distance.
+struct SsspIn {
+  using T = int64_t;
+  const int32_t *rsrc;
+  const int32_t *rw;
+  const int32_t *hdist;
+  const uint32_t *hact;
+  const int32_t *dst;
+  int32_t *dist;
+  uint32_t *active, *ovf, *flags;
+  __device__ static int64_t identity() { return I64_INF; }
+  __device__ static int64_t combine(int64_t a, int64_t b) { return a < b ? a : b; }
+  __device__ int32_t vstate(int32_t) const { return 0; }
+  __device__ static bool live(int32_t) { return true; }
+  __device__ int64_t term(int32_t, int64_t e) const {
+    const int32_t u = rsrc[e];
+    return ((hact[u >> 5] >> (u & 31)) & 1u) ? (int64_t)hdist[u] + (int64_t)rw[e] : I64_INF;
+  }
+  __device__ void finish(int32_t slot, int64_t r) const {
+    if (r == I64_INF) return;
+    const int32_t v = dst[slot];
+    if (r >= (int64_t)TG_INF) {
+      if (dist[v] == TG_INF) {
+        atomicOr(ovf + (v >> 5), 1u << (v & 31));
+        flags[0] = 1u;
+      }
+    } else if (r < (int64_t)dist[v]) {
+      dist[v] = (int32_t)r;
+      atomicOr(active + (v >> 5), 1u << (v & 31));
     }
-  } else if (m.val < dist[v]) {
-    dist[v] = m.val;
-    atomicOr(active + (v >> 5), 1u << (v & 31));
   }
-}
+};
 
-__global__ void k_inbox_pr(const int32_t *__restrict__ dst, const float *__restrict__ msg, int64_t n,
-                           double *ghost) {
-  const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (k < n) ghost[dst[k]] = (double)msg[k];
-}
+// PageRank: ghost(v) = sum of the host in-neighbours' contributions.
+struct PrIn : SumF64 {
+  const int32_t *rsrc;
+  const float *hc;
+  const int32_t *dst;
+  double *ghost;
+  __device__ int32_t vstate(int32_t) const { return 0; }
+  __device__ double term(int32_t, int64_t e) const { return (double)hc[rsrc[e]]; }
+  __device__ void finish(int32_t slot, double r) const { ghost[dst[slot]] = r; }
+};
 
-// BC forward: a vertex not yet placed (level unset) is reached at the next
-// level; its sigma starts from the message.
-__global__ void k_inbox_sigma(const int32_t *__restrict__ dst, const Msg<double> *__restrict__ ent, int64_t n,
-                              const int32_t *__restrict__ level, double *sigma, uint32_t *visited) {
+// BC forward: a GPU vertex not yet placed (level unset) takes the sum of
+// sigma over its host in-neighbours on frontier L and is reached at L + 1.
+struct SigmaIn : SumF64 {
+  const int32_t *rsrc;
+  const uint32_t *hfront;
+  const double *hsig;
+  const int32_t *dst;
+  const int32_t *level;
+  double *sigma;
+  uint32_t *visited;
+  __device__ int32_t vstate(int32_t slot) const { return level[dst[slot]]; }
+  __device__ static bool live(int32_t lv) { return lv == TG_INF; }
+  __device__ double term(int32_t, int64_t e) const {
+    const int32_t u = rsrc[e];
+    return ((hfront[u >> 5] >> (u & 31)) & 1u) ? hsig[u] : 0.0;
+  }
+  __device__ void finish(int32_t slot, double r) const {
+    if (r == 0.0) return;
+    const int32_t v = dst[slot];
+    if (level[v] != TG_INF) return;
+    sigma[v] = r;
+    atomicOr(visited + (v >> 5), 1u << (v & 31));
+  }
+};
+
+// The host's (vertex, value) list into the dense host-state arrays and the
+// membership bitmap (cleared before; ids are distinct).
+template <typename T>
+__global__ void k_host_state(const Msg<T> *__restrict__ ent, int64_t n, T *val, uint32_t *bits) {
   const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (k >= n) return;
-  const Msg<double> m = ent[k];
-  const int32_t v = dst[m.slot];
-  if (level[v] != TG_INF) return;
-  sigma[v] = m.val;
-  atomicOr(visited + (v >> 5), 1u << (v & 31));
+  const Msg<T> m = ent[k];
+  val[m.id] = m.val;
+  atomicOr(bits + (m.id >> 5), 1u << (m.id & 31));
 }
 
+// BC backward: deltas of host vertices (by GPU-to-host slot).
 __global__ void k_inbox_delta(const Msg<float> *__restrict__ ent, int64_t n, float *gh_del) {
   const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (k < n) gh_del[ent[k].slot] = ent[k].val;
+  if (k < n) gh_del[ent[k].id] = ent[k].val;
 }
 
 // BC: level and sigma of the GPU's host-to-GPU receivers, for the host.
@@ -396,17 +451,16 @@ __global__ void k_set_f64h(double *p, int64_t i, double v) {
 inline unsigned nblk(int64_t n) { return (unsigned)std::max<int64_t>((n + BLOCK - 1) / BLOCK, 1); }
 inline unsigned select_grid(int64_t n) { return (unsigned)std::min<int64_t>(nblk(n), 8192); }
 
-// The slot plan, its hub chunk prefix and the partials buffer were sized at
-// partition time with splan_hub_chunk; a later retune must not change the
-// chunking they were built for.
+// Reduces a device channel's slots with `op`.  The slot plan, its hub chunk
+// prefix and the partials were sized at partition time with dc.hub_chunk; a
+// later retune does not change the chunking they were built for.
 template <class Op>
-int launch_outbox(HybridState &h, hipStream_t s, Op op, typename Op::T *partials) {
-  if (h.g2c.nslots == 0) return TG_OK;
-  hipLaunchKernelGGL(k_gather<Op>, dim3(launch_grid(h.h_splan.vb[NBIN])), dim3(BLOCK), 0, s, h.d_splan,
-                     h.d_slot_order, h.d_shubpref, h.d_roff, h.splan_hub_chunk, partials, op);
-  if (h.h_splan.pos[1] > h.h_splan.pos[0])
-    hipLaunchKernelGGL(k_gather_hubs<Op>, dim3(64), dim3(BLOCK), 0, s, h.d_splan, h.d_slot_order, h.d_shubpref,
-                       partials, op);
+int launch_gather(const DevChannel &dc, hipStream_t s, Op op, typename Op::T *partials) {
+  if (dc.nslots == 0) return TG_OK;
+  hipLaunchKernelGGL(k_gather<Op>, dim3(launch_grid(dc.h_plan.vb[NBIN])), dim3(BLOCK), 0, s, dc.d_plan, dc.order,
+                     dc.hubpref, dc.roff, dc.hub_chunk, partials, op);
+  if (dc.h_plan.pos[1] > dc.h_plan.pos[0])
+    hipLaunchKernelGGL(k_gather_hubs<Op>, dim3(64), dim3(BLOCK), 0, s, dc.d_plan, dc.order, dc.hubpref, partials, op);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
@@ -500,21 +554,6 @@ inline bool atomic_min_i32(int32_t *p, int32_t v) {
     if (__atomic_compare_exchange_n(p, &cur, v, true, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) return true;
   return false;
 }
-// fp64 add by compare-and-swap on the bits (the sums here are integers
-// below 2^53, exact in any order)
-inline void atomic_add_f64(double *p, double v) {
-  uint64_t *q = reinterpret_cast<uint64_t *>(p);
-  uint64_t cur = __atomic_load_n(q, __ATOMIC_RELAXED);
-  for (;;) {
-    double d;
-    memcpy(&d, &cur, sizeof d);
-    d += v;
-    uint64_t nxt;
-    memcpy(&nxt, &d, sizeof d);
-    if (__atomic_compare_exchange_n(q, &cur, nxt, true, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) return;
-  }
-}
-
 void concat(std::vector<std::vector<int32_t>> &parts, std::vector<int32_t> &out) {
   out.clear();
   for (auto &v : parts) {
@@ -592,14 +631,14 @@ int stage_host_f32(HybridState &h, const std::vector<float> &vals, float *out, h
 }  // namespace
 
 // ------------------------------------------------------------------- BFS
-// Messages are bitmaps over the slots: bit k set when slot k's receiver is
-// reached for the first time through this channel.  Each side remembers the
-// slots it has sent (a receiver's level is final when first reached), so a
-// search sends each slot at most once.  The host's outbox pushes from the
-// frontier's boundary lists while that frontier's boundary edges are fewer
-// than half of the edges of the slots not yet sent, and otherwise pulls over
-// the unsent slots' source lists, stopping at the first source found on the
-// frontier.
+// The GPU side runs the device-resident superstep of the GPU-only path
+// (top-down or bottom-up over local edges, Beamer's switch on the device);
+// the host reads the frontier size back every superstep.  GPU to host: a
+// bitmap over the GPU-to-host slots, bit k set when slot k's host vertex is
+// reached for the first time through the channel (each slot at most once
+// per search: a receiver's level is final when first reached).  Host to
+// GPU: the host frontier as a bitmap over host vertices, sent at the start
+// of the superstep; the GPU reduces the host-to-GPU channel itself.
 int hybrid_bfs(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *levels, int32_t *parents,
                hipStream_t s) {
   if (parents) return set_error(TG_EUNSUPPORTED, "bfs: parents are not produced on hybrid partitions");
@@ -610,12 +649,11 @@ int hybrid_bfs(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *level
   const Tuning &t = p->tune;
   TG_TRY(ws.ensure(g, 0));
   const int64_t V = p->g->n;
-  const int64_t no = h.g2c.nslots, ni = h.c2g.nslots;
-  const int64_t nwo = (no + 31) / 32, nwi = (ni + 31) / 32;
-  TG_TRY(hybrid_boxes(h, (size_t)nwo * 4, (size_t)nwi * 4));
+  const int64_t no = h.g2c.nslots;
+  const int64_t nwo = (no + 31) / 32, nwc = (C.n + 31) / 32;
+  TG_TRY(hybrid_boxes(h, (size_t)nwo * 4, (size_t)nwc * 4));
   std::vector<uint8_t> cvis((size_t)C.n);
   std::vector<int32_t> clev((size_t)C.n);
-  std::vector<uint32_t> hsent((size_t)nwi);
   std::vector<int32_t> cfront, cnext;
   std::vector<std::vector<int32_t>> tl((size_t)omp_get_max_threads());
   Phase ph;
@@ -624,53 +662,64 @@ int hybrid_bfs(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *level
   for (int32_t r = 0; r < nr; ++r) {
     const int32_t root = roots[r];
     const int32_t gl = p->h_l_of_g[root];
-    uint32_t *visited = ws.bits_a, *prev = ws.bits_b;
+    uint32_t *visited = ws.bits_a;
     TG_HIP(hipMemsetAsync(visited, 0, ws.nwords * sizeof(uint32_t), s));
-    TG_HIP(hipMemsetAsync(prev, 0, ws.nwords * sizeof(uint32_t), s));
+    TG_HIP(hipMemsetAsync(ws.bits_b, 0, ws.nwords * sizeof(uint32_t), s));
     TG_TRY(fill_i32(ws.state, g.n, TG_INF, s));
     if (no) TG_TRY(fill_i32(h.d_osent, no, 0, s));
     std::fill(cvis.begin(), cvis.end(), 0);
     std::fill(clev.begin(), clev.end(), TG_INF);
-    std::fill(hsent.begin(), hsent.end(), 0u);
-    int64_t unsent_edges = h.c2g.edges();
     cfront.clear();
-    if (gl >= 0) {
-      TG_TRY(set_bit(visited, gl, s));
-    } else {
+    if (gl < 0) {
       const int32_t cl = C.l_of_g[root];
       if (cl < 0) return set_error(TG_EDEVICE, "hybrid bfs: root %d is on neither side", root);
       cvis[cl] = 1;
       clev[cl] = 0;
       cfront.push_back(cl);
     }
-    TG_TRY(frontier_compact(g, ws, 0, visited, prev, ws.queue, ws.state, 0, s));
-    TG_TRY(frontier_plan(g, ws, ws.queue, t, s, true));
+    TG_TRY(bfs_dev_start(g, ws, gl, s));  // gl < 0: no GPU root
+    TG_TRY(frontier_compact_bfs_dev(g, ws, t, s));
+    TG_HIP(hipMemcpyAsync(ws.h_plan, ws.plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
+    TG_HIP(hipStreamSynchronize(s));
     for (int32_t L = 0;; ++L) {
-      const bool gpu_front = ws.h_plan->count > 0;
-      if (!gpu_front && cfront.empty()) break;
+      const bool gpu_front = ws.h_plan->count > 0, host_front = !cfront.empty();
+      if (!gpu_front && !host_front) break;
       if (L > V) return set_error(TG_EDEVICE, "hybrid bfs: more supersteps than vertices");
       ++ph.supersteps;
       const int b = L & 1;
-      // GPU: expand the local frontier, reduce the outbox, start its copy
+      TG_HIP(hipEventRecord(ev.e[0], s));
+      // GPU: direction and plan, the expansion, the GPU-to-host reduction
+      TG_TRY(frontier_plan_bfs_dev(g, ws, t, s));
       if (gpu_front) {
-        TG_HIP(hipEventRecord(ev.e[0], s));
         TG_TRY(clear_words(reinterpret_cast<uint32_t *>(h.out.d[b]), nwo, s));
-        TG_TRY(bfs_expand_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], t, s));
-        TG_TRY(launch_outbox(h, s, BfsOut{h.d_rsrc, ws.state, L, h.d_osent, reinterpret_cast<uint32_t *>(h.out.d[b])},
-                             reinterpret_cast<int32_t *>(h.d_shub_partials_i)));
-        TG_HIP(hipEventRecord(ev.e[1], s));
+        TG_TRY(bfs_dev_step(g, ws, t, s, true));
+        TG_TRY(launch_gather(h.dout, s,
+                             BfsOut{h.dout.rsrc, ws.state, L, h.d_osent, reinterpret_cast<uint32_t *>(h.out.d[b])},
+                             reinterpret_cast<int32_t *>(h.dout.partials_i)));
         TG_TRY(post_d2h(h, b, (size_t)nwo * 4, s));
       }
-      // host: expand its frontier and reduce its outbox while the GPU runs
+      // the host frontier to the GPU, which reduces the host-to-GPU channel
+      if (host_front) {
+        const auto tc = clk::now();
+        uint32_t *hb = reinterpret_cast<uint32_t *>(h.in.h[b]);
+        memset(hb, 0, (size_t)nwc * 4);
+        for (int32_t v : cfront) hb[v >> 5] |= 1u << (v & 31);
+        ph.cpu_ms += ms_since(tc);
+        TG_TRY(post_h2d(h, b, 0, (size_t)nwc * 4, s));
+        TG_TRY(launch_gather(h.din, s,
+                             BfsIn{h.din.rsrc, reinterpret_cast<const uint32_t *>(h.in.d[b]), h.din.dst, visited,
+                                   ws.state, L + 1},
+                             reinterpret_cast<int32_t *>(h.din.partials_i)));
+        ph.bytes += (double)nwc * 4;
+        ph.h2d_bytes += (double)nwc * 4;
+      }
+      TG_TRY(bfs_dev_resume(ws, L, s));
+      TG_TRY(frontier_compact_bfs_dev(g, ws, t, s));
+      TG_HIP(hipEventRecord(ev.e[1], s));
+      TG_HIP(hipMemcpyAsync(ws.h_plan, ws.plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
+      // host: expand its frontier over its local edges while the GPU runs
       const auto tc = clk::now();
-      uint32_t *ib = reinterpret_cast<uint32_t *>(h.in.h[b]);
-      int64_t nsent = 0, sent_edges = 0;
-      double fb = 0;
-      for (int32_t v : cfront) fb += (double)C.bdeg[v];
-      const bool pull = !cfront.empty() && fb * 2 >= (double)unsent_edges;
-      ph.host_pulls += pull ? 1 : 0;
-      if (!cfront.empty()) memset(ib, 0, (size_t)nwi * 4);
-#pragma omp parallel reduction(+ : nsent, sent_edges)
+#pragma omp parallel
       {
         auto &mine = tl[omp_get_thread_num()];
 #pragma omp for schedule(dynamic, 64)
@@ -684,62 +733,15 @@ int hybrid_bfs(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *level
             }
           }
         }
-        if (pull) {
-#pragma omp for schedule(dynamic, 64)
-          for (int64_t w = 0; w < nwi; ++w) {
-            uint32_t todo = ~hsent[w];
-            if (w == nwi - 1 && (ni & 31)) todo &= (1u << (ni & 31)) - 1u;
-            uint32_t got = 0;
-            while (todo) {
-              const int j = __builtin_ctz(todo);
-              todo &= todo - 1u;
-              const int64_t k = w * 32 + j;
-              for (int64_t e = h.c2g.roff[k]; e < h.c2g.roff[k + 1]; ++e)
-                if (clev[h.c2g.rsrc[e]] == L) {
-                  got |= 1u << j;
-                  sent_edges += h.c2g.roff[k + 1] - h.c2g.roff[k];
-                  break;
-                }
-            }
-            ib[w] = got;
-            hsent[w] |= got;
-            nsent += __builtin_popcount(got);
-          }
-        } else {
-#pragma omp for schedule(dynamic, 64)
-          for (size_t i = 0; i < cfront.size(); ++i) {
-            const int32_t v = cfront[i];
-            for (int64_t e = h.hb_off[v]; e < h.hb_off[v + 1]; ++e) {
-              const int32_t k = h.hb_slot[e];
-              const uint32_t bit = 1u << (k & 31);
-              if (__atomic_load_n(&hsent[k >> 5], __ATOMIC_RELAXED) & bit) continue;
-              if (__atomic_fetch_or(&hsent[k >> 5], bit, __ATOMIC_RELAXED) & bit) continue;
-              __atomic_fetch_or(&ib[k >> 5], bit, __ATOMIC_RELAXED);
-              ++nsent;
-              sent_edges += h.c2g.roff[k + 1] - h.c2g.roff[k];
-            }
-          }
-        }
       }
       concat(tl, cnext);
-      unsent_edges -= sent_edges;
       ph.cpu_ms += ms_since(tc);
       ph.cpu_edges += frontier_edges(C, cfront);
-      // exchange: the host's bits to the GPU inbox; fold them in and compact
-      if (nsent) {
-        TG_TRY(post_h2d(h, b, 0, (size_t)nwi * 4, s));
-        hipLaunchKernelGGL(k_inbox_bits, dim3(nblk(ni)), dim3(BLOCK), 0, s, h.d_in_dst,
-                           reinterpret_cast<const uint32_t *>(h.in.d[b]), ni, visited);
-        TG_HIP(hipGetLastError());
-        ph.bytes += (double)nwi * 4;
-        ph.h2d_bytes += (double)nwi * 4;
-      }
-      TG_TRY(frontier_compact(g, ws, 0, visited, prev, ws.queue, ws.state, L + 1, s));
-      TG_TRY(frontier_plan(g, ws, ws.queue, t, s, true));  // waits for the GPU stream
-      if (nsent) ph.exchange_ms += h2d_ms(h, b);
+      TG_HIP(hipStreamSynchronize(s));  // the GPU's next frontier size is on the host
+      ph.gpu_ms += elapsed(ev.e[0], ev.e[1]);
+      if (host_front) ph.exchange_ms += h2d_ms(h, b);
       // the GPU's bits: its frontier's first reach of host vertices
       if (gpu_front) {
-        ph.gpu_ms += elapsed(ev.e[0], ev.e[1]);
         TG_TRY(wait_d2h(h, b, &ph.exchange_ms));
         ph.bytes += (double)nwo * 4;
         const auto tc2 = clk::now();
@@ -768,9 +770,10 @@ int hybrid_bfs(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *level
 }
 
 // ------------------------------------------------------------------ SSSP
-// Messages are (slot, distance) lists of the slots whose candidate improved
-// on the last value sent.  The host pushes its frontier's boundary edges
-// into per-slot minima.
+// GPU to host: (slot, distance) lists of the slots whose candidate improved
+// on the last value sent.  Host to GPU: (vertex, distance) of the host's
+// active set, sent at the start of the superstep; the GPU reduces the
+// host-to-GPU channel over it.
 int hybrid_sssp(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *dist_out, hipStream_t s) {
   HybridState &h = *p->hy;
   GpuPart &g = p->gpu;
@@ -779,13 +782,13 @@ int hybrid_sssp(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *dist
   const Tuning &t = p->tune;
   TG_TRY(ws.ensure(g, 0));
   const int64_t V = p->g->n;
-  const int64_t no = h.g2c.nslots, ni = h.c2g.nslots;
-  const int64_t nwo = (no + 31) / 32;
-  TG_TRY(hybrid_boxes(h, list_bytes<int32_t>(no), list_bytes<int32_t>(ni)));
-  std::vector<int32_t> cdist((size_t)C.n), hbest((size_t)ni);
-  std::vector<uint8_t> cin_next((size_t)C.n), covf((size_t)C.n), htouch((size_t)ni), hovf((size_t)ni);
-  std::vector<int32_t> cfront, cnext, touched, ovfs;
-  std::vector<std::vector<int32_t>> tl((size_t)omp_get_max_threads()), tt(tl.size()), to(tl.size());
+  const int64_t no = h.g2c.nslots;
+  const int64_t nwo = (no + 31) / 32, nwc = (C.n + 31) / 32;
+  TG_TRY(hybrid_boxes(h, list_bytes<int32_t>(no), list_bytes<int32_t>(C.n)));
+  std::vector<int32_t> cdist((size_t)C.n);
+  std::vector<uint8_t> cin_next((size_t)C.n), covf((size_t)C.n);
+  std::vector<int32_t> cfront, cnext;
+  std::vector<std::vector<int32_t>> tl((size_t)omp_get_max_threads());
   Phase ph;
   Events ev;
   TG_TRY(ev.init());
@@ -804,9 +807,6 @@ int hybrid_sssp(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *dist
     std::fill(cdist.begin(), cdist.end(), TG_INF);
     std::fill(cin_next.begin(), cin_next.end(), 0);
     std::fill(covf.begin(), covf.end(), 0);
-    std::fill(hbest.begin(), hbest.end(), TG_INF);
-    std::fill(htouch.begin(), htouch.end(), 0);
-    std::fill(hovf.begin(), hovf.end(), 0);
     cfront.clear();
     if (gl >= 0) {
       hipLaunchKernelGGL(k_set_i32h, dim3(1), dim3(64), 0, s, dist, (int64_t)gl, 0);
@@ -820,29 +820,46 @@ int hybrid_sssp(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *dist
     TG_TRY(frontier_compact(g, ws, 2, active, cur, ws.queue, nullptr, 0, s));
     TG_TRY(frontier_plan(g, ws, ws.queue, t, s, true));
     for (int64_t step = 0;; ++step) {
-      const bool gpu_front = ws.h_plan->count > 0;
-      if (!gpu_front && cfront.empty()) break;
+      const bool gpu_front = ws.h_plan->count > 0, host_front = !cfront.empty();
+      if (!gpu_front && !host_front) break;
       if (step > V) return set_error(TG_EDEVICE, "hybrid sssp: no convergence");
       ++ph.supersteps;
       const int b = (int)(step & 1);
+      TG_HIP(hipEventRecord(ev.e[0], s));
       if (gpu_front) {
-        TG_HIP(hipEventRecord(ev.e[0], s));
         TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], t, s));
-        TG_TRY(launch_outbox(h, s, SsspOut{h.d_rsrc, h.d_rw, dist, cur, h.d_osent, h.d_oval, h.d_ochg},
-                             h.d_shub_partials_i));
+        TG_TRY(launch_gather(h.dout, s, SsspOut{h.dout.rsrc, h.dout.rw, dist, cur, h.d_osent, h.d_oval, h.d_ochg},
+                             h.dout.partials_i));
         TG_TRY(launch_select<int32_t>(SelChangedI32{h.d_ochg, h.d_oval}, no, h.out.d[b], s));
         TG_TRY(clear_words(h.d_ochg, nwo, s));
-        TG_HIP(hipEventRecord(ev.e[1], s));
         TG_TRY(post_d2h(h, b, list_prefix_bytes<int32_t>(no), s));
       }
-      // host: relax its frontier, push its outbox
+      // the host's active set with its distances to the GPU, which reduces
+      // the host-to-GPU channel over it
+      if (host_front) {
+        Msg<int32_t> *ie = entries<int32_t>(h.in.h[b]);
+        const int64_t n_in = (int64_t)cfront.size();
+        for (int64_t i = 0; i < n_in; ++i) ie[i] = Msg<int32_t>{cfront[i], cdist[cfront[i]]};
+        const size_t bytes = (size_t)n_in * sizeof(Msg<int32_t>);
+        TG_TRY(post_h2d(h, b, LIST_HDR, bytes, s));
+        TG_TRY(clear_words(h.d_hbits, nwc, s));
+        hipLaunchKernelGGL(k_host_state<int32_t>, dim3(nblk(n_in)), dim3(BLOCK), 0, s, entries<int32_t>(h.in.d[b]),
+                           n_in, h.d_hdist, h.d_hbits);
+        TG_HIP(hipGetLastError());
+        TG_TRY(launch_gather(h.din, s,
+                             SsspIn{h.din.rsrc, h.din.rw, h.d_hdist, h.d_hbits, h.din.dst, dist, active, ovf,
+                                    ws.counters},
+                             h.din.partials_i));
+        ph.bytes += (double)bytes;
+        ph.h2d_bytes += (double)bytes;
+      }
+      TG_HIP(hipEventRecord(ev.e[1], s));
+      TG_TRY(frontier_compact(g, ws, 2, active, cur, ws.queue, nullptr, 0, s));
+      // host: relax its frontier over its local edges while the GPU runs
       const auto tc = clk::now();
 #pragma omp parallel
       {
-        const int tid = omp_get_thread_num();
-        auto &mine = tl[tid];
-        auto &mt = tt[tid];
-        auto &mo = to[tid];
+        auto &mine = tl[omp_get_thread_num()];
 #pragma omp for schedule(dynamic, 64)
         for (size_t i = 0; i < cfront.size(); ++i) {
           const int32_t v = cfront[i];
@@ -856,52 +873,21 @@ int hybrid_sssp(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *dist
             }
             if (atomic_min_i32(&cdist[x], (int32_t)nd) && !test_and_set(&cin_next[x])) mine.push_back(x);
           }
-          for (int64_t e = h.hb_off[v]; e < h.hb_off[v + 1]; ++e) {
-            const int32_t k = h.hb_slot[e];
-            const int64_t nd = dv + h.hb_w[e];
-            if (nd >= (int64_t)TG_INF) {
-              if (__atomic_load_n(&hbest[k], __ATOMIC_RELAXED) == TG_INF && !test_and_set(&hovf[k])) mo.push_back(k);
-              continue;
-            }
-            if (atomic_min_i32(&hbest[k], (int32_t)nd) && !test_and_set(&htouch[k])) mt.push_back(k);
-          }
         }
       }
       concat(tl, cnext);
-      concat(tt, touched);
-      concat(to, ovfs);
-      Msg<int32_t> *ie = entries<int32_t>(h.in.h[b]);
-      int64_t n_in = 0;
-      for (int32_t k : touched) {
-        ie[n_in++] = Msg<int32_t>{k, hbest[k]};
-        htouch[k] = 0;
-      }
-      for (int32_t k : ovfs) {
-        if (hbest[k] == TG_INF) ie[n_in++] = Msg<int32_t>{k, OVF_MSG};  // no finite value sent
-        hovf[k] = 0;
-      }
       ph.cpu_ms += ms_since(tc);
       ph.cpu_edges += frontier_edges(C, cfront);
-      if (n_in) {
-        const size_t bytes = (size_t)n_in * sizeof(Msg<int32_t>);
-        TG_TRY(post_h2d(h, b, LIST_HDR, bytes, s));
-        hipLaunchKernelGGL(k_inbox_sssp, dim3(nblk(n_in)), dim3(BLOCK), 0, s, h.d_in_dst,
-                           entries<int32_t>(h.in.d[b]), n_in, dist, active, ovf, ws.counters);
-        TG_HIP(hipGetLastError());
-        ph.bytes += (double)bytes;
-        ph.h2d_bytes += (double)bytes;
-      }
-      TG_TRY(frontier_compact(g, ws, 2, active, cur, ws.queue, nullptr, 0, s));
       TG_TRY(frontier_plan(g, ws, ws.queue, t, s, true));
-      if (n_in) ph.exchange_ms += h2d_ms(h, b);
+      ph.gpu_ms += elapsed(ev.e[0], ev.e[1]);
+      if (host_front) ph.exchange_ms += h2d_ms(h, b);
       if (gpu_front) {
-        ph.gpu_ms += elapsed(ev.e[0], ev.e[1]);
         int64_t n_out = 0;
         TG_TRY(fetch_list<int32_t>(h, b, &n_out, &ph.bytes, &ph.exchange_ms));
         const auto tc2 = clk::now();
         const Msg<int32_t> *oe = entries<int32_t>(h.out.h[b]);
         for (int64_t i = 0; i < n_out; ++i) {
-          const int32_t x = h.g2c.dst[oe[i].slot];
+          const int32_t x = h.g2c.dst[oe[i].id];
           const int32_t m = oe[i].val;
           if (m == OVF_MSG) {
             if (cdist[x] == TG_INF) covf[x] = 1;
@@ -937,28 +923,32 @@ int hybrid_sssp(tg_partition *p, const int32_t *roots, int32_t nr, int32_t *dist
 }
 
 // -------------------------------------------------------------- PageRank
-// Iteration k: both outboxes are reduced at once (GPU kernel, host threads);
-// the GPU step starts when the host's sums have arrived, and the host's
-// gather starts when the GPU's have, so the two gathers overlap.  The
-// dangling mass of both sides is combined before the next iteration.
+// Iteration k: the GPU reduces the GPU-to-host channel from its
+// contributions and sends the sums; the host sends its contributions (one
+// fp32 per host vertex, kept in the pinned box: the gather of iteration k
+// writes those of k+1 into the other buffer) and the GPU reduces the
+// host-to-GPU channel over them before its step.  The host's gather needs
+// only the GPU's sums, so it runs beside the GPU's step.  The dangling mass
+// of both sides is combined before the next iteration.
 int hybrid_pagerank(tg_partition *p, double damping, int32_t iters, int mode, float *rank, hipStream_t s) {
   HybridState &h = *p->hy;
   GpuPart &g = p->gpu;
   Workspace &ws = p->ws;
   CpuPart &C = h.cpu;
-  const int64_t no = h.g2c.nslots, ni = h.c2g.nslots;
+  const int64_t no = h.g2c.nslots;
   const double N = (double)p->g->n;
   const double base = (1.0 - damping) / N;
   const bool drop = mode == TG_PR_DANGLING_DROP;
   double D = (double)(g.n_dangling + C.n_dangling) / N;
-  TG_TRY(hybrid_boxes(h, (size_t)no * sizeof(float), (size_t)ni * sizeof(float)));
+  TG_TRY(hybrid_boxes(h, (size_t)no * sizeof(float), (size_t)C.n * sizeof(float)));
   TG_TRY(gpu_pagerank_setup(p, damping, mode, s, h.d_bdeg, D));
   TG_TRY(fill_f64(h.d_ghost, g.n, 0.0, s));
-  std::vector<float> cc((size_t)C.n), cn((size_t)C.n), crank((size_t)C.n);
+  std::vector<float> crank((size_t)C.n);
   std::vector<double> ghost((size_t)C.n, 0.0);
+  float *cc0 = reinterpret_cast<float *>(h.in.h[0]);
   for (int64_t i = 0; i < C.n; ++i) {
     const int64_t od = C.off[i + 1] - C.off[i] + C.bdeg[i];
-    cc[i] = od > 0 ? (float)(1.0 / (N * (double)od)) : 0.0f;
+    cc0[i] = od > 0 ? (float)(1.0 / (N * (double)od)) : 0.0f;
   }
   Phase ph;
   Events ev;
@@ -971,34 +961,26 @@ int hybrid_pagerank(tg_partition *p, double damping, int32_t iters, int mode, fl
     ++ph.supersteps;
     const bool last = k == iters - 1;
     const int b = k & 1;
-    // outboxes: per remote vertex, the sum of the contributions bound for it
+    const float *cc = reinterpret_cast<const float *>(h.in.h[b]);
+    float *cn = reinterpret_cast<float *>(h.in.h[b ^ 1]);
+    // GPU-to-host sums, then the host's contributions and the GPU step
     TG_HIP(hipEventRecord(ev.e[0], s));
-    TG_TRY(launch_outbox(h, s, PrOut{{}, h.d_rsrc, ws.cbuf[k & 1], reinterpret_cast<float *>(h.out.d[b])},
-                         h.d_shub_partials_f));
+    TG_TRY(launch_gather(h.dout, s,
+                         PrOut{{}, h.dout.rsrc, ws.cbuf[k & 1], reinterpret_cast<float *>(h.out.d[b])},
+                         h.dout.partials_f));
     TG_HIP(hipEventRecord(ev.e[1], s));
     TG_TRY(post_d2h(h, b, (size_t)no * sizeof(float), s));
-    const auto tc = clk::now();
-    float *hin = reinterpret_cast<float *>(h.in.h[b]);
-#pragma omp parallel for schedule(dynamic, 256)
-    for (int64_t q = 0; q < ni; ++q) {
-      double m = 0.0;
-      for (int64_t e = h.c2g.roff[q]; e < h.c2g.roff[q + 1]; ++e) m += (double)cc[h.c2g.rsrc[e]];
-      hin[q] = (float)m;
-    }
-    ph.cpu_ms += ms_since(tc);
-    // the GPU step as soon as the host's sums are there
-    TG_TRY(post_h2d(h, b, 0, (size_t)ni * sizeof(float), s));
+    TG_TRY(post_h2d(h, b, 0, (size_t)C.n * sizeof(float), s));
     TG_HIP(hipEventRecord(ev.e[2], s));
-    if (ni)
-      hipLaunchKernelGGL(k_inbox_pr, dim3(nblk(ni)), dim3(BLOCK), 0, s, h.d_in_dst,
-                         reinterpret_cast<const float *>(h.in.d[b]), ni, h.d_ghost);
-    // GPU gather with the inbox sums; its dangling mass lands in scalars[(k+1)&1]
+    TG_TRY(launch_gather(h.din, s, PrIn{{}, h.din.rsrc, reinterpret_cast<const float *>(h.in.d[b]), h.din.dst, h.d_ghost},
+                         h.din.partials_f));
+    // GPU gather with the ghost sums; its dangling mass lands in scalars[(k+1)&1]
     TG_TRY(gpu_pagerank_step(p, damping, mode, k, last, rank, s, h.d_ghost, h.d_bdeg));
     TG_HIP(hipMemcpyAsync(&ws.h_work[2], ws.scalars + ((k + 1) & 1), sizeof(double), hipMemcpyDeviceToHost, s));
     TG_HIP(hipEventRecord(ev.e[3], s));
     // host gather, beside the GPU step
     TG_TRY(wait_d2h(h, b, &ph.exchange_ms));
-    const auto tc2 = clk::now();
+    const auto tc = clk::now();
     const float *hout = reinterpret_cast<const float *>(h.out.h[b]);
     for (int64_t q = 0; q < no; ++q) ghost[h.g2c.dst[q]] = (double)hout[q];
     const double add = base + (drop ? 0.0 : damping * D / N);
@@ -1013,16 +995,15 @@ int hybrid_pagerank(tg_partition *p, double damping, int32_t iters, int mode, fl
       cn[v] = od > 0 ? (float)(r / (double)od) : 0.0f;
       if (od == 0) d_cpu += r;
     }
-    cc.swap(cn);
-    ph.cpu_ms += ms_since(tc2);
+    ph.cpu_ms += ms_since(tc);
     TG_HIP(hipEventSynchronize(ev.e[3]));
     double d_gpu = 0.0;
     memcpy(&d_gpu, &ws.h_work[2], sizeof(double));
     ph.gpu_ms += elapsed(ev.e[0], ev.e[1]) + elapsed(ev.e[2], ev.e[3]);
     ph.exchange_ms += h2d_ms(h, b);
-    ph.bytes += (double)(no + ni) * sizeof(float);
-    ph.h2d_bytes += (double)ni * sizeof(float);
-    ph.cpu_edges += (double)(C.m + h.c2g.edges());
+    ph.bytes += (double)(no + C.n) * sizeof(float);
+    ph.h2d_bytes += (double)C.n * sizeof(float);
+    ph.cpu_edges += (double)C.m;
     D = d_gpu + d_cpu;
     h.h_scalar[0] = D;
     TG_HIP(hipMemcpyAsync(ws.scalars + ((k + 1) & 1), h.h_scalar, sizeof(double), hipMemcpyHostToDevice, s));
@@ -1039,9 +1020,9 @@ namespace {
 
 // Host-side state of one BC source.
 struct HostBc {
-  std::vector<uint8_t> vis, hsent, htouch;
+  std::vector<uint8_t> vis;
   std::vector<int32_t> lev, hg_lev, slot_of;  // slot_of: host vertex -> GPU-to-host slot
-  std::vector<double> sig, del, hsig, hg_sig;
+  std::vector<double> sig, del, hg_sig;
   std::vector<float> hg_del;
 };
 
@@ -1060,7 +1041,7 @@ int hybrid_bc_source(tg_partition *p, int32_t src, hipStream_t s, std::vector<do
   const Tuning &t = p->tune;
   const int64_t V = p->g->n;
   const int64_t no = h.g2c.nslots, ni = h.c2g.nslots;
-  const int64_t nwo = (no + 31) / 32;
+  const int64_t nwo = (no + 31) / 32, nwc = (C.n + 31) / 32;
   uint32_t *visited = ws.bits_a, *prev = ws.bits_b;
   int32_t *level = ws.state;
   TG_HIP(hipMemsetAsync(visited, 0, ws.nwords * sizeof(uint32_t), s));
@@ -1077,10 +1058,9 @@ int hybrid_bc_source(tg_partition *p, int32_t src, hipStream_t s, std::vector<do
   std::fill(H.lev.begin(), H.lev.end(), TG_INF);
   std::fill(H.sig.begin(), H.sig.end(), 0.0);
   std::fill(H.del.begin(), H.del.end(), 0.0);
-  std::fill(H.hsent.begin(), H.hsent.end(), 0);
   std::fill(H.hg_del.begin(), H.hg_del.end(), 0.0f);
-  std::vector<int32_t> cfront, cnext, touched;
-  std::vector<std::vector<int32_t>> tl((size_t)omp_get_max_threads()), tt(tl.size());
+  std::vector<int32_t> cfront, cnext;
+  std::vector<std::vector<int32_t>> tl((size_t)omp_get_max_threads());
   const int32_t gl = p->h_l_of_g[src];
   if (gl >= 0) {
     hipLaunchKernelGGL(k_set_f64h, dim3(1), dim3(64), 0, s, ws.sigma, (int64_t)gl, 1.0);
@@ -1112,14 +1092,32 @@ int hybrid_bc_source(tg_partition *p, int32_t src, hipStream_t s, std::vector<do
     const int b = L & 1;
     if (gpu_front) {
       TG_TRY(bfs_expand_launch(g, ws, ws.queue + off, cur.vb[NBIN], t, s));
-      TG_TRY(launch_outbox(h, s, SigmaOut{{}, h.d_rsrc, level, ws.sigma, L, h.d_osent, h.d_oval, h.d_ochg},
-                           h.d_shub_partials_f));
+      TG_TRY(launch_gather(h.dout, s, SigmaOut{{}, h.dout.rsrc, level, ws.sigma, L, h.d_osent, h.d_oval, h.d_ochg},
+                           h.dout.partials_f));
       TG_TRY(launch_select<double>(SelChangedF64{h.d_ochg, h.d_oval}, no, h.out.d[b], s));
       TG_TRY(clear_words(h.d_ochg, nwo, s));
       TG_TRY(post_d2h(h, b, list_prefix_bytes<double>(no), s));
     }
-    // host: expand, sigma of its new vertices (pull over local in-edges),
-    // sigma sums to the GPU for slots not sent before
+    // the host frontier with its sigma to the GPU, which reduces the
+    // host-to-GPU channel over it
+    int64_t n_in = 0;
+    if (!cfront.empty()) {
+      Msg<double> *ie = entries<double>(h.in.h[b]);
+      n_in = (int64_t)cfront.size();
+      for (int64_t i = 0; i < n_in; ++i) ie[i] = Msg<double>{cfront[i], H.sig[cfront[i]]};
+      const size_t bytes = (size_t)n_in * sizeof(Msg<double>);
+      TG_TRY(post_h2d(h, b, LIST_HDR, bytes, s));
+      TG_TRY(clear_words(h.d_hbits, nwc, s));
+      hipLaunchKernelGGL(k_host_state<double>, dim3(nblk(n_in)), dim3(BLOCK), 0, s, entries<double>(h.in.d[b]), n_in,
+                         h.d_hsig, h.d_hbits);
+      TG_HIP(hipGetLastError());
+      TG_TRY(launch_gather(h.din, s, SigmaIn{{}, h.din.rsrc, h.d_hbits, h.d_hsig, h.din.dst, level, ws.sigma, visited},
+                           h.din.partials_f));
+      ph.bytes += (double)bytes;
+      ph.h2d_bytes += (double)bytes;
+    }
+    // host: expand over its local edges, sigma of its new vertices (pull
+    // over local in-edges)
     const auto tc = clk::now();
 #pragma omp parallel
     {
@@ -1137,48 +1135,16 @@ int hybrid_bc_source(tg_partition *p, int32_t src, hipStream_t s, std::vector<do
       }
     }
     concat(tl, cnext);
-#pragma omp parallel
-    {
-      auto &mt = tt[omp_get_thread_num()];
-#pragma omp for schedule(dynamic, 64) nowait
-      for (size_t i = 0; i < cnext.size(); ++i) {
-        const int32_t x = cnext[i];
-        double sg = 0.0;
-        for (int64_t e = C.ioff[x]; e < C.ioff[x + 1]; ++e)
-          if (H.lev[C.icol[e]] == L) sg += H.sig[C.icol[e]];
-        H.sig[x] = sg;
-      }
-#pragma omp for schedule(dynamic, 64)
-      for (size_t i = 0; i < cfront.size(); ++i) {
-        const int32_t v = cfront[i];
-        for (int64_t e = h.hb_off[v]; e < h.hb_off[v + 1]; ++e) {
-          const int32_t k = h.hb_slot[e];
-          if (H.hsent[k]) continue;
-          atomic_add_f64(&H.hsig[k], H.sig[v]);
-          if (!test_and_set(&H.htouch[k])) mt.push_back(k);
-        }
-      }
-    }
-    concat(tt, touched);
-    Msg<double> *ie = entries<double>(h.in.h[b]);
-    int64_t n_in = 0;
-    for (int32_t k : touched) {
-      ie[n_in++] = Msg<double>{k, H.hsig[k]};
-      H.hsent[k] = 1;
-      H.htouch[k] = 0;
-      H.hsig[k] = 0.0;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (size_t i = 0; i < cnext.size(); ++i) {
+      const int32_t x = cnext[i];
+      double sg = 0.0;
+      for (int64_t e = C.ioff[x]; e < C.ioff[x + 1]; ++e)
+        if (H.lev[C.icol[e]] == L) sg += H.sig[C.icol[e]];
+      H.sig[x] = sg;
     }
     ph.cpu_ms += ms_since(tc);
     ph.cpu_edges += frontier_edges(C, cfront);
-    if (n_in) {
-      const size_t bytes = (size_t)n_in * sizeof(Msg<double>);
-      TG_TRY(post_h2d(h, b, LIST_HDR, bytes, s));
-      hipLaunchKernelGGL(k_inbox_sigma, dim3(nblk(n_in)), dim3(BLOCK), 0, s, h.d_in_dst, entries<double>(h.in.d[b]),
-                         n_in, level, ws.sigma, visited);
-      TG_HIP(hipGetLastError());
-      ph.bytes += (double)bytes;
-      ph.h2d_bytes += (double)bytes;
-    }
     // GPU: the next frontier and its sigma
     const int64_t noff = off + cur.count;
     TG_TRY(frontier_compact(g, ws, 0, visited, prev, ws.queue + noff, level, L + 1, s));
@@ -1205,7 +1171,7 @@ int hybrid_bc_source(tg_partition *p, int32_t src, hipStream_t s, std::vector<do
       TG_TRY(fetch_list<double>(h, b, &n_out, &ph.bytes, &ph.exchange_ms));
       const Msg<double> *oe = entries<double>(h.out.h[b]);
       for (int64_t i = 0; i < n_out; ++i) {
-        const int32_t x = h.g2c.dst[oe[i].slot];
+        const int32_t x = h.g2c.dst[oe[i].id];
         if (H.lev[x] == TG_INF) {
           H.vis[x] = 1;
           H.lev[x] = L + 1;
@@ -1231,7 +1197,7 @@ int hybrid_bc_source(tg_partition *p, int32_t src, hipStream_t s, std::vector<do
   if (ni) {
     double *sig_o = reinterpret_cast<double *>(h.out.d[0]);
     int32_t *lev_o = reinterpret_cast<int32_t *>(h.out.d[0] + (size_t)ni * sizeof(double));
-    hipLaunchKernelGGL(k_ghost_out, dim3(nblk(ni)), dim3(BLOCK), 0, s, h.d_in_dst, ni, level, ws.sigma, sig_o, lev_o);
+    hipLaunchKernelGGL(k_ghost_out, dim3(nblk(ni)), dim3(BLOCK), 0, s, h.din.dst, ni, level, ws.sigma, sig_o, lev_o);
     TG_HIP(hipGetLastError());
     TG_TRY(post_d2h(h, 0, (size_t)ni * 12, s));
   }
@@ -1264,7 +1230,7 @@ int hybrid_bc_source(tg_partition *p, int32_t src, hipStream_t s, std::vector<do
     const int b = lv & 1;
     // deltas at level lv+1 of the receivers on the other side
     if (ni) {
-      TG_TRY(launch_select<float>(SelLevelDelta{h.d_in_dst, level, ws.delta, lv + 1}, ni, h.out.d[b], s));
+      TG_TRY(launch_select<float>(SelLevelDelta{h.din.dst, level, ws.delta, lv + 1}, ni, h.out.d[b], s));
       TG_TRY(post_d2h(h, b, list_prefix_bytes<float>(ni), s));
     }
     int64_t n_in = 0;
@@ -1284,7 +1250,7 @@ int hybrid_bc_source(tg_partition *p, int32_t src, hipStream_t s, std::vector<do
       int64_t n_out = 0;
       TG_TRY(fetch_list<float>(h, b, &n_out, &ph.bytes, &ph.exchange_ms));
       const Msg<float> *oe = entries<float>(h.out.h[b]);
-      for (int64_t i = 0; i < n_out; ++i) H.hg_del[oe[i].slot] = oe[i].val;
+      for (int64_t i = 0; i < n_out; ++i) H.hg_del[oe[i].id] = oe[i].val;
     }
     // GPU: delta of level lv, boundary children first
     const Plan &P = plans[lv];
@@ -1344,18 +1310,17 @@ int hybrid_bc(tg_partition *p, const int32_t *sources, int32_t ns, float *scores
   TG_TRY(ws.ensure(g, h.g2c.edges() / p->tune.hub_chunk + g.max_out_hubs + 1));
   const int64_t no = h.g2c.nslots, ni = h.c2g.nslots;
   // GPU -> host: sigma lists over GPU-to-host slots, delta lists and the
-  // (sigma, level) arrays over host-to-GPU slots; host -> GPU: the reverse
+  // (sigma, level) arrays over host-to-GPU slots; host -> GPU: sigma lists
+  // over host vertices, delta lists and the (sigma, level) arrays over
+  // GPU-to-host slots
   const size_t ob = std::max({list_bytes<double>(no), list_bytes<float>(ni), (size_t)ni * 12 + 16});
-  const size_t ib = std::max({list_bytes<double>(ni), list_bytes<float>(no), (size_t)no * 12 + 16});
+  const size_t ib = std::max({list_bytes<double>(C.n), list_bytes<float>(no), (size_t)no * 12 + 16});
   TG_TRY(hybrid_boxes(h, ob, ib));
   HostBc H;
   H.vis.resize((size_t)C.n);
   H.lev.resize((size_t)C.n);
   H.sig.resize((size_t)C.n);
   H.del.resize((size_t)C.n);
-  H.hsent.resize((size_t)ni);
-  H.htouch.assign((size_t)ni, 0);
-  H.hsig.assign((size_t)ni, 0.0);
   H.hg_lev.resize((size_t)ni);
   H.hg_sig.resize((size_t)ni);
   H.hg_del.resize((size_t)ni);

@@ -411,6 +411,12 @@ int frontier_plan_off(const GpuPart &g, Workspace &ws, const int32_t *queue, con
 int bfs_dev_start(const GpuPart &g, Workspace &ws, int32_t root, hipStream_t s);
 int frontier_compact_bfs_dev(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s);
 int frontier_plan_bfs_dev(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s);
+// Before the compaction of superstep L of a search fed from outside the
+// partition: reactivate the control block if its own frontier ran empty,
+// and set its level to L.  (`root` < 0 in bfs_dev_start: no local root.)
+int bfs_dev_resume(Workspace &ws, int32_t L, hipStream_t s);
+// bfs.hip: one device-resident superstep's expansion (no plan, no compaction)
+int bfs_dev_step(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s, bool timed);
 int launch_grid(int64_t vblocks);
 // bfs.hip: expansion of the frontier in `queue` (plan in ws.plan) into ws.bits_a
 int bfs_expand_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks,
