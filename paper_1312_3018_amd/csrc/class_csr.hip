@@ -112,9 +112,16 @@ int build_class_csr(const int64_t *off, const int32_t *col, const int32_t *w, in
   }
   TG_TRY(dalloc(C.arena, &C.soff, hsoff.size()));
   TG_HIP(hipMemcpyAsync(C.soff, hsoff.data(), hsoff.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  // padded: a block of a class without edges may re-read the class's first slot
+  // padded: a block of a class without edges re-reads the class's first
+  // slot, which for the last classes lies past every edge, and gathers at
+  // the id it finds there (its value is discarded); the padding holds id 0
+  // so that gather stays inside the vertex arrays
   TG_TRY(dalloc(C.arena, &C.scol, (size_t)m + 64));
-  if (w) TG_TRY(dalloc(C.arena, &C.sw, (size_t)m + 64));
+  TG_HIP(hipMemsetAsync(C.scol + m, 0, 64 * sizeof(int32_t), s));
+  if (w) {
+    TG_TRY(dalloc(C.arena, &C.sw, (size_t)m + 64));
+    TG_HIP(hipMemsetAsync(C.sw + m, 0, 64 * sizeof(int32_t), s));
+  }
   hipLaunchKernelGGL(k_class_fill, dim3(grid), dim3(BLOCK), 0, s, off, col, w, n, C.soff, C.cb, C.scol, C.sw);
   TG_HIP(hipGetLastError());
   TG_HIP(hipStreamSynchronize(s));
