@@ -133,7 +133,10 @@ int partition_by_degree(const tg_graph *g, int strategy, double cpu_edge_share,
  *                "sssp_lanes" (roots in flight, 1..4), "sssp_pull" (a
  *                superstep whose frontier holds more than this percentage
  *                of the edges pulls over in-edges; 0: never), "sssp_grid",
- *                "sssp_lds_verts", "sssp_xcd" (per-XCD destination classes);
+ *                "sssp_lds_verts", "sssp_xcd" (per-XCD destination classes),
+ *                "sssp_packed" (1: relax from one 32-bit word per edge,
+ *                id | weight << 24, which the partition keeps when every
+ *                local id fits in 24 bits and every weight in 8);
  *   layout       "mapped_edges" (1: the edge arrays -- neighbour ids, weights,
  *                in-edge ids -- stay in pinned host memory mapped into the
  *                GPU and kernels read them over the host link, for graphs

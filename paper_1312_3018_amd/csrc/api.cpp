@@ -326,6 +326,7 @@ Tuning default_tuning() {
   t.bfs_bu_grid = 4096;
   t.sssp_pull = 0;  // measured slower on R-MAT (pull steps lose the chaining of push steps)
   t.sssp_lanes = 4;
+  t.sssp_packed = 1;
   t.bfs_graph = 0;  // replaying captured chunks measured 1-2% slower than direct launches
   t.mapped_edges = 0;
   return t;
@@ -373,12 +374,14 @@ int parse_tuning(const char *json, Tuning *t) {
   if (json_int(json, "bfs_bu_grid", &v)) t->bfs_bu_grid = v;
   if (json_int(json, "sssp_pull", &v)) t->sssp_pull = v;
   if (json_int(json, "sssp_lanes", &v)) t->sssp_lanes = v;
+  if (json_int(json, "sssp_packed", &v)) t->sssp_packed = v;
   if (json_int(json, "bfs_graph", &v)) t->bfs_graph = v;
   if (json_int(json, "mapped_edges", &v)) t->mapped_edges = v;
   if (t->mapped_edges != 0 && t->mapped_edges != 1) return set_error(TG_EINVAL, "tuning: mapped_edges must be 0 or 1");
   if (t->bfs_graph != 0 && t->bfs_graph != 1) return set_error(TG_EINVAL, "tuning: bfs_graph must be 0 or 1");
   if (t->sssp_pull < 0 || t->sssp_pull > 100) return set_error(TG_EINVAL, "tuning: sssp_pull must be in [0, 100]");
   if (t->sssp_lanes < 1 || t->sssp_lanes > MAX_LANES) return set_error(TG_EINVAL, "tuning: sssp_lanes outside [1, 4]");
+  if (t->sssp_packed != 0 && t->sssp_packed != 1) return set_error(TG_EINVAL, "tuning: sssp_packed must be 0 or 1");
   if (t->bfs_lanes != 1 && t->bfs_lanes != 2) return set_error(TG_EINVAL, "tuning: bfs_lanes must be 1 or 2");
   if (t->bfs_td_grid < 1 || t->bfs_td_grid > 16384 || t->bfs_bu_grid < 2 || t->bfs_bu_grid > 16384)
     return set_error(TG_EINVAL, "tuning: bfs_td_grid must be in [1, 16384] and bfs_bu_grid in [2, 16384]");
@@ -712,6 +715,17 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
   };
   TG_TRY(edges(&gp.out.col, col));
   if (G.has_w) TG_TRY(edges(&gp.out.w, w));
+  if (G.has_w && n <= (int64_t)1 << 24) {
+    // the relaxation's edge stream in one word per edge, if every weight fits in 8 bits
+    bool small = true;
+    for (int64_t e = 0; e < m && small; ++e) small = w[e] >= 0 && w[e] < 256;
+    if (small) {
+      std::vector<int32_t> cw((size_t)m);
+#pragma omp parallel for schedule(static)
+      for (int64_t e = 0; e < m; ++e) cw[e] = (int32_t)((uint32_t)col[e] | ((uint32_t)w[e] << 24));
+      TG_TRY(edges(reinterpret_cast<int32_t **>(&gp.out.cw), cw));
+    }
+  }
   gp.out.n = n;
   gp.out.m = m;
   gp.h_out_off = off;
@@ -951,7 +965,7 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld,"
            "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld,\"pr_xcd\":%lld,\"pr_rows\":%lld,"
            "\"bfs_do\":%lld,\"bfs_alpha\":%lld,\"bfs_beta\":%lld,\"sssp_xcd\":%lld,\"bfs_lanes\":%lld,"
-           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld,\"sssp_pull\":%lld,\"sssp_lanes\":%lld,\"bfs_graph\":%lld,\"mapped_edges\":%lld}",
+           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld,\"sssp_pull\":%lld,\"sssp_lanes\":%lld,\"bfs_graph\":%lld,\"mapped_edges\":%lld,\"sssp_packed\":%lld}",
            (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
            (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk,
            (long long)p->tune.pr_lds_verts, (long long)p->tune.pr_grid, (long long)p->tune.bfs_lds_words,
@@ -960,7 +974,8 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            (long long)p->tune.pr_rows, (long long)p->tune.bfs_do, (long long)p->tune.bfs_alpha,
            (long long)p->tune.bfs_beta, (long long)p->tune.sssp_xcd, (long long)p->tune.bfs_lanes,
            (long long)p->tune.bfs_td_grid, (long long)p->tune.bfs_bu_grid, (long long)p->tune.sssp_pull,
-           (long long)p->tune.sssp_lanes, (long long)p->tune.bfs_graph, (long long)p->tune.mapped_edges);
+           (long long)p->tune.sssp_lanes, (long long)p->tune.bfs_graph, (long long)p->tune.mapped_edges,
+           (long long)p->tune.sssp_packed);
   s += buf;
   s += ",\"tuning_source\":\"" + p->tuning_source + "\"";
   s += hybrid_info_json(p);

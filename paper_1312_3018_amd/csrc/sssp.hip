@@ -65,12 +65,29 @@ __device__ __forceinline__ const int32_t *dist_ptr(const int32_t *dist, const in
   return nb < hot ? lds_d + nb : dist + nb;  // generic pointer: one load for LDS or HBM
 }
 
+// An edge's neighbour and weight: from the packed word (id | w << 24) or
+// from the two arrays.
+template <bool PACKED>
+__device__ __forceinline__ void load_edge(const int32_t *__restrict__ col, const int32_t *__restrict__ wgt,
+                                          const uint32_t *__restrict__ cw, int64_t e, int32_t &nb, int32_t &wt) {
+  if (PACKED) {
+    const uint32_t x = stream_load(cw + e);
+    nb = (int32_t)(x & 0xFFFFFFu);
+    wt = (int32_t)(x >> 24);
+  } else {
+    nb = stream_load(col + e);
+    wt = stream_load(wgt + e);
+  }
+}
+
+template <bool PACKED>
 __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ Pp,
                                                       const int32_t *__restrict__ queue,
                                                       const int64_t *__restrict__ hubpref,
                                                       const int64_t *__restrict__ off,
                                                       const int32_t *__restrict__ col,
-                                                      const int32_t *__restrict__ wgt, int32_t *dist,
+                                                      const int32_t *__restrict__ wgt,
+                                                      const uint32_t *__restrict__ cw, int32_t *dist,
                                                       uint32_t *active, uint32_t *ovf, uint32_t *flags,
                                                       int64_t hub_chunk, unsigned long long *work, int32_t hot,
                                                       int vb_bin_lo) {
@@ -95,18 +112,16 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
     for (; e + 3 * st < a.e_end; e += 4 * st) {
       int32_t nb[4], wt[4], cur[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        nb[k] = stream_load(col + e + k * st);
-        wt[k] = stream_load(wgt + e + k * st);
-      }
+      for (int k = 0; k < 4; ++k) load_edge<PACKED>(col, wgt, cw, e + k * st, nb[k], wt[k]);
 #pragma unroll
       for (int k = 0; k < 4; ++k) cur[k] = *dist_ptr(dist, lds_d, hot, nb[k]);
 #pragma unroll
       for (int k = 0; k < 4; ++k) relax(dist, lds_d, hot, active, ovf, flags, dv, nb[k], wt[k], cur[k]);
     }
     for (; e < a.e_end; e += st) {
-      const int32_t n0 = stream_load(col + e);
-      relax(dist, lds_d, hot, active, ovf, flags, dv, n0, stream_load(wgt + e), *dist_ptr(dist, lds_d, hot, n0));
+      int32_t n0, w0;
+      load_edge<PACKED>(col, wgt, cw, e, n0, w0);
+      relax(dist, lds_d, hot, active, ovf, flags, dv, n0, w0, *dist_ptr(dist, lds_d, hot, n0));
     }
   }
   n_edges = block_sum(n_edges);
@@ -191,9 +206,14 @@ int sssp_relax_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int
   const int32_t hot = (int32_t)std::min<int64_t>(t.sssp_lds_verts, g.n);
   const int grid = hot > 0 ? (int)std::min<int64_t>(launch_grid(vblocks), t.sssp_grid) : launch_grid(vblocks);
   const int tk = ktimer_start(s);
-  hipLaunchKernelGGL(k_sssp_relax, dim3(grid), dim3(BLOCK), (size_t)hot * sizeof(int32_t), s, ws.plan, queue,
-                     ws.hubpref, g.out.off, g.out.col, g.out.w, ws.state, ws.bits_a, ws.bits_c, ws.counters,
-                     t.hub_chunk, ws.work, hot, 0);
+  if (t.sssp_packed && g.out.cw)
+    hipLaunchKernelGGL(k_sssp_relax<true>, dim3(grid), dim3(BLOCK), (size_t)hot * sizeof(int32_t), s, ws.plan, queue,
+                       ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, ws.bits_a, ws.bits_c,
+                       ws.counters, t.hub_chunk, ws.work, hot, 0);
+  else
+    hipLaunchKernelGGL(k_sssp_relax<false>, dim3(grid), dim3(BLOCK), (size_t)hot * sizeof(int32_t), s, ws.plan,
+                       queue, ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, ws.bits_a, ws.bits_c,
+                       ws.counters, t.hub_chunk, ws.work, hot, 0);
   ktimer_stop(tk, s, "sssp_relax");
   TG_HIP(hipGetLastError());
   return TG_OK;
@@ -290,9 +310,9 @@ static int sssp_relax_cls_launch(const GpuPart &g, Workspace &ws, const int32_t 
                        ws.work, (int)BIN_G16);
   }
   if (vb_lo_n > 0)
-    hipLaunchKernelGGL(k_sssp_relax, dim3(launch_grid(vb_lo_n)), dim3(BLOCK), 0, s, ws.plan, queue, ws.hubpref,
-                       g.out.off, g.out.col, g.out.w, ws.state, ws.bits_a, ws.bits_c, ws.counters, t.hub_chunk,
-                       ws.work, 0, (int)BIN_G16);
+    hipLaunchKernelGGL(k_sssp_relax<false>, dim3(launch_grid(vb_lo_n)), dim3(BLOCK), 0, s, ws.plan, queue,
+                       ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, ws.bits_a, ws.bits_c,
+                       ws.counters, t.hub_chunk, ws.work, 0, (int)BIN_G16);
   ktimer_stop(tk, s, "sssp_relax");
   TG_HIP(hipGetLastError());
   return TG_OK;

@@ -92,6 +92,7 @@ struct Tuning {
   int64_t bfs_bu_grid;           // BFS: blocks of a bottom-up launch's one-thread-per-vertex part
   int64_t sssp_pull;             // SSSP: pull a superstep whose frontier has more than this % of the edges (0: never)
   int64_t sssp_lanes;            // SSSP: searches in flight on their own streams (1..4)
+  int64_t sssp_packed;           // SSSP: relax from the packed id|weight words when the partition has them
   int64_t bfs_graph;             // BFS: 1 = chunks of supersteps replayed as captured HIP graphs
   int64_t mapped_edges;          // partition build: 1 = edge arrays in mapped host memory
 };
@@ -151,6 +152,9 @@ struct DevCSR {
   int64_t *off = nullptr;
   int32_t *col = nullptr;
   int32_t *w = nullptr;
+  // id and weight in one word, id | w << 24, where every id fits in 24 bits
+  // and every weight in 8 (out-edges of a weighted partition only)
+  uint32_t *cw = nullptr;
 };
 
 struct PrSlices;
