@@ -69,7 +69,7 @@ def load_traffic(kernel: str, workload: str):
 # launch of each bench kernel, and the pass directories (<algo>_fetch,
 # <algo>_write, <algo>_hit) their counters come from.
 TRAFFIC_ROWS = {
-    "sssp_relax": ("sssp", ["k_sssp_relax"]),
+    "sssp_relax": ("sssp", ["k_sssp_relax<true>"]),
     "pr_gather": ("pr", ["k_pr_rows<true, int, 8>", "k_pr_long<true>", "k_pr_combine", "k_pr_dsum"]),
     "bfs_step": ("bfs", ["k_bfs_step<int>"]),
 }
@@ -871,7 +871,11 @@ def main():
     # algorithmic bytes (int32 ids, int64 offsets)
     bfs_bytes = 4.125 * bfs_edges + 20.0 * bfs_verts            # whole top-down BFS, all roots
     pr_bytes_iter = 8.0 * E + 16.0 * V                          # one pull iteration
-    sssp_bytes = 12.0 * ss.get("relaxations", 0) + 16.0 * ss.get("activations", 0)
+    # per relaxation the edge (packed id|weight word, or id + weight) and
+    # the neighbour's distance; per activation offsets, queue, own distance
+    pinfo = tg.partition_info(P)
+    packed = bool(pinfo.get("packed_edges")) and pinfo["tuning"].get("sssp_packed", 1) == 1
+    sssp_bytes = (8.0 if packed else 12.0) * ss.get("relaxations", 0) + 16.0 * ss.get("activations", 0)
     # what the direction-optimizing BFS kernels read: top-down, per edge
     # scanned its id and visited bit, per vertex expanded its offsets and
     # queue entry; bottom-up, per vertex examined two int32 offsets, per

@@ -136,7 +136,12 @@ int partition_by_degree(const tg_graph *g, int strategy, double cpu_edge_share,
  *                "sssp_lds_verts", "sssp_xcd" (per-XCD destination classes),
  *                "sssp_packed" (1: relax from one 32-bit word per edge,
  *                id | weight << 24, which the partition keeps when every
- *                local id fits in 24 bits and every weight in 8);
+ *                local id fits in 24 bits and every weight in 8),
+ *                "sssp_ring" (1: the near/far step keeps active vertices
+ *                in a ring of bucket bitmaps by distance and filters only
+ *                the current bucket, when at most 16 buckets of width
+ *                sssp_delta span the largest weight; 0: one far pile,
+ *                rescanned every superstep);
  *   layout       "mapped_edges" (1: the edge arrays -- neighbour ids, weights,
  *                in-edge ids -- stay in pinned host memory mapped into the
  *                GPU and kernels read them over the host link, for graphs

@@ -138,6 +138,8 @@ int Workspace::ensure(const GpuPart &g, int64_t hub_chunks_needed) {
   arena.release();
   fd = nullptr;
   pull_part = nullptr;
+  buckets = nullptr;
+  buckets_k = 0;
   pull_part_cap = 0;
   const int64_t n = g.n;
   nwords = ((n + 31) / 32 + 1023) / 1024 * 1024;
@@ -327,6 +329,7 @@ Tuning default_tuning() {
   t.sssp_pull = 0;  // measured slower on R-MAT (pull steps lose the chaining of push steps)
   t.sssp_lanes = 4;
   t.sssp_packed = 1;
+  t.sssp_ring = 1;
   t.bfs_graph = 0;  // replaying captured chunks measured 1-2% slower than direct launches
   t.mapped_edges = 0;
   return t;
@@ -375,6 +378,7 @@ int parse_tuning(const char *json, Tuning *t) {
   if (json_int(json, "sssp_pull", &v)) t->sssp_pull = v;
   if (json_int(json, "sssp_lanes", &v)) t->sssp_lanes = v;
   if (json_int(json, "sssp_packed", &v)) t->sssp_packed = v;
+  if (json_int(json, "sssp_ring", &v)) t->sssp_ring = v;
   if (json_int(json, "bfs_graph", &v)) t->bfs_graph = v;
   if (json_int(json, "mapped_edges", &v)) t->mapped_edges = v;
   if (t->mapped_edges != 0 && t->mapped_edges != 1) return set_error(TG_EINVAL, "tuning: mapped_edges must be 0 or 1");
@@ -382,6 +386,7 @@ int parse_tuning(const char *json, Tuning *t) {
   if (t->sssp_pull < 0 || t->sssp_pull > 100) return set_error(TG_EINVAL, "tuning: sssp_pull must be in [0, 100]");
   if (t->sssp_lanes < 1 || t->sssp_lanes > MAX_LANES) return set_error(TG_EINVAL, "tuning: sssp_lanes outside [1, 4]");
   if (t->sssp_packed != 0 && t->sssp_packed != 1) return set_error(TG_EINVAL, "tuning: sssp_packed must be 0 or 1");
+  if (t->sssp_ring != 0 && t->sssp_ring != 1) return set_error(TG_EINVAL, "tuning: sssp_ring must be 0 or 1");
   if (t->bfs_lanes != 1 && t->bfs_lanes != 2) return set_error(TG_EINVAL, "tuning: bfs_lanes must be 1 or 2");
   if (t->bfs_td_grid < 1 || t->bfs_td_grid > 16384 || t->bfs_bu_grid < 2 || t->bfs_bu_grid > 16384)
     return set_error(TG_EINVAL, "tuning: bfs_td_grid must be in [1, 16384] and bfs_bu_grid in [2, 16384]");
@@ -715,6 +720,9 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
   };
   TG_TRY(edges(&gp.out.col, col));
   if (G.has_w) TG_TRY(edges(&gp.out.w, w));
+  gp.max_w = 0;
+  if (G.has_w)
+    for (int64_t e = 0; e < m; ++e) gp.max_w = std::max(gp.max_w, w[e]);
   if (G.has_w && n <= (int64_t)1 << 24) {
     // the relaxation's edge stream in one word per edge, if every weight fits in 8 bits
     bool small = true;
@@ -945,9 +953,11 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
   std::string s = "{";
   snprintf(buf, sizeof(buf),
            "\"V\":%lld,\"E\":%lld,\"strategy\":%d,\"cpu_edge_share\":%.6f,\"gpu_vertices\":%lld,"
-           "\"gpu_edges\":%lld,\"gpu_device_bytes\":%zu,\"symmetric\":%s,\"dangling\":%lld,",
+           "\"gpu_edges\":%lld,\"gpu_device_bytes\":%zu,\"symmetric\":%s,\"dangling\":%lld,"
+           "\"packed_edges\":%s,",
            (long long)p->g->n, (long long)p->g->m, p->strategy, p->alpha, (long long)g.n, (long long)g.m,
-           p->arena.bytes, p->g->symmetric ? "true" : "false", (long long)g.n_dangling);
+           p->arena.bytes, p->g->symmetric ? "true" : "false", (long long)g.n_dangling,
+           g.out.cw ? "true" : "false");
   s += buf;
   s += "\"out_bins\":[";
   for (int b = 0; b <= NBIN; ++b) {
@@ -965,7 +975,7 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld,"
            "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld,\"pr_xcd\":%lld,\"pr_rows\":%lld,"
            "\"bfs_do\":%lld,\"bfs_alpha\":%lld,\"bfs_beta\":%lld,\"sssp_xcd\":%lld,\"bfs_lanes\":%lld,"
-           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld,\"sssp_pull\":%lld,\"sssp_lanes\":%lld,\"bfs_graph\":%lld,\"mapped_edges\":%lld,\"sssp_packed\":%lld}",
+           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld,\"sssp_pull\":%lld,\"sssp_lanes\":%lld,\"bfs_graph\":%lld,\"mapped_edges\":%lld,\"sssp_packed\":%lld,\"sssp_ring\":%lld}",
            (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
            (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk,
            (long long)p->tune.pr_lds_verts, (long long)p->tune.pr_grid, (long long)p->tune.bfs_lds_words,
@@ -975,7 +985,7 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            (long long)p->tune.bfs_beta, (long long)p->tune.sssp_xcd, (long long)p->tune.bfs_lanes,
            (long long)p->tune.bfs_td_grid, (long long)p->tune.bfs_bu_grid, (long long)p->tune.sssp_pull,
            (long long)p->tune.sssp_lanes, (long long)p->tune.bfs_graph, (long long)p->tune.mapped_edges,
-           (long long)p->tune.sssp_packed);
+           (long long)p->tune.sssp_packed, (long long)p->tune.sssp_ring);
   s += buf;
   s += ",\"tuning_source\":\"" + p->tuning_source + "\"";
   s += hybrid_info_json(p);

@@ -39,10 +39,32 @@ __global__ void k_set_i32(int32_t *p, int64_t i, int32_t v) {
   if (threadIdx.x == 0) p[i] = v;
 }
 
+// any[j] = 1 if bitmap j of the ring has a set bit (grid.y = bitmap; any
+// zeroed before).
+__global__ __launch_bounds__(BLOCK) void k_ring_any(const uint32_t *__restrict__ ring, int64_t nwords,
+                                                    uint32_t *any) {
+  const uint32_t *b = ring + (int64_t)blockIdx.y * nwords;
+  uint32_t acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nwords; i += (int64_t)gridDim.x * BLOCK) acc |= b[i];
+  if (__syncthreads_or(acc != 0u) && threadIdx.x == 0) any[blockIdx.y] = 1u;
+}
+
+// Where an improved vertex is marked active: one bitmap, or (near/far with
+// a bucket ring) bitmap (d / delta) mod k of the ring, nwords words apart.
+struct ActiveSet {
+  uint32_t *base;
+  int32_t delta;
+  int32_t k;  // 0: one bitmap
+  int64_t nwords;
+  __device__ __forceinline__ uint32_t *of(int32_t d) const {
+    return k ? base + (int64_t)((d / delta) % k) * nwords : base;
+  }
+};
+
 // Relax one edge.  `cur` is the neighbour's distance as this block knows it:
 // an LDS snapshot for the hottest vertices (never below the true value, since
 // distances only decrease) or the global value.
-__device__ __forceinline__ void relax(int32_t *dist, int32_t *lds_d, int32_t hot, uint32_t *active, uint32_t *ovf,
+__device__ __forceinline__ void relax(int32_t *dist, int32_t *lds_d, int32_t hot, const ActiveSet &act, uint32_t *ovf,
                                       uint32_t *flags, int32_t dv, int32_t nb, int32_t wt, int32_t cur) {
   const int64_t nd = (int64_t)dv + (int64_t)wt;
   const uint32_t bit = 1u << (nb & 31);
@@ -57,7 +79,7 @@ __device__ __forceinline__ void relax(int32_t *dist, int32_t *lds_d, int32_t hot
   if (nd < (int64_t)cur) {
     atomicMin(dist + nb, (int32_t)nd);  // no return value: nothing waits on it
     if (nb < hot) atomicMin(lds_d + nb, (int32_t)nd);
-    atomicOr(active + (nb >> 5), bit);
+    atomicOr(act.of((int32_t)nd) + (nb >> 5), bit);
   }
 }
 
@@ -88,7 +110,7 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
                                                       const int32_t *__restrict__ col,
                                                       const int32_t *__restrict__ wgt,
                                                       const uint32_t *__restrict__ cw, int32_t *dist,
-                                                      uint32_t *active, uint32_t *ovf, uint32_t *flags,
+                                                      const ActiveSet act, uint32_t *ovf, uint32_t *flags,
                                                       int64_t hub_chunk, unsigned long long *work, int32_t hot,
                                                       int vb_bin_lo) {
   extern __shared__ int32_t lds_d[];
@@ -116,12 +138,12 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
 #pragma unroll
       for (int k = 0; k < 4; ++k) cur[k] = *dist_ptr(dist, lds_d, hot, nb[k]);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) relax(dist, lds_d, hot, active, ovf, flags, dv, nb[k], wt[k], cur[k]);
+      for (int k = 0; k < 4; ++k) relax(dist, lds_d, hot, act, ovf, flags, dv, nb[k], wt[k], cur[k]);
     }
     for (; e < a.e_end; e += st) {
       int32_t n0, w0;
       load_edge<PACKED>(col, wgt, cw, e, n0, w0);
-      relax(dist, lds_d, hot, active, ovf, flags, dv, n0, w0, *dist_ptr(dist, lds_d, hot, n0));
+      relax(dist, lds_d, hot, act, ovf, flags, dv, n0, w0, *dist_ptr(dist, lds_d, hot, n0));
     }
   }
   n_edges = block_sum(n_edges);
@@ -172,11 +194,11 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax_cls(const Plan *__restrict
 #pragma unroll
       for (int q = 0; q < 4; ++q) cur[q] = dist[nb4[q]];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) relax(dist, nullptr, 0, active, ovf, flags, dv, nb4[q], wt[q], cur[q]);
+      for (int q = 0; q < 4; ++q) relax(dist, nullptr, 0, ActiveSet{active, 0, 0, 0}, ovf, flags, dv, nb4[q], wt[q], cur[q]);
     }
     for (; e < a.e_end; e += st) {
       const int32_t n0 = stream_load(scol + e);
-      relax(dist, nullptr, 0, active, ovf, flags, dv, n0, stream_load(sw + e), dist[n0]);
+      relax(dist, nullptr, 0, ActiveSet{active, 0, 0, 0}, ovf, flags, dv, n0, stream_load(sw + e), dist[n0]);
     }
   }
   n_edges = block_sum(n_edges);
@@ -201,18 +223,21 @@ __global__ __launch_bounds__(BLOCK) void k_overflow_check(const uint32_t *__rest
 namespace tg {
 
 int sssp_relax_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks, const Tuning &t,
-                      hipStream_t s) {
+                      hipStream_t s, int32_t bucket_delta, int32_t bucket_k) {
   if (vblocks <= 0) return TG_OK;
   const int32_t hot = (int32_t)std::min<int64_t>(t.sssp_lds_verts, g.n);
   const int grid = hot > 0 ? (int)std::min<int64_t>(launch_grid(vblocks), t.sssp_grid) : launch_grid(vblocks);
+  // improved vertices: the active bitmap, or the bucket ring of their new distance
+  const ActiveSet act = bucket_k > 0 ? ActiveSet{ws.buckets, bucket_delta, bucket_k, ws.nwords}
+                                     : ActiveSet{ws.bits_a, 0, 0, 0};
   const int tk = ktimer_start(s);
   if (t.sssp_packed && g.out.cw)
     hipLaunchKernelGGL(k_sssp_relax<true>, dim3(grid), dim3(BLOCK), (size_t)hot * sizeof(int32_t), s, ws.plan, queue,
-                       ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, ws.bits_a, ws.bits_c,
+                       ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, act, ws.bits_c,
                        ws.counters, t.hub_chunk, ws.work, hot, 0);
   else
     hipLaunchKernelGGL(k_sssp_relax<false>, dim3(grid), dim3(BLOCK), (size_t)hot * sizeof(int32_t), s, ws.plan,
-                       queue, ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, ws.bits_a, ws.bits_c,
+                       queue, ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, act, ws.bits_c,
                        ws.counters, t.hub_chunk, ws.work, hot, 0);
   ktimer_stop(tk, s, "sssp_relax");
   TG_HIP(hipGetLastError());
@@ -311,12 +336,64 @@ static int sssp_relax_cls_launch(const GpuPart &g, Workspace &ws, const int32_t 
   }
   if (vb_lo_n > 0)
     hipLaunchKernelGGL(k_sssp_relax<false>, dim3(launch_grid(vb_lo_n)), dim3(BLOCK), 0, s, ws.plan, queue,
-                       ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, ws.bits_a, ws.bits_c,
-                       ws.counters, t.hub_chunk, ws.work, 0, (int)BIN_G16);
+                       ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, ActiveSet{ws.bits_a, 0, 0, 0},
+                       ws.bits_c, ws.counters, t.hub_chunk, ws.work, 0, (int)BIN_G16);
   ktimer_stop(tk, s, "sssp_relax");
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
+
+namespace {
+
+// The near/far schedule over a ring of k bucket bitmaps (see gpu_sssp).
+// Distances, settled values and overflow marks are set up by the caller.
+int gpu_sssp_ring(tg_partition *p, Workspace &ws, int32_t root, hipStream_t s, int32_t k, int64_t *rounds_out,
+                  int64_t *pulls_out) {
+  GpuPart &g = p->gpu;
+  const int64_t delta = p->tune.sssp_delta;
+  const BinBounds &bb = g.out_bins;
+  if (!ws.buckets || ws.buckets_k < k) {
+    TG_TRY(dalloc(ws.arena, &ws.buckets, (size_t)k * ws.nwords));
+    ws.buckets_k = k;
+  }
+  TG_HIP(hipMemsetAsync(ws.buckets, 0, (size_t)k * ws.nwords * sizeof(uint32_t), s));
+  TG_TRY(set_bit(ws.buckets, root, s));  // bucket 0: distance 0
+  int64_t lo = 0, rounds = 0;
+  for (;;) {
+    if (rounds > 2 * g.n + 2 || lo > (int64_t)TG_INF)
+      return set_error(TG_EDEVICE, "sssp: no convergence after %lld rounds", (long long)rounds);
+    uint32_t *bits = ws.buckets + ((lo / delta) % k) * ws.nwords;
+    // every unsettled bit of the current bucket is in [lo, lo + delta): all are taken
+    TG_TRY(frontier_compact_sssp(g, ws, bits, ws.queue, ws.state, ws.settled, TG_INF, false, bb, s, nullptr));
+    TG_TRY(frontier_plan_bins(g, ws, ws.queue, bb, nullptr, p->tune, s, true));
+    if (ws.h_plan->count > 0) {
+      ++rounds;
+      TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s, (int32_t)delta, k));
+      continue;
+    }
+    // the current bucket is empty: move to the next bucket with a set bit,
+    // if any (the ring holds every active vertex)
+    TG_HIP(hipMemsetAsync(ws.counters + 16, 0, (size_t)k * sizeof(uint32_t), s));
+    const unsigned bx = (unsigned)std::min<int64_t>((ws.nwords + BLOCK - 1) / BLOCK, 64);
+    hipLaunchKernelGGL(k_ring_any, dim3(bx, (unsigned)k), dim3(BLOCK), 0, s, ws.buckets, ws.nwords, ws.counters + 16);
+    TG_HIP(hipGetLastError());
+    TG_HIP(hipMemcpyAsync(ws.h_flags + 16, ws.counters + 16, (size_t)k * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    TG_HIP(hipStreamSynchronize(s));
+    const int64_t cur = (lo / delta) % k;
+    int64_t step = 0;
+    for (int64_t j = 1; j < k && step == 0; ++j)
+      if (ws.h_flags[16 + (cur + j) % k]) step = j;
+    if (step == 0) break;  // no active vertex left
+    lo += step * delta;
+  }
+  if (pulls_out) *pulls_out = 0;
+  TG_TRY(sssp_overflow_check(g, ws, s));
+  if (ws.h_flags[1]) return set_error(TG_ERANGE, "sssp: a shortest-path distance does not fit below INT32_MAX");
+  if (rounds_out) *rounds_out = rounds;
+  return TG_OK;
+}
+
+}  // namespace
 
 int gpu_sssp(tg_partition *p, Workspace &ws, int32_t root, hipStream_t s, int64_t *rounds_out, int64_t *pulls_out) {
   GpuPart &g = p->gpu;
@@ -337,6 +414,15 @@ int gpu_sssp(tg_partition *p, Workspace &ws, int32_t root, hipStream_t s, int64_
   if (cls) TG_TRY(build_sssp_slices(p, s));
   const BinBounds &bb = cls ? g.sslices->bins : g.out_bins;
   const int32_t *len = cls ? g.sslices->maxlen : nullptr;
+  // near/far over a ring of bucket bitmaps (plain push steps): while the
+  // bucket of distances [lo, lo + delta) is processed, a relaxation yields at
+  // most lo + delta - 1 + max_w, so every active vertex lies within
+  // ceil((max_w + 1) / delta) + 1 buckets of lo and bitmap (d / delta) mod k
+  // of a ring of that many holds it; a superstep filters only the current
+  // bucket, and the ones beyond wait untouched
+  const int64_t ring_k = delta > 0 ? (g.max_w + 1 + delta - 1) / delta + 1 : 0;
+  if (p->tune.sssp_ring && delta > 0 && !cls && !(p->tune.sssp_pull > 0 && sssp_pull_supported(g)) && ring_k <= 16)
+    return gpu_sssp_ring(p, ws, root, s, (int32_t)ring_k, rounds_out, pulls_out);
   int64_t thresh = delta;  // near/far: only active vertices below thresh relax
   // pull supersteps for frontiers with a large share of the edges: the
   // compaction sums the frontier's out-degrees (spread counter 4)

@@ -93,6 +93,7 @@ struct Tuning {
   int64_t sssp_pull;             // SSSP: pull a superstep whose frontier has more than this % of the edges (0: never)
   int64_t sssp_lanes;            // SSSP: searches in flight on their own streams (1..4)
   int64_t sssp_packed;           // SSSP: relax from the packed id|weight words when the partition has them
+  int64_t sssp_ring;             // SSSP near/far: a ring of bucket bitmaps (1) or one far pile rescanned per step (0)
   int64_t bfs_graph;             // BFS: 1 = chunks of supersteps replayed as captured HIP graphs
   int64_t mapped_edges;          // partition build: 1 = edge arrays in mapped host memory
 };
@@ -265,6 +266,7 @@ struct GpuPart {
   BinBounds out_bins{};          // out-degree bins over local ids
   BinBounds in_bins{};           // in-degree bins as positions in decreasing in-degree order (symmetric whole graph: out_bins)
   int64_t n_dangling = 0;        // vertices with out-degree 0
+  int32_t max_w = 0;             // largest edge weight (weighted partitions)
   int64_t n_isolated = 0;        // out-degree 0 and in-degree 0 (ZERO bin of in_bins when symmetric)
   int64_t max_out_hubs = 0;      // vertices in the HUB bin (out-degree)
   int32_t *in_off32 = nullptr;   // in-edge offsets as int32 when m < 2^31 (the bottom-up BFS step), else null
@@ -312,6 +314,8 @@ struct Workspace {
   uint32_t *h_flags = nullptr;   // pinned host flags
   int32_t *fd = nullptr;         // SSSP pull steps: frontier distances (n), allocated on first use
   uint32_t *pull_part = nullptr; // SSSP pull steps: least candidate per chunk block, allocated on first use
+  uint32_t *buckets = nullptr;   // SSSP near/far: a ring of bucket bitmaps (nwords each), allocated on first use
+  int32_t buckets_k = 0;         // bitmaps in the ring
   int64_t pull_part_cap = 0;
   tgk::BfsCtl *ctl = nullptr;    // device-resident BFS control block
   tgk::BfsCtl *h_ctl = nullptr;  // pinned host copy of it (read once per chunk of supersteps)
@@ -429,9 +433,11 @@ int set_bit(uint32_t *bits, int32_t v, hipStream_t s);
 
 void sssp_slices_free(GpuPart &g);
 // sssp.hip: relaxation of the frontier in `queue` (dist in ws.state, next
-// active set in ws.bits_a, overflow marks in ws.bits_c)
+// active set in ws.bits_a, or with bucket_k > 0 in bitmap
+// (d / bucket_delta) mod bucket_k of the ring ws.buckets; overflow marks in
+// ws.bits_c)
 int sssp_relax_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks, const Tuning &t,
-                      hipStream_t s);
+                      hipStream_t s, int32_t bucket_delta = 0, int32_t bucket_k = 0);
 int sssp_overflow_check(const GpuPart &g, Workspace &ws, hipStream_t s);
 // sssp_pull.hip: one superstep in the pull direction for the frontier whose
 // members are the set bits of `taken` (distances in ws.state, next active set

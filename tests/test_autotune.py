@@ -116,7 +116,7 @@ def test_traffic_from_counter_csvs(tmp_path):
     launches, summed over a bench kernel's kernels, scaled by the copy
     calibration; the L2 hit rate from the hit/miss pass."""
     rows = {"fetch": "FETCH_SIZE", "write": "WRITE_SIZE"}
-    names = {"sssp": ["k_sssp_relax(int const*)"],
+    names = {"sssp": ["k_sssp_relax<true>(int const*)"],
              "pr": ["k_pr_rows<true, int, 8>(Args)", "k_pr_long<true>(Args)", "k_pr_combine(x)", "k_pr_dsum(y)"],
              "bfs": ["k_bfs_step<int>(a)"]}
     for algo, kernels in names.items():
