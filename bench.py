@@ -617,7 +617,6 @@ def bench_hybrid(args):
                      "bfs_h2d_bytes": int(sum(s.get("exchange_h2d_bytes", 0) for s in st_b)),
                      "bfs_cpu_edges": int(sum(s.get("cpu_edges", 0) for s in st_b)),
                      "bfs_supersteps": int(sum(s.get("supersteps", 0) for s in st_b)),
-                     "bfs_host_pulls": int(sum(s.get("host_outbox_pulls", 0) for s in st_b)),
                      "pr_ms_per_iter": round(pr_ms / args.pr_iters, 2),
                      "pr_gteps": round(g.nnz * args.pr_iters / (pr_ms / 1e3) / 1e9, 3),
                      "pr_gpu_ms": round(sp.get("gpu_ms", 0), 2), "pr_cpu_ms": round(sp.get("cpu_ms", 0), 2),
@@ -647,12 +646,14 @@ def pearson(x, y):
 def hybrid_model(rows, num_edges, log):
     """The performance model of section 3 (Equations 1-4) against the measured
     splits.  Inputs, all measured in the same run:
-      r_cpu  the host threads' rate (their edges / their compute time) at the
-             split that gives them the most edges (HIGH, largest alpha): the
-             stand-in for a host-only run, which this engine does not make;
-      c      messages per second over PCIe: the host-to-GPU bytes of the BFS
-             exchange over its timed window, divided by 8-byte messages;
-      alpha  the share of edges whose source is on the host;
+      r_cpu  the host threads' rate (the local edges they processed / their
+             compute time) at the split that gives them the most edges
+             (HIGH, largest alpha): the stand-in for a host-only run, which
+             this engine does not make;
+      c      the copy rate over PCIe: bytes over copy time of the largest
+             exchange (PageRank's, 4 bytes per message), in messages/s;
+      alpha  the share of edges the host processes (its local edges; the
+             boundary edges of both sides are reduced on the GPU);
       beta   messages per edge after the reduction of section 3.4 (one per
              distinct remote vertex and direction).
     Predicted speedup over the host alone (Equation 4):
@@ -665,12 +666,14 @@ def hybrid_model(rows, num_edges, log):
     ref = max((r for r in pts_rows if r["strategy"] == "high"), key=lambda r: r["alpha"], default=pts_rows[0])
     rate = lambda r, alg: r[f"{alg}_cpu_edges"] / (r[f"{alg}_cpu_ms"] / 1e3)
     r_cpu = {"bfs": rate(ref, "bfs"), "pagerank": rate(ref, "pr")}
-    cs = sorted(r["bfs_h2d_bytes"] / (r["bfs_exchange_ms"] / 1e3) for r in pts_rows if r["bfs_exchange_ms"] > 0)
-    c_bytes = cs[len(cs) // 2]
-    c = c_bytes / 8.0
+    big = max(pts_rows, key=lambda r: r.get("pr_exchange_bytes", 0))
+    c_bytes = big["pr_exchange_bytes"] / (big["pr_exchange_ms"] / 1e3) if big.get("pr_exchange_ms", 0) > 0 else 0.0
+    c = c_bytes / 4.0
+    if c <= 0:
+        return None
     pts = []
     for r in pts_rows:
-        a = (r["cpu_edges"] + r["cpu_boundary_edges"]) / num_edges
+        a = r["cpu_edges"] / num_edges
         b = r["beta_reduced"]
         pt = {"strategy": r["strategy"], "alpha_set": r["alpha"], "alpha": round(a, 4), "beta": b,
               "r_cpu_bfs": round(rate(r, "bfs")), "r_cpu_pagerank": round(rate(r, "pr"))}

@@ -324,10 +324,9 @@ int partition_info(const tg_partition *p, char *json, size_t cap);
  * edges scanned or relaxations, and on hybrid partitions per-phase
  * milliseconds (gpu_ms: the GPU's kernels; cpu_ms: the host threads;
  * exchange_ms: the copies of both directions on their copy streams), bytes
- * exchanged (exchange_bytes, of which exchange_h2d_bytes host-to-GPU), the
- * host vertices' out-edges processed (cpu_edges) and the supersteps whose
- * host outbox was pulled over the slots' source lists rather than pushed
- * from the frontier (host_outbox_pulls).  Same return convention as
+ * exchanged (exchange_bytes, of which exchange_h2d_bytes host-to-GPU) and
+ * the local out-edges the host threads processed (cpu_edges; the boundary
+ * edges of both sides are reduced on the GPU).  Same return convention as
  * partition_info. */
 int tg_last_stats(char *json, size_t cap);
 

@@ -562,13 +562,13 @@ void concat(std::vector<std::vector<int32_t>> &parts, std::vector<int32_t> &out)
   }
 }
 
-// Per-call accounting.  cpu_edges: out-edges (local and boundary) of the
-// host vertices the host processed; exchange_ms: time of the copies in both
-// directions; exchange_bytes: what they moved, of which h2d_bytes went to
-// the GPU.
+// Per-call accounting.  cpu_edges: the local out-edges the host threads
+// processed; exchange_ms: time of the copies in both directions (copy
+// stream events); exchange_bytes: what they moved, of which h2d_bytes went
+// to the GPU.
 struct Phase {
   double gpu_ms = 0, cpu_ms = 0, exchange_ms = 0, bytes = 0, cpu_edges = 0, h2d_bytes = 0;
-  int64_t supersteps = 0, host_pulls = 0;
+  int64_t supersteps = 0;
 };
 
 void add_phase_stats(const Phase &ph) {
@@ -579,13 +579,13 @@ void add_phase_stats(const Phase &ph) {
   stats_add("exchange_bytes", ph.bytes);
   stats_add("exchange_h2d_bytes", ph.h2d_bytes);
   stats_add("cpu_edges", ph.cpu_edges);
-  stats_add("host_outbox_pulls", (double)ph.host_pulls);
 }
 
-// Out-edges of a host frontier, local and boundary.
+// Local out-edges of a host frontier: the edges the host threads process
+// (its boundary edges are reduced on the GPU).
 double frontier_edges(const CpuPart &C, const std::vector<int32_t> &front) {
   double s = 0;
-  for (int32_t v : front) s += (double)(C.off[v + 1] - C.off[v] + C.bdeg[v]);
+  for (int32_t v : front) s += (double)(C.off[v + 1] - C.off[v]);
   return s;
 }
 

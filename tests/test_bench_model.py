@@ -6,25 +6,24 @@ import math
 import bench
 
 
-def row(strategy, alpha, *, E, host_frac, beta, bfs_ms, pr_ms, host_rate, c_bytes):
-    # a split whose host partition holds alpha*E edges and processes them at
-    # host_rate edges/s; the exchange window moves c_bytes bytes per second
+def row(strategy, alpha, *, E, beta, bfs_ms, pr_ms, host_rate, c_bytes):
+    # a split whose host threads process alpha*E local edges at host_rate
+    # edges/s; the PageRank exchange moves c_bytes bytes per second of copy
     cpu_edges = alpha * E
-    return {"strategy": strategy, "alpha": alpha, "cpu_edges": int(cpu_edges * host_frac),
-            "cpu_boundary_edges": int(cpu_edges * (1 - host_frac)), "beta_reduced": beta,
+    return {"strategy": strategy, "alpha": alpha, "cpu_edges": int(cpu_edges), "beta_reduced": beta,
             "bfs_cpu_edges": int(cpu_edges), "bfs_cpu_ms": cpu_edges / host_rate * 1e3,
-            "bfs_h2d_bytes": int(c_bytes), "bfs_exchange_ms": 1000.0, "bfs_edges": E, "bfs_ms": bfs_ms,
+            "bfs_edges": E, "bfs_ms": bfs_ms, "pr_exchange_bytes": int(c_bytes), "pr_exchange_ms": 1000.0,
             "pr_cpu_edges": int(cpu_edges), "pr_cpu_ms": cpu_edges / host_rate * 1e3, "pr_ms_per_iter": pr_ms}
 
 
 def test_model_matches_equation_4():
-    E, r, c_bytes = 10**9, 2e9, 8e9  # c = 1e9 messages/s of 8 bytes
+    E, r, c_bytes = 10**9, 2e9, 4e9  # c = 1e9 messages/s of 4 bytes
     rows = [{"strategy": "high", "alpha": 0.0, "bfs_cpu_ms": 0}]
     # hybrid time = exactly the host's share of the host-only time: the
     # achieved speedup is 1/alpha, the model's beta = 0 limit
     for a in (0.1, 0.25, 0.5):
         t = a * E / r * 1e3
-        rows.append(row("high", a, E=E, host_frac=0.5, beta=0.0, bfs_ms=t, pr_ms=t, host_rate=r, c_bytes=c_bytes))
+        rows.append(row("high", a, E=E, beta=0.0, bfs_ms=t, pr_ms=t, host_rate=r, c_bytes=c_bytes))
     m = bench.hybrid_model(rows, E, lambda s: None)
     assert m["r_cpu_from"] == "high alpha=0.5"
     assert math.isclose(m["r_cpu_eps"]["bfs"], r, rel_tol=1e-6)
@@ -39,9 +38,8 @@ def test_model_matches_equation_4():
 
 def test_model_communication_term():
     # beta * r_cpu / c adds to alpha in the denominator (Equation 4)
-    E, r, c_bytes, beta = 10**9, 4e9, 8e9, 0.05
-    rows = [row("high", 0.2, E=E, host_frac=1.0, beta=beta, bfs_ms=100.0, pr_ms=100.0, host_rate=r,
-                c_bytes=c_bytes)]
+    E, r, c_bytes, beta = 10**9, 4e9, 4e9, 0.05
+    rows = [row("high", 0.2, E=E, beta=beta, bfs_ms=100.0, pr_ms=100.0, host_rate=r, c_bytes=c_bytes)]
     m = bench.hybrid_model(rows, E, lambda s: None)
     p = m["points"][0]
     expect = 1.0 / (beta * r / 1e9 + 0.2)
