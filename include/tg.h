@@ -141,7 +141,10 @@ int partition_by_degree(const tg_graph *g, int strategy, double cpu_edge_share,
  *                in a ring of bucket bitmaps by distance and filters only
  *                the current bucket, when at most 16 buckets of width
  *                sssp_delta span the largest weight; 0: one far pile,
- *                rescanned every superstep);
+ *                rescanned every superstep), "sssp_split" (1, with the ring
+ *                and packed rows: a bucket's vertices relax their edges
+ *                lighter than sssp_delta while it is processed and their
+ *                heavier edges once when it is done);
  *   layout       "mapped_edges" (1: the edge arrays -- neighbour ids, weights,
  *                in-edge ids -- stay in pinned host memory mapped into the
  *                GPU and kernels read them over the host link, for graphs

@@ -330,6 +330,7 @@ Tuning default_tuning() {
   t.sssp_lanes = 4;
   t.sssp_packed = 1;
   t.sssp_ring = 1;
+  t.sssp_split = 1;
   t.bfs_graph = 0;  // replaying captured chunks measured 1-2% slower than direct launches
   t.mapped_edges = 0;
   return t;
@@ -379,6 +380,7 @@ int parse_tuning(const char *json, Tuning *t) {
   if (json_int(json, "sssp_lanes", &v)) t->sssp_lanes = v;
   if (json_int(json, "sssp_packed", &v)) t->sssp_packed = v;
   if (json_int(json, "sssp_ring", &v)) t->sssp_ring = v;
+  if (json_int(json, "sssp_split", &v)) t->sssp_split = v;
   if (json_int(json, "bfs_graph", &v)) t->bfs_graph = v;
   if (json_int(json, "mapped_edges", &v)) t->mapped_edges = v;
   if (t->mapped_edges != 0 && t->mapped_edges != 1) return set_error(TG_EINVAL, "tuning: mapped_edges must be 0 or 1");
@@ -387,6 +389,7 @@ int parse_tuning(const char *json, Tuning *t) {
   if (t->sssp_lanes < 1 || t->sssp_lanes > MAX_LANES) return set_error(TG_EINVAL, "tuning: sssp_lanes outside [1, 4]");
   if (t->sssp_packed != 0 && t->sssp_packed != 1) return set_error(TG_EINVAL, "tuning: sssp_packed must be 0 or 1");
   if (t->sssp_ring != 0 && t->sssp_ring != 1) return set_error(TG_EINVAL, "tuning: sssp_ring must be 0 or 1");
+  if (t->sssp_split != 0 && t->sssp_split != 1) return set_error(TG_EINVAL, "tuning: sssp_split must be 0 or 1");
   if (t->bfs_lanes != 1 && t->bfs_lanes != 2) return set_error(TG_EINVAL, "tuning: bfs_lanes must be 1 or 2");
   if (t->bfs_td_grid < 1 || t->bfs_td_grid > 16384 || t->bfs_bu_grid < 2 || t->bfs_bu_grid > 16384)
     return set_error(TG_EINVAL, "tuning: bfs_td_grid must be in [1, 16384] and bfs_bu_grid in [2, 16384]");
@@ -728,9 +731,16 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
     bool small = true;
     for (int64_t e = 0; e < m && small; ++e) small = w[e] >= 0 && w[e] < 256;
     if (small) {
+      // each row by weight (the word's top byte), so that the edges lighter
+      // than a bound are a prefix of the row (the light/heavy split)
       std::vector<int32_t> cw((size_t)m);
-#pragma omp parallel for schedule(static)
-      for (int64_t e = 0; e < m; ++e) cw[e] = (int32_t)((uint32_t)col[e] | ((uint32_t)w[e] << 24));
+#pragma omp parallel for schedule(dynamic, 1024)
+      for (int64_t v = 0; v < n; ++v) {
+        uint32_t *row = reinterpret_cast<uint32_t *>(cw.data()) + off[v];
+        const int64_t len = off[v + 1] - off[v];
+        for (int64_t k = 0; k < len; ++k) row[k] = (uint32_t)col[off[v] + k] | ((uint32_t)w[off[v] + k] << 24);
+        std::sort(row, row + len);
+      }
       TG_TRY(edges(reinterpret_cast<int32_t **>(&gp.out.cw), cw));
     }
   }
@@ -975,7 +985,7 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld,"
            "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld,\"pr_xcd\":%lld,\"pr_rows\":%lld,"
            "\"bfs_do\":%lld,\"bfs_alpha\":%lld,\"bfs_beta\":%lld,\"sssp_xcd\":%lld,\"bfs_lanes\":%lld,"
-           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld,\"sssp_pull\":%lld,\"sssp_lanes\":%lld,\"bfs_graph\":%lld,\"mapped_edges\":%lld,\"sssp_packed\":%lld,\"sssp_ring\":%lld}",
+           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld,\"sssp_pull\":%lld,\"sssp_lanes\":%lld,\"bfs_graph\":%lld,\"mapped_edges\":%lld,\"sssp_packed\":%lld,\"sssp_ring\":%lld,\"sssp_split\":%lld}",
            (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
            (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk,
            (long long)p->tune.pr_lds_verts, (long long)p->tune.pr_grid, (long long)p->tune.bfs_lds_words,
@@ -985,7 +995,7 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            (long long)p->tune.bfs_beta, (long long)p->tune.sssp_xcd, (long long)p->tune.bfs_lanes,
            (long long)p->tune.bfs_td_grid, (long long)p->tune.bfs_bu_grid, (long long)p->tune.sssp_pull,
            (long long)p->tune.sssp_lanes, (long long)p->tune.bfs_graph, (long long)p->tune.mapped_edges,
-           (long long)p->tune.sssp_packed, (long long)p->tune.sssp_ring);
+           (long long)p->tune.sssp_packed, (long long)p->tune.sssp_ring, (long long)p->tune.sssp_split);
   s += buf;
   s += ",\"tuning_source\":\"" + p->tuning_source + "\"";
   s += hybrid_info_json(p);

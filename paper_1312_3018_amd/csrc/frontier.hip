@@ -105,14 +105,16 @@ __device__ __forceinline__ void sssp_filter_words(uint32_t (&w)[N], int64_t word
 }
 
 // SSSP compaction, first pass: filter the active bitmap (sssp_filter_words),
-// leave the untaken active bits in `bits`, the taken ones in `keep_out`, and
-// each block's count in bcount.  With rest_cnt, the vertices left active
-// beyond the threshold are counted into it and their least distance goes
-// into rest_min (both spread counters; rest_min's slots start all ones).
+// leave the untaken active bits in `bits`, the taken ones in `keep_out`
+// (and, with `members`, also OR them into it), and each block's count in
+// bcount.  With rest_cnt, the vertices left active beyond the threshold are
+// counted into it and their least distance goes into rest_min (both spread
+// counters; rest_min's slots start all ones).
 __global__ __launch_bounds__(CT) void k_sssp_filter(uint32_t *__restrict__ bits, uint32_t *__restrict__ keep_out,
                                                     uint32_t *__restrict__ bcount, const int32_t *__restrict__ dist,
                                                     int32_t *__restrict__ settled, int32_t thresh,
-                                                    unsigned long long *rest_cnt, unsigned long long *rest_min) {
+                                                    unsigned long long *rest_cnt, unsigned long long *rest_min,
+                                                    uint32_t *__restrict__ members) {
   const int64_t q = (int64_t)blockIdx.x * CT + threadIdx.x;  // word index
   const uint32_t v = bits[q];
   uint32_t w[1] = {v}, keep[1], dr[1];
@@ -121,6 +123,7 @@ __global__ __launch_bounds__(CT) void k_sssp_filter(uint32_t *__restrict__ bits,
   sssp_filter_words<1>(w, q, dist, settled, thresh, keep, dr, r, rmin);
   bits[q] = v & ~(keep[0] | dr[0]);
   keep_out[q] = keep[0];
+  if (members && keep[0]) members[q] |= keep[0];
   if (rest_cnt) {
     r = cblock_sum(r);
     for (int o = 32; o > 0; o >>= 1) {
@@ -438,7 +441,7 @@ int frontier_plan_bfs_dev(const GpuPart &g, Workspace &ws, const Tuning &t, hipS
 
 int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
                           int32_t *settled, int32_t thresh, bool near, const BinBounds &bb, hipStream_t s,
-                          unsigned long long *degsum) {
+                          unsigned long long *degsum, uint32_t *members) {
   const int blocks = (int)(ws.nwords / WPB);
   unsigned long long *rest_cnt = nullptr, *rest_min = nullptr;
   if (near) {
@@ -451,7 +454,7 @@ int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32
   }
   // the taken bits go to bits_b (free during SSSP and connected components)
   hipLaunchKernelGGL(k_sssp_filter, dim3(blocks), dim3(CT), 0, s, bits, ws.bits_b, ws.bcount, dist, settled,
-                     near ? thresh : TG_INF, rest_cnt, rest_min);
+                     near ? thresh : TG_INF, rest_cnt, rest_min, members);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, ws.bits_b, nullptr, 4, ws.bcount, queue,
                      nullptr, 0, bb, g.n, ws.plan, nullptr, degsum ? g.out.off : nullptr, degsum, nullptr, (int64_t)0);
   TG_HIP(hipGetLastError());

@@ -99,6 +99,13 @@ __device__ __forceinline__ int segment_of(int64_t vb, const Plan &P) {
   return b;
 }
 
+// As assign_work_rows, with vertex v's edges [first(v), last(v)); a hub's
+// chunks start at first(v).
+template <typename FirstF, typename LastF>
+__device__ __forceinline__ Assign assign_work_range(int64_t vb, const Plan &P, const int32_t *queue,
+                                                    const int32_t *order, const int64_t *hubpref, FirstF first,
+                                                    LastF last, int64_t hub_chunk);
+
 // Map virtual block `vb` to this thread's work.  `queue == nullptr` means the
 // identity frontier (every vertex, in id order) optionally through `order`.
 // `row(i)` returns the offset of row i (rows v and v+1 bound vertex v's edges).
@@ -106,6 +113,14 @@ template <typename RowF>
 __device__ __forceinline__ Assign assign_work_rows(int64_t vb, const Plan &P, const int32_t *queue,
                                                    const int32_t *order, const int64_t *hubpref, RowF row,
                                                    int64_t hub_chunk) {
+  return assign_work_range(vb, P, queue, order, hubpref, [row](int32_t v) { return row(v); },
+                           [row](int32_t v) { return row((int64_t)v + 1); }, hub_chunk);
+}
+
+template <typename FirstF, typename LastF>
+__device__ __forceinline__ Assign assign_work_range(int64_t vb, const Plan &P, const int32_t *queue,
+                                                    const int32_t *order, const int64_t *hubpref, FirstF first,
+                                                    LastF last, int64_t hub_chunk) {
   Assign a;
   a.ok = false;
   a.chunk = -1;
@@ -124,8 +139,8 @@ __device__ __forceinline__ Assign assign_work_rows(int64_t vb, const Plan &P, co
     qi = P.pos[0] + lo;
     int32_t v = queue ? queue[qi] : (order ? order[qi] : qi);
     int64_t k = local - hubpref[lo];
-    a.e_begin = row(v) + k * hub_chunk;
-    int64_t end = row(v + 1);
+    a.e_begin = first(v) + k * hub_chunk;
+    int64_t end = last(v);
     a.e_end = (a.e_begin + hub_chunk < end) ? a.e_begin + hub_chunk : end;
     a.v = v;
     a.qi = qi;
@@ -144,8 +159,8 @@ __device__ __forceinline__ Assign assign_work_rows(int64_t vb, const Plan &P, co
   if (qi < P.pos[b + 1]) {
     int32_t v = queue ? stream_load(queue + qi) : (order ? stream_load(order + qi) : qi);
     a.v = v;
-    a.e_begin = row(v);
-    a.e_end = row(v + 1);
+    a.e_begin = first(v);
+    a.e_end = last(v);
     a.ok = true;
   }
   return a;

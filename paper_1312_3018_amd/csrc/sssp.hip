@@ -49,6 +49,23 @@ __global__ __launch_bounds__(BLOCK) void k_ring_any(const uint32_t *__restrict__
   if (__syncthreads_or(acc != 0u) && threadIdx.x == 0) any[blockIdx.y] = 1u;
 }
 
+// Per vertex: how many of its packed out-edges (row sorted by weight) are
+// lighter than delta (< 256), and how many are not.
+__global__ void k_light_counts(const int64_t *__restrict__ off, const uint32_t *__restrict__ cw, int64_t n,
+                               uint32_t bound, int32_t *__restrict__ lcnt, int32_t *__restrict__ hcnt) {
+  const int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (v >= n) return;
+  int64_t lo = off[v], hi = off[v + 1];
+  const int64_t b = lo, e = hi;
+  while (lo < hi) {  // first word >= bound (weight >= delta)
+    const int64_t mid = (lo + hi) >> 1;
+    if (cw[mid] < bound) lo = mid + 1;
+    else hi = mid;
+  }
+  lcnt[v] = (int32_t)(lo - b);
+  hcnt[v] = (int32_t)(e - lo);
+}
+
 // Where an improved vertex is marked active: one bitmap, or (near/far with
 // a bucket ring) bitmap (d / delta) mod k of the ring, nwords words apart.
 struct ActiveSet {
@@ -102,7 +119,12 @@ __device__ __forceinline__ void load_edge(const int32_t *__restrict__ col, const
   }
 }
 
-template <bool PACKED>
+// Which edges of a frontier vertex relax: its whole row, or (packed rows,
+// sorted by weight) its first lcnt[v] edges (lighter than the step) or the
+// rest.
+enum RelaxRange { ROW_ALL = 0, ROW_LIGHT = 1, ROW_HEAVY = 2 };
+
+template <bool PACKED, int RANGE>
 __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ Pp,
                                                       const int32_t *__restrict__ queue,
                                                       const int64_t *__restrict__ hubpref,
@@ -112,7 +134,7 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
                                                       const uint32_t *__restrict__ cw, int32_t *dist,
                                                       const ActiveSet act, uint32_t *ovf, uint32_t *flags,
                                                       int64_t hub_chunk, unsigned long long *work, int32_t hot,
-                                                      int vb_bin_lo) {
+                                                      int vb_bin_lo, const int32_t *__restrict__ lcnt) {
   extern __shared__ int32_t lds_d[];
   for (int32_t i = threadIdx.x; i < hot; i += BLOCK) lds_d[i] = dist[i];
   const Plan &P = load_plan(Pp);  // (its barrier also publishes lds_d)
@@ -120,11 +142,17 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
   unsigned long long n_edges = 0, n_verts = 0;
   // virtual blocks of bins vb_bin_lo.. only
   for (int64_t vb = P.vb[vb_bin_lo] + blockIdx.x; vb < total; vb += gridDim.x) {
-    const Assign a = assign_work(vb, P, queue, nullptr, hubpref, off, hub_chunk);
+    const auto first = [off, lcnt](int32_t v) -> int64_t {
+      return RANGE == ROW_HEAVY ? stream_load(off + v) + (int64_t)lcnt[v] : stream_load(off + v);
+    };
+    const auto last = [off, lcnt](int32_t v) -> int64_t {
+      return RANGE == ROW_LIGHT ? stream_load(off + v) + (int64_t)lcnt[v] : stream_load(off + v + 1);
+    };
+    const Assign a = assign_work_range(vb, P, queue, nullptr, hubpref, first, last, hub_chunk);
     if (!a.ok) continue;
     if (a.lane == 0) {
       n_edges += (unsigned long long)(a.e_end - a.e_begin);
-      n_verts += (a.bin != BIN_HUB || a.e_begin == off[a.v]) ? 1 : 0;
+      n_verts += (a.bin != BIN_HUB || a.e_begin == first(a.v)) ? 1 : 0;
     }
     const int32_t dv = dist[a.v];
     const int64_t st = a.stride;
@@ -223,22 +251,35 @@ __global__ __launch_bounds__(BLOCK) void k_overflow_check(const uint32_t *__rest
 namespace tg {
 
 int sssp_relax_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks, const Tuning &t,
-                      hipStream_t s, int32_t bucket_delta, int32_t bucket_k) {
+                      hipStream_t s, int32_t bucket_delta, int32_t bucket_k, int range) {
   if (vblocks <= 0) return TG_OK;
   const int32_t hot = (int32_t)std::min<int64_t>(t.sssp_lds_verts, g.n);
   const int grid = hot > 0 ? (int)std::min<int64_t>(launch_grid(vblocks), t.sssp_grid) : launch_grid(vblocks);
   // improved vertices: the active bitmap, or the bucket ring of their new distance
   const ActiveSet act = bucket_k > 0 ? ActiveSet{ws.buckets, bucket_delta, bucket_k, ws.nwords}
                                      : ActiveSet{ws.bits_a, 0, 0, 0};
+  const size_t lds = (size_t)hot * sizeof(int32_t);
   const int tk = ktimer_start(s);
-  if (t.sssp_packed && g.out.cw)
-    hipLaunchKernelGGL(k_sssp_relax<true>, dim3(grid), dim3(BLOCK), (size_t)hot * sizeof(int32_t), s, ws.plan, queue,
-                       ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, act, ws.bits_c,
-                       ws.counters, t.hub_chunk, ws.work, hot, 0);
-  else
-    hipLaunchKernelGGL(k_sssp_relax<false>, dim3(grid), dim3(BLOCK), (size_t)hot * sizeof(int32_t), s, ws.plan,
-                       queue, ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, act, ws.bits_c,
-                       ws.counters, t.hub_chunk, ws.work, hot, 0);
+  if (range == ROW_LIGHT || range == ROW_HEAVY) {
+    // the split needs the packed rows sorted by weight and the light counts
+    if (!g.out.cw || !g.lcnt) return set_error(TG_EDEVICE, "sssp: light/heavy relaxation without packed rows");
+    if (range == ROW_LIGHT)
+      hipLaunchKernelGGL((k_sssp_relax<true, ROW_LIGHT>), dim3(grid), dim3(BLOCK), lds, s, ws.plan, queue,
+                         ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, act, ws.bits_c, ws.counters,
+                         t.hub_chunk, ws.work, hot, 0, g.lcnt);
+    else
+      hipLaunchKernelGGL((k_sssp_relax<true, ROW_HEAVY>), dim3(grid), dim3(BLOCK), lds, s, ws.plan, queue,
+                         ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, act, ws.bits_c, ws.counters,
+                         t.hub_chunk, ws.work, hot, 0, g.lcnt);
+  } else if (t.sssp_packed && g.out.cw) {
+    hipLaunchKernelGGL((k_sssp_relax<true, ROW_ALL>), dim3(grid), dim3(BLOCK), lds, s, ws.plan, queue, ws.hubpref,
+                       g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, act, ws.bits_c, ws.counters, t.hub_chunk,
+                       ws.work, hot, 0, nullptr);
+  } else {
+    hipLaunchKernelGGL((k_sssp_relax<false, ROW_ALL>), dim3(grid), dim3(BLOCK), lds, s, ws.plan, queue, ws.hubpref,
+                       g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, act, ws.bits_c, ws.counters, t.hub_chunk,
+                       ws.work, hot, 0, nullptr);
+  }
   ktimer_stop(tk, s, "sssp_relax");
   TG_HIP(hipGetLastError());
   return TG_OK;
@@ -335,9 +376,10 @@ static int sssp_relax_cls_launch(const GpuPart &g, Workspace &ws, const int32_t 
                        ws.work, (int)BIN_G16);
   }
   if (vb_lo_n > 0)
-    hipLaunchKernelGGL(k_sssp_relax<false>, dim3(launch_grid(vb_lo_n)), dim3(BLOCK), 0, s, ws.plan, queue,
-                       ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state, ActiveSet{ws.bits_a, 0, 0, 0},
-                       ws.bits_c, ws.counters, t.hub_chunk, ws.work, 0, (int)BIN_G16);
+    hipLaunchKernelGGL((k_sssp_relax<false, ROW_ALL>), dim3(launch_grid(vb_lo_n)), dim3(BLOCK), 0, s, ws.plan,
+                       queue, ws.hubpref, g.out.off, g.out.col, g.out.w, g.out.cw, ws.state,
+                       ActiveSet{ws.bits_a, 0, 0, 0}, ws.bits_c, ws.counters, t.hub_chunk, ws.work, 0, (int)BIN_G16,
+                       nullptr);
   ktimer_stop(tk, s, "sssp_relax");
   TG_HIP(hipGetLastError());
   return TG_OK;
@@ -345,31 +387,56 @@ static int sssp_relax_cls_launch(const GpuPart &g, Workspace &ws, const int32_t 
 
 namespace {
 
+// Whether the ring schedule splits rows into light and heavy parts.
+bool sssp_split_on(const tg_partition *p) {
+  const Tuning &t = p->tune;
+  return t.sssp_split && t.sssp_packed && p->gpu.out.cw && t.sssp_delta > 0 && t.sssp_delta < 256;
+}
+
 // The near/far schedule over a ring of k bucket bitmaps (see gpu_sssp).
 // Distances, settled values and overflow marks are set up by the caller.
+// With the light/heavy split (Meyer and Sanders' delta-stepping): while a
+// bucket is processed its vertices relax only their edges lighter than
+// delta, which may land in the same bucket; once it is empty its members'
+// distances are final and each relaxes its heavy edges once, into later
+// buckets.
 int gpu_sssp_ring(tg_partition *p, Workspace &ws, int32_t root, hipStream_t s, int32_t k, int64_t *rounds_out,
                   int64_t *pulls_out) {
   GpuPart &g = p->gpu;
   const int64_t delta = p->tune.sssp_delta;
-  const BinBounds &bb = g.out_bins;
-  if (!ws.buckets || ws.buckets_k < k) {
-    TG_TRY(dalloc(ws.arena, &ws.buckets, (size_t)k * ws.nwords));
-    ws.buckets_k = k;
+  const bool split = sssp_split_on(p) && g.lcnt && g.split_delta == delta;
+  const BinBounds &bb = split ? g.light_bins : g.out_bins;
+  const int kb = k + (split ? 1 : 0);  // the bucket's members after the ring
+  if (!ws.buckets || ws.buckets_k < kb) {
+    TG_TRY(dalloc(ws.arena, &ws.buckets, (size_t)kb * ws.nwords));
+    ws.buckets_k = kb;
   }
-  TG_HIP(hipMemsetAsync(ws.buckets, 0, (size_t)k * ws.nwords * sizeof(uint32_t), s));
+  uint32_t *members = split ? ws.buckets + (int64_t)k * ws.nwords : nullptr;
+  TG_HIP(hipMemsetAsync(ws.buckets, 0, (size_t)kb * ws.nwords * sizeof(uint32_t), s));
   TG_TRY(set_bit(ws.buckets, root, s));  // bucket 0: distance 0
   int64_t lo = 0, rounds = 0;
   for (;;) {
-    if (rounds > 2 * g.n + 2 || lo > (int64_t)TG_INF)
+    if (rounds > 4 * g.n + 4 || lo > (int64_t)TG_INF)
       return set_error(TG_EDEVICE, "sssp: no convergence after %lld rounds", (long long)rounds);
     uint32_t *bits = ws.buckets + ((lo / delta) % k) * ws.nwords;
     // every unsettled bit of the current bucket is in [lo, lo + delta): all are taken
-    TG_TRY(frontier_compact_sssp(g, ws, bits, ws.queue, ws.state, ws.settled, TG_INF, false, bb, s, nullptr));
-    TG_TRY(frontier_plan_bins(g, ws, ws.queue, bb, nullptr, p->tune, s, true));
+    TG_TRY(frontier_compact_sssp(g, ws, bits, ws.queue, ws.state, ws.settled, TG_INF, false, bb, s, nullptr,
+                                 members));
+    TG_TRY(frontier_plan_bins(g, ws, ws.queue, bb, split ? g.lcnt : nullptr, p->tune, s, true));
     if (ws.h_plan->count > 0) {
       ++rounds;
-      TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s, (int32_t)delta, k));
+      TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s, (int32_t)delta, k,
+                               split ? 1 : 0));
       continue;
+    }
+    if (split) {
+      // the bucket is settled: its members relax their heavy edges once
+      TG_TRY(frontier_compact(g, ws, 1, members, nullptr, ws.queue, nullptr, 0, s));
+      TG_TRY(frontier_plan_bins(g, ws, ws.queue, g.out_bins, g.hcnt, p->tune, s, true));
+      if (ws.h_plan->count > 0) {
+        ++rounds;
+        TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s, (int32_t)delta, k, 2));
+      }
     }
     // the current bucket is empty: move to the next bucket with a set bit,
     // if any (the ring holds every active vertex)
@@ -394,6 +461,49 @@ int gpu_sssp_ring(tg_partition *p, Workspace &ws, int32_t root, hipStream_t s, i
 }
 
 }  // namespace
+
+// Light counts and light-degree bins for the split at the current step
+// (once per partition and step, before lanes share them).  The bins place
+// vertex v by its expected light degree, deg(v) times the graph's share of
+// light edges (at least 1 for a vertex with edges): a contiguous id range
+// per bin, as the compaction needs.
+int sssp_split_prepare(tg_partition *p, hipStream_t s) {
+  GpuPart &g = p->gpu;
+  const Tuning &t = p->tune;
+  if (!sssp_split_on(p) || g.split_delta == t.sssp_delta) return TG_OK;
+  const int64_t n = g.n;
+  if (!g.lcnt) {
+    TG_TRY(dalloc(p->arena, &g.lcnt, (size_t)std::max<int64_t>(n, 1)));
+    TG_TRY(dalloc(p->arena, &g.hcnt, (size_t)std::max<int64_t>(n, 1)));
+  }
+  if (n > 0) {
+    hipLaunchKernelGGL(k_light_counts, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, g.out.off,
+                       g.out.cw, n, (uint32_t)t.sssp_delta << 24, g.lcnt, g.hcnt);
+    TG_HIP(hipGetLastError());
+  }
+  std::vector<int32_t> lc((size_t)n);
+  if (n > 0) TG_HIP(hipMemcpyAsync(lc.data(), g.lcnt, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  TG_HIP(hipStreamSynchronize(s));
+  double light = 0;
+  for (int32_t c : lc) light += c;
+  const double frac = g.m > 0 ? light / (double)g.m : 0.0;
+  int64_t i = 0;
+  BinBounds bb{};
+  // at least one: the degree-0 bin gets no work, and a vertex with edges
+  // may have light ones whatever its expected count
+  const auto light_deg = [&](int64_t i) {
+    const int64_t d = g.h_deg[i];
+    return d > 0 ? std::max<int64_t>(1, (int64_t)((double)d * frac + 0.5)) : (int64_t)0;
+  };
+  for (int b = 0; b < NBIN; ++b) {
+    while (i < n && bin_of_degree(light_deg(i), t) < b) ++i;
+    bb.bstart[b] = i;
+  }
+  bb.bstart[NBIN] = n;
+  g.light_bins = bb;
+  g.split_delta = t.sssp_delta;
+  return TG_OK;
+}
 
 int gpu_sssp(tg_partition *p, Workspace &ws, int32_t root, hipStream_t s, int64_t *rounds_out, int64_t *pulls_out) {
   GpuPart &g = p->gpu;
@@ -529,6 +639,7 @@ int gpu_sssp_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int3
   // per-partition layouts are built here, once, before lanes share them
   if (t.sssp_xcd) TG_TRY(build_sssp_slices(p, s));
   if (t.sssp_pull > 0 && t.sssp_xcd == 0 && sssp_pull_supported(p->gpu)) TG_TRY(sssp_pull_prepare(p, s));
+  TG_TRY(sssp_split_prepare(p, s));
   const int nl = (int)std::max<int64_t>(1, std::min<int64_t>(t.sssp_lanes, nr));
   hipStream_t st[MAX_LANES];
   for (int l = 0; l < nl; ++l) TG_TRY(lane_stream(p, l, s, &st[l]));

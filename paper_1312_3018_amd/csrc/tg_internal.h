@@ -94,6 +94,7 @@ struct Tuning {
   int64_t sssp_lanes;            // SSSP: searches in flight on their own streams (1..4)
   int64_t sssp_packed;           // SSSP: relax from the packed id|weight words when the partition has them
   int64_t sssp_ring;             // SSSP near/far: a ring of bucket bitmaps (1) or one far pile rescanned per step (0)
+  int64_t sssp_split;            // SSSP ring: edges lighter than the step relax per pass, heavier ones once per bucket
   int64_t bfs_graph;             // BFS: 1 = chunks of supersteps replayed as captured HIP graphs
   int64_t mapped_edges;          // partition build: 1 = edge arrays in mapped host memory
 };
@@ -154,7 +155,8 @@ struct DevCSR {
   int32_t *col = nullptr;
   int32_t *w = nullptr;
   // id and weight in one word, id | w << 24, where every id fits in 24 bits
-  // and every weight in 8 (out-edges of a weighted partition only)
+  // and every weight in 8 (out-edges of a weighted partition only); each
+  // row sorted by weight
   uint32_t *cw = nullptr;
 };
 
@@ -267,6 +269,12 @@ struct GpuPart {
   BinBounds in_bins{};           // in-degree bins as positions in decreasing in-degree order (symmetric whole graph: out_bins)
   int64_t n_dangling = 0;        // vertices with out-degree 0
   int32_t max_w = 0;             // largest edge weight (weighted partitions)
+  // SSSP light/heavy split at split_delta (packed rows only): per vertex the
+  // number of out-edges lighter than it and the rest, and degree bins for the
+  // light parts
+  int32_t *lcnt = nullptr, *hcnt = nullptr;
+  int64_t split_delta = 0;
+  BinBounds light_bins{};
   int64_t n_isolated = 0;        // out-degree 0 and in-degree 0 (ZERO bin of in_bins when symmetric)
   int64_t max_out_hubs = 0;      // vertices in the HUB bin (out-degree)
   int32_t *in_off32 = nullptr;   // in-edge offsets as int32 when m < 2^31 (the bottom-up BFS step), else null
@@ -398,10 +406,11 @@ int frontier_plan(const GpuPart &g, Workspace &ws, const int32_t *queue, const T
 // with `near`, dist < thresh; stale bits are dropped; with `near` the others
 // stay active and spread counters 5 and 6 get their count and least
 // distance.
-// With `degsum`, the taken frontier's out-degree sum is added to it.
+// With `degsum`, the taken frontier's out-degree sum is added to it; with
+// `members`, the taken bits are also ORed into that bitmap.
 int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
                           int32_t *settled, int32_t thresh, bool near, const BinBounds &bb, hipStream_t s,
-                          unsigned long long *degsum = nullptr);
+                          unsigned long long *degsum = nullptr, uint32_t *members = nullptr);
 // Plan over the queue with bins `bb` (queue positions set by a compaction
 // with the same bins) and hub chunks sized by len[v] edges.
 int frontier_plan_bins(const GpuPart &g, Workspace &ws, const int32_t *queue, const BinBounds &bb,
@@ -435,9 +444,10 @@ void sssp_slices_free(GpuPart &g);
 // sssp.hip: relaxation of the frontier in `queue` (dist in ws.state, next
 // active set in ws.bits_a, or with bucket_k > 0 in bitmap
 // (d / bucket_delta) mod bucket_k of the ring ws.buckets; overflow marks in
-// ws.bits_c)
+// ws.bits_c).  range 1 / 2: only the light / heavy part of each row (the
+// packed rows, split at p->gpu.split_delta)
 int sssp_relax_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks, const Tuning &t,
-                      hipStream_t s, int32_t bucket_delta = 0, int32_t bucket_k = 0);
+                      hipStream_t s, int32_t bucket_delta = 0, int32_t bucket_k = 0, int range = 0);
 int sssp_overflow_check(const GpuPart &g, Workspace &ws, hipStream_t s);
 // sssp_pull.hip: one superstep in the pull direction for the frontier whose
 // members are the set bits of `taken` (distances in ws.state, next active set

@@ -196,20 +196,25 @@ def test_sssp_variants(gpu, rmat14, xcd, delta):
                 assert np.array_equal(dist[i], oracle.sssp(graph.offsets, graph.cols, wt, r)), (tuning, graph.n, r)
 
 
-@pytest.mark.parametrize("ring", [0, 1])
-def test_sssp_bucket_ring(gpu, rmat14, ring):
-    """The near/far step over a ring of bucket bitmaps (and, with ring = 0,
-    over one far pile) gives the oracle's distances for bucket widths that
-    need 3 to 12 bitmaps with weights 1..255, and for widths 1 and 2 with
-    weights 1..3 (up to 5 bitmaps), on symmetric and directed graphs, for
-    several roots in a row on one partition."""
+@pytest.mark.parametrize("ring,split", [(0, 0), (1, 0), (1, 1)])
+def test_sssp_bucket_ring(gpu, rmat14, ring, split):
+    """The near/far step over a ring of bucket bitmaps (with and without
+    the light/heavy split of each row, and, with ring = 0, over one far
+    pile) gives the oracle's distances for bucket widths that need 3 to 12
+    bitmaps with weights 1..255, and for widths 1 and 2 with weights 1..3
+    (width 1: no light edges at all), on symmetric and directed graphs, with
+    hub rows split into chunks, for several roots in a row on one
+    partition."""
     g, w = rmat14
     gd = graphgen.rmat(12, symmetrize=False)
     wd = graphgen.weights(gd, seed=4)
     w3 = (w % 3 + 1).astype(np.int32)  # 1..3, one value per undirected edge like w
-    cases = [(g, w, d) for d in (24, 32, 128)] + [(gd, wd, 32), (g, w3, 1), (g, w3, 2)]
-    for graph, wt, delta in cases:
-        P = load(gpu, graph, wt, {"sssp_delta": delta, "sssp_ring": ring})
+    small = {"hub_min_deg": 300, "block_min_deg": 100, "wave_min_deg": 24, "g16_min_deg": 6, "g4_min_deg": 2,
+             "hub_chunk": 256}
+    cases = [(g, w, d, None) for d in (24, 32, 128)] + [(g, w, 24, small), (gd, wd, 32, None), (g, w3, 1, None),
+                                                       (g, w3, 2, small)]
+    for graph, wt, delta, bins in cases:
+        P = load(gpu, graph, wt, dict(bins or {}, sssp_delta=delta, sssp_ring=ring, sssp_split=split))
         roots = graphgen.sample_roots(graph, 3, seed=delta)
         dist = gpu.sssp(P, roots).cpu().numpy()
         for i, r in enumerate(roots):
