@@ -65,13 +65,15 @@ def load_traffic(kernel: str, workload: str):
     return None
 
 
-# Rows of profiles/traffic.json: the kernels whose HBM bytes make up one
-# launch of each bench kernel, and the pass directories (<algo>_fetch,
-# <algo>_write, <algo>_hit) their counters come from.
+# Rows of profiles/traffic.json: the pass directories (<algo>_fetch,
+# <algo>_write, <algo>_hit) their counters come from, the kernels, and how
+# they make up one launch of the bench kernel: "sum" (each launch runs all of
+# them: their per-launch means add) or "pool" (each launch is one of them:
+# the mean over all their launches).
 TRAFFIC_ROWS = {
-    "sssp_relax": ("sssp", ["k_sssp_relax<true>"]),
-    "pr_gather": ("pr", ["k_pr_rows<true, int, 8>", "k_pr_long<true>", "k_pr_combine", "k_pr_dsum"]),
-    "bfs_step": ("bfs", ["k_bfs_step<int>"]),
+    "sssp_relax": ("sssp", ["k_sssp_relax<true, 1>", "k_sssp_relax<true, 2>"], "pool"),
+    "pr_gather": ("pr", ["k_pr_rows<true, int, 8>", "k_pr_long<true>", "k_pr_combine", "k_pr_dsum"], "sum"),
+    "bfs_step": ("bfs", ["k_bfs_step<int>"], "sum"),
 }
 # A 1 GiB device-to-device copy (--copy-calibration) reads FETCH_SIZE =
 # 524317 KiB and WRITE_SIZE = 1048576 KiB on MI355X.
@@ -91,24 +93,32 @@ def traffic_from(pmc_dir: str, workload: str = "rmat24") -> dict:
         m = re.search(r"(k_[a-z_0-9]+)(<[^>(]*>)?", s)
         return m.group(1) + (m.group(2) or "") if m else s.split("(")[0]
 
-    def mean_by_kernel(tag):
+    def values_by_kernel(tag):
         agg = {}
         with open(os.path.join(pmc_dir, tag, "run_counter_collection.csv")) as fh:
             for r in csv.DictReader(fh):
                 agg.setdefault((kname(r["Kernel_Name"]), r["Counter_Name"]), []).append(float(r["Counter_Value"]))
-        return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
+        return agg
+
+    def per_launch(agg, names, counter, how):
+        lists = [agg.get((n, counter), []) for n in names]
+        if how == "pool":
+            vals = [x for lst in lists for x in lst]
+            return (sum(vals) / len(vals) if vals else 0.0), len(vals)
+        return sum(sum(lst) / len(lst) for lst in lists if lst), (len(lists[0]) if lists else 0)
 
     out = {}
-    for kernel, (algo, names) in TRAFFIC_ROWS.items():
-        fe, wr, hit = (mean_by_kernel(f"{algo}_{kind}") for kind in ("fetch", "write", "hit"))
-        f = sum(fe.get((n, "FETCH_SIZE"), (0.0, 0))[0] for n in names) * FETCH_SCALE * 1024
-        w = sum(wr.get((n, "WRITE_SIZE"), (0.0, 0))[0] for n in names) * WRITE_SCALE * 1024
-        h = sum(hit.get((n, "TCC_HIT_sum"), (0.0, 0))[0] for n in names)
-        m = sum(hit.get((n, "TCC_MISS_sum"), (0.0, 0))[0] for n in names)
+    for kernel, (algo, names, how) in TRAFFIC_ROWS.items():
+        fe, wr, hit = (values_by_kernel(f"{algo}_{kind}") for kind in ("fetch", "write", "hit"))
+        f, launches = per_launch(fe, names, "FETCH_SIZE", how)
+        f *= FETCH_SCALE * 1024
+        w = per_launch(wr, names, "WRITE_SIZE", how)[0] * WRITE_SCALE * 1024
+        h = per_launch(hit, names, "TCC_HIT_sum", how)[0]
+        m = per_launch(hit, names, "TCC_MISS_sum", how)[0]
         out[kernel] = {"bytes_per_launch": round(f + w), "fetch_bytes": round(f), "write_bytes": round(w),
                        "l2_hit_rate": round(h / max(h + m, 1.0), 4),
                        "sources": kernel_sources_digest(KERNEL_FILES[kernel]),
-                       "launches_sampled": fe.get((names[0], "FETCH_SIZE"), (0.0, 0))[1]}
+                       "launches_sampled": launches}
     return {workload: out, "calibration": {"fetch_scale": round(FETCH_SCALE, 4), "write_scale": WRITE_SCALE,
                                            "copy_bytes": 1073741824}}
 
