@@ -56,55 +56,75 @@ __device__ __forceinline__ uint32_t cblock_exclusive_scan(uint32_t x, uint32_t &
   return before + inc - x;
 }
 
-// SSSP filter over the set bits of a thread's N words.  A bit whose
-// vertex has dist >= settled (the distance it had when it last relaxed its
-// edges) is dropped: an attempt to lower it set the bit but found it already
-// as low.  Of the rest, bits with dist < thresh are kept (the near set; their
-// settled distance is updated here) and the others are counted, with their
-// least distance, and stay active.  Eight set bits are handled at a time so
-// that their distance loads are in flight together.
-template <int N>
-__device__ __forceinline__ void sssp_filter_words(uint32_t (&w)[N], int64_t word0, const int32_t *__restrict__ dist,
-                                                  int32_t *__restrict__ settled, int32_t thresh, uint32_t (&keep)[N],
-                                                  uint32_t (&dropped)[N], uint32_t &rest, int32_t &rest_min) {
+// SSSP filter of one wave's 64 bitmap words (2048 vertices).  A set bit
+// whose vertex has dist >= settled (the distance it had when it last relaxed
+// its edges) is dropped: an attempt to lower it set the bit but found it
+// already as low.  Of the rest, bits with dist < thresh are kept (the near
+// set; their settled distance is updated here) and the others are counted,
+// with their least distance, and stay active.  The wave walks its words two
+// at a time, one vertex per lane, so that the distance and settled loads of
+// 64 consecutive vertices are one coalesced access each; pairs of zero words
+// are skipped, and up to four pairs are in flight at once.  Lane l ends with
+// the keep and drop masks of its own word.
+__device__ __forceinline__ void sssp_filter_wave(uint32_t w, int64_t word0, const int32_t *__restrict__ dist,
+                                                 int32_t *__restrict__ settled, int32_t thresh, uint32_t &keep,
+                                                 uint32_t &dropped, uint32_t &rest, int32_t &rest_min) {
+  const int lane = threadIdx.x & 63;
+  keep = 0;
+  dropped = 0;
+  // bit 2p: word 2p or 2p + 1 has a set bit
+  const unsigned long long nz = __ballot(w != 0u);
+  unsigned long long pairs = (nz | (nz >> 1)) & 0x5555555555555555ull;
+  while (pairs) {
+    int p[4];
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
-    keep[k] = 0;
-    dropped[k] = 0;
-    uint32_t x = w[k];
-    const int64_t base = (word0 + k) * 32;
-    while (x) {
-      int b[8];
+    for (int j = 0; j < 4; ++j) {
+      p[j] = pairs ? __ffsll((long long)pairs) - 1 : -1;
+      pairs &= pairs - 1;
+    }
+    bool mine[4];
+    int32_t d[4], st[4];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        b[j] = x ? __ffs(x) - 1 : -1;
-        x &= x - 1;
-      }
-      int32_t d[8], st[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int64_t v = base + (b[j] >= 0 ? b[j] : b[0]);
+    for (int j = 0; j < 4; ++j) {
+      mine[j] = false;
+      if (p[j] < 0) continue;
+      const uint32_t wa = (uint32_t)__builtin_amdgcn_readlane((int)w, p[j]);
+      const uint32_t wb = (uint32_t)__builtin_amdgcn_readlane((int)w, p[j] + 1);
+      mine[j] = ((lane < 32 ? wa >> lane : wb >> (lane - 32)) & 1u) != 0u;
+      if (mine[j]) {
+        const int64_t v = (word0 + p[j]) * 32 + lane;
         d[j] = dist[v];
         st[j] = settled[v];
       }
+    }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        if (b[j] < 0) continue;
-        const uint32_t bit = 1u << b[j];
-        if (d[j] >= st[j]) dropped[k] |= bit;
-        else if (d[j] < thresh) {
-          keep[k] |= bit;
-          settled[base + b[j]] = d[j];  // the distance it relaxes with (at least)
+    for (int j = 0; j < 4; ++j) {
+      if (p[j] < 0) continue;  // wave-uniform
+      bool k = false, dr = false;
+      if (mine[j]) {
+        if (d[j] >= st[j]) {
+          dr = true;
+        } else if (d[j] < thresh) {
+          k = true;
+          settled[(word0 + p[j]) * 32 + lane] = d[j];  // the distance it relaxes with (at least)
         } else {
           ++rest;
           rest_min = d[j] < rest_min ? d[j] : rest_min;
         }
       }
+      const unsigned long long km = __ballot(k), dm = __ballot(dr);
+      if (lane == p[j]) {
+        keep = (uint32_t)km;
+        dropped = (uint32_t)dm;
+      } else if (lane == p[j] + 1) {
+        keep = (uint32_t)(km >> 32);
+        dropped = (uint32_t)(dm >> 32);
+      }
     }
   }
 }
 
-// SSSP compaction, first pass: filter the active bitmap (sssp_filter_words),
+// SSSP compaction, first pass: filter the active bitmap (sssp_filter_wave),
 // leave the untaken active bits in `bits`, the taken ones in `keep_out`
 // (and, with `members`, also OR them into it), and each block's count in
 // bcount.  With rest_cnt, the vertices left active beyond the threshold are
@@ -117,13 +137,13 @@ __global__ __launch_bounds__(CT) void k_sssp_filter(uint32_t *__restrict__ bits,
                                                     uint32_t *__restrict__ members) {
   const int64_t q = (int64_t)blockIdx.x * CT + threadIdx.x;  // word index
   const uint32_t v = bits[q];
-  uint32_t w[1] = {v}, keep[1], dr[1];
+  uint32_t keep, dr;
   uint32_t r = 0;
   int32_t rmin = TG_INF;
-  sssp_filter_words<1>(w, q, dist, settled, thresh, keep, dr, r, rmin);
-  bits[q] = v & ~(keep[0] | dr[0]);
-  keep_out[q] = keep[0];
-  if (members && keep[0]) members[q] |= keep[0];
+  sssp_filter_wave(v, q - (threadIdx.x & 63), dist, settled, thresh, keep, dr, r, rmin);
+  bits[q] = v & ~(keep | dr);
+  keep_out[q] = keep;
+  if (members && keep) members[q] |= keep;
   if (rest_cnt) {
     r = cblock_sum(r);
     for (int o = 32; o > 0; o >>= 1) {
@@ -134,7 +154,7 @@ __global__ __launch_bounds__(CT) void k_sssp_filter(uint32_t *__restrict__ bits,
       atomicMin(rest_min + (size_t)(blockIdx.x & (STAT_SLOTS - 1)) * STAT_STRIDE, (unsigned long long)rmin);
     if (threadIdx.x == 0 && r) stat_add(rest_cnt, (unsigned long long)r);
   }
-  const uint32_t c = cblock_sum((uint32_t)__popc(keep[0]));
+  const uint32_t c = cblock_sum((uint32_t)__popc(keep));
   if (threadIdx.x == 0) bcount[blockIdx.x] = c;
 }
 
@@ -210,37 +230,51 @@ __global__ __launch_bounds__(CT) void k_compact_write(uint32_t *__restrict__ bit
   uint32_t o = excl + (uint32_t)__popc(nw);
   unsigned long long deg = 0;
   if (!skip_queue || level || degsum) {
-    // the word's vertices eight at a time, so that their offset loads are
-    // in flight together
-    uint32_t k = excl;
-    for (uint32_t w = nw; w;) {
-      int32_t vv[8];
+    // the wave's words two at a time, one vertex per lane: a vertex's queue
+    // slot is its word pair's first slot plus the set bits below it, so the
+    // queue, level and offset accesses of a pair are coalesced; pairs of
+    // zero words are skipped and up to four pairs are in flight at once
+    const int lane = threadIdx.x & 63;
+    const int64_t word0 = q - lane;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const unsigned long long nz = __ballot(nw != 0u);
+    unsigned long long pairs = (nz | (nz >> 1)) & 0x5555555555555555ull;
+    while (pairs) {
+      int32_t vv[4];
+      uint32_t pos[4];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        vv[j] = w ? (int32_t)(q * 32 + (__ffs(w) - 1)) : -1;
-        w &= w - 1;
+      for (int j = 0; j < 4; ++j) {
+        vv[j] = -1;
+        if (!pairs) continue;
+        const int pr = __ffsll((long long)pairs) - 1;
+        pairs &= pairs - 1;
+        const unsigned long long m = (unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)nw, pr) |
+                                     ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)nw, pr + 1) << 32);
+        if ((m >> lane) & 1ull) {
+          vv[j] = (int32_t)((word0 + pr) * 32 + lane);
+          pos[j] = (uint32_t)__builtin_amdgcn_readlane((int)excl, pr) + (uint32_t)__popcll(m & below);
+        }
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (vv[j] >= 0 && !skip_queue) queue[k + j] = vv[j];
+      for (int j = 0; j < 4; ++j)
+        if (vv[j] >= 0 && !skip_queue) queue[pos[j]] = vv[j];
       if (level) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
+        for (int j = 0; j < 4; ++j)
           if (vv[j] >= 0) level[vv[j]] = level_value;
       }
       if (degsum) {
-        int64_t a[8], b[8];
+        int64_t a[4], b[4];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < 4; ++j) {
           const int32_t x = vv[j] >= 0 ? vv[j] : 0;
           a[j] = off[x];
           b[j] = off[x + 1];
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
+        for (int j = 0; j < 4; ++j)
           if (vv[j] >= 0) deg += (unsigned long long)(b[j] - a[j]);
       }
-      k += 8;
     }
   }
   if (degsum) {
