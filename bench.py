@@ -46,6 +46,7 @@ KERNEL_FILES = {
     "pr_gather": ["pagerank.hip", "pr_sliced.hip", "pr_rows.hip", "kcommon.h", "../tuning_cache.json"],
     "bfs_step": ["bfs.hip", "frontier.hip", "kcommon.h", "../tuning_cache.json"],
     "sssp_relax": ["sssp.hip", "kcommon.h", "../tuning_cache.json"],
+    "sssp_pull": ["sssp.hip", "frontier.hip", "kcommon.h", "../tuning_cache.json"],
 }
 
 
@@ -915,6 +916,12 @@ def main():
         kernels["bfs_step"] = kern(sb, "bfs_step", bfs_step_bytes)
     if "sssp_relax_ms" in ss:
         kernels["sssp_relax"] = kern(ss, "sssp_relax", sssp_bytes)
+    if "sssp_pull_ms" in ss:
+        # a bucket's heavy edges pulled: per unsettled vertex its offsets,
+        # light count and distance, per edge checked its packed word and the
+        # member bit of its source
+        kernels["sssp_pull"] = kern(ss, "sssp_pull", 4.125 * ss.get("heavy_pull_edges_checked", 0) +
+                                    16.0 * ss.get("heavy_pull_vertices", 0))
     roofs = {}
     for k, v in kernels.items():
         n = max(v["n"], 1)
@@ -987,6 +994,8 @@ def main():
         "sssp": {"gteps": round(sssp_edges / (t_sssp / 1e3) / 1e9, 2), "ms_per_root": round(t_sssp / nr, 4),
                  "supersteps_per_root": round(ss.get("supersteps", 0) / nr, 1),
                  "work_efficiency": round(ss.get("relaxations", 0) / max(sssp_edges, 1), 3),
+                 "heavy_pull_edges_checked_per_root": round(ss.get("heavy_pull_edges_checked", 0) / nr),
+                 "heavy_pulls_per_root": round(ss.get("pull_supersteps", 0) / nr, 2),
                  "ms_per_root_over_steps": dist_stats([x / nr for x in phase_list(stats, 1)])},
         "gather_reference": None,
         "pagerank": {"gteps": round(pr_edges / (t_pr / 1e3) / 1e9, 2),

@@ -144,7 +144,11 @@ int partition_by_degree(const tg_graph *g, int strategy, double cpu_edge_share,
  *                rescanned every superstep), "sssp_split" (1, with the ring
  *                and packed rows: a bucket's vertices relax their edges
  *                lighter than sssp_delta while it is processed and their
- *                heavier edges once when it is done);
+ *                heavier edges once when it is done), "sssp_hpull" (100,
+ *                with the split on a TG_SYMMETRIC graph: that heavy pass
+ *                is pulled by the vertices whose distance is not yet final
+ *                when their out-degree sum times sssp_hpull / 100 is below
+ *                the bucket's; 0: always pushed);
  *   layout       "mapped_edges" (1: the edge arrays -- neighbour ids, weights,
  *                in-edge ids -- stay in pinned host memory mapped into the
  *                GPU and kernels read them over the host link, for graphs

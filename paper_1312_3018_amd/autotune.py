@@ -24,7 +24,7 @@ DEFAULTS = {
     "hub_chunk": 4096, "pr_lds_verts": 40960, "pr_grid": 256, "bfs_lds_words": 4096, "bfs_grid": 2048,
     "bfs_lds_min_vblocks": 4096, "sssp_delta": 32, "sssp_lds_verts": 0, "sssp_grid": 2048, "pr_xcd": 1,
     "pr_rows": 512, "bfs_do": 1, "bfs_alpha": 14, "bfs_beta": 24, "sssp_xcd": 0,
-    "bfs_lanes": 2, "bfs_td_grid": 1024, "bfs_bu_grid": 4096, "sssp_lanes": 4, "sssp_pull": 0, "sssp_packed": 1, "sssp_ring": 1, "sssp_split": 1,
+    "bfs_lanes": 2, "bfs_td_grid": 1024, "bfs_bu_grid": 4096, "sssp_lanes": 4, "sssp_pull": 0, "sssp_packed": 1, "sssp_ring": 1, "sssp_split": 1, "sssp_hpull": 100,
     "bfs_graph": 0,
 }
 
@@ -51,6 +51,7 @@ SPACE = {
     "sssp_packed": [0, 1],
     "sssp_ring": [0, 1],
     "sssp_split": [0, 1],
+    "sssp_hpull": [0, 50, 100, 200],
     "sssp_lds_verts": [0, 2048, 4096, 8192],
     "sssp_grid": [1024, 2048, 4096, 16384],
     "sssp_xcd": [0, 1],
@@ -60,7 +61,7 @@ FAMILY = {k: "all" for k in ("hub_min_deg", "block_min_deg", "wave_min_deg", "g1
                              "hub_chunk")}
 FAMILY.update({"pr_xcd": "pr", "pr_rows": "pr", "pr_lds_verts": "pr", "pr_grid": "pr", "bfs_td_grid": "bfs",
                "bfs_bu_grid": "bfs", "bfs_lanes": "bfs", "bfs_graph": "bfs", "bfs_alpha": "bfs", "bfs_beta": "bfs",
-               "sssp_delta": "sssp", "sssp_lds_verts": "sssp", "sssp_lanes": "sssp", "sssp_pull": "sssp", "sssp_packed": "sssp", "sssp_ring": "sssp", "sssp_split": "sssp",
+               "sssp_delta": "sssp", "sssp_lds_verts": "sssp", "sssp_lanes": "sssp", "sssp_pull": "sssp", "sssp_packed": "sssp", "sssp_ring": "sssp", "sssp_split": "sssp", "sssp_hpull": "sssp",
                "sssp_grid": "sssp", "sssp_xcd": "sssp"})
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")

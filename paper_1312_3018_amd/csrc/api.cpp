@@ -331,6 +331,7 @@ Tuning default_tuning() {
   t.sssp_packed = 1;
   t.sssp_ring = 1;
   t.sssp_split = 1;
+  t.sssp_hpull = 100;
   t.bfs_graph = 0;  // replaying captured chunks measured 1-2% slower than direct launches
   t.mapped_edges = 0;
   return t;
@@ -381,6 +382,7 @@ int parse_tuning(const char *json, Tuning *t) {
   if (json_int(json, "sssp_packed", &v)) t->sssp_packed = v;
   if (json_int(json, "sssp_ring", &v)) t->sssp_ring = v;
   if (json_int(json, "sssp_split", &v)) t->sssp_split = v;
+  if (json_int(json, "sssp_hpull", &v)) t->sssp_hpull = v;
   if (json_int(json, "bfs_graph", &v)) t->bfs_graph = v;
   if (json_int(json, "mapped_edges", &v)) t->mapped_edges = v;
   if (t->mapped_edges != 0 && t->mapped_edges != 1) return set_error(TG_EINVAL, "tuning: mapped_edges must be 0 or 1");
@@ -390,6 +392,8 @@ int parse_tuning(const char *json, Tuning *t) {
   if (t->sssp_packed != 0 && t->sssp_packed != 1) return set_error(TG_EINVAL, "tuning: sssp_packed must be 0 or 1");
   if (t->sssp_ring != 0 && t->sssp_ring != 1) return set_error(TG_EINVAL, "tuning: sssp_ring must be 0 or 1");
   if (t->sssp_split != 0 && t->sssp_split != 1) return set_error(TG_EINVAL, "tuning: sssp_split must be 0 or 1");
+  if (t->sssp_hpull < 0 || t->sssp_hpull > 100000)
+    return set_error(TG_EINVAL, "tuning: sssp_hpull must be in [0, 100000]");
   if (t->bfs_lanes != 1 && t->bfs_lanes != 2) return set_error(TG_EINVAL, "tuning: bfs_lanes must be 1 or 2");
   if (t->bfs_td_grid < 1 || t->bfs_td_grid > 16384 || t->bfs_bu_grid < 2 || t->bfs_bu_grid > 16384)
     return set_error(TG_EINVAL, "tuning: bfs_td_grid must be in [1, 16384] and bfs_bu_grid in [2, 16384]");
@@ -985,7 +989,7 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            "\"pr_grid\":%lld,\"bfs_lds_words\":%lld,\"bfs_grid\":%lld,\"bfs_lds_min_vblocks\":%lld,"
            "\"sssp_delta\":%lld,\"sssp_lds_verts\":%lld,\"sssp_grid\":%lld,\"pr_xcd\":%lld,\"pr_rows\":%lld,"
            "\"bfs_do\":%lld,\"bfs_alpha\":%lld,\"bfs_beta\":%lld,\"sssp_xcd\":%lld,\"bfs_lanes\":%lld,"
-           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld,\"sssp_pull\":%lld,\"sssp_lanes\":%lld,\"bfs_graph\":%lld,\"mapped_edges\":%lld,\"sssp_packed\":%lld,\"sssp_ring\":%lld,\"sssp_split\":%lld}",
+           "\"bfs_td_grid\":%lld,\"bfs_bu_grid\":%lld,\"sssp_pull\":%lld,\"sssp_lanes\":%lld,\"bfs_graph\":%lld,\"mapped_edges\":%lld,\"sssp_packed\":%lld,\"sssp_ring\":%lld,\"sssp_split\":%lld,\"sssp_hpull\":%lld}",
            (long long)p->tune.min_deg[0], (long long)p->tune.min_deg[1], (long long)p->tune.min_deg[2],
            (long long)p->tune.min_deg[3], (long long)p->tune.min_deg[4], (long long)p->tune.hub_chunk,
            (long long)p->tune.pr_lds_verts, (long long)p->tune.pr_grid, (long long)p->tune.bfs_lds_words,
@@ -995,7 +999,7 @@ extern "C" int partition_info(const tg_partition *p, char *json, size_t cap) {
            (long long)p->tune.bfs_beta, (long long)p->tune.sssp_xcd, (long long)p->tune.bfs_lanes,
            (long long)p->tune.bfs_td_grid, (long long)p->tune.bfs_bu_grid, (long long)p->tune.sssp_pull,
            (long long)p->tune.sssp_lanes, (long long)p->tune.bfs_graph, (long long)p->tune.mapped_edges,
-           (long long)p->tune.sssp_packed, (long long)p->tune.sssp_ring, (long long)p->tune.sssp_split);
+           (long long)p->tune.sssp_packed, (long long)p->tune.sssp_ring, (long long)p->tune.sssp_split, (long long)p->tune.sssp_hpull);
   s += buf;
   s += ",\"tuning_source\":\"" + p->tuning_source + "\"";
   s += hybrid_info_json(p);

@@ -158,15 +158,23 @@ __global__ __launch_bounds__(CT) void k_sssp_filter(uint32_t *__restrict__ bits,
   if (threadIdx.x == 0) bcount[blockIdx.x] = c;
 }
 
+// Bits of word q that stand for vertices below n.
+__device__ __forceinline__ uint32_t valid_bits(int64_t q, int64_t n) {
+  const int64_t lo = q * 32;
+  return lo + 32 <= n ? 0xFFFFFFFFu : lo >= n ? 0u : (1u << (n - lo)) - 1u;
+}
+
 // With a BFS control block (`ctl`), a search that has ended skips the pass.
+// `invert` counts the vertices below n in neither bitmap (bits nor prev).
 __global__ __launch_bounds__(CT) void k_compact_count(const uint32_t *__restrict__ bits,
                                                       const uint32_t *__restrict__ prev,
                                                       uint32_t *__restrict__ bcount,
-                                                      const BfsCtl *__restrict__ ctl) {
+                                                      const BfsCtl *__restrict__ ctl, int invert, int64_t n) {
   if (ctl && !ctl->active) return;
   const int64_t q = (int64_t)blockIdx.x * CT + threadIdx.x;  // word index
   uint32_t v = bits[q];
-  if (prev) v &= ~prev[q];
+  if (invert) v = ~(v | prev[q]) & valid_bits(q, n);
+  else if (prev) v &= ~prev[q];
   const uint32_t c = cblock_sum((uint32_t)__popc(v));
   if (threadIdx.x == 0) bcount[blockIdx.x] = c;
 }
@@ -214,6 +222,9 @@ __global__ __launch_bounds__(CT) void k_compact_write(uint32_t *__restrict__ bit
     if (fbits) fbits[q] = nw;  // the new frontier
   } else if (mode == 4) {
     // a bitmap already filtered (k_sssp_filter): take it as it is
+  } else if (mode == 5) {
+    // the vertices below n in neither bitmap; both stay as they are
+    nw = ~(v | prev[q]) & valid_bits(q, n);
   } else {
     if (mode == 2) prev[q] = v;  // prev := the set taken
     bits[q] = 0;
@@ -284,6 +295,18 @@ __global__ __launch_bounds__(CT) void k_compact_write(uint32_t *__restrict__ bit
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == CT - 1) {
     plan->count = (int32_t)o;
     if (ctl) plan->queue_skipped = skip_queue ? 1 : 0;
+  }
+}
+
+// done |= members; members := 0.
+__global__ __launch_bounds__(BLOCK) void k_bits_merge_clear(uint32_t *__restrict__ done, uint32_t *__restrict__ members,
+                                                            int64_t nwords) {
+  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (q >= nwords) return;
+  const uint32_t m = members[q];
+  if (m) {
+    done[q] |= m;
+    members[q] = 0u;
   }
 }
 
@@ -435,7 +458,7 @@ int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, 
                      int32_t *queue, int32_t *level, int32_t level_value, hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
   hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(CT), 0, s, bits, mode == 0 ? prev : nullptr, ws.bcount,
-                     nullptr);
+                     nullptr, 0, (int64_t)0);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, bits, prev, mode, ws.bcount, queue, level,
                      level_value, g.out_bins, g.n, ws.plan, nullptr, nullptr, nullptr, nullptr, (int64_t)0);
   TG_HIP(hipGetLastError());
@@ -457,7 +480,8 @@ int bfs_dev_resume(Workspace &ws, int32_t L, hipStream_t s) {
 
 int frontier_compact_bfs_dev(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
-  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(CT), 0, s, ws.bits_a, ws.bits_b, ws.bcount, ws.ctl);
+  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(CT), 0, s, ws.bits_a, ws.bits_b, ws.bcount, ws.ctl, 0,
+                     (int64_t)0);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, ws.bits_a, ws.bits_b, 0, ws.bcount, ws.queue,
                      ws.state, 0, g.out_bins, g.n, ws.plan, ws.bits_c, g.out.off, stat_counter(ws.work, 4), ws.ctl,
                      t.bfs_do ? g.n / t.bfs_beta : INT64_MAX);
@@ -469,6 +493,25 @@ int frontier_plan_bfs_dev(const GpuPart &g, Workspace &ws, const Tuning &t, hipS
   hipLaunchKernelGGL(k_plan_bfs, dim3(1), dim3(BLOCK), 0, s, ws.plan, g.out_bins, g.n, ws.queue, g.out.off,
                      t.hub_chunk, ws.hubpref, ws.ctl, stat_counter(ws.work, 4), stat_counter(ws.work, 3), t.bfs_alpha,
                      t.bfs_beta, (int)t.bfs_do);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int frontier_compact_bucket_end(const GpuPart &g, Workspace &ws, uint32_t *members, uint32_t *done, bool pull,
+                                int32_t *queue, unsigned long long *degsum, hipStream_t s) {
+  const int blocks = (int)(ws.nwords / WPB);
+  hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(CT), 0, s, members, pull ? done : nullptr, ws.bcount,
+                     nullptr, pull ? 1 : 0, g.n);
+  hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, members, done, pull ? 5 : 4, ws.bcount, queue,
+                     nullptr, 0, g.out_bins, g.n, ws.plan, nullptr, degsum ? g.out.off : nullptr, degsum, nullptr,
+                     (int64_t)0);
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+int bitmap_merge_clear(Workspace &ws, uint32_t *done, uint32_t *members, hipStream_t s) {
+  hipLaunchKernelGGL(k_bits_merge_clear, dim3((unsigned)((ws.nwords + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, done,
+                     members, ws.nwords);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }

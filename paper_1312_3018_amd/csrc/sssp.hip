@@ -182,6 +182,88 @@ __global__ __launch_bounds__(BLOCK) void k_sssp_relax(const Plan *__restrict__ P
   }
 }
 
+// The heavy edges of a settled bucket, pulled (symmetric graphs only: a
+// vertex's out-edges are its in-edges, with the same weights).  The queue
+// holds every vertex whose distance is not yet final; each takes the least
+// dist[u] + w over its heavy edges from members u of the bucket.  A heavy
+// candidate is at least the bucket's end, so final vertices could not gain
+// and are skipped, which is what makes the pull cheaper than the push when
+// the bucket's members hold more edges than the unsettled rest.  Each lane
+// folds its share of a row and lowers the distance once, with the bit of the
+// new distance's bucket set as a push relaxation would set it.
+__global__ __launch_bounds__(BLOCK) void k_sssp_pull_heavy(const Plan *__restrict__ Pp,
+                                                           const int32_t *__restrict__ queue,
+                                                           const int64_t *__restrict__ hubpref,
+                                                           const int64_t *__restrict__ off,
+                                                           const uint32_t *__restrict__ cw,
+                                                           const int32_t *__restrict__ lcnt, int32_t *dist,
+                                                           const uint32_t *__restrict__ members, const ActiveSet act,
+                                                           uint32_t *ovf, uint32_t *flags, int64_t hub_chunk,
+                                                           unsigned long long *work) {
+  const Plan &P = load_plan(Pp);
+  const int64_t total = P.vb[NBIN];
+  unsigned long long n_edges = 0, n_verts = 0;
+  for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    const auto first = [off, lcnt](int32_t v) -> int64_t { return stream_load(off + v) + (int64_t)lcnt[v]; };
+    const auto last = [off](int32_t v) -> int64_t { return stream_load(off + v + 1); };
+    const Assign a = assign_work_range(vb, P, queue, nullptr, hubpref, first, last, hub_chunk);
+    if (!a.ok) continue;
+    if (a.lane == 0) {
+      n_edges += (unsigned long long)(a.e_end - a.e_begin);
+      n_verts += (a.bin != BIN_HUB || a.e_begin == first(a.v)) ? 1 : 0;
+    }
+    int64_t best = INT64_MAX;
+    const int64_t st = a.stride;
+    int64_t e = a.e_begin + a.lane;
+    // four edges per lane in flight: words, then member bits, then the
+    // members' distances
+    for (; e + 3 * st < a.e_end; e += 4 * st) {
+      uint32_t x[4], mw[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[k] = stream_load(cw + e + k * st);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) mw[k] = members[(x[k] & 0xFFFFFFu) >> 5];
+      int32_t du[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t u = x[k] & 0xFFFFFFu;
+        du[k] = ((mw[k] >> (u & 31)) & 1u) ? dist[u] : TG_INF;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (du[k] < TG_INF) best = min(best, (int64_t)du[k] + (int64_t)(x[k] >> 24));
+    }
+    for (; e < a.e_end; e += st) {
+      const uint32_t x = stream_load(cw + e);
+      const uint32_t u = x & 0xFFFFFFu;
+      if ((members[u >> 5] >> (u & 31)) & 1u) {
+        const int32_t du = dist[u];
+        if (du < TG_INF) best = min(best, (int64_t)du + (int64_t)(x >> 24));
+      }
+    }
+    if (best == INT64_MAX) continue;
+    const int32_t v = a.v;
+    const uint32_t bit = 1u << (v & 31);
+    const int32_t cur = dist[v];
+    if (best >= (int64_t)TG_INF) {
+      // cannot improve a finite distance; matters only if v stays unreached
+      if (cur == TG_INF) {
+        atomicOr(ovf + (v >> 5), bit);
+        flags[0] = 1u;
+      }
+    } else if (best < (int64_t)cur) {
+      atomicMin(dist + v, (int32_t)best);
+      atomicOr(act.of((int32_t)best) + (v >> 5), bit);
+    }
+  }
+  n_edges = block_sum(n_edges);
+  n_verts = block_sum(n_verts);
+  if (threadIdx.x == 0 && n_edges + n_verts > 0) {
+    stat_add(stat_counter(work, 2), n_edges);
+    stat_add(stat_counter(work, 3), n_verts);
+  }
+}
+
 // One class per XCD: workgroup i relaxes class (i mod 8) of every frontier
 // vertex's out-edges.
 __global__ __launch_bounds__(BLOCK) void k_sssp_relax_cls(const Plan *__restrict__ Pp,
@@ -281,6 +363,24 @@ int sssp_relax_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int
                        ws.work, hot, 0, nullptr);
   }
   ktimer_stop(tk, s, "sssp_relax");
+  TG_HIP(hipGetLastError());
+  return TG_OK;
+}
+
+// The pull form of a bucket's heavy pass over the queue of unsettled
+// vertices (k_sssp_pull_heavy); `members` is the bucket's member bitmap.
+int sssp_pull_heavy_launch(const GpuPart &g, Workspace &ws, const int32_t *queue, int64_t vblocks,
+                           const uint32_t *members, const Tuning &t, hipStream_t s, int32_t bucket_delta,
+                           int32_t bucket_k) {
+  if (vblocks <= 0) return TG_OK;
+  if (!g.out.cw || !g.lcnt || !g.in_alias)
+    return set_error(TG_EDEVICE, "sssp: heavy pull needs packed rows, light counts and a symmetric graph");
+  const ActiveSet act{ws.buckets, bucket_delta, bucket_k, ws.nwords};
+  const int tk = ktimer_start(s);
+  hipLaunchKernelGGL(k_sssp_pull_heavy, dim3(launch_grid(vblocks)), dim3(BLOCK), 0, s, ws.plan, queue, ws.hubpref,
+                     g.out.off, g.out.cw, g.lcnt, ws.state, members, act, ws.bits_c, ws.counters, t.hub_chunk,
+                     ws.work);
+  ktimer_stop(tk, s, "sssp_pull");
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
@@ -406,12 +506,17 @@ int gpu_sssp_ring(tg_partition *p, Workspace &ws, int32_t root, hipStream_t s, i
   const int64_t delta = p->tune.sssp_delta;
   const bool split = sssp_split_on(p) && g.lcnt && g.split_delta == delta;
   const BinBounds &bb = split ? g.light_bins : g.out_bins;
-  const int kb = k + (split ? 1 : 0);  // the bucket's members after the ring
+  // heavy passes may pull (symmetric graphs): then the vertices whose
+  // distance is final are tracked too
+  const bool hpull = split && g.in_alias && p->tune.sssp_hpull > 0;
+  const int kb = k + (split ? 1 : 0) + (hpull ? 1 : 0);  // the bucket's members, then the final set, after the ring
   if (!ws.buckets || ws.buckets_k < kb) {
     TG_TRY(dalloc(ws.arena, &ws.buckets, (size_t)kb * ws.nwords));
     ws.buckets_k = kb;
   }
   uint32_t *members = split ? ws.buckets + (int64_t)k * ws.nwords : nullptr;
+  uint32_t *done = hpull ? ws.buckets + (int64_t)(k + 1) * ws.nwords : nullptr;
+  int64_t done_deg = 0, hpulls = 0;  // out-degree sum of the final set; pulled heavy passes
   TG_HIP(hipMemsetAsync(ws.buckets, 0, (size_t)kb * ws.nwords * sizeof(uint32_t), s));
   TG_TRY(set_bit(ws.buckets, root, s));  // bucket 0: distance 0
   int64_t lo = 0, rounds = 0;
@@ -429,7 +534,33 @@ int gpu_sssp_ring(tg_partition *p, Workspace &ws, int32_t root, hipStream_t s, i
                                split ? 1 : 0));
       continue;
     }
-    if (split) {
+    if (hpull) {
+      // the bucket is settled: its members' heavy edges are relaxed once,
+      // pushed from the members or pulled by the vertices not yet final,
+      // whichever side holds fewer edges (out-degree sums; the pull's
+      // weighted by sssp_hpull percent)
+      TG_TRY(stat_zero(ws, 4, s));
+      TG_TRY(frontier_compact_bucket_end(g, ws, members, done, false, ws.queue, stat_counter(ws.work, 4), s));
+      TG_TRY(stat_fetch(ws, 4, s));
+      TG_TRY(frontier_plan_bins(g, ws, ws.queue, g.out_bins, g.hcnt, p->tune, s, true));
+      const int64_t push_deg = (int64_t)stat_sum(ws, 4);
+      const int64_t pull_deg = g.m - done_deg - push_deg;
+      done_deg += push_deg;
+      if (ws.h_plan->count > 0 && pull_deg * 100 < push_deg * (int64_t)p->tune.sssp_hpull) {
+        TG_TRY(frontier_compact_bucket_end(g, ws, members, done, true, ws.queue, nullptr, s));
+        TG_TRY(frontier_plan_bins(g, ws, ws.queue, g.out_bins, g.hcnt, p->tune, s, true));
+        if (ws.h_plan->count > 0) {
+          ++rounds;
+          ++hpulls;
+          TG_TRY(sssp_pull_heavy_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], members, p->tune, s, (int32_t)delta,
+                                        k));
+        }
+      } else if (ws.h_plan->count > 0) {
+        ++rounds;
+        TG_TRY(sssp_relax_launch(g, ws, ws.queue, ws.h_plan->vb[NBIN], p->tune, s, (int32_t)delta, k, 2));
+      }
+      TG_TRY(bitmap_merge_clear(ws, done, members, s));
+    } else if (split) {
       // the bucket is settled: its members relax their heavy edges once
       TG_TRY(frontier_compact(g, ws, 1, members, nullptr, ws.queue, nullptr, 0, s));
       TG_TRY(frontier_plan_bins(g, ws, ws.queue, g.out_bins, g.hcnt, p->tune, s, true));
@@ -453,7 +584,7 @@ int gpu_sssp_ring(tg_partition *p, Workspace &ws, int32_t root, hipStream_t s, i
     if (step == 0) break;  // no active vertex left
     lo += step * delta;
   }
-  if (pulls_out) *pulls_out = 0;
+  if (pulls_out) *pulls_out = hpulls;
   TG_TRY(sssp_overflow_check(g, ws, s));
   if (ws.h_flags[1]) return set_error(TG_ERANGE, "sssp: a shortest-path distance does not fit below INT32_MAX");
   if (rounds_out) *rounds_out = rounds;
@@ -588,7 +719,7 @@ struct LaneResult {
   int rc = TG_OK;
   std::string msg;
   int64_t rounds = 0, pulls = 0;
-  unsigned long long relax = 0, act = 0;
+  unsigned long long relax = 0, act = 0, pull_checks = 0, pull_verts = 0;
   KTimes timers;
 };
 
@@ -616,10 +747,12 @@ void sssp_lane(tg_partition *p, int lane, hipStream_t s, const int32_t *roots_lo
       res->pulls += pulls;
       TG_TRY(collect_i32(p->gpu, ws->state, dist + (int64_t)r * V, s));
     }
-    for (int k = 0; k < 2; ++k) TG_TRY(stat_fetch(*ws, k, s));
+    for (int k = 0; k < 4; ++k) TG_TRY(stat_fetch(*ws, k, s));
     TG_HIP(hipStreamSynchronize(s));
     res->relax = stat_sum(*ws, 0);
     res->act = stat_sum(*ws, 1);
+    res->pull_checks = stat_sum(*ws, 2);
+    res->pull_verts = stat_sum(*ws, 3);
     return TG_OK;
   };
   res->rc = run();
@@ -674,19 +807,23 @@ int gpu_sssp_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int3
     if (res[0].rc == TG_OK) sssp_lane(p, 0, s, roots_local, nr, dist, &next, &failed, &res[0], ref);
     for (auto &x : th) x.join();
     int64_t rd = 0, pl = 0;
-    unsigned long long rx = 0, ac = 0;
+    unsigned long long rx = 0, ac = 0, pc = 0, pv = 0;
     for (int l = 0; l < nl; ++l) {
       if (rc == TG_OK && res[l].rc != TG_OK) rc = set_error(res[l].rc, "%s", res[l].msg.c_str());
       rd += res[l].rounds;
       pl += res[l].pulls;
       rx += res[l].relax;
       ac += res[l].act;
+      pc += res[l].pull_checks;
+      pv += res[l].pull_verts;
       if (l > 0) ktimer_import(res[l].timers);
     }
     *rounds = rd;
     *pulls = pl;
     stats_add("relaxations", (double)rx);
     stats_add("activations", (double)ac);
+    stats_add("heavy_pull_edges_checked", (double)pc);
+    stats_add("heavy_pull_vertices", (double)pv);
     stats_add("lanes", nl);
     // the caller's stream waits for the other lanes (already finished)
     for (int l = 1; l < nl && rc == TG_OK; ++l)

@@ -95,6 +95,8 @@ struct Tuning {
   int64_t sssp_packed;           // SSSP: relax from the packed id|weight words when the partition has them
   int64_t sssp_ring;             // SSSP near/far: a ring of bucket bitmaps (1) or one far pile rescanned per step (0)
   int64_t sssp_split;            // SSSP ring: edges lighter than the step relax per pass, heavier ones once per bucket
+  int64_t sssp_hpull;            // SSSP split, symmetric graphs: a bucket's heavy pass pulls when the unsettled
+                                 // vertices' degree sum times this percent is below the members' (0: always push)
   int64_t bfs_graph;             // BFS: 1 = chunks of supersteps replayed as captured HIP graphs
   int64_t mapped_edges;          // partition build: 1 = edge arrays in mapped host memory
 };
@@ -411,6 +413,15 @@ int frontier_plan(const GpuPart &g, Workspace &ws, const int32_t *queue, const T
 int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
                           int32_t *settled, int32_t thresh, bool near, const BinBounds &bb, hipStream_t s,
                           unsigned long long *degsum = nullptr, uint32_t *members = nullptr);
+// The end of an SSSP bucket (light/heavy split): with `pull` false, the
+// bucket's members (bitmap `members`, left as it is) go to the queue and
+// their out-degree sum is added to `degsum`; with `pull` true, the vertices
+// in neither `members` nor `done` (those whose distance is not yet final)
+// go to the queue.  Either queue is sorted by id and binned by out_bins.
+int frontier_compact_bucket_end(const GpuPart &g, Workspace &ws, uint32_t *members, uint32_t *done, bool pull,
+                                int32_t *queue, unsigned long long *degsum, hipStream_t s);
+// done |= members, members := 0 (ws.nwords words each).
+int bitmap_merge_clear(Workspace &ws, uint32_t *done, uint32_t *members, hipStream_t s);
 // Plan over the queue with bins `bb` (queue positions set by a compaction
 // with the same bins) and hub chunks sized by len[v] edges.
 int frontier_plan_bins(const GpuPart &g, Workspace &ws, const int32_t *queue, const BinBounds &bb,

@@ -196,25 +196,31 @@ def test_sssp_variants(gpu, rmat14, xcd, delta):
                 assert np.array_equal(dist[i], oracle.sssp(graph.offsets, graph.cols, wt, r)), (tuning, graph.n, r)
 
 
-@pytest.mark.parametrize("ring,split", [(0, 0), (1, 0), (1, 1)])
-def test_sssp_bucket_ring(gpu, rmat14, ring, split):
+@pytest.mark.parametrize("ring,split,hpull", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 100), (1, 1, 100000)])
+def test_sssp_bucket_ring(gpu, rmat14, ring, split, hpull):
     """The near/far step over a ring of bucket bitmaps (with and without
     the light/heavy split of each row, and, with ring = 0, over one far
     pile) gives the oracle's distances for bucket widths that need 3 to 12
     bitmaps with weights 1..255, and for widths 1 and 2 with weights 1..3
-    (width 1: no light edges at all), on symmetric and directed graphs, with
-    hub rows split into chunks, for several roots in a row on one
-    partition."""
+    (width 1: no light edges at all), on symmetric and directed graphs, a
+    star and a path, with hub rows split into chunks, for several roots in a
+    row on one partition.  With the split, a bucket's heavy edges are always
+    pushed (hpull 0), pulled when the unsettled vertices hold fewer edges
+    (100), or pulled almost always (100000; directed graphs always push)."""
     g, w = rmat14
     gd = graphgen.rmat(12, symmetrize=False)
     wd = graphgen.weights(gd, seed=4)
     w3 = (w % 3 + 1).astype(np.int32)  # 1..3, one value per undirected edge like w
+    gs = graphgen.from_edges(20001, np.zeros(20000, dtype=int), np.arange(1, 20001), symmetrize=True)
+    gp = graphgen.from_edges(700, np.arange(699), np.arange(1, 700), symmetrize=True)
     small = {"hub_min_deg": 300, "block_min_deg": 100, "wave_min_deg": 24, "g16_min_deg": 6, "g4_min_deg": 2,
              "hub_chunk": 256}
     cases = [(g, w, d, None) for d in (24, 32, 128)] + [(g, w, 24, small), (gd, wd, 32, None), (g, w3, 1, None),
-                                                       (g, w3, 2, small)]
+                                                       (g, w3, 2, small), (gs, graphgen.weights(gs, seed=5), 32, small),
+                                                       (gp, graphgen.weights(gp, seed=6), 16, None)]
     for graph, wt, delta, bins in cases:
-        P = load(gpu, graph, wt, dict(bins or {}, sssp_delta=delta, sssp_ring=ring, sssp_split=split))
+        P = load(gpu, graph, wt, dict(bins or {}, sssp_delta=delta, sssp_ring=ring, sssp_split=split,
+                                      sssp_hpull=hpull))
         roots = graphgen.sample_roots(graph, 3, seed=delta)
         dist = gpu.sssp(P, roots).cpu().numpy()
         for i, r in enumerate(roots):
