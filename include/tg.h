@@ -130,7 +130,7 @@ int partition_by_degree(const tg_graph *g, int strategy, double cpu_edge_share,
  *                "bfs_grid", "bfs_lds_min_vblocks" for the top-down steps of
  *                betweenness and hybrid searches;
  *   SSSP         "sssp_delta" (0: plain frontier; > 0: near/far step),
- *                "sssp_lanes" (roots in flight, 1..4), "sssp_pull" (a
+ *                "sssp_lanes" (roots in flight, 1..8), "sssp_pull" (a
  *                superstep whose frontier holds more than this percentage
  *                of the edges pulls over in-edges; 0: never), "sssp_grid",
  *                "sssp_lds_verts", "sssp_xcd" (per-XCD destination classes),

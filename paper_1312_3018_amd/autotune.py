@@ -46,7 +46,7 @@ SPACE = {
     "bfs_alpha": [4, 14, 32, 64],
     "bfs_beta": [8, 24, 64],
     "sssp_delta": [0, 16, 24, 32, 48, 64, 128],
-    "sssp_lanes": [1, 2, 3, 4],
+    "sssp_lanes": [1, 2, 3, 4, 6, 8],
     "sssp_pull": [0, 50, 70],
     "sssp_packed": [0, 1],
     "sssp_ring": [0, 1],

@@ -388,7 +388,8 @@ int parse_tuning(const char *json, Tuning *t) {
   if (t->mapped_edges != 0 && t->mapped_edges != 1) return set_error(TG_EINVAL, "tuning: mapped_edges must be 0 or 1");
   if (t->bfs_graph != 0 && t->bfs_graph != 1) return set_error(TG_EINVAL, "tuning: bfs_graph must be 0 or 1");
   if (t->sssp_pull < 0 || t->sssp_pull > 100) return set_error(TG_EINVAL, "tuning: sssp_pull must be in [0, 100]");
-  if (t->sssp_lanes < 1 || t->sssp_lanes > MAX_LANES) return set_error(TG_EINVAL, "tuning: sssp_lanes outside [1, 4]");
+  if (t->sssp_lanes < 1 || t->sssp_lanes > MAX_LANES)
+    return set_error(TG_EINVAL, "tuning: sssp_lanes outside [1, %d]", MAX_LANES);
   if (t->sssp_packed != 0 && t->sssp_packed != 1) return set_error(TG_EINVAL, "tuning: sssp_packed must be 0 or 1");
   if (t->sssp_ring != 0 && t->sssp_ring != 1) return set_error(TG_EINVAL, "tuning: sssp_ring must be 0 or 1");
   if (t->sssp_split != 0 && t->sssp_split != 1) return set_error(TG_EINVAL, "tuning: sssp_split must be 0 or 1");

@@ -360,7 +360,7 @@ unsigned long long stat_sum(const Workspace &ws, int k);
 struct HybridState;
 struct SlotEngine;
 struct BcBatchState;
-constexpr int MAX_LANES = 4;  // searches in flight of one multi-root call
+constexpr int MAX_LANES = 8;  // searches in flight of one multi-root call
 
 }  // namespace tg
 
