@@ -65,12 +65,16 @@ __device__ __forceinline__ uint32_t cblock_exclusive_scan(uint32_t x, uint32_t &
 // at a time, one vertex per lane, so that the distance and settled loads of
 // 64 consecutive vertices are one coalesced access each; pairs of zero words
 // are skipped, and up to four pairs are in flight at once.  Lane l ends with
-// the keep and drop masks of its own word.
+// the keep and drop masks of its own word.  With `lcnt`, `queued` is the
+// part of keep whose vertices have at least one light edge (the others have
+// nothing to relax in a light pass); without, it equals keep.
 __device__ __forceinline__ void sssp_filter_wave(uint32_t w, int64_t word0, const int32_t *__restrict__ dist,
-                                                 int32_t *__restrict__ settled, int32_t thresh, uint32_t &keep,
+                                                 int32_t *__restrict__ settled, const int32_t *__restrict__ lcnt,
+                                                 int32_t thresh, uint32_t &keep, uint32_t &queued,
                                                  uint32_t &dropped, uint32_t &rest, int32_t &rest_min) {
   const int lane = threadIdx.x & 63;
   keep = 0;
+  queued = 0;
   dropped = 0;
   // bit 2p: word 2p or 2p + 1 has a set bit
   const unsigned long long nz = __ballot(w != 0u);
@@ -83,7 +87,7 @@ __device__ __forceinline__ void sssp_filter_wave(uint32_t w, int64_t word0, cons
       pairs &= pairs - 1;
     }
     bool mine[4];
-    int32_t d[4], st[4];
+    int32_t d[4], st[4], lc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       mine[j] = false;
@@ -95,6 +99,7 @@ __device__ __forceinline__ void sssp_filter_wave(uint32_t w, int64_t word0, cons
         const int64_t v = (word0 + p[j]) * 32 + lane;
         d[j] = dist[v];
         st[j] = settled[v];
+        lc[j] = lcnt ? lcnt[v] : 1;
       }
     }
 #pragma unroll
@@ -112,12 +117,14 @@ __device__ __forceinline__ void sssp_filter_wave(uint32_t w, int64_t word0, cons
           rest_min = d[j] < rest_min ? d[j] : rest_min;
         }
       }
-      const unsigned long long km = __ballot(k), dm = __ballot(dr);
+      const unsigned long long km = __ballot(k), dm = __ballot(dr), qm = __ballot(k && lc[j] > 0);
       if (lane == p[j]) {
         keep = (uint32_t)km;
+        queued = (uint32_t)qm;
         dropped = (uint32_t)dm;
       } else if (lane == p[j] + 1) {
         keep = (uint32_t)(km >> 32);
+        queued = (uint32_t)(qm >> 32);
         dropped = (uint32_t)(dm >> 32);
       }
     }
@@ -134,15 +141,16 @@ __global__ __launch_bounds__(CT) void k_sssp_filter(uint32_t *__restrict__ bits,
                                                     uint32_t *__restrict__ bcount, const int32_t *__restrict__ dist,
                                                     int32_t *__restrict__ settled, int32_t thresh,
                                                     unsigned long long *rest_cnt, unsigned long long *rest_min,
-                                                    uint32_t *__restrict__ members) {
+                                                    uint32_t *__restrict__ members,
+                                                    const int32_t *__restrict__ lcnt) {
   const int64_t q = (int64_t)blockIdx.x * CT + threadIdx.x;  // word index
   const uint32_t v = bits[q];
-  uint32_t keep, dr;
+  uint32_t keep, queued, dr;
   uint32_t r = 0;
   int32_t rmin = TG_INF;
-  sssp_filter_wave(v, q - (threadIdx.x & 63), dist, settled, thresh, keep, dr, r, rmin);
+  sssp_filter_wave(v, q - (threadIdx.x & 63), dist, settled, lcnt, thresh, keep, queued, dr, r, rmin);
   bits[q] = v & ~(keep | dr);
-  keep_out[q] = keep;
+  keep_out[q] = queued;
   if (members && keep) members[q] |= keep;
   if (rest_cnt) {
     r = cblock_sum(r);
@@ -154,7 +162,7 @@ __global__ __launch_bounds__(CT) void k_sssp_filter(uint32_t *__restrict__ bits,
       atomicMin(rest_min + (size_t)(blockIdx.x & (STAT_SLOTS - 1)) * STAT_STRIDE, (unsigned long long)rmin);
     if (threadIdx.x == 0 && r) stat_add(rest_cnt, (unsigned long long)r);
   }
-  const uint32_t c = cblock_sum((uint32_t)__popc(keep));
+  const uint32_t c = cblock_sum((uint32_t)__popc(queued));
   if (threadIdx.x == 0) bcount[blockIdx.x] = c;
 }
 
@@ -518,7 +526,7 @@ int bitmap_merge_clear(Workspace &ws, uint32_t *done, uint32_t *members, hipStre
 
 int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
                           int32_t *settled, int32_t thresh, bool near, const BinBounds &bb, hipStream_t s,
-                          unsigned long long *degsum, uint32_t *members) {
+                          unsigned long long *degsum, uint32_t *members, const int32_t *lcnt) {
   const int blocks = (int)(ws.nwords / WPB);
   unsigned long long *rest_cnt = nullptr, *rest_min = nullptr;
   if (near) {
@@ -531,7 +539,7 @@ int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32
   }
   // the taken bits go to bits_b (free during SSSP and connected components)
   hipLaunchKernelGGL(k_sssp_filter, dim3(blocks), dim3(CT), 0, s, bits, ws.bits_b, ws.bcount, dist, settled,
-                     near ? thresh : TG_INF, rest_cnt, rest_min, members);
+                     near ? thresh : TG_INF, rest_cnt, rest_min, members, lcnt);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, ws.bits_b, nullptr, 4, ws.bcount, queue,
                      nullptr, 0, bb, g.n, ws.plan, nullptr, degsum ? g.out.off : nullptr, degsum, nullptr, (int64_t)0);
   TG_HIP(hipGetLastError());

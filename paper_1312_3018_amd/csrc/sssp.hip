@@ -39,14 +39,29 @@ __global__ void k_set_i32(int32_t *p, int64_t i, int32_t v) {
   if (threadIdx.x == 0) p[i] = v;
 }
 
-// any[j] = 1 if bitmap j of the ring has a set bit (grid.y = bitmap; any
-// zeroed before).
-__global__ __launch_bounds__(BLOCK) void k_ring_any(const uint32_t *__restrict__ ring, int64_t nwords,
-                                                    uint32_t *any) {
-  const uint32_t *b = ring + (int64_t)blockIdx.y * nwords;
-  uint32_t acc = 0;
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nwords; i += (int64_t)gridDim.x * BLOCK) acc |= b[i];
-  if (__syncthreads_or(acc != 0u) && threadIdx.x == 0) any[blockIdx.y] = 1u;
+// The next non-empty bitmap of the ring after bitmap `cur`: the blocks scan
+// bitmaps cur+1, cur+2, ... (mod k) in turn, each block its share of every
+// word range, and any[b] = 1 marks bitmap b as having a set bit (any zeroed
+// before).  A block stops once a nearer bitmap is marked: then no later one
+// can be the next.  Every block scans each bitmap up to and including the
+// nearest non-empty one, so that one is always marked; marks beyond it may
+// be missing, and the caller takes the nearest mark.
+__global__ __launch_bounds__(BLOCK) void k_ring_next(const uint32_t *__restrict__ ring, int64_t nwords, int k,
+                                                     int cur, uint32_t *any) {
+  for (int j = 1; j < k; ++j) {
+    bool nearer = false;
+    if (threadIdx.x == 0)
+      for (int m = 1; m < j; ++m)
+        nearer |= __hip_atomic_load(any + (cur + m) % k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    if (__syncthreads_or(nearer)) return;
+    const int b = (cur + j) % k;
+    const uint32_t *bits = ring + (int64_t)b * nwords;
+    uint32_t acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nwords; i += (int64_t)gridDim.x * BLOCK)
+      acc |= bits[i];
+    if (__syncthreads_or(acc != 0u) && threadIdx.x == 0)
+      __hip_atomic_store(any + b, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // Per vertex: how many of its packed out-edges (row sorted by weight) are
@@ -525,8 +540,10 @@ int gpu_sssp_ring(tg_partition *p, Workspace &ws, int32_t root, hipStream_t s, i
       return set_error(TG_EDEVICE, "sssp: no convergence after %lld rounds", (long long)rounds);
     uint32_t *bits = ws.buckets + ((lo / delta) % k) * ws.nwords;
     // every unsettled bit of the current bucket is in [lo, lo + delta): all are taken
+    // (with the split, a vertex without light edges joins the bucket's
+    // members but not the light pass)
     TG_TRY(frontier_compact_sssp(g, ws, bits, ws.queue, ws.state, ws.settled, TG_INF, false, bb, s, nullptr,
-                                 members));
+                                 members, split ? g.lcnt : nullptr));
     TG_TRY(frontier_plan_bins(g, ws, ws.queue, bb, split ? g.lcnt : nullptr, p->tune, s, true));
     if (ws.h_plan->count > 0) {
       ++rounds;
@@ -571,13 +588,14 @@ int gpu_sssp_ring(tg_partition *p, Workspace &ws, int32_t root, hipStream_t s, i
     }
     // the current bucket is empty: move to the next bucket with a set bit,
     // if any (the ring holds every active vertex)
+    const int64_t cur = (lo / delta) % k;
     TG_HIP(hipMemsetAsync(ws.counters + 16, 0, (size_t)k * sizeof(uint32_t), s));
-    const unsigned bx = (unsigned)std::min<int64_t>((ws.nwords + BLOCK - 1) / BLOCK, 64);
-    hipLaunchKernelGGL(k_ring_any, dim3(bx, (unsigned)k), dim3(BLOCK), 0, s, ws.buckets, ws.nwords, ws.counters + 16);
+    const unsigned bx = (unsigned)std::min<int64_t>((ws.nwords + 8 * BLOCK - 1) / (8 * BLOCK), 512);
+    hipLaunchKernelGGL(k_ring_next, dim3(bx), dim3(BLOCK), 0, s, ws.buckets, ws.nwords, (int)k, (int)cur,
+                       ws.counters + 16);
     TG_HIP(hipGetLastError());
     TG_HIP(hipMemcpyAsync(ws.h_flags + 16, ws.counters + 16, (size_t)k * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     TG_HIP(hipStreamSynchronize(s));
-    const int64_t cur = (lo / delta) % k;
     int64_t step = 0;
     for (int64_t j = 1; j < k && step == 0; ++j)
       if (ws.h_flags[16 + (cur + j) % k]) step = j;

@@ -409,10 +409,13 @@ int frontier_plan(const GpuPart &g, Workspace &ws, const int32_t *queue, const T
 // stay active and spread counters 5 and 6 get their count and least
 // distance.
 // With `degsum`, the taken frontier's out-degree sum is added to it; with
-// `members`, the taken bits are also ORed into that bitmap.
+// `members`, the taken bits are also ORed into that bitmap; with `lcnt`,
+// taken vertices with no light edge (lcnt[v] == 0) are left out of the
+// queue (they are still taken, and still ORed into `members`).
 int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32_t *queue, const int32_t *dist,
                           int32_t *settled, int32_t thresh, bool near, const BinBounds &bb, hipStream_t s,
-                          unsigned long long *degsum = nullptr, uint32_t *members = nullptr);
+                          unsigned long long *degsum = nullptr, uint32_t *members = nullptr,
+                          const int32_t *lcnt = nullptr);
 // The end of an SSSP bucket (light/heavy split): with `pull` false, the
 // bucket's members (bitmap `members`, left as it is) go to the queue and
 // their out-degree sum is added to `degsum`; with `pull` true, the vertices
