@@ -73,6 +73,7 @@ def load_traffic(kernel: str, workload: str):
 # the mean over all their launches).
 TRAFFIC_ROWS = {
     "sssp_relax": ("sssp", ["k_sssp_relax<true, 1>", "k_sssp_relax<true, 2>"], "pool"),
+    "sssp_pull": ("ssspp", ["k_sssp_pull_heavy"], "sum"),
     "pr_gather": ("pr", ["k_pr_rows<true, int, 8>", "k_pr_long<true>", "k_pr_combine", "k_pr_dsum"], "sum"),
     "bfs_step": ("bfs", ["k_bfs_step<int>"], "sum"),
 }
@@ -110,6 +111,8 @@ def traffic_from(pmc_dir: str, workload: str = "rmat24") -> dict:
 
     out = {}
     for kernel, (algo, names, how) in TRAFFIC_ROWS.items():
+        if not os.path.isdir(os.path.join(pmc_dir, f"{algo}_fetch")):
+            continue  # no passes taken for this kernel
         fe, wr, hit = (values_by_kernel(f"{algo}_{kind}") for kind in ("fetch", "write", "hit"))
         f, launches = per_launch(fe, names, "FETCH_SIZE", how)
         f *= FETCH_SCALE * 1024

@@ -117,6 +117,7 @@ def test_traffic_from_counter_csvs(tmp_path):
     calibration; the L2 hit rate from the hit/miss pass."""
     rows = {"fetch": "FETCH_SIZE", "write": "WRITE_SIZE"}
     names = {"sssp": ["k_sssp_relax<true, 1>(int const*)", "k_sssp_relax<true, 2>(int const*)"],
+             "ssspp": ["k_sssp_pull_heavy(Plan const*)"],
              "pr": ["k_pr_rows<true, int, 8>(Args)", "k_pr_long<true>(Args)", "k_pr_combine(x)", "k_pr_dsum(y)"],
              "bfs": ["k_bfs_step<int>(a)"]}
     for algo, kernels in names.items():
@@ -137,5 +138,6 @@ def test_traffic_from_counter_csvs(tmp_path):
     assert t["sssp_relax"]["launches_sampled"] == 4  # pooled: two launches of each variant
     assert t["pr_gather"]["fetch_bytes"] == round(4 * kib * bench.FETCH_SCALE)
     assert t["bfs_step"]["write_bytes"] == kib
+    assert t["sssp_pull"]["fetch_bytes"] == round(kib * bench.FETCH_SCALE)
     assert all(r["l2_hit_rate"] == 0.75 for r in t.values())
     assert t["sssp_relax"]["sources"] == bench.kernel_sources_digest(bench.KERNEL_FILES["sssp_relax"])
