@@ -934,8 +934,12 @@ def main():
         bytes_per_launch = v["bytes"] / n
         achieved = bytes_per_launch / (eff_ms / 1e3) / 1e9
         tr = load_traffic(k, args.workload)
+        # the same bytes over the mean launch duration (which, with launches
+        # of concurrent searches overlapping, also counts their waits)
+        on_mean = bytes_per_launch / (v["ms"] / n / 1e3) / 1e9 if v["ms"] > 0 else 0.0
         roofs[k] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "frac_on_mean_launch": round(on_mean / HBM_PEAK_GBS, 4),
                     "traffic": tr, "algorithmic_bytes_per_launch": round(bytes_per_launch),
                     "avg_launch_ms": round(v["ms"] / n, 5), "busy_ms_per_launch": round(eff_ms, 5),
                     "launches": int(v["n"]), "share_of_step": round(v["busy"] / prof_ms_step, 4)}

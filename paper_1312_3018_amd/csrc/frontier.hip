@@ -193,7 +193,8 @@ __global__ __launch_bounds__(CT) void k_compact_write(uint32_t *__restrict__ bit
                                                       int32_t level_value, BinBounds bb, int64_t n,
                                                       Plan *__restrict__ plan, uint32_t *__restrict__ fbits,
                                                       const int64_t *__restrict__ off, unsigned long long *degsum,
-                                                      const BfsCtl *__restrict__ ctl, int64_t skip_min) {
+                                                      const BfsCtl *__restrict__ ctl, int64_t skip_min,
+                                                      int64_t valid_n) {
   bool bu = false;
   if (ctl) {
     // device-resident BFS: the level and whether to sum degrees come from
@@ -231,8 +232,8 @@ __global__ __launch_bounds__(CT) void k_compact_write(uint32_t *__restrict__ bit
   } else if (mode == 4) {
     // a bitmap already filtered (k_sssp_filter): take it as it is
   } else if (mode == 5) {
-    // the vertices below n in neither bitmap; both stay as they are
-    nw = ~(v | prev[q]) & valid_bits(q, n);
+    // the vertices below valid_n in neither bitmap; both stay as they are
+    nw = ~(v | prev[q]) & valid_bits(q, valid_n);
   } else {
     if (mode == 2) prev[q] = v;  // prev := the set taken
     bits[q] = 0;
@@ -468,7 +469,7 @@ int frontier_compact(const GpuPart &g, Workspace &ws, int mode, uint32_t *bits, 
   hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(CT), 0, s, bits, mode == 0 ? prev : nullptr, ws.bcount,
                      nullptr, 0, (int64_t)0);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, bits, prev, mode, ws.bcount, queue, level,
-                     level_value, g.out_bins, g.n, ws.plan, nullptr, nullptr, nullptr, nullptr, (int64_t)0);
+                     level_value, g.out_bins, g.n, ws.plan, nullptr, nullptr, nullptr, nullptr, (int64_t)0, g.n);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
@@ -492,7 +493,7 @@ int frontier_compact_bfs_dev(const GpuPart &g, Workspace &ws, const Tuning &t, h
                      (int64_t)0);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, ws.bits_a, ws.bits_b, 0, ws.bcount, ws.queue,
                      ws.state, 0, g.out_bins, g.n, ws.plan, ws.bits_c, g.out.off, stat_counter(ws.work, 4), ws.ctl,
-                     t.bfs_do ? g.n / t.bfs_beta : INT64_MAX);
+                     t.bfs_do ? g.n / t.bfs_beta : INT64_MAX, g.n);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
@@ -508,11 +509,13 @@ int frontier_plan_bfs_dev(const GpuPart &g, Workspace &ws, const Tuning &t, hipS
 int frontier_compact_bucket_end(const GpuPart &g, Workspace &ws, uint32_t *members, uint32_t *done, bool pull,
                                 int32_t *queue, unsigned long long *degsum, hipStream_t s) {
   const int blocks = (int)(ws.nwords / WPB);
+  // vertices of out-degree 0 (the last ids) have no edge to pull over
+  const int64_t nz = g.out_bins.bstart[BIN_ZERO];
   hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(CT), 0, s, members, pull ? done : nullptr, ws.bcount,
-                     nullptr, pull ? 1 : 0, g.n);
+                     nullptr, pull ? 1 : 0, nz);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, members, done, pull ? 5 : 4, ws.bcount, queue,
                      nullptr, 0, g.out_bins, g.n, ws.plan, nullptr, degsum ? g.out.off : nullptr, degsum, nullptr,
-                     (int64_t)0);
+                     (int64_t)0, nz);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }
@@ -541,7 +544,8 @@ int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32
   hipLaunchKernelGGL(k_sssp_filter, dim3(blocks), dim3(CT), 0, s, bits, ws.bits_b, ws.bcount, dist, settled,
                      near ? thresh : TG_INF, rest_cnt, rest_min, members, lcnt);
   hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(CT), 0, s, ws.bits_b, nullptr, 4, ws.bcount, queue,
-                     nullptr, 0, bb, g.n, ws.plan, nullptr, degsum ? g.out.off : nullptr, degsum, nullptr, (int64_t)0);
+                     nullptr, 0, bb, g.n, ws.plan, nullptr, degsum ? g.out.off : nullptr, degsum, nullptr, (int64_t)0,
+                     g.n);
   TG_HIP(hipGetLastError());
   return TG_OK;
 }

@@ -419,8 +419,9 @@ int frontier_compact_sssp(const GpuPart &g, Workspace &ws, uint32_t *bits, int32
 // The end of an SSSP bucket (light/heavy split): with `pull` false, the
 // bucket's members (bitmap `members`, left as it is) go to the queue and
 // their out-degree sum is added to `degsum`; with `pull` true, the vertices
-// in neither `members` nor `done` (those whose distance is not yet final)
-// go to the queue.  Either queue is sorted by id and binned by out_bins.
+// with out-edges in neither `members` nor `done` (those whose distance is
+// not yet final and that have edges to pull over) go to the queue.  Either
+// queue is sorted by id and binned by out_bins.
 int frontier_compact_bucket_end(const GpuPart &g, Workspace &ws, uint32_t *members, uint32_t *done, bool pull,
                                 int32_t *queue, unsigned long long *degsum, hipStream_t s);
 // done |= members, members := 0 (ws.nwords words each).
