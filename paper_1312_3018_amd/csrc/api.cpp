@@ -640,6 +640,19 @@ int apply_tuning(tg_partition *p, const Tuning &t) {
 // A 32-bit copy of CSR offsets when every offset fits (m < 2^31): half the
 // offset bytes of a bottom-up BFS step, which reads them for every
 // unvisited vertex.  Left null otherwise.
+// The first four in-neighbours of every vertex, four int32 per vertex (-1
+// past the row): a bottom-up BFS step reads them with one 16-byte load per
+// vertex, consecutive vertices side by side, and usually finds a parent
+// among them (rows are sorted by id, i.e. by decreasing degree).
+int upload_head(DevArena &A, int32_t **d, const std::vector<int64_t> &off, const std::vector<int32_t> &col,
+                int64_t n) {
+  std::vector<int32_t> head((size_t)std::max<int64_t>(n, 1) * 4, -1);
+#pragma omp parallel for schedule(static)
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t j = 0; j < 4 && off[v] + j < off[v + 1]; ++j) head[(size_t)v * 4 + j] = col[off[v] + j];
+  return upload(A, d, head.data(), head.size());
+}
+
 int upload_off32(DevArena &A, int32_t **d, const std::vector<int64_t> &off, int64_t m) {
   if (m >= (int64_t)INT32_MAX) return TG_OK;
   std::vector<int32_t> o32(off.size());
@@ -763,6 +776,7 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
     for (int64_t i = 0; i < n; ++i) gp.n_dangling += (deg_in_order[i] == 0);
     gp.n_isolated = gp.n_dangling;
     TG_TRY(upload_off32(A, &gp.in_off32, off, m));
+    TG_TRY(upload_head(A, &gp.in_head, off, col, n));
   } else {
     std::vector<int64_t> ioff;
     std::vector<int32_t> icol;
@@ -770,6 +784,7 @@ int build_gpu_part(tg_partition *p, const std::vector<int32_t> &verts, BoundaryE
     TG_TRY(upload(A, &gp.in.off, ioff.data(), (size_t)n + 1));
     TG_TRY(edges(&gp.in.col, icol));
     TG_TRY(upload_off32(A, &gp.in_off32, ioff, m));
+    TG_TRY(upload_head(A, &gp.in_head, ioff, icol, n));
     gp.in.n = n;
     gp.in.m = m;
     gp.in_alias = false;

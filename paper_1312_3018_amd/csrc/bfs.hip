@@ -124,13 +124,16 @@ struct LevelOut {
 
 // Bottom-up step, one thread per vertex in [v0, v1): an unvisited vertex
 // looks at its in-neighbours four at a time and joins the next frontier at
-// the first one found in `fbits` (the level-L set).  The out-degrees of the
+// the first one found in `fbits` (the level-L set).  The first four come
+// from `head` (one 16-byte load per vertex, consecutive vertices side by
+// side), the rest from the in-edge rows.  The out-degrees of the
 // vertices that join are summed into `joined` (the direction switch's m_f).
 // Waves cover whole bitmap words (lanes 0-31 one word, 32-63 the next), so
 // the joins of a word are set with one atomic instead of one per lane.
 // Blocks [blk0, blk0 + nblk) of the grid share the range.
 template <typename OffT>
 __device__ __forceinline__ void bottom_up_threads(const OffT *__restrict__ ioff, const int32_t *__restrict__ icol,
+                                                  const int4 *__restrict__ head,
                                                   const uint32_t *__restrict__ fbits, uint32_t *visited, int64_t v0,
                                                   int64_t v1, const int64_t *__restrict__ ooff, int64_t blk,
                                                   int64_t nblk, const LevelOut &lo, unsigned long long &checked,
@@ -143,7 +146,20 @@ __device__ __forceinline__ void bottom_up_threads(const OffT *__restrict__ ioff,
     if (v >= v0 && v < v1 && !(visited[v >> 5] & (1u << (v & 31)))) {
       ++examined;
       const int64_t e0 = (int64_t)ioff[v], e1 = (int64_t)ioff[v + 1];
-      for (int64_t e = e0; e < e1; e += 4) {
+      bool hhit = false;
+      if (head) {
+        const int4 h = head[v];
+        const int32_t hu[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) hhit |= hu[k] >= 0 && ((fbits[hu[k] >> 5] >> (hu[k] & 31)) & 1u);
+        checked += (unsigned long long)(e1 - e0 < 4 ? e1 - e0 : 4);
+        if (hhit) {
+          joins = true;
+          joined += joined_degree(ooff, v, e0, e1);
+          lo.put((int32_t)v);
+        }
+      }
+      for (int64_t e = e0 + (head ? 4 : 0); !hhit && e < e1; e += 4) {
         int32_t u[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) u[k] = icol[e + k < e1 ? e + k : e1 - 1];
@@ -208,6 +224,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_step(const Plan *__restrict__ Pp,
                                                     const int64_t *__restrict__ off, const int32_t *__restrict__ col,
                                                     uint32_t *visited, int64_t hub_chunk, unsigned long long *work,
                                                     const OffT *__restrict__ ioff, const int32_t *__restrict__ icol,
+                                                    const int4 *__restrict__ head,
                                                     const uint32_t *__restrict__ fbits, int64_t wave_end,
                                                     int64_t n_end, int64_t wave_blocks,
                                                     const int64_t *__restrict__ ooff, unsigned long long *degsum,
@@ -232,7 +249,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_step(const Plan *__restrict__ Pp,
     bottom_up_waves(ioff, icol, fbits, visited, 0, wave_end, ooff, blockIdx.x, wave_blocks, lo, checked, joined,
                     examined);
   else
-    bottom_up_threads(ioff, icol, fbits, visited, wave_end, n_end, ooff, blockIdx.x - wave_blocks,
+    bottom_up_threads(ioff, icol, head, fbits, visited, wave_end, n_end, ooff, blockIdx.x - wave_blocks,
                       gridDim.x - wave_blocks, lo, checked, joined, examined);
   checked = block_sum(checked);
   joined = block_sum(joined);
@@ -292,11 +309,13 @@ int bfs_dev_step(const GpuPart &g, Workspace &ws, const Tuning &t, hipStream_t s
   const int tk = timed ? ktimer_start(s) : -1;
   if (g.in_off32)
     hipLaunchKernelGGL(k_bfs_step<int32_t>, dim3(grid), dim3(BLOCK), 0, s, ws.plan, ws.queue, ws.hubpref, g.out.off,
-                       g.out.col, ws.bits_a, t.hub_chunk, ws.work, g.in_off32, g.in.col, ws.bits_c, wave_end, n_end,
+                       g.out.col, ws.bits_a, t.hub_chunk, ws.work, g.in_off32, g.in.col,
+                       reinterpret_cast<const int4 *>(g.in_head), ws.bits_c, wave_end, n_end,
                        wave_blocks, ooff, stat_counter(ws.work, 4), ws.state, ws.ctl);
   else
     hipLaunchKernelGGL(k_bfs_step<int64_t>, dim3(grid), dim3(BLOCK), 0, s, ws.plan, ws.queue, ws.hubpref, g.out.off,
-                       g.out.col, ws.bits_a, t.hub_chunk, ws.work, g.in.off, g.in.col, ws.bits_c, wave_end, n_end,
+                       g.out.col, ws.bits_a, t.hub_chunk, ws.work, g.in.off, g.in.col,
+                       reinterpret_cast<const int4 *>(g.in_head), ws.bits_c, wave_end, n_end,
                        wave_blocks, ooff, stat_counter(ws.work, 4), ws.state, ws.ctl);
   ktimer_stop(tk, s, "bfs_step");
   TG_HIP(hipGetLastError());

@@ -280,6 +280,7 @@ struct GpuPart {
   int64_t n_isolated = 0;        // out-degree 0 and in-degree 0 (ZERO bin of in_bins when symmetric)
   int64_t max_out_hubs = 0;      // vertices in the HUB bin (out-degree)
   int32_t *in_off32 = nullptr;   // in-edge offsets as int32 when m < 2^31 (the bottom-up BFS step), else null
+  int32_t *in_head = nullptr;    // 4 per vertex: its first four in-neighbours, -1 past the row (bottom-up BFS)
   bool mapped_edges = false;     // edge arrays (col, w; in-edge col) in mapped host memory (fixed at build)
   std::vector<int64_t> h_out_off;  // host copy of the local out offsets
   std::vector<int64_t> h_deg;      // out-degree of each local id (non-increasing)
