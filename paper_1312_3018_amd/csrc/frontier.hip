@@ -145,6 +145,12 @@ __global__ __launch_bounds__(CT) void k_sssp_filter(uint32_t *__restrict__ bits,
                                                     const int32_t *__restrict__ lcnt) {
   const int64_t q = (int64_t)blockIdx.x * CT + threadIdx.x;  // word index
   const uint32_t v = bits[q];
+  if (!__syncthreads_or(v != 0u)) {
+    // no active bit in the block's words: nothing taken
+    keep_out[q] = 0u;
+    if (threadIdx.x == 0) bcount[blockIdx.x] = 0u;
+    return;
+  }
   uint32_t keep, queued, dr;
   uint32_t r = 0;
   int32_t rmin = TG_INF;
@@ -207,6 +213,17 @@ __global__ __launch_bounds__(CT) void k_compact_write(uint32_t *__restrict__ bit
       degsum = nullptr;
       level = nullptr;
     }
+  }
+  if (mode == 4 && bcount[blockIdx.x] == 0u && blockIdx.x != gridDim.x - 1) {
+    // a filtered block with nothing taken writes nothing, unless a degree
+    // bin starts in its words (the bin's queue position is set here)
+    bool starts = false;
+#pragma unroll
+    for (int b = 0; b < NBIN; ++b) {
+      const int64_t w = bb.bstart[b] >> 5;
+      starts |= bb.bstart[b] < n && w >= (int64_t)blockIdx.x * CT && w < ((int64_t)blockIdx.x + 1) * CT;
+    }
+    if (!starts) return;
   }
   const int64_t q = (int64_t)blockIdx.x * CT + threadIdx.x;  // word index
   const uint32_t v = bits[q];
