@@ -394,11 +394,18 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+# The server runs SSSP on graphs of at least this many vertices as single
+# searches (its default sssp_solo_min_vertices).
+SERVE_SOLO_MIN_VERTICES = 1 << 22
+
+
 def serve_capacity(tg, parts, log, batch=64):
-    """GPU time per query of each (graph, kind) lane when its engine is full:
-    one batch of `batch` queries through the slot engine, and a few queries
-    one at a time, each after a warm-up.  The mix's capacity is the inverse of
-    the mean batched time per query over the lanes (the queries are spread
+    """GPU time per query of each (graph, kind) lane when it is full: one
+    batch of `batch` queries through the slot engine, the same queries as
+    single searches (several in flight, as the server runs SSSP on large
+    graphs), and a few queries one at a time, each after a warm-up.  The
+    mix's capacity is the inverse of the mean time per query over the lanes,
+    each lane taken the way the server serves it (the queries are spread
     evenly over graphs and kinds)."""
     import numpy as np
     import torch
@@ -419,9 +426,18 @@ def serve_capacity(tg, parts, log, batch=64):
             solo(P, roots[:8], out[:8])
             torch.cuda.synchronize()
             ts = (time.perf_counter() - t) / 8
-            lanes.append({"graph": SERVE_GRAPHS[gi], "kind": kind, "ms_per_query_batched": round(tb * 1e3, 3),
-                          "ms_per_query_solo": round(ts * 1e3, 3)})
-            per_query.append(tb)
+            row = {"graph": SERVE_GRAPHS[gi], "kind": kind, "ms_per_query_batched": round(tb * 1e3, 3),
+                   "ms_per_query_solo": round(ts * 1e3, 3)}
+            served = tb
+            if kind == "sssp" and g.n >= SERVE_SOLO_MIN_VERTICES:
+                t = time.perf_counter()
+                solo(P, roots, out)
+                torch.cuda.synchronize()
+                served = (time.perf_counter() - t) / batch
+                row["ms_per_query_single_searches"] = round(served * 1e3, 3)
+            row["served_by"] = "single searches" if served is not tb else "slot engine"
+            lanes.append(row)
+            per_query.append(served)
         del out
     cap = round(1.0 / float(np.mean(per_query)), 1)
     log(f"[serve] capacity of the mix with full engines: {cap} queries/s")

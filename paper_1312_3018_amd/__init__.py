@@ -346,11 +346,14 @@ TG_QUERY_BFS, TG_QUERY_SSSP = 0, 1
 class Server:
     """Continuous-batching query server (server_* in the C ABI)."""
 
-    def __init__(self, max_slots: int = 64, memory_cap_bytes: Optional[int] = None):
+    def __init__(self, max_slots: int = 64, memory_cap_bytes: Optional[int] = None,
+                 sssp_solo_min_vertices: Optional[int] = None):
         lib = _load()
         opts = {"max_slots": int(max_slots)}
         if memory_cap_bytes is not None:
             opts["memory_cap_bytes"] = int(memory_cap_bytes)
+        if sssp_solo_min_vertices is not None:
+            opts["sssp_solo_min_vertices"] = int(sssp_solo_min_vertices)
         h = ctypes.c_void_p()
         _check(lib.server_create(json.dumps(opts).encode(), ctypes.byref(h)))
         self._h = h.value

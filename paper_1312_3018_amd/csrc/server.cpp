@@ -7,16 +7,25 @@
 // own stream, so different graphs' supersteps overlap on the device), then
 // completes them, retires finished slots (results are in the caller's buffer)
 // and admits waiting queries.
+//
+// SSSP on a large graph is served by solo searches instead: the slot engine
+// relaxes every active (vertex, query) pair each superstep, which costs more
+// than the delta-stepping schedule of a single search once the graph is
+// large.  Such a lane has its own host threads (up to the partition's
+// sssp_lanes, at most max_slots), each running one query at a time with the
+// single-search schedule on its own workspace and stream.
 #include <hip/hip_runtime.h>
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -49,6 +58,10 @@ struct Lane {  // one (graph, kind) engine
   Query *slot_q[kSlots] = {};
   bool launched = false;
   int64_t engine_bytes = 0;
+  // solo SSSP lane: its queries run as single searches on these threads
+  bool solo = false;
+  std::vector<std::thread> solo_workers;
+  int running = 0;  // queries the solo threads are running
 };
 
 bool json_num(const char *json, const char *key, double *out) {
@@ -75,6 +88,7 @@ struct tg_server {
   std::unordered_map<uint64_t, std::unique_ptr<Query>> queries;
   uint64_t next_ticket = 1;
   int max_slots = kSlots;
+  int64_t solo_min_n = int64_t(1) << 22;  // SSSP lanes of graphs this large run solo searches
   int64_t mem_cap = INT64_MAX;
   int64_t mem_used = 0;
   int device = 0;
@@ -84,6 +98,7 @@ struct tg_server {
   int64_t completed = 0, supersteps = 0, max_concurrent = 0;
 
   void run();
+  void solo_worker(Lane *L);
 };
 
 namespace {
@@ -106,6 +121,58 @@ void finish(tg_server *S, Query *q, int status, const std::string &err) {
 
 }  // namespace
 
+// One thread of a solo SSSP lane: take the next waiting query that fits the
+// memory cap, run it as a single search, write its distances, repeat.
+void tg_server::solo_worker(Lane *L) {
+  TG_QUIET(hipSetDevice(device));
+  tg_partition *p = L->p;
+  Workspace ws;
+  hipStream_t st = nullptr;
+  int setup = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess
+                  ? TG_OK
+                  : set_error(TG_EDEVICE, "server: hipStreamCreateWithFlags failed");
+  if (setup == TG_OK) setup = ws.ensure(p->gpu, 0);
+  const std::string setup_err = setup == TG_OK ? "" : tg_last_error();
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    cv_work.wait(lk, [&] {
+      return stop || (!L->waiting.empty() && (setup != TG_OK || mem_used + L->waiting.front()->bytes <= mem_cap));
+    });
+    if (stop) break;
+    Query *q = L->waiting.front();
+    L->waiting.pop_front();
+    if (setup != TG_OK) {
+      finish(this, q, setup, setup_err);
+      cv_done.notify_all();
+      continue;
+    }
+    mem_used += q->bytes;
+    ++L->running;
+    int64_t running = 0;
+    for (auto &lp : lanes) running += lp->running + (lp->eng ? __builtin_popcountll(lp->eng->busy) : 0);
+    if (running > max_concurrent) max_concurrent = running;
+    const int32_t root = p->h_l_of_g[q->root];
+    lk.unlock();
+    int64_t rounds = 0, pulls = 0;
+    int rc = gpu_sssp(p, ws, root, st, &rounds, &pulls);
+    if (rc == TG_OK) rc = collect_i32(p->gpu, ws.state, q->out, st);
+    if (rc == TG_OK && hipStreamSynchronize(st) != hipSuccess)
+      rc = set_error(TG_EDEVICE, "server: hipStreamSynchronize failed");
+    const std::string err = rc == TG_OK ? "" : tg_last_error();
+    ktimer_flush();
+    lk.lock();
+    --L->running;
+    finish(this, q, rc, err);
+    cv_done.notify_all();
+    cv_work.notify_all();  // memory freed: other lanes may admit
+  }
+  lk.unlock();
+  if (st) {
+    TG_QUIET(hipStreamSynchronize(st));
+    TG_QUIET(hipStreamDestroy(st));
+  }
+}
+
 void tg_server::run() {
   TG_QUIET(hipSetDevice(device));
   std::unique_lock<std::mutex> lk(mu);
@@ -115,7 +182,7 @@ void tg_server::run() {
     bool in_flight = false;
     for (auto &lp : lanes) {
       Lane &L = *lp;
-      if (!L.p) continue;
+      if (!L.p || L.solo) continue;
       if (L.launched) {
         in_flight = true;
         continue;
@@ -157,8 +224,7 @@ void tg_server::run() {
       }
     }
     int64_t running = 0;
-    for (auto &lp : lanes)
-      if (lp->eng) running += __builtin_popcountll(lp->eng->busy);
+    for (auto &lp : lanes) running += lp->running + (lp->eng ? __builtin_popcountll(lp->eng->busy) : 0);
     if (running > max_concurrent) max_concurrent = running;
     if (!in_flight) {
       if (stop) break;
@@ -223,6 +289,7 @@ extern "C" int server_create(const char *opts_json, tg_server **out) {
   double v;
   if (json_num(opts_json, "max_slots", &v)) S->max_slots = (int)v;
   if (json_num(opts_json, "memory_cap_bytes", &v)) S->mem_cap = (int64_t)v;
+  if (json_num(opts_json, "sssp_solo_min_vertices", &v)) S->solo_min_n = (int64_t)v;
   if (S->max_slots < 1 || S->max_slots > kSlots) {
     delete S;
     return set_error(TG_EINVAL, "server_create: max_slots must be in [1, 64]");
@@ -230,6 +297,10 @@ extern "C" int server_create(const char *opts_json, tg_server **out) {
   if (S->mem_cap < 0) {
     delete S;
     return set_error(TG_EINVAL, "server_create: memory_cap_bytes < 0");
+  }
+  if (S->solo_min_n < 0) {
+    delete S;
+    return set_error(TG_EINVAL, "server_create: sssp_solo_min_vertices < 0");
   }
   if (hipGetDevice(&S->device) != hipSuccess) {
     delete S;
@@ -247,12 +318,35 @@ extern "C" int server_add_graph(tg_server *S, const tg_partition *p, int32_t *gr
   std::lock_guard<std::mutex> lk(S->mu);
   const int32_t id = (int32_t)S->graphs.size();
   S->graphs.push_back(const_cast<tg_partition *>(p));
+  tg_partition *pm = const_cast<tg_partition *>(p);
+  const bool solo = p->g->has_w && p->gpu.n >= S->solo_min_n;
+  if (solo) {
+    // the layouts the single-search schedule reads, built before its
+    // threads share the partition
+    hipStream_t st = nullptr;
+    TG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    int rc = sssp_prepare(pm, st);
+    if (hipStreamSynchronize(st) != hipSuccess && rc == TG_OK)
+      rc = set_error(TG_EDEVICE, "server_add_graph: hipStreamSynchronize failed");
+    TG_QUIET(hipStreamDestroy(st));
+    if (rc != TG_OK) return rc;
+  }
   for (int kind = 0; kind < 2; ++kind) {
     std::unique_ptr<Lane> L(new Lane());
-    L->p = const_cast<tg_partition *>(p);
+    L->p = pm;
     L->kind = kind;
     TG_HIP(hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking));
+    L->solo = solo && kind == kSlotSssp;
     S->lanes.push_back(std::move(L));
+  }
+  Lane *SL = S->lanes.back().get();
+  if (SL->solo) {
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(p->tune.sssp_lanes, S->max_slots));
+    try {
+      for (int i = 0; i < nt; ++i) SL->solo_workers.emplace_back([S, SL] { S->solo_worker(SL); });
+    } catch (const std::system_error &) {
+      return set_error(TG_EDEVICE, "server_add_graph: could not start a solo SSSP thread");
+    }
   }
   *graph_id = id;
   return TG_OK;
@@ -285,7 +379,7 @@ extern "C" int server_submit(tg_server *S, int32_t graph_id, int32_t kind, int32
   S->lanes[(size_t)graph_id * 2 + k]->waiting.push_back(q.get());
   *ticket = q->ticket;
   S->queries.emplace(q->ticket, std::move(q));
-  S->cv_work.notify_one();
+  S->cv_work.notify_all();
   return TG_OK;
 }
 
@@ -341,6 +435,9 @@ extern "C" void server_destroy(tg_server *S) {
   }
   S->cv_work.notify_all();
   if (S->worker.joinable()) S->worker.join();
+  for (auto &lp : S->lanes)
+    for (auto &t : lp->solo_workers)
+      if (t.joinable()) t.join();
   for (auto &lp : S->lanes) {
     lp->eng.reset();
     if (lp->stream) TG_QUIET(hipStreamDestroy(lp->stream));

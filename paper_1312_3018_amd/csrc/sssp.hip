@@ -784,13 +784,19 @@ void sssp_lane(tg_partition *p, int lane, hipStream_t s, const int32_t *roots_lo
 
 }  // namespace
 
+int sssp_prepare(tg_partition *p, hipStream_t s) {
+  const Tuning &t = p->tune;
+  if (t.sssp_xcd) TG_TRY(build_sssp_slices(p, s));
+  if (t.sssp_pull > 0 && t.sssp_xcd == 0 && sssp_pull_supported(p->gpu)) TG_TRY(sssp_pull_prepare(p, s));
+  TG_TRY(sssp_split_prepare(p, s));
+  return TG_OK;
+}
+
 int gpu_sssp_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32_t *dist, hipStream_t s,
                    int64_t *rounds, int64_t *pulls) {
   const Tuning &t = p->tune;
   // per-partition layouts are built here, once, before lanes share them
-  if (t.sssp_xcd) TG_TRY(build_sssp_slices(p, s));
-  if (t.sssp_pull > 0 && t.sssp_xcd == 0 && sssp_pull_supported(p->gpu)) TG_TRY(sssp_pull_prepare(p, s));
-  TG_TRY(sssp_split_prepare(p, s));
+  TG_TRY(sssp_prepare(p, s));
   const int nl = (int)std::max<int64_t>(1, std::min<int64_t>(t.sssp_lanes, nr));
   hipStream_t st[MAX_LANES];
   for (int l = 0; l < nl; ++l) TG_TRY(lane_stream(p, l, s, &st[l]));

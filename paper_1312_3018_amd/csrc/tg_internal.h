@@ -524,6 +524,10 @@ size_t bfs_scratch_bytes(const GpuPart &g);
 // SSSP from local root on workspace ws (distances left in ws.state).
 int gpu_sssp(tg_partition *p, Workspace &ws, int32_t root_local, hipStream_t s, int64_t *rounds_out,
              int64_t *pulls_out = nullptr);
+// Per-partition layouts the SSSP schedules read (light counts and bins of
+// the split, pull and per-XCD layouts when enabled); built once, before
+// several searches share the partition.
+int sssp_prepare(tg_partition *p, hipStream_t s);
 // SSSP from each local root, row r of dist (original ids, V per row), with
 // up to tune.sssp_lanes searches in flight (a host thread, workspace and
 // stream each); *rounds and *pulls get the superstep counts summed over the

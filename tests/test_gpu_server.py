@@ -59,6 +59,38 @@ def test_continuous_batching_results_match_solo(gpu, graphs):
     S.close()
 
 
+@pytest.mark.parametrize("max_slots", [64, 1])
+def test_solo_sssp_lanes(gpu, graphs, max_slots):
+    """SSSP queries served as single searches (sssp_solo_min_vertices = 0:
+    every graph), beside BFS queries in the slot engines: every result
+    equals the oracle; with max_slots 1 one query per (graph, kind) runs at
+    a time."""
+    S = gpu.Server(max_slots=max_slots, sssp_solo_min_vertices=0)
+    st = run_mix(gpu, graphs, S, 96, seed=3)
+    assert st["completed"] == 96
+    if max_slots == 1:
+        assert st["max_concurrent"] <= 2 * len(graphs)
+    S.close()
+
+
+def test_solo_sssp_memory_cap(gpu, graphs):
+    """A memory cap of one SSSP query admits solo searches one at a time."""
+    import torch
+    g, w, _, P = graphs[0]
+    per_sssp = 4 * g.n + (2 * g.n + 7) // 8
+    S = gpu.Server(memory_cap_bytes=per_sssp, sssp_solo_min_vertices=0)
+    gid = S.add_graph(P)
+    roots = graphgen.sample_roots(g, 10, seed=4)
+    outs = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in roots]
+    ts = [S.submit(gid, gpu.TG_QUERY_SSSP, int(r), o) for r, o in zip(roots, outs)]
+    for t in ts:
+        S.wait(t)
+    for r, o in zip(roots, outs):
+        assert np.array_equal(o.cpu().numpy(), oracle.sssp(g.offsets, g.cols, w, int(r)))
+    assert S.stats()["max_concurrent"] == 1
+    S.close()
+
+
 def test_one_at_a_time_mode(gpu, graphs):
     S = gpu.Server(max_slots=1)
     st = run_mix(gpu, graphs, S, 24, seed=2)
@@ -116,10 +148,12 @@ def test_timeout_and_errors(gpu):
     S.close()
 
 
-def test_overflowing_query_does_not_poison_its_lane(gpu):
+@pytest.mark.parametrize("solo", [None, 0])
+def test_overflowing_query_does_not_poison_its_lane(gpu, solo):
     """An SSSP query whose distances do not fit in int32 fails with
     TG_ERANGE; queries before, beside and after it on the same (graph, SSSP)
-    lane keep their exact results (the overflow verdict is per query)."""
+    lane keep their exact results (the overflow verdict is per query), in
+    the slot engine and with solo searches."""
     import torch
     big = 2**31 - 10
     # 0 -> 1 -> 2 with huge weights (root 0 overflows at vertex 2); a path
@@ -132,7 +166,7 @@ def test_overflowing_query_does_not_poison_its_lane(gpu):
                   for v in g.cols[g.offsets[u]:g.offsets[u + 1]]], dtype=np.int32)
     G = gpu.graph_load_csr(g.n, g.offsets, g.cols, w)
     P = gpu.partition_by_degree(G)
-    S = gpu.Server()
+    S = gpu.Server(sssp_solo_min_vertices=solo)
     gid = S.add_graph(P)
     roots_before = [3, 1, 10]
     roots_after = [0, 3, 1, 50, 4, 0, 200, 1]
