@@ -184,12 +184,17 @@ int bfs(const tg_partition *p, const int32_t *roots, int32_t num_roots,
 int bfs_batched(const tg_partition *p, const int32_t *roots, int32_t num_roots,
                 int32_t *levels, void *stream);
 
-/* Single-source shortest paths by frontier Bellman-Ford (section 7.3,
- * Figure 20) over the int32 weights given to graph_load_csr.  By default a
- * superstep relaxes only active vertices below a distance threshold that
- * advances in steps of "sssp_delta" (near/far), and up to "sssp_lanes"
- * roots run at once on library streams and workspaces of their own; the
- * distances do not depend on either.
+/* Single-source shortest paths (section 7.3, Figure 20: the superstep
+ * relaxation of active vertices' out-edges) over the int32 weights given to
+ * graph_load_csr.  The schedule is the tuning's: by default delta-stepping
+ * with buckets of width "sssp_delta" kept in a ring of bitmaps
+ * ("sssp_ring"), edges lighter than the width relaxed per pass and heavier
+ * ones once per bucket ("sssp_split"), pulled instead of pushed on
+ * TG_SYMMETRIC graphs when that touches fewer edges ("sssp_hpull");
+ * "sssp_ring": 0 and "sssp_delta": 0 give the paper's frontier
+ * Bellman-Ford.  Up to "sssp_lanes" roots run at once on library streams
+ * and workspaces of their own.  The distances do not depend on any of
+ * these.
  *   dist      device int32 [num_roots * V] (TG_INF when unreachable).
  * Errors: TG_EUNSUPPORTED (graph loaded without weights), TG_ERANGE (a
  * finite distance is >= INT32_MAX), TG_EINVAL, TG_ENOMEM, TG_EDEVICE. */
