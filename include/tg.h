@@ -123,7 +123,7 @@ int partition_by_degree(const tg_graph *g, int strategy, double cpu_edge_share,
  *                (edges per block of a hub);
  *   BFS          "bfs_do" (1: direction-optimizing steps), "bfs_alpha",
  *                "bfs_beta" (the switch thresholds), "bfs_lanes" (searches
- *                in flight, 1 or 2), "bfs_td_grid", "bfs_bu_grid" (blocks of
+ *                in flight, 1..4), "bfs_td_grid", "bfs_bu_grid" (blocks of
  *                the top-down and bottom-up steps), "bfs_graph" (1: chunks of
  *                supersteps captured once as HIP graphs and replayed; kernel
  *                timing off only); "bfs_lds_words",

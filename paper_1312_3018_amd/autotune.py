@@ -41,7 +41,7 @@ SPACE = {
     "pr_grid": [256, 512, 1024],
     "bfs_td_grid": [512, 1024, 2048],
     "bfs_bu_grid": [2048, 4096, 8192],
-    "bfs_lanes": [1, 2],
+    "bfs_lanes": [1, 2, 3, 4],
     "bfs_graph": [0, 1],
     "bfs_alpha": [4, 14, 32, 64],
     "bfs_beta": [8, 24, 64],

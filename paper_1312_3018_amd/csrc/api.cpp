@@ -395,7 +395,8 @@ int parse_tuning(const char *json, Tuning *t) {
   if (t->sssp_split != 0 && t->sssp_split != 1) return set_error(TG_EINVAL, "tuning: sssp_split must be 0 or 1");
   if (t->sssp_hpull < 0 || t->sssp_hpull > 100000)
     return set_error(TG_EINVAL, "tuning: sssp_hpull must be in [0, 100000]");
-  if (t->bfs_lanes != 1 && t->bfs_lanes != 2) return set_error(TG_EINVAL, "tuning: bfs_lanes must be 1 or 2");
+  if (t->bfs_lanes < 1 || t->bfs_lanes > MAX_BFS_LANES)
+    return set_error(TG_EINVAL, "tuning: bfs_lanes outside [1, %d]", MAX_BFS_LANES);
   if (t->bfs_td_grid < 1 || t->bfs_td_grid > 16384 || t->bfs_bu_grid < 2 || t->bfs_bu_grid > 16384)
     return set_error(TG_EINVAL, "tuning: bfs_td_grid must be in [1, 16384] and bfs_bu_grid in [2, 16384]");
   if (t->sssp_xcd != 0 && t->sssp_xcd != 1) return set_error(TG_EINVAL, "tuning: sssp_xcd must be 0 or 1");
@@ -1058,9 +1059,10 @@ extern "C" int bfs(const tg_partition *pc, const int32_t *roots, int32_t num_roo
   for (int32_t r = 0; r < num_roots; ++r) local[r] = p->h_l_of_g[roots[r]];
   int64_t supersteps = 0;
   TG_TRY(gpu_bfs_roots(p, local.data(), num_roots, levels, parents, s, &supersteps));
-  // counters of both lanes (the second lane's work is ordered before s)
-  Workspace *lanes[2] = {&p->ws, p->lane_ws[0].get()};
-  const int nl = (p->tune.bfs_lanes > 1 && num_roots > 1) ? 2 : 1;
+  // counters of every lane (the other lanes' work is ordered before s)
+  const int nl = bfs_lane_count(p->tune, num_roots);
+  Workspace *lanes[MAX_BFS_LANES] = {&p->ws};
+  for (int l = 1; l < nl; ++l) lanes[l] = p->lane_ws[l - 1].get();
   for (int l = 0; l < nl; ++l)
     for (int k = 0; k < 6; ++k) TG_TRY(stat_fetch(*lanes[l], k, s));
   TG_HIP(hipStreamSynchronize(s));

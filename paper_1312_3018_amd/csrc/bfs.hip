@@ -391,25 +391,25 @@ struct BfsLane {
 // Supersteps run on the device in chunks: a search starts with as many
 // supersteps as the previous one needed (plus the one that finds the empty
 // frontier), and the host reads the control block once per chunk, adding
-// two more supersteps at a time if the search is still going.  With two
-// lanes, two searches run on two streams with a workspace each, so one
-// lane's read-back overlaps the other's kernels.
+// two more supersteps at a time if the search is still going.  With
+// several lanes (up to four), as many searches run on streams with a
+// workspace each, so one lane's read-back overlaps the others' kernels.
 int gpu_bfs_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32_t *levels, int32_t *parents,
                   hipStream_t s, int64_t *supersteps) {
   GpuPart &g = p->gpu;
   const Tuning &t = p->tune;
-  const int nl = (t.bfs_lanes > 1 && nr > 1) ? 2 : 1;
+  const int nl = bfs_lane_count(t, nr);
   // captured chunks replay without per-kernel timing events; capture needs
   // streams of the library's own (the caller's may be the null stream)
   const bool graph = t.bfs_graph != 0 && !timing_enabled();
-  BfsLane lane[2];
+  BfsLane lane[MAX_BFS_LANES];
   lane[0].ws = &p->ws;
   lane[0].s = s;
   if (graph) TG_TRY(graph_stream(p, 0, &lane[0].s));
-  if (nl == 2) {
-    TG_TRY(lane_workspace(p, 1, &lane[1].ws));
-    if (graph) TG_TRY(graph_stream(p, 1, &lane[1].s));
-    else TG_TRY(lane_stream(p, 1, s, &lane[1].s));
+  for (int l = 1; l < nl; ++l) {
+    TG_TRY(lane_workspace(p, l, &lane[l].ws));
+    if (graph) TG_TRY(graph_stream(p, l, &lane[l].s));
+    else TG_TRY(lane_stream(p, l, s, &lane[l].s));
   }
   const int64_t V = g.n_global;
   int rc = TG_OK;
@@ -451,7 +451,9 @@ int gpu_bfs_roots(tg_partition *p, const int32_t *roots_local, int32_t nr, int32
     BfsLane &L = lane[cur];
     cur = (cur + 1) % nl;
     if (L.r < 0) {
-      if (lane[0].r < 0 && lane[nl - 1].r < 0) break;
+      bool busy = false;
+      for (int l = 0; l < nl; ++l) busy |= lane[l].r >= 0;
+      if (!busy) break;
       continue;
     }
     if (hipEventSynchronize(L.ev) != hipSuccess) {

@@ -362,6 +362,13 @@ struct HybridState;
 struct SlotEngine;
 struct BcBatchState;
 constexpr int MAX_LANES = 8;  // searches in flight of one multi-root call
+constexpr int MAX_BFS_LANES = 4;  // BFS searches in flight (within MAX_LANES)
+// BFS searches in flight for nr roots under tuning t.
+inline int bfs_lane_count(const Tuning &t, int64_t nr) {
+  int64_t n = t.bfs_lanes < nr ? t.bfs_lanes : nr;
+  if (n > MAX_BFS_LANES) n = MAX_BFS_LANES;
+  return n < 1 ? 1 : (int)n;
+}
 
 }  // namespace tg
 

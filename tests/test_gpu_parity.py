@@ -105,6 +105,21 @@ def test_rmat12_bc(gpu, tuning):
     assert bc_close(got, ref)
 
 
+@pytest.mark.parametrize("lanes", [1, 3, 4])
+def test_bfs_lanes(gpu, rmat14, lanes):
+    """Several BFS searches in flight (a workspace and stream each, served in
+    turn): every row equals the oracle, with more roots than lanes and one
+    root repeated."""
+    g, w = rmat14
+    P = load(gpu, g, w, {"bfs_lanes": lanes})
+    roots = graphgen.sample_roots(g, 9, seed=31).tolist()
+    roots.append(roots[2])
+    lev = gpu.bfs(P, roots).cpu().numpy()
+    for i, r in enumerate(roots):
+        assert np.array_equal(lev[i], oracle.bfs(g.offsets, g.cols, r)), (lanes, r)
+    assert gpu.tg_last_stats()["lanes"] == min(lanes, len(roots))
+
+
 @pytest.mark.parametrize("delta", [1, 300, 1 << 20])
 def test_sssp_near_far_thresholds(gpu, rmat14, delta):
     g, w = rmat14
