@@ -345,8 +345,10 @@ extern "C" int server_add_graph(tg_server *S, const tg_partition *p, int32_t *gr
     try {
       for (int i = 0; i < nt; ++i) SL->solo_workers.emplace_back([S, SL] { S->solo_worker(SL); });
     } catch (const std::system_error &) {
-      return set_error(TG_EDEVICE, "server_add_graph: could not start a solo SSSP thread");
+      // fewer threads than asked for serve the lane; with none, its slot
+      // engine does
     }
+    if (SL->solo_workers.empty()) SL->solo = false;
   }
   *graph_id = id;
   return TG_OK;
