@@ -47,6 +47,7 @@ struct Query {
   int status = TG_OK;
   std::string err;
   int64_t bytes = 0;
+  bool held = false;  // admitted: its bytes count in mem_used
 };
 
 struct Lane {  // one (graph, kind) engine
@@ -61,7 +62,6 @@ struct Lane {  // one (graph, kind) engine
   // solo SSSP lane: its queries run as single searches on these threads
   bool solo = false;
   std::vector<std::thread> solo_workers;
-  int running = 0;  // queries the solo threads are running
 };
 
 bool json_num(const char *json, const char *key, double *out) {
@@ -91,6 +91,7 @@ struct tg_server {
   int64_t solo_min_n = int64_t(1) << 22;  // SSSP lanes of graphs this large run solo searches
   int64_t mem_cap = INT64_MAX;
   int64_t mem_used = 0;
+  int64_t held = 0;  // queries admitted and not yet finished
   int device = 0;
   bool stop = false;
   std::thread worker;
@@ -115,8 +116,17 @@ void finish(tg_server *S, Query *q, int status, const std::string &err) {
   q->err = err;
   q->done_at = clk::now();
   q->done = true;
-  S->mem_used -= q->bytes;
+  if (q->held) {  // queries that fail before admission never held memory
+    S->mem_used -= q->bytes;
+    --S->held;
+  }
   ++S->completed;
+}
+
+void admit(tg_server *S, Query *q) {
+  S->mem_used += q->bytes;
+  q->held = true;
+  if (++S->held > S->max_concurrent) S->max_concurrent = S->held;
 }
 
 }  // namespace
@@ -146,11 +156,7 @@ void tg_server::solo_worker(Lane *L) {
       cv_done.notify_all();
       continue;
     }
-    mem_used += q->bytes;
-    ++L->running;
-    int64_t running = 0;
-    for (auto &lp : lanes) running += lp->running + (lp->eng ? __builtin_popcountll(lp->eng->busy) : 0);
-    if (running > max_concurrent) max_concurrent = running;
+    admit(this, q);
     const int32_t root = p->h_l_of_g[q->root];
     lk.unlock();
     int64_t rounds = 0, pulls = 0;
@@ -161,7 +167,6 @@ void tg_server::solo_worker(Lane *L) {
     const std::string err = rc == TG_OK ? "" : tg_last_error();
     ktimer_flush();
     lk.lock();
-    --L->running;
     finish(this, q, rc, err);
     cv_done.notify_all();
     cv_work.notify_all();  // memory freed: other lanes may admit
@@ -206,7 +211,7 @@ void tg_server::run() {
         const int slot = L.eng->free_slot();
         if (slot < 0 || used >= max_slots || mem_used + q->bytes > mem_cap) break;
         L.waiting.pop_front();
-        mem_used += q->bytes;
+        admit(this, q);
         L.slot_q[slot] = q;
         int rc = L.eng->join(slot, L.p->h_l_of_g[q->root], L.kind == kSlotBfs ? q->out : nullptr);
         if (rc != TG_OK) {
@@ -223,9 +228,6 @@ void tg_server::run() {
         }
       }
     }
-    int64_t running = 0;
-    for (auto &lp : lanes) running += lp->running + (lp->eng ? __builtin_popcountll(lp->eng->busy) : 0);
-    if (running > max_concurrent) max_concurrent = running;
     if (!in_flight) {
       if (stop) break;
       cv_work.wait(lk);
@@ -316,8 +318,6 @@ extern "C" int server_add_graph(tg_server *S, const tg_partition *p, int32_t *gr
   if (!S || !p || !graph_id) return set_error(TG_EINVAL, "server_add_graph: NULL argument");
   if (p->alpha > 0.0) return set_error(TG_EUNSUPPORTED, "server_add_graph: hybrid partitions are not served");
   std::lock_guard<std::mutex> lk(S->mu);
-  const int32_t id = (int32_t)S->graphs.size();
-  S->graphs.push_back(const_cast<tg_partition *>(p));
   tg_partition *pm = const_cast<tg_partition *>(p);
   const bool solo = p->g->has_w && p->gpu.n >= S->solo_min_n;
   if (solo) {
@@ -331,14 +331,24 @@ extern "C" int server_add_graph(tg_server *S, const tg_partition *p, int32_t *gr
     TG_QUIET(hipStreamDestroy(st));
     if (rc != TG_OK) return rc;
   }
+  // the graph is registered only once both lanes exist: a lane is found
+  // at index 2 * id + kind
+  std::unique_ptr<Lane> made[2];
   for (int kind = 0; kind < 2; ++kind) {
-    std::unique_ptr<Lane> L(new Lane());
-    L->p = pm;
-    L->kind = kind;
-    TG_HIP(hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking));
-    L->solo = solo && kind == kSlotSssp;
-    S->lanes.push_back(std::move(L));
+    made[kind].reset(new Lane());
+    made[kind]->p = pm;
+    made[kind]->kind = kind;
+    made[kind]->solo = solo && kind == kSlotSssp;
+    const hipError_t e = hipStreamCreateWithFlags(&made[kind]->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      for (auto &L : made)
+        if (L && L->stream) TG_QUIET(hipStreamDestroy(L->stream));
+      return set_error(TG_EDEVICE, "server_add_graph: hipStreamCreateWithFlags failed: %s", hipGetErrorString(e));
+    }
   }
+  const int32_t id = (int32_t)S->graphs.size();
+  S->graphs.push_back(pm);
+  for (auto &L : made) S->lanes.push_back(std::move(L));
   Lane *SL = S->lanes.back().get();
   if (SL->solo) {
     const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(p->tune.sssp_lanes, S->max_slots));

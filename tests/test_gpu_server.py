@@ -187,6 +187,8 @@ def test_overflowing_query_does_not_poison_its_lane(gpu, solo):
     o = torch.empty(g.n, dtype=torch.int32, device="cuda")
     S.wait(S.submit(gid, gpu.TG_QUERY_SSSP, 3, o))
     assert np.array_equal(o.cpu().numpy(), oracle.sssp(g.offsets, g.cols, w, 3))
+    # every query, failed or not, gave its admitted bytes back
+    assert S.stats()["memory_in_use"] == 0
     S.close()
     with pytest.raises(gpu.TGError) as ei:
         gpu.sssp(P, [0])
