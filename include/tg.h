@@ -293,8 +293,12 @@ int server_submit(tg_server *s, int32_t graph_id, int32_t kind, int32_t root,
  * error. */
 int server_wait(tg_server *s, uint64_t ticket, int64_t timeout_us, double *latency_us);
 
-/* JSON counters (completed, supersteps, max_concurrent, waiting,
- * memory_in_use); same return convention as partition_info. */
+/* JSON counters: completed (queries finished, failed ones included),
+ * supersteps (slot-engine supersteps), max_concurrent (most queries admitted
+ * and not yet finished at once), waiting (queries not yet admitted),
+ * memory_in_use (the device bytes the admitted queries hold, at most the
+ * memory cap; 0 once every query has finished), max_slots; same return
+ * convention as partition_info. */
 int server_stats(tg_server *s, char *json, size_t cap);
 
 /* Stop the worker after running queries finish; waiting queries are
