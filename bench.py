@@ -394,9 +394,21 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
-# The server runs SSSP on graphs of at least this many vertices as single
-# searches (its default sssp_solo_min_vertices).
+# The server runs SSSP on graphs of at least this many vertices, whose
+# largest out-degree is at least this many times the mean, as single
+# searches (its defaults sssp_solo_min_vertices and sssp_solo_min_skew).
 SERVE_SOLO_MIN_VERTICES = 1 << 22
+SERVE_SOLO_MIN_SKEW = 16.0
+
+
+def serve_solo(g) -> bool:
+    """Whether the server's default rule runs this graph's SSSP queries as
+    single searches."""
+    import numpy as np
+    deg = np.diff(np.asarray(g.offsets))
+    mean = float(deg.sum()) / max(g.n, 1)
+    skew = float(deg.max()) / mean if mean > 0 else 0.0
+    return g.n >= SERVE_SOLO_MIN_VERTICES and skew >= SERVE_SOLO_MIN_SKEW
 
 
 def serve_capacity(tg, parts, log, batch=64):
@@ -429,7 +441,7 @@ def serve_capacity(tg, parts, log, batch=64):
             row = {"graph": SERVE_GRAPHS[gi], "kind": kind, "ms_per_query_batched": round(tb * 1e3, 3),
                    "ms_per_query_solo": round(ts * 1e3, 3)}
             served = tb
-            if kind == "sssp" and g.n >= SERVE_SOLO_MIN_VERTICES:
+            if kind == "sssp" and serve_solo(g):
                 t = time.perf_counter()
                 solo(P, roots, out)
                 torch.cuda.synchronize()

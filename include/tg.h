@@ -257,18 +257,19 @@ int cc(const tg_partition *p, int32_t *labels, void *stream);
  * queries are in flight; each query's result is the same as a solo bfs() /
  * sssp() run.  One worker thread drives all graphs; each (graph, kind) has its
  * own stream so different graphs' supersteps overlap on the device.  SSSP
- * queries on a graph of at least sssp_solo_min_vertices vertices run instead
- * as single searches (the sssp() schedule), up to the partition's
- * sssp_lanes (at most max_slots) at a time, each on its own host thread,
- * workspace and stream. */
+ * queries on a graph of at least sssp_solo_min_vertices vertices whose
+ * largest out-degree is at least sssp_solo_min_skew times its mean degree
+ * run instead as single searches (the sssp() schedule), up to the
+ * partition's sssp_lanes (at most max_slots) at a time, each on its own host
+ * thread, workspace and stream. */
 typedef struct tg_server tg_server;
 enum { TG_QUERY_BFS = 0, TG_QUERY_SSSP = 1 };
 
 /* opts_json: NULL or {"max_slots": 1..64 (concurrent queries per graph and
  * kind; 1 = one query at a time), "memory_cap_bytes": N (device bytes that
  * running queries may hold; a query over the cap waits),
- * "sssp_solo_min_vertices": N (default 2^22; 0 = every graph's SSSP queries
- * run as single searches)}.
+ * "sssp_solo_min_vertices": N (default 2^22), "sssp_solo_min_skew": X
+ * (default 16; both 0 = every graph's SSSP queries run as single searches)}.
  * Errors: TG_EINVAL, TG_ENOMEM, TG_EDEVICE. */
 int server_create(const char *opts_json, tg_server **out);
 

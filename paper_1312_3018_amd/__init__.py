@@ -347,13 +347,16 @@ class Server:
     """Continuous-batching query server (server_* in the C ABI)."""
 
     def __init__(self, max_slots: int = 64, memory_cap_bytes: Optional[int] = None,
-                 sssp_solo_min_vertices: Optional[int] = None):
+                 sssp_solo_min_vertices: Optional[int] = None,
+                 sssp_solo_min_skew: Optional[float] = None):
         lib = _load()
         opts = {"max_slots": int(max_slots)}
         if memory_cap_bytes is not None:
             opts["memory_cap_bytes"] = int(memory_cap_bytes)
         if sssp_solo_min_vertices is not None:
             opts["sssp_solo_min_vertices"] = int(sssp_solo_min_vertices)
+        if sssp_solo_min_skew is not None:
+            opts["sssp_solo_min_skew"] = float(sssp_solo_min_skew)
         h = ctypes.c_void_p()
         _check(lib.server_create(json.dumps(opts).encode(), ctypes.byref(h)))
         self._h = h.value

@@ -8,10 +8,12 @@
 // completes them, retires finished slots (results are in the caller's buffer)
 // and admits waiting queries.
 //
-// SSSP on a large graph is served by solo searches instead: the slot engine
-// relaxes every active (vertex, query) pair each superstep, which costs more
-// than the delta-stepping schedule of a single search once the graph is
-// large.  Such a lane has its own host threads (up to the partition's
+// SSSP on a large graph with hubs is served by solo searches instead: the
+// slot engine relaxes every active (vertex, query) pair each superstep,
+// which costs more than the delta-stepping schedule of a single search once
+// the graph is large and its degrees are skewed (the step schedule settles
+// a hub's neighbourhood once instead of at every superstep); on a large
+// graph without hubs the slot engine stays ahead.  Such a lane has its own host threads (up to the partition's
 // sssp_lanes, at most max_slots), each running one query at a time with the
 // single-search schedule on its own workspace and stream.
 #include <hip/hip_runtime.h>
@@ -88,7 +90,10 @@ struct tg_server {
   std::unordered_map<uint64_t, std::unique_ptr<Query>> queries;
   uint64_t next_ticket = 1;
   int max_slots = kSlots;
-  int64_t solo_min_n = int64_t(1) << 22;  // SSSP lanes of graphs this large run solo searches
+  // SSSP lanes of graphs at least this large, whose largest out-degree is at
+  // least solo_min_skew times the mean, run solo searches
+  int64_t solo_min_n = int64_t(1) << 22;
+  double solo_min_skew = 16.0;
   int64_t mem_cap = INT64_MAX;
   int64_t mem_used = 0;
   int64_t held = 0;  // queries admitted and not yet finished
@@ -292,6 +297,7 @@ extern "C" int server_create(const char *opts_json, tg_server **out) {
   if (json_num(opts_json, "max_slots", &v)) S->max_slots = (int)v;
   if (json_num(opts_json, "memory_cap_bytes", &v)) S->mem_cap = (int64_t)v;
   if (json_num(opts_json, "sssp_solo_min_vertices", &v)) S->solo_min_n = (int64_t)v;
+  if (json_num(opts_json, "sssp_solo_min_skew", &v)) S->solo_min_skew = v;
   if (S->max_slots < 1 || S->max_slots > kSlots) {
     delete S;
     return set_error(TG_EINVAL, "server_create: max_slots must be in [1, 64]");
@@ -303,6 +309,10 @@ extern "C" int server_create(const char *opts_json, tg_server **out) {
   if (S->solo_min_n < 0) {
     delete S;
     return set_error(TG_EINVAL, "server_create: sssp_solo_min_vertices < 0");
+  }
+  if (!(S->solo_min_skew >= 0.0)) {
+    delete S;
+    return set_error(TG_EINVAL, "server_create: sssp_solo_min_skew must be >= 0");
   }
   if (hipGetDevice(&S->device) != hipSuccess) {
     delete S;
@@ -319,7 +329,11 @@ extern "C" int server_add_graph(tg_server *S, const tg_partition *p, int32_t *gr
   if (p->alpha > 0.0) return set_error(TG_EUNSUPPORTED, "server_add_graph: hybrid partitions are not served");
   std::lock_guard<std::mutex> lk(S->mu);
   tg_partition *pm = const_cast<tg_partition *>(p);
-  const bool solo = p->g->has_w && p->gpu.n >= S->solo_min_n;
+  // degree skew: largest local out-degree (local ids run by decreasing
+  // out-degree) over the mean
+  const double mean_deg = p->gpu.n > 0 ? (double)p->gpu.out.m / (double)p->gpu.n : 0.0;
+  const double skew = mean_deg > 0.0 && !p->gpu.h_deg.empty() ? (double)p->gpu.h_deg[0] / mean_deg : 0.0;
+  const bool solo = p->g->has_w && p->gpu.n >= S->solo_min_n && skew >= S->solo_min_skew;
   if (solo) {
     // the layouts the single-search schedule reads, built before its
     // threads share the partition

@@ -65,7 +65,7 @@ def test_solo_sssp_lanes(gpu, graphs, max_slots):
     every graph), beside BFS queries in the slot engines: every result
     equals the oracle; with max_slots 1 one query per (graph, kind) runs at
     a time."""
-    S = gpu.Server(max_slots=max_slots, sssp_solo_min_vertices=0)
+    S = gpu.Server(max_slots=max_slots, sssp_solo_min_vertices=0, sssp_solo_min_skew=0)
     st = run_mix(gpu, graphs, S, 96, seed=3)
     assert st["completed"] == 96
     if max_slots == 1:
@@ -73,12 +73,39 @@ def test_solo_sssp_lanes(gpu, graphs, max_slots):
     S.close()
 
 
+def test_solo_rule_follows_degree_skew(gpu):
+    """With no size floor, the default skew rule serves SSSP on a star (hub
+    degree far above the mean) as single searches, which run no slot-engine
+    supersteps, and on a ring (every degree 2) through the slot engine; both
+    give the oracle's distances."""
+    import torch
+    n = 2000
+    star = graphgen.from_edges(n, np.zeros(n - 1, dtype=np.int64), np.arange(1, n), symmetrize=True)
+    ring = graphgen.from_edges(n, np.arange(n), (np.arange(n) + 1) % n, symmetrize=True)
+    for g, solo in ((star, True), (ring, False)):
+        w = graphgen.weights(g, seed=6)
+        P = gpu.partition_by_degree(gpu.graph_load_csr(g.n, g.offsets, g.cols, w))
+        S = gpu.Server(sssp_solo_min_vertices=0)
+        gid = S.add_graph(P)
+        roots = [0, 1, n // 2, n - 1]
+        outs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in roots]
+        for t in [S.submit(gid, gpu.TG_QUERY_SSSP, r, o) for r, o in zip(roots, outs)]:
+            S.wait(t)
+        for r, o in zip(roots, outs):
+            assert np.array_equal(o.cpu().numpy(), oracle.sssp(g.offsets, g.cols, w, r)), (solo, r)
+        assert (S.stats()["supersteps"] == 0) == solo
+        S.close()
+    with pytest.raises(gpu.TGError) as ei:
+        gpu.Server(sssp_solo_min_skew=-1)
+    assert ei.value.code == gpu.TG_EINVAL
+
+
 def test_solo_sssp_memory_cap(gpu, graphs):
     """A memory cap of one SSSP query admits solo searches one at a time."""
     import torch
     g, w, _, P = graphs[0]
     per_sssp = 4 * g.n + (2 * g.n + 7) // 8
-    S = gpu.Server(memory_cap_bytes=per_sssp, sssp_solo_min_vertices=0)
+    S = gpu.Server(memory_cap_bytes=per_sssp, sssp_solo_min_vertices=0, sssp_solo_min_skew=0)
     gid = S.add_graph(P)
     roots = graphgen.sample_roots(g, 10, seed=4)
     outs = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in roots]
@@ -166,7 +193,7 @@ def test_overflowing_query_does_not_poison_its_lane(gpu, solo):
                   for v in g.cols[g.offsets[u]:g.offsets[u + 1]]], dtype=np.int32)
     G = gpu.graph_load_csr(g.n, g.offsets, g.cols, w)
     P = gpu.partition_by_degree(G)
-    S = gpu.Server(sssp_solo_min_vertices=solo)
+    S = gpu.Server(sssp_solo_min_vertices=solo, sssp_solo_min_skew=solo)
     gid = S.add_graph(P)
     roots_before = [3, 1, 10]
     roots_after = [0, 3, 1, 50, 4, 0, 200, 1]
