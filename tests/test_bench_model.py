@@ -51,3 +51,19 @@ def test_model_communication_term():
 
 def test_model_without_splits():
     assert bench.hybrid_model([{"strategy": "high", "alpha": 0.0, "bfs_cpu_ms": 0}], 10, lambda s: None) is None
+
+
+def test_serve_solo_rule(monkeypatch):
+    """The serving bench takes a lane the way the server's default rule
+    serves it: single searches only on graphs at or above the vertex floor
+    whose largest out-degree is at least 16 times the mean (host logic)."""
+    import numpy as np
+
+    import graphgen
+    n = 2000
+    star = graphgen.from_edges(n, np.zeros(n - 1, dtype=np.int64), np.arange(1, n), symmetrize=True)
+    ring = graphgen.from_edges(n, np.arange(n), (np.arange(n) + 1) % n, symmetrize=True)
+    assert not bench.serve_solo(star)  # below the 2^22-vertex floor
+    monkeypatch.setattr(bench, "SERVE_SOLO_MIN_VERTICES", 0)
+    assert bench.serve_solo(star)  # skew about 1000
+    assert not bench.serve_solo(ring)  # every degree 2: skew 1
