@@ -76,3 +76,13 @@ def test_sizes_checked():
     assert lib.graph_load_csr(2**31, 0, None, None, None, 0, None, ctypes.byref(out)) == tg.TG_EINVAL
     assert lib.graph_load_csr(1, 0, None, None, None, 0, None, ctypes.byref(out)) == tg.TG_EINVAL
     assert "row_offsets is NULL" in tg.tg_last_error()
+
+
+@pytest.mark.parametrize("opts", ['{"max_slots": 0}', '{"max_slots": 65}', '{"memory_cap_bytes": -1}',
+                                  '{"sssp_solo_min_vertices": -1}', '{"sssp_solo_min_skew": -0.5}'])
+def test_server_options_checked_on_host(opts):
+    """server_create rejects out-of-range options before it touches a device."""
+    lib = tg._load()
+    h = ctypes.c_void_p()
+    assert lib.server_create(opts.encode(), ctypes.byref(h)) == tg.TG_EINVAL
+    assert not h.value
